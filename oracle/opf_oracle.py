@@ -1,0 +1,544 @@
+"""Plain FP64 CPU oracle for the per-iteration model evaluation of the
+multi-period AC OPF (Shin, Rao, Schanen, Maldonado, Anitescu, "Scalable
+Multi-Period AC Optimal Power Flow Utilizing GPUs with High Memory
+Capacities", arXiv 2405.14032).
+
+TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  It shares no code with
+the HIP library: the physics is written in complex-power form
+(S = V * conj(I) on the pi-model admittances) with hand-derived derivatives
+of that form, while the device path uses an expanded real trigonometric
+form.  Every routine is written for clarity, vectorised with numpy over
+elements, never blocked or fused.
+
+Model (Sec. II, eq. (1a)-(1k)), with the readings this build takes where the
+paper is silent or its printed formula is garbled:
+
+* branch l = (i -> j) is a pi-model line with series admittance
+  y = 1/(r + jx), total charging b_c, tap tau and shift phi; four flow
+  variables per branch: the complex power S_f = pf + j qf entering the line
+  at its from end and S_t = pt + j qt entering it at its to end
+  (eq. (1d)-(1e) as the standard pi-model; the printed pair only shows the
+  mutual term of one end);
+* flow definition rows c = x_flow - phi(V) (eq. (1d)-(1e));
+* bus balance: generation minus the flows leaving the bus through each
+  incident line end minus the load (eq. (1b)-(1c));
+* thermal limit in squared form at both ends (eq. (1f));
+* angle difference theta_i - theta_j per line (eq. (1j));
+* one two-sided ramp row per generator and period t >= 1 (eq. (1k));
+* one reference-angle row va[ref, t] = 0 per period (needed for the
+  constraint counts of Table II);
+* quadratic cost c2 p^2 + c1 p + c0 per generator and period (eq. (1a)).
+
+Lagrangian Hessian convention: sigma * Hess f + sum_i lambda_i Hess c_i
+(Sec. III-B defines W as the Hessian of the Lagrangian; the sign of the
+multipliers is the caller's).  Condensed matrix:
+K = H + diag(diag_x) + J^T diag(d) J, lower triangle (Sec. III-B, M_cond,
+with diag_x = delta_w + Sigma_x and d = D supplied by the caller).
+
+Canonical 0-based layouts (a contract shared with the library):
+  x per period: [vm N | va N | pg G | qg G | pf B | qf B | pt B | qt B]
+  c per period: [balP N | balQ N | ref 1 | cpf B | cqf B | cpt B | cqt B |
+                 thf B | tht B | ang B], then ramp rows (t-1)*G + g, t >= 1.
+  J COO per period (index = block base + local * count + element):
+     gen-balance (2 locals x G), branch-balance (4 x B), ref (1),
+     flows ((k*5 + local) x B; k in pf,qf,pt,qt; local in own,vm_i,vm_j,
+     va_i,va_j), thermal (4 x B), angle (2 x B); then the ramp block
+     (t-1)*2G + local*G + g.
+  H COO per period, lower (row >= col), duplicates kept:
+     objective (G), flows ((k*9 + local) x B), thermal (4 x B).
+  K: CSR, rows in x order, lower triangle, columns ascending, duplicates
+     merged, diagonal always present.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# flow kinds: 0 = pf, 1 = qf, 2 = pt, 3 = qt
+# local variable order of a branch: 0 = vm_i, 1 = vm_j, 2 = va_i, 3 = va_j
+PAIRS_FROM = [(0, 0), (1, 0), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2), (3, 3)]
+PAIRS_TO = [(1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2), (3, 3)]
+
+
+# ----------------------------------------------------------------------------
+# sizes and layout
+# ----------------------------------------------------------------------------
+def period_sizes(N, B, G):
+    """Per-period counts: variables, constraint rows, J entries, H entries."""
+    n_p = 2 * N + 2 * G + 4 * B
+    m_p = 2 * N + 7 * B + 1
+    nnzj_p = 2 * G + 30 * B + 1
+    nnzh_p = G + 40 * B
+    return n_p, m_p, nnzj_p, nnzh_p
+
+
+def dims(N, B, G, T):
+    """Total n, m, nnz(J), nnz(H) of a T-period instance (Sec. II, eq. (1);
+    the ramp rows of eq. (1k) exist only for t >= 2 in the paper's 1-based
+    numbering)."""
+    n_p, m_p, nnzj_p, nnzh_p = period_sizes(N, B, G)
+    return dict(n=T * n_p, m=T * m_p + G * (T - 1),
+                nnz_jac=T * nnzj_p + 2 * G * (T - 1), nnz_hess=T * nnzh_p)
+
+
+class Layout:
+    """Index arithmetic for the canonical x / c layouts."""
+
+    def __init__(self, net):
+        N, B, G, T = net.N, net.B, net.G, net.T
+        self.N, self.B, self.G, self.T = N, B, G, T
+        self.n_p, self.m_p, self.nnzj_p, self.nnzh_p = period_sizes(N, B, G)
+        # x block offsets inside one period
+        self.vm, self.va = 0, N
+        self.pg, self.qg = 2 * N, 2 * N + G
+        self.flow = [2 * N + 2 * G + k * B for k in range(4)]
+        # c block offsets inside one period
+        self.balp, self.balq, self.ref = 0, N, 2 * N
+        self.cflow = [2 * N + 1 + k * B for k in range(4)]
+        self.thf, self.tht = 2 * N + 1 + 4 * B, 2 * N + 1 + 5 * B
+        self.ang = 2 * N + 1 + 6 * B
+        d = dims(N, B, G, T)
+        self.n, self.m = d["n"], d["m"]
+
+    def xt(self, t):
+        """(T, 1) period offsets into x."""
+        return (np.arange(self.T) * self.n_p)[:, None] if t is None else t * self.n_p
+
+    def ct(self):
+        return (np.arange(self.T) * self.m_p)[:, None]
+
+    def ramp_row(self, t, g):
+        return self.T * self.m_p + (t - 1) * self.G + g
+
+
+def unpack_x(net, x):
+    """Split x into (T, .) blocks vm, va, pg, qg, pf, qf, pt, qt."""
+    L = Layout(net)
+    X = np.asarray(x, dtype=np.float64).reshape(net.T, L.n_p)
+    N, B, G = net.N, net.B, net.G
+    vm = X[:, 0:N]
+    va = X[:, N:2 * N]
+    pg = X[:, 2 * N:2 * N + G]
+    qg = X[:, 2 * N + G:2 * N + 2 * G]
+    fl = [X[:, L.flow[k]:L.flow[k] + B] for k in range(4)]
+    return vm, va, pg, qg, fl
+
+
+# ----------------------------------------------------------------------------
+# physics in complex-power form
+# ----------------------------------------------------------------------------
+def admittances(net):
+    """Pi-model branch admittances (Y_ff, Y_ft, Y_tf, Y_tt): series y between
+    the ends, j b_c / 2 shunt at each end, ideal transformer tau e^{j phi} on
+    the from side."""
+    y = 1.0 / (net.r + 1j * net.x)
+    a = net.tap * np.exp(1j * net.shift)
+    ytt = y + 0.5j * net.b_charge
+    yff = ytt / (net.tap ** 2)
+    yft = -y / np.conj(a)
+    ytf = -y / a
+    return yff, yft, ytf, ytt
+
+
+def branch_power(net, vm, va):
+    """Complex power entering each line at its from and to ends,
+    S = V conj(I) with I = Y V (the definition; flows of eq. (1d)-(1e))."""
+    yff, yft, ytf, ytt = admittances(net)
+    V = vm * np.exp(1j * va)
+    vf = V[:, net.f_bus]
+    vt = V[:, net.t_bus]
+    i_f = yff * vf + yft * vt
+    i_t = ytf * vf + ytt * vt
+    return vf * np.conj(i_f), vt * np.conj(i_t)
+
+
+def _end_terms(net, vm, va):
+    """Per end: self coefficient A and mutual term E of
+    S = A |V_o|^2 + E V_i V_j  (expanded S = V conj(Y V)), with
+    E_f = conj(Y_ft) e^{j delta}, E_t = conj(Y_tf) e^{-j delta},
+    delta = va_i - va_j."""
+    yff, yft, ytf, ytt = admittances(net)
+    vi = vm[:, net.f_bus]
+    vj = vm[:, net.t_bus]
+    delta = va[:, net.f_bus] - va[:, net.t_bus]
+    ef = np.conj(yft) * np.exp(1j * delta)
+    et = np.conj(ytf) * np.exp(-1j * delta)
+    return vi, vj, np.conj(yff), ef, np.conj(ytt), et, (np.abs(yff), np.abs(yft), np.abs(ytf), np.abs(ytt))
+
+
+def _first_derivs(vi, vj, af, ef, at, et):
+    """dS/d(vm_i, vm_j, va_i, va_j) for both ends (lists of 4 complex (T,B)).
+    From end: S_f = A_f vi^2 + E_f vi vj, dE_f/dva_i = jE_f, dE_f/dva_j = -jE_f.
+    To end:   S_t = A_t vj^2 + E_t vi vj, dE_t/dva_i = -jE_t, dE_t/dva_j = jE_t."""
+    dsf = [2 * af * vi + ef * vj, ef * vi, 1j * ef * vi * vj, -1j * ef * vi * vj]
+    dst = [et * vj, 2 * at * vj + et * vi, -1j * et * vi * vj, 1j * et * vi * vj]
+    return dsf, dst
+
+
+def _second_derivs(vi, vj, a_self, e, self_on_i, s):
+    """Symmetric 4x4 second derivatives of S = A vo^2 + E vi vj w.r.t.
+    (vm_i, vm_j, va_i, va_j); s = +1 for the from end (dE/dva_i = jE),
+    s = -1 for the to end.  Returned as dict {(a, b): complex (T,B)}."""
+    js = 1j * s
+    zero = np.zeros_like(e)
+    d = {}
+    d[(0, 0)] = 2 * a_self * np.ones_like(vi) if self_on_i else zero
+    d[(1, 1)] = zero if self_on_i else 2 * a_self * np.ones_like(vi)
+    d[(1, 0)] = e
+    d[(2, 0)] = js * e * vj
+    d[(2, 1)] = js * e * vi
+    d[(3, 0)] = -js * e * vj
+    d[(3, 1)] = -js * e * vi
+    d[(2, 2)] = (js * js) * e * vi * vj
+    d[(3, 3)] = (js * js) * e * vi * vj
+    d[(3, 2)] = (js * -js) * e * vi * vj
+    return d
+
+
+# ----------------------------------------------------------------------------
+# objective, gradient, constraints (eq. (1a)-(1k))
+# ----------------------------------------------------------------------------
+def objective(net, x):
+    """f = sum_t sum_g c2 pg^2 + c1 pg + c0 (eq. (1a), quadratic cost)."""
+    _, _, pg, _, _ = unpack_x(net, x)
+    return float(np.sum(net.c2 * pg ** 2 + net.c1 * pg + net.c0))
+
+
+def objective_mag(net, x):
+    _, _, pg, _, _ = unpack_x(net, x)
+    return float(np.sum(np.abs(net.c2 * pg ** 2) + np.abs(net.c1 * pg) + np.abs(net.c0)))
+
+
+def gradient(net, x):
+    """grad f: 2 c2 pg + c1 on the pg entries, zero elsewhere (eq. (1a))."""
+    L = Layout(net)
+    _, _, pg, _, _ = unpack_x(net, x)
+    g = np.zeros((net.T, L.n_p))
+    g[:, L.pg:L.pg + net.G] = 2 * net.c2 * pg + net.c1
+    return g.reshape(-1)
+
+
+def gradient_mag(net, x):
+    L = Layout(net)
+    _, _, pg, _, _ = unpack_x(net, x)
+    g = np.zeros((net.T, L.n_p))
+    g[:, L.pg:L.pg + net.G] = np.abs(2 * net.c2 * pg) + np.abs(net.c1)
+    return g.reshape(-1)
+
+
+def constraints(net, x, pd=None, qd=None, with_mag=False):
+    """All constraint rows in canonical order (eq. (1b)-(1f), (1j), (1k) and
+    the reference-angle row).  With ``with_mag`` also returns, per row, the
+    sum of the absolute values of its terms (the cancellation scale)."""
+    L = Layout(net)
+    pd = net.pd if pd is None else np.asarray(pd).reshape(net.T, net.N)
+    qd = net.qd if qd is None else np.asarray(qd).reshape(net.T, net.N)
+    T, N, B, G = net.T, net.N, net.B, net.G
+    vm, va, pg, qg, (pf, qf, pt, qt) = unpack_x(net, x)
+    sf, st = branch_power(net, vm, va)
+    C = np.zeros((T, L.m_p))
+    M = np.zeros((T, L.m_p))
+    # balance: generation - flows leaving through each incident end - load
+    balp = -pd.copy()
+    balq = -qd.copy()
+    magp = np.abs(pd).copy()
+    magq = np.abs(qd).copy()
+    for (arr, mag, gen, fr, to) in ((balp, magp, pg, pf, pt), (balq, magq, qg, qf, qt)):
+        np.add.at(arr, (slice(None), net.gen_bus), gen)
+        np.add.at(arr, (slice(None), net.f_bus), -fr)
+        np.add.at(arr, (slice(None), net.t_bus), -to)
+        np.add.at(mag, (slice(None), net.gen_bus), np.abs(gen))
+        np.add.at(mag, (slice(None), net.f_bus), np.abs(fr))
+        np.add.at(mag, (slice(None), net.t_bus), np.abs(to))
+    C[:, L.balp:L.balp + N] = balp
+    C[:, L.balq:L.balq + N] = balq
+    M[:, L.balp:L.balp + N] = magp
+    M[:, L.balq:L.balq + N] = magq
+    C[:, L.ref] = va[:, net.ref_bus]
+    M[:, L.ref] = np.abs(va[:, net.ref_bus])
+    # flow definitions: x_flow - phi(V)
+    phis = [sf.real, sf.imag, st.real, st.imag]
+    yff, yft, ytf, ytt = (np.abs(v) for v in admittances(net))
+    vi = vm[:, net.f_bus]
+    vj = vm[:, net.t_bus]
+    smag = [yff * vi ** 2 + yft * vi * vj] * 2 + [ytt * vj ** 2 + ytf * vi * vj] * 2
+    for k, (xv, phi) in enumerate(zip((pf, qf, pt, qt), phis)):
+        C[:, L.cflow[k]:L.cflow[k] + B] = xv - phi
+        M[:, L.cflow[k]:L.cflow[k] + B] = np.abs(xv) + smag[k]
+    # thermal limits, squared, both ends
+    C[:, L.thf:L.thf + B] = pf ** 2 + qf ** 2
+    C[:, L.tht:L.tht + B] = pt ** 2 + qt ** 2
+    M[:, L.thf:L.thf + B] = pf ** 2 + qf ** 2
+    M[:, L.tht:L.tht + B] = pt ** 2 + qt ** 2
+    # angle difference
+    C[:, L.ang:L.ang + B] = va[:, net.f_bus] - va[:, net.t_bus]
+    M[:, L.ang:L.ang + B] = np.abs(va[:, net.f_bus]) + np.abs(va[:, net.t_bus])
+    # ramp rows for t >= 1 (0-based)
+    ramp = (pg[1:] - pg[:-1]).reshape(-1)
+    rampm = (np.abs(pg[1:]) + np.abs(pg[:-1])).reshape(-1)
+    c = np.concatenate([C.reshape(-1), ramp])
+    if with_mag:
+        return c, np.concatenate([M.reshape(-1), rampm])
+    return c
+
+
+def bounds(net):
+    """Variable and row bounds (eq. (1f)-(1k); flows and angles free)."""
+    L = Layout(net)
+    T, N, B, G = net.T, net.N, net.B, net.G
+    inf = np.inf
+    lv = np.full((T, L.n_p), -inf)
+    uv = np.full((T, L.n_p), inf)
+    lv[:, L.vm:L.vm + N] = net.vmin
+    uv[:, L.vm:L.vm + N] = net.vmax
+    lv[:, L.pg:L.pg + G] = net.pmin
+    uv[:, L.pg:L.pg + G] = net.pmax
+    lv[:, L.qg:L.qg + G] = net.qmin
+    uv[:, L.qg:L.qg + G] = net.qmax
+    lc = np.zeros((T, L.m_p))
+    uc = np.zeros((T, L.m_p))
+    lc[:, L.thf:L.thf + B] = -inf
+    lc[:, L.tht:L.tht + B] = -inf
+    uc[:, L.thf:L.thf + B] = net.rate ** 2
+    uc[:, L.tht:L.tht + B] = net.rate ** 2
+    lc[:, L.ang:L.ang + B] = net.angmin
+    uc[:, L.ang:L.ang + B] = net.angmax
+    lr = np.tile(-net.ramp, T - 1)
+    ur = np.tile(net.ramp, T - 1)
+    return (lv.reshape(-1), uv.reshape(-1),
+            np.concatenate([lc.reshape(-1), lr]), np.concatenate([uc.reshape(-1), ur]))
+
+
+# ----------------------------------------------------------------------------
+# sparse Jacobian (Sec. III-A: COO expanded per pattern)
+# ----------------------------------------------------------------------------
+def jacobian(net, x, with_mag=False):
+    """Constraint Jacobian in canonical COO order: (rows, cols, vals[, mag])."""
+    L = Layout(net)
+    T, N, B, G = net.T, net.N, net.B, net.G
+    xo = (np.arange(T) * L.n_p)[:, None]
+    co = (np.arange(T) * L.m_p)[:, None]
+    f, tb, gb = net.f_bus[None, :], net.t_bus[None, :], net.gen_bus[None, :]
+    vm, va, pg, qg, fl = unpack_x(net, x)
+    vi, vj, af, ef, at, et, (myff, myft, mytf, mytt) = _end_terms(net, vm, va)
+    dsf, dst = _first_derivs(vi, vj, af, ef, at, et)
+    # magnitude bounds of the derivative terms
+    mdsf = [2 * myff * vi + myft * vj, myft * vi, myft * vi * vj, myft * vi * vj]
+    mdst = [mytf * vj, 2 * mytt * vj + mytf * vi, mytf * vi * vj, mytf * vi * vj]
+    R, Cc, V, Mg = [], [], [], []
+
+    def put(r, c, v, mg=None):
+        shape = np.broadcast_shapes(np.shape(r), np.shape(c), np.shape(v))
+        R.append(np.broadcast_to(r, shape))
+        Cc.append(np.broadcast_to(c, shape))
+        vv = np.broadcast_to(np.asarray(v, dtype=np.float64), shape)
+        V.append(vv)
+        Mg.append(np.abs(vv) if mg is None else np.broadcast_to(mg, shape))
+
+    ones_g = np.ones((T, G))
+    ones_b = np.ones((T, B))
+    # 1. generator terms of the balance rows
+    put(co + L.balp + gb, xo + L.pg + np.arange(G)[None, :], ones_g)
+    put(co + L.balq + gb, xo + L.qg + np.arange(G)[None, :], ones_g)
+    # 2. line-end terms of the balance rows
+    bidx = np.arange(B)[None, :]
+    put(co + L.balp + f, xo + L.flow[0] + bidx, -ones_b)
+    put(co + L.balq + f, xo + L.flow[1] + bidx, -ones_b)
+    put(co + L.balp + tb, xo + L.flow[2] + bidx, -ones_b)
+    put(co + L.balq + tb, xo + L.flow[3] + bidx, -ones_b)
+    # 3. reference angle
+    put(co + L.ref, xo + L.va + net.ref_bus, np.ones((T, 1)))
+    # 4. flow definitions, kind-major then local then line
+    busvar = [xo + L.vm + f, xo + L.vm + tb, xo + L.va + f, xo + L.va + tb]
+    for k in range(4):
+        ds = dsf if k < 2 else dst
+        mds = mdsf if k < 2 else mdst
+        part = (lambda z: z.real) if k % 2 == 0 else (lambda z: z.imag)
+        row = co + L.cflow[k] + bidx
+        put(row, xo + L.flow[k] + bidx, ones_b)
+        for a in range(4):
+            put(row, busvar[a], -part(ds[a]), mds[a])
+    # 5. thermal rows
+    put(co + L.thf + bidx, xo + L.flow[0] + bidx, 2 * fl[0])
+    put(co + L.thf + bidx, xo + L.flow[1] + bidx, 2 * fl[1])
+    put(co + L.tht + bidx, xo + L.flow[2] + bidx, 2 * fl[2])
+    put(co + L.tht + bidx, xo + L.flow[3] + bidx, 2 * fl[3])
+    # 6. angle rows
+    put(co + L.ang + bidx, busvar[2], ones_b)
+    put(co + L.ang + bidx, busvar[3], -ones_b)
+    rows = np.concatenate([r.astype(np.int64) for r in R], axis=1).reshape(-1)
+    cols = np.concatenate([c.astype(np.int64) for c in Cc], axis=1).reshape(-1)
+    vals = np.concatenate(V, axis=1).reshape(-1)
+    mags = np.concatenate(Mg, axis=1).reshape(-1)
+    # ramp block: (ramp(t,g), pg_t) = +1 then (ramp(t,g), pg_{t-1}) = -1
+    if T > 1:
+        t = np.arange(1, T)[:, None]
+        g = np.arange(G)[None, :]
+        rr = L.ramp_row(t, g)
+        r_rows = np.concatenate([rr, rr], axis=1).reshape(-1)
+        r_cols = np.concatenate([t * L.n_p + L.pg + g, (t - 1) * L.n_p + L.pg + g], axis=1).reshape(-1)
+        r_vals = np.concatenate([np.ones((T - 1, G)), -np.ones((T - 1, G))], axis=1).reshape(-1)
+        rows = np.concatenate([rows, r_rows])
+        cols = np.concatenate([cols, r_cols])
+        vals = np.concatenate([vals, r_vals])
+        mags = np.concatenate([mags, np.abs(r_vals)])
+    if with_mag:
+        return rows, cols, vals, mags
+    return rows, cols, vals
+
+
+# ----------------------------------------------------------------------------
+# sparse Lagrangian Hessian (Sec. III-A/III-B: W = Hessian of the Lagrangian)
+# ----------------------------------------------------------------------------
+def hessian(net, x, lam, sigma=1.0, with_mag=False):
+    """Lower-triangular COO of sigma Hess f + sum_i lam_i Hess c_i, canonical
+    order, duplicates kept."""
+    L = Layout(net)
+    T, N, B, G = net.T, net.N, net.B, net.G
+    lam = np.asarray(lam, dtype=np.float64)
+    xo = (np.arange(T) * L.n_p)[:, None]
+    LAM = lam[:T * L.m_p].reshape(T, L.m_p)
+    f, tb = net.f_bus[None, :], net.t_bus[None, :]
+    vm, va, pg, qg, fl = unpack_x(net, x)
+    vi, vj, af, ef, at, et, (myff, myft, mytf, mytt) = _end_terms(net, vm, va)
+    d2f = _second_derivs(vi, vj, af, ef, True, +1)
+    d2t = _second_derivs(vi, vj, at, et, False, -1)
+    # magnitude bounds: |A|, |E| times the same monomials
+    m2f = _second_derivs(vi, vj, myff, myft * np.ones_like(vi), True, +1)
+    m2t = _second_derivs(vi, vj, mytt, mytf * np.ones_like(vi), False, -1)
+    busvar = [xo + L.vm + f, xo + L.vm + tb, xo + L.va + f, xo + L.va + tb]
+    R, Cc, V, Mg = [], [], [], []
+    # 1. objective
+    gidx = xo + L.pg + np.arange(G)[None, :]
+    hobj = np.broadcast_to(2.0 * sigma * net.c2, (T, G))
+    R.append(gidx)
+    Cc.append(gidx)
+    V.append(hobj)
+    Mg.append(np.abs(hobj))
+    # 2. flow rows: -lam_k * Hess phi_k
+    for k in range(4):
+        d2, m2, pairs = (d2f, m2f, PAIRS_FROM) if k < 2 else (d2t, m2t, PAIRS_TO)
+        part = (lambda z: z.real) if k % 2 == 0 else (lambda z: z.imag)
+        lk = LAM[:, L.cflow[k]:L.cflow[k] + B]
+        for (a, b) in pairs:
+            ra, rb = busvar[a], busvar[b]
+            R.append(np.maximum(ra, rb))
+            Cc.append(np.minimum(ra, rb))
+            V.append(-lk * part(d2[(a, b)]))
+            Mg.append(np.abs(lk) * np.abs(m2[(a, b)]))
+    # 3. thermal rows: 2 lam on the squared flow variables
+    bidx = np.arange(B)[None, :]
+    for k, th in ((0, L.thf), (1, L.thf), (2, L.tht), (3, L.tht)):
+        v = xo + L.flow[k] + bidx
+        h = 2.0 * LAM[:, th:th + B]
+        R.append(v)
+        Cc.append(v)
+        V.append(h)
+        Mg.append(np.abs(h))
+    rows = np.concatenate([np.broadcast_to(r, (T, r.shape[1])).astype(np.int64) for r in R], axis=1).reshape(-1)
+    cols = np.concatenate([np.broadcast_to(c, (T, c.shape[1])).astype(np.int64) for c in Cc], axis=1).reshape(-1)
+    vals = np.concatenate([np.broadcast_to(v, (T, v.shape[1])) for v in V], axis=1).reshape(-1)
+    mags = np.concatenate([np.broadcast_to(v, (T, v.shape[1])) for v in Mg], axis=1).reshape(-1)
+    if with_mag:
+        return rows, cols, vals, mags
+    return rows, cols, vals
+
+
+# ----------------------------------------------------------------------------
+# adjoint products
+# ----------------------------------------------------------------------------
+def jtprod(net, x, v, with_mag=False):
+    """J^T v by a COO sparse product over this module's own Jacobian."""
+    import scipy.sparse as sp
+    L = Layout(net)
+    rows, cols, vals, mags = jacobian(net, x, with_mag=True)
+    J = sp.coo_matrix((vals, (rows, cols)), shape=(L.m, L.n))
+    out = J.T @ np.asarray(v, dtype=np.float64)
+    if with_mag:
+        Jm = sp.coo_matrix((mags, (rows, cols)), shape=(L.m, L.n))
+        return out, Jm.T @ np.abs(v)
+    return out
+
+
+def load_adjoint(net, lam):
+    """d(lam^T c)/d(pd, qd): the load enters the balance rows with
+    coefficient -1 (eq. (1b)-(1c)), so the adjoint is -lam_balP, -lam_balQ,
+    each shaped (T, N)."""
+    L = Layout(net)
+    LAM = np.asarray(lam)[:net.T * L.m_p].reshape(net.T, L.m_p)
+    return -LAM[:, L.balp:L.balp + net.N].copy(), -LAM[:, L.balq:L.balq + net.N].copy()
+
+
+# ----------------------------------------------------------------------------
+# condensed KKT matrix (Sec. III-B: M_cond = W + delta_w I + Sigma_x + A^T D A)
+# ----------------------------------------------------------------------------
+def condensed(n, jac, hess, diag_x, dcon, row_mask=None):
+    """K = lower(H + diag(diag_x) + J^T diag(dcon) J) by sort-and-reduce of
+    every contribution (row, col, value).
+
+    jac = (rows, cols, vals) with unique (row, col); hess = lower COO.
+    Returns (rowptr int64 [n+1], colind int64, vals, mag) where mag is the
+    per-slot sum of |contribution|.  ``row_mask`` (bool [n]) restricts the
+    output to the selected rows (rowptr then still spans all n rows; the
+    values of the selected rows are exactly those of the full matrix)."""
+    jr, jc, jv = (np.asarray(a) for a in jac)
+    hr, hc, hv = (np.asarray(a) for a in hess)
+    dcon = np.asarray(dcon, dtype=np.float64)
+    if diag_x is None:
+        diag_x = np.zeros(n)
+    if row_mask is not None:
+        # keep J rows that touch a selected column; H entries in selected rows
+        touch = row_mask[jc]
+        keep_rows = np.zeros(int(jr.max()) + 1 if jr.size else 1, dtype=bool)
+        keep_rows[jr[touch]] = True
+        sel = keep_rows[jr]
+        jr, jc, jv = jr[sel], jc[sel], jv[sel]
+        hs = row_mask[hr]
+        hr, hc, hv = hr[hs], hc[hs], hv[hs]
+    # pairs of entries within each J row (entry with itself included)
+    order = np.lexsort((jc, jr))
+    jr, jc, jv = jr[order], jc[order], jv[order]
+    if jr.size:
+        key = jr * (n + 1) + jc
+        if np.any(key[1:] == key[:-1]):
+            raise ValueError("J has duplicate (row, col) entries")
+    first = np.ones(jr.size, dtype=bool)
+    first[1:] = jr[1:] != jr[:-1]
+    start = np.maximum.accumulate(np.where(first, np.arange(jr.size), 0))
+    pos = np.arange(jr.size) - start
+    cnt = pos + 1
+    e = np.repeat(np.arange(jr.size), cnt)
+    q = np.arange(int(cnt.sum())) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    p = start[e] + q
+    pr = np.maximum(jc[e], jc[p])
+    pc = np.minimum(jc[e], jc[p])
+    pv = dcon[jr[e]] * jv[e] * jv[p]
+    diag_idx = np.arange(n) if row_mask is None else np.nonzero(row_mask)[0]
+    R = np.concatenate([pr, hr, diag_idx])
+    C = np.concatenate([pc, hc, diag_idx])
+    Vv = np.concatenate([pv, hv, np.asarray(diag_x, dtype=np.float64)[diag_idx]])
+    if row_mask is not None:
+        s = row_mask[R]
+        R, C, Vv = R[s], C[s], Vv[s]
+    if np.any(C > R):
+        raise ValueError("upper-triangular contribution")
+    key = R.astype(np.int64) * n + C.astype(np.int64)
+    o = np.argsort(key, kind="stable")
+    key, Vv = key[o], Vv[o]
+    uniq, first_idx = np.unique(key, return_index=True)
+    vals = np.add.reduceat(Vv, first_idx) if key.size else np.zeros(0)
+    mag = np.add.reduceat(np.abs(Vv), first_idx) if key.size else np.zeros(0)
+    rows = uniq // n
+    cols = uniq % n
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return rowptr, cols.astype(np.int64), vals, mag
+
+
+def hessian_dense(n, hess):
+    """Dense symmetric matrix of a lower COO with duplicates (for tests)."""
+    hr, hc, hv = hess
+    H = np.zeros((n, n))
+    np.add.at(H, (hr, hc), hv)
+    return H + np.tril(H, -1).T

@@ -1,0 +1,243 @@
+"""The oracle pinned to the paper and the mathematics (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import opf_oracle as O
+from paper_2405_14032_amd import synth
+
+import pins
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_table2_counts():
+    # Table II: every printed nvars / ncons reproduced by the closed forms
+    assert pins.check_table2_counts(os.path.join(GOLDEN, "table2_counts.txt")) == 0
+
+
+def test_table2_counts_reject_alternatives(tmp_path):
+    # a single thermal row per line, or two one-sided ramp rows, or no
+    # reference row would not reproduce Table II (the readings are forced)
+    orig = O.dims
+
+    def one_thermal(N, B, G, T):
+        d = orig(N, B, G, T)
+        d["m"] -= T * B
+        return d
+
+    def two_sided_ramp(N, B, G, T):
+        d = orig(N, B, G, T)
+        d["m"] += G * (T - 1)
+        return d
+
+    path = os.path.join(GOLDEN, "table2_counts.txt")
+    for alt in (one_thermal, two_sided_ramp):
+        O.dims = alt
+        try:
+            assert pins.check_table2_counts(path) > 0
+        finally:
+            O.dims = orig
+
+
+def test_flat_start_closed_form():
+    net = synth.config_network("tiny")
+    assert pins.check_flat_start(net) <= 1e-15
+    net.b_charge[:] = 0.0
+    assert pins.check_flat_start(net) <= 1e-15
+
+
+def test_lossless_line_closed_form():
+    assert pins.check_lossless_line() <= 1e-13
+
+
+def test_line_energy_conservation():
+    net, pt = pins.tiny_case()
+    assert pins.check_conservation(net, pt) <= 1e-13
+    net, pt = pins.tiny_case(stress=True)
+    assert pins.check_conservation(net, pt) <= 1e-13
+
+
+def test_two_bus_hand_example():
+    assert pins.check_two_bus_balance() <= 1e-15
+
+
+def test_objective_and_gradient():
+    net, pt = pins.tiny_case()
+    assert pins.check_objective(net, pt) <= 1e-14
+    assert pins.check_gradient_fd(net, pt) <= 1e-6
+
+
+def test_jacobian_structure_counts():
+    net, pt = pins.tiny_case()
+    assert pins.check_jacobian_structure(net, pt) == 0
+
+
+def test_jacobian_central_differences():
+    net, pt = pins.tiny_case()
+    assert pins.check_jacobian_fd(net, pt) <= 1e-7
+    net, pt = pins.tiny_case(seed=21, stress=True)
+    assert pins.check_jacobian_fd(net, pt) <= 1e-7
+
+
+def test_jacobian_invariants():
+    net, pt = pins.tiny_case(seed=5, stress=True)
+    assert pins.check_jacobian_invariants(net, pt) <= 1e-13
+
+
+def test_jacobian_dc_limit():
+    assert pins.check_dc_limit() <= 1e-14
+
+
+def test_hessian_central_differences():
+    net, pt = pins.tiny_case()
+    assert pins.check_hessian_fd(net, pt) <= 1e-6
+    pt.sigma = 0.37
+    assert pins.check_hessian_fd(net, pt) <= 1e-6
+
+
+def test_hessian_euler():
+    net, pt = pins.tiny_case(seed=9, stress=True)
+    assert pins.check_hessian_euler(net, pt) <= 1e-13
+
+
+def test_jtprod_directional_derivative():
+    net, pt = pins.tiny_case()
+    assert pins.check_jtprod_directional(net, pt) <= 1e-8
+
+
+def test_load_adjoint_central_differences():
+    net, pt = pins.tiny_case()
+    assert pins.check_load_adjoint_fd(net, pt) <= 1e-8
+
+
+def test_condensed_dense_brute_force():
+    net, pt = pins.tiny_case()
+    assert pins.check_condensed_dense(net, pt) <= 1e-13
+
+
+def test_condensed_quadratic_form_identity():
+    net = synth.make_network(300, 480, 60, 6, 77)
+    pt = synth.make_point(net, 77)
+    assert pins.check_condensed_quadratic(net, pt) <= 1e-10
+
+
+def test_condensed_pattern_count_closed_form():
+    for (N, B, G, T, seed) in ((14, 20, 5, 4, 1), (200, 320, 40, 3, 8)):
+        net = synth.make_network(N, B, G, T, seed)
+        pt = synth.make_point(net, seed)
+        L = O.Layout(net)
+        rowptr, colind, _, _ = O.condensed(L.n, O.jacobian(net, pt.x), O.hessian(net, pt.x, pt.lam),
+                                           pt.diag_x, pt.dcon)
+        assert rowptr[-1] == pins.nnz_kkt_closed_form(net)
+
+
+def test_condensed_row_mask_matches_full():
+    net, pt = pins.tiny_case()
+    L = O.Layout(net)
+    jac = O.jacobian(net, pt.x)
+    hess = O.hessian(net, pt.x, pt.lam)
+    rp, ci, v, mg = O.condensed(L.n, jac, hess, pt.diag_x, pt.dcon)
+    mask = np.zeros(L.n, dtype=bool)
+    mask[[0, 5, L.n_p + 2 * net.N + 1, L.n - 1, 2 * L.n_p + 2 * net.N + 2 * net.G + 3]] = True
+    rp2, ci2, v2, mg2 = O.condensed(L.n, jac, hess, pt.diag_x, pt.dcon, row_mask=mask)
+    for r in np.nonzero(mask)[0]:
+        a, b = rp[r], rp[r + 1]
+        a2, b2 = rp2[r], rp2[r + 1]
+        assert np.array_equal(ci[a:b], ci2[a2:b2])
+        assert np.allclose(v[a:b], v2[a2:b2], rtol=1e-15, atol=0)
+
+
+def test_bounds_layout():
+    net, pt = pins.tiny_case()
+    L = O.Layout(net)
+    lv, uv, lc, uc = O.bounds(net)
+    assert lv.shape == (L.n,) and lc.shape == (L.m,)
+    X = lv.reshape(net.T, L.n_p)
+    assert np.all(X[:, :net.N] == 0.9) and np.all(np.isinf(X[:, net.N:2 * net.N]))
+    assert np.all(uc[net.T * L.m_p:] == 0.2) and np.all(lc[net.T * L.m_p:] == -0.2)
+    # the synthetic point lies inside the variable bounds
+    assert np.all(pt.x >= lv) and np.all(pt.x <= uv)
+
+
+# ------------------------------------------------------------------ planted
+# Mistakes planted in the oracle (on the CPU) must be caught by the pins.
+def _mutate(monkeypatch, name, fn):
+    monkeypatch.setattr(O, name, fn)
+
+
+def test_planted_wrong_mutual_admittance_sign(monkeypatch):
+    orig = O.admittances
+
+    def bad(net):
+        yff, yft, ytf, ytt = orig(net)
+        return yff, -yft, ytf, ytt
+
+    _mutate(monkeypatch, "admittances", bad)
+    net, pt = pins.tiny_case()
+    assert pins.check_conservation(net, pt) > 1e-3
+
+
+def test_planted_dropped_charging(monkeypatch):
+    orig = O.admittances
+
+    def bad(net):
+        yff, yft, ytf, ytt = orig(net)
+        return yff - 0.5j * net.b_charge, yft, ytf, ytt
+
+    _mutate(monkeypatch, "admittances", bad)
+    net, pt = pins.tiny_case()
+    assert pins.check_flat_start(net) > 1e-3
+
+
+def test_planted_derivative_sign(monkeypatch):
+    orig = O._first_derivs
+
+    def bad(vi, vj, af, ef, at, et):
+        dsf, dst = orig(vi, vj, af, ef, at, et)
+        dsf[2] = -dsf[2]
+        return dsf, dst
+
+    _mutate(monkeypatch, "_first_derivs", bad)
+    net, pt = pins.tiny_case()
+    assert pins.check_jacobian_fd(net, pt) > 1e-3
+
+
+def test_planted_dropped_self_term(monkeypatch):
+    orig = O._first_derivs
+
+    def bad(vi, vj, af, ef, at, et):
+        dsf, dst = orig(vi, vj, af, ef, at, et)
+        dst[1] = et * vi
+        return dsf, dst
+
+    _mutate(monkeypatch, "_first_derivs", bad)
+    net, pt = pins.tiny_case()
+    assert pins.check_jacobian_invariants(net, pt) > 1e-3
+
+
+def test_planted_hessian_cross_term(monkeypatch):
+    orig = O._second_derivs
+
+    def bad(vi, vj, a_self, e, self_on_i, s):
+        d = orig(vi, vj, a_self, e, self_on_i, s)
+        d[(3, 2)] = -d[(3, 2)]
+        return d
+
+    _mutate(monkeypatch, "_second_derivs", bad)
+    net, pt = pins.tiny_case()
+    assert pins.check_hessian_fd(net, pt) > 1e-3
+
+
+def test_planted_transposed_condensation(monkeypatch):
+    # J D J^T in place of J^T D J cannot even be formed on the variables;
+    # a missing factor on the pair products is the plausible slip
+    orig = O.condensed
+
+    def bad(n, jac, hess, diag_x, dcon, row_mask=None):
+        return orig(n, jac, hess, diag_x, np.sqrt(np.asarray(dcon)), row_mask)
+
+    _mutate(monkeypatch, "condensed", bad)
+    net, pt = pins.tiny_case()
+    assert pins.check_condensed_dense(net, pt) > 1e-3
