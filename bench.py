@@ -1,0 +1,316 @@
+"""Benchmark of the multi-period AC OPF evaluation sweep on one MI355X.
+
+A step is one whole per-iteration evaluation sweep (objective, gradient,
+constraints, Jacobian, Hessian, J^T v and the condensed KKT matrix) of the
+paper-scale synthetic instance (N=10000 buses, B=13000 lines, G=2000
+generators, T=168 periods: 12.77M variables), inputs resident in HBM.
+value = (nnz J + nnz H + nnz K) per step / step time.  The same run times
+the batched form (64 uneven instances, one graph replay vs 64 plain sweeps)
+and the adjoint form (16 mid instances, matrix-free vs per-instance
+Jacobian + COO product), and the CPU oracle on a bounded sample.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Jac+Hess+KKT nnz/s and HBM GB/s at 12.7M vars; batched & adjoint vs plain"
+TUNE_CACHE = os.path.join(ROOT, "paper_2405_14032_amd", "tune", "mi355x.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def call_bytes(net, model):
+    """Algorithmic bytes per call (8-byte values moved at least once)."""
+    N, B, G, T = net.N, net.B, net.G, net.T
+    n, m, nj, nh, nk = model.n, model.m, model.nnz_jac, model.nnz_hess, model.nnz_kkt
+    return {
+        "obj": 8 * (G * T),
+        "grad": 8 * (n + G * T),
+        "cons": 8 * (m + n + 2 * N * T),
+        "jac": 8 * (nj + 2 * N * T + 4 * B * T),
+        "hess": 8 * (nh + 2 * N * T + 6 * B * T + G),
+        "jtprod": 8 * (2 * n + m),
+        "condensed": 8 * (nj + nh + m + n + nk),
+    }
+
+
+def event_time(torch, fn, reps):
+    """Average milliseconds of fn() over reps, HIP events on the current stream."""
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(periods: int = 24):
+    """The oracle as it stands, on the paper-scale grid over a shorter
+    horizon (a bounded sample), one full sweep; nnz/s like the GPU value."""
+    from oracle import opf_oracle as O
+    from paper_2405_14032_amd import synth
+    net = synth.make_network(10000, 13000, 2000, periods, 3)
+    pt = synth.make_point(net, 3)
+    L = O.Layout(net)
+    t0 = time.perf_counter()
+    O.objective(net, pt.x)
+    O.gradient(net, pt.x)
+    O.constraints(net, pt.x)
+    jac = O.jacobian(net, pt.x)
+    hess = O.hessian(net, pt.x, pt.lam, pt.sigma)
+    O.jtprod(net, pt.x, pt.lam)
+    rp, _, _, _ = O.condensed(L.n, jac, hess, pt.diag_x, pt.dcon)
+    dt = time.perf_counter() - t0
+    nnz = len(jac[0]) + len(hess[0]) + int(rp[-1])
+    return {"value": nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full sweep of the paper-scale grid (N=10000, B=13000, G=2000) over T={periods} "
+                      f"periods: {nnz} J+H+K nnz in {dt:.2f} s, numpy/scipy single thread"}
+
+
+def make_inputs(torch, dev, net, pt):
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    return t(pt.x), t(pt.lam), t(pt.diag_x), t(pt.dcon)
+
+
+def outputs(torch, dev, model):
+    e = lambda k: torch.empty(k, dtype=torch.float64, device=dev)
+    return dict(f=e(model.ninst), grad=e(model.n), c=e(model.m), jvals=e(model.nnz_jac),
+                hvals=e(model.nnz_hess), jtv=e(model.n), kvals=e(model.nnz_kkt))
+
+
+def bench_plain(torch, dev, args):
+    from paper_2405_14032_amd import capi, synth
+    net = synth.config_network("paper")
+    pt = synth.make_point(net, 3)
+    log(f"paper-scale instance: N={net.N} B={net.B} G={net.G} T={net.T}")
+    M = capi.Model([net], device=0)
+    M.use_current_torch_stream()
+    M.autotune(args.tune_cache)
+    X, LAM, DX, D = make_inputs(torch, dev, net, pt)
+    out = outputs(torch, dev, M)
+    sa = M.sweep_args(x=X, lam=LAM, sigma=pt.sigma, v=LAM, diag_x=DX, dcon=D, **out)
+    for _ in range(args.warmup):
+        M.sweep(sa)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        M.sweep(sa)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1e3 * dt / args.steps
+    nnz = M.nnz_jac + M.nnz_hess + M.nnz_kkt
+    by = call_bytes(net, M)
+    # per-call times, events on the model's (current) stream
+    calls = {
+        "obj": lambda: M.eval_obj(X, out["f"]),
+        "grad": lambda: M.eval_grad(X, out["grad"]),
+        "cons": lambda: M.eval_cons(X, out["c"]),
+        "jac": lambda: M.eval_jac(X, out["jvals"]),
+        "hess": lambda: M.eval_hess(X, LAM, pt.sigma, out["hvals"]),
+        "jtprod": lambda: M.jtprod(X, LAM, out["jtv"]),
+        "condensed": lambda: M.assemble_condensed(out["hvals"], out["jvals"], DX, D, out["kvals"]),
+    }
+    per = {}
+    for name, fn in calls.items():
+        t = event_time(torch, fn, args.call_reps)
+        per[name] = {"ms": round(t, 4), "gbs": round(by[name] / t / 1e6, 1)}
+    graph_ms = event_time(torch, lambda: M.sweep_graph(sa), args.call_reps)
+    sweep_bytes = sum(by.values())
+    res = {
+        "value": nnz / (ms / 1e3),
+        "ms_per_step": ms,
+        "config": {"workload": "paper-scale multi-period AC OPF evaluation sweep (synthetic grid)",
+                   "N": net.N, "B": net.B, "G": net.G, "T": net.T, "n": M.n, "m": M.m,
+                   "nnz_jac": M.nnz_jac, "nnz_hess": M.nnz_hess, "nnz_kkt": M.nnz_kkt, "seed": 3},
+        "hbm_gbs": sweep_bytes / (ms / 1e3) / 1e9,
+        "sweep_bytes": sweep_bytes,
+        "graph_sweep_ms": round(graph_ms, 4),
+        "calls": per,
+        "jhk_only_ms": round(per["jac"]["ms"] + per["hess"]["ms"] + per["condensed"]["ms"], 4),
+    }
+    kt = per["condensed"]["ms"]
+    res["roofline"] = {"bound": "hbm", "kernel": "opf_assemble_condensed (k_kkt_a + k_kkt_b)",
+                       "achieved": round(by["condensed"] / kt / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(by["condensed"] / kt / 1e6 / HBM_PEAK_GBS, 4),
+                       "algorithmic_bytes": by["condensed"], "traffic": None}
+    M.close()
+    return res
+
+
+def bench_batched(torch, dev, args):
+    from paper_2405_14032_amd import capi, synth
+    nets = synth.batched_networks(64)
+    pts = [synth.make_point(n, synth.BATCH_SEED0 + k) for k, n in enumerate(nets)]
+    log(f"batched: 64 instances, sum n = {sum(n.n for n in nets)}")
+    MB = capi.Model(nets, device=0)
+    MB.use_current_torch_stream()
+    MB.autotune(args.tune_cache)
+    cat = lambda key: np.concatenate([getattr(p, key) for p in pts])
+    pb = type("P", (), {})()
+    pb.x, pb.lam, pb.diag_x, pb.dcon = cat("x"), cat("lam"), cat("diag_x"), cat("dcon")
+    X, LAM, DX, D = make_inputs(torch, dev, None, pb)
+    ob = outputs(torch, dev, MB)
+    sb = MB.sweep_args(x=X, lam=LAM, sigma=1.0, v=LAM, diag_x=DX, dcon=D, **ob)
+    plain = []
+    for k, (net, pt) in enumerate(zip(nets, pts)):
+        Mk = capi.Model([net], device=0)
+        Mk.use_current_torch_stream()
+        xs = make_inputs(torch, dev, net, pt)
+        ok = outputs(torch, dev, Mk)
+        plain.append((Mk, xs, ok, Mk.sweep_args(x=xs[0], lam=xs[1], sigma=1.0, v=xs[1], diag_x=xs[2],
+                                                 dcon=xs[3], **ok)))
+
+    def run_plain():
+        for Mk, _, _, sk in plain:
+            Mk.sweep(sk)
+
+    g_ms = event_time(torch, lambda: MB.sweep_graph(sb), args.call_reps)
+    e_ms = event_time(torch, lambda: MB.sweep(sb), args.call_reps)
+    p_ms = event_time(torch, run_plain, max(2, args.call_reps // 4))
+    torch.cuda.synchronize()
+    # agreement: element values bit-identical, objective within 1e-12
+    worst_f = 0.0
+    identical = True
+    for k, (Mk, _, ok, _) in enumerate(plain):
+        for key, offs in (("grad", MB.x_off), ("c", MB.c_off), ("jvals", MB.j_off), ("hvals", MB.h_off),
+                          ("jtv", MB.x_off), ("kvals", MB.k_off)):
+            a = ob[key][offs[k]:offs[k + 1]]
+            identical &= bool(torch.equal(a, ok[key]))
+        fb, fp = float(ob["f"][k]), float(ok["f"][0])
+        worst_f = max(worst_f, abs(fb - fp) / max(abs(fp), 1e-300))
+    nnz = MB.nnz_jac + MB.nnz_hess + MB.nnz_kkt
+    res = {"instances": 64, "sum_n": MB.n, "graph_ms": round(g_ms, 4), "eager_persistent_ms": round(e_ms, 4),
+           "plain_64_ms": round(p_ms, 4), "speedup_vs_plain": round(p_ms / g_ms, 3),
+           "nnz_per_s": nnz / (g_ms / 1e3), "elements_bit_identical": identical, "objective_max_rel_diff": worst_f}
+    for Mk, *_ in plain:
+        Mk.close()
+    MB.close()
+    return res
+
+
+def bench_adjoint(torch, dev, args):
+    from paper_2405_14032_amd import capi, synth
+    from paper_2405_14032_amd.autograd import OpfCons
+    nets = synth.adjoint_networks(16)
+    pts = [synth.make_point(n, synth.ADJOINT_SEED0 + k) for k, n in enumerate(nets)]
+    log("adjoint: 16 mid instances")
+    MA = capi.Model(nets, device=0)
+    MA.use_current_torch_stream()
+    MA.autotune(args.tune_cache)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    X = t(np.concatenate([p.x for p in pts])).requires_grad_(True)
+    PD = t(np.concatenate([n.pd.reshape(-1) for n in nets])).requires_grad_(True)
+    QD = t(np.concatenate([n.qd.reshape(-1) for n in nets])).requires_grad_(True)
+    LAM = t(np.concatenate([p.lam for p in pts]))
+
+    def fused():
+        X.grad = PD.grad = QD.grad = None
+        c = OpfCons.apply(X, PD, QD, MA)
+        c.backward(LAM)
+
+    # plain per-instance path: eval_cons, eval_jac + COO product, load slice
+    plain = []
+    for k, (net, pt) in enumerate(zip(nets, pts)):
+        Mk = capi.Model([net], device=0)
+        Mk.use_current_torch_stream()
+        rows = torch.empty(Mk.nnz_jac, dtype=torch.int32, device=dev)
+        cols = torch.empty(Mk.nnz_jac, dtype=torch.int32, device=dev)
+        Mk.jac_structure(rows, cols)
+        a, b = MA.c_off[k], MA.c_off[k + 1]
+        xk = X.detach()[MA.x_off[k]:MA.x_off[k + 1]]
+        lk = LAM[a:b]
+        pdk = PD.detach()[k * net.T * net.N:(k + 1) * net.T * net.N]
+        qdk = QD.detach()[k * net.T * net.N:(k + 1) * net.T * net.N]
+        plain.append(dict(M=Mk, rows=rows.long(), cols=cols.long(), x=xk, lam=lk, pd=pdk, qd=qdk,
+                          jv=torch.empty(Mk.nnz_jac, dtype=torch.float64, device=dev),
+                          c=torch.empty(Mk.m, dtype=torch.float64, device=dev),
+                          g=torch.zeros(Mk.n, dtype=torch.float64, device=dev), net=net))
+
+    def run_plain():
+        for p in plain:
+            M, net = p["M"], p["net"]
+            M.set_load(p["pd"], p["qd"])
+            M.eval_cons(p["x"], p["c"])
+            M.eval_jac(p["x"], p["jv"])
+            p["g"].zero_()
+            p["g"].index_add_(0, p["cols"], p["jv"] * p["lam"][p["rows"]])
+            mp = 2 * net.N + 7 * net.B + 1
+            lam_t = p["lam"][:net.T * mp].view(net.T, mp)
+            p["gpd"] = -lam_t[:, :net.N]
+            p["gqd"] = -lam_t[:, net.N:2 * net.N]
+
+    f_ms = event_time(torch, fused, args.call_reps)
+    p_ms = event_time(torch, run_plain, max(2, args.call_reps // 4))
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, p in enumerate(plain):
+        a = X.grad[MA.x_off[k]:MA.x_off[k + 1]]
+        worst = max(worst, float(((a - p["g"]).abs() / (1 + p["g"].abs())).max()))
+    res = {"instances": 16, "fused_fwd_bwd_ms": round(f_ms, 4), "plain_ms": round(p_ms, 4),
+           "speedup_vs_plain": round(p_ms / f_ms, 3), "jtv_max_rel_diff_vs_plain": worst}
+    for p in plain:
+        p["M"].close()
+    MA.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--call-reps", type=int, default=20)
+    ap.add_argument("--tune-cache", default=TUNE_CACHE)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-plain", action="store_true", help="skip the batched and adjoint legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the evaluation path has no "
+              "multi-GPU mode in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
+    res = bench_plain(torch, dev, args)
+    log(f"plain sweep: {res['ms_per_step']:.3f} ms/step")
+    line = {"metric": METRIC, "value": res["value"], "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic (seeded grids standing in for the paper's public cases)",
+            "config": res["config"], "hbm_gbs": res["hbm_gbs"], "sweep_bytes": res["sweep_bytes"],
+            "graph_sweep_ms": res["graph_sweep_ms"], "jhk_only_ms": res["jhk_only_ms"],
+            "calls": res["calls"], "roofline": res["roofline"]}
+    if not args.only_plain:
+        line["batched"] = bench_batched(torch, dev, args)
+        log(f"batched: {line['batched']}")
+        line["adjoint"] = bench_adjoint(torch, dev, args)
+        log(f"adjoint: {line['adjoint']}")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

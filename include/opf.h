@@ -1,0 +1,215 @@
+/*
+ * opf.h -- C ABI of libopf: per-iteration model evaluation of a multi-period
+ * AC optimal power flow on one AMD MI355X (gfx950), FP64.
+ *
+ * The model is the multi-period AC OPF of Shin et al., "Scalable Multi-Period
+ * AC Optimal Power Flow Utilizing GPUs with High Memory Capacities"
+ * (arXiv 2405.14032), Sec. II, eq. (1a)-(1k), evaluated the way an
+ * interior-point iteration needs it (Sec. III): objective, gradient,
+ * constraints, sparse Jacobian and Lagrangian Hessian in COO form with
+ * sparsity fixed per repeated pattern (Sec. III-A), and the condensed KKT
+ * matrix W + delta_w I + Sigma_x + A^T D A of the lifted-KKT method
+ * (Sec. III-B).
+ *
+ * Conventions
+ *  - Indices are 0-based.  Value arrays are double.  Index arrays are int32,
+ *    CSR row pointers int64.  Creation fails with OPF_ERANGE if any global
+ *    row or column index would not fit int32.
+ *  - Status: every function returns OPF_OK (0) or a negative code; the
+ *    thread-local message of the last failure is opf_last_error().  No C++
+ *    exception crosses this boundary.
+ *  - Unless stated otherwise, array arguments of the evaluation calls are
+ *    DEVICE pointers (hipMalloc'd or torch CUDA tensors on the model's
+ *    device), owned by the caller, and the work is enqueued asynchronously on
+ *    the model's stream (opf_set_stream); the caller synchronises.
+ *  - A model is not re-entrant: calls on one model must not overlap (they
+ *    share the model's scratch).  Distinct models are independent.
+ *  - A model may hold several instances (ninst > 1, the batched form): it is
+ *    block-diagonal; x, c, the J/H COO arrays and the K CSR are the
+ *    instance-major concatenation of the per-instance arrays, with row and
+ *    column indices offset by the instance's x / c offsets
+ *    (opf_instance_offsets).  Every call evaluates all instances.
+ *
+ * Canonical per-instance layouts (N buses, B lines, G generators, T periods):
+ *  x, per period t:  [vm N | va N | pg G | qg G | pf B | qf B | pt B | qt B]
+ *                    (pf, qf: complex power entering line l = (i -> j) at
+ *                    its from end i; pt, qt: entering at its to end j)
+ *  c, per period t:  [balP N | balQ N | ref 1 | cpf B | cqf B | cpt B |
+ *                     cqt B | thf B | tht B | ang B]
+ *                    then ramp rows (t-1)*G + g for t = 1..T-1.
+ *  J COO, per period t (offset t*(2G+30B+1)); index = base + local*cnt + e:
+ *     gen-balance   2 x G : (balP[bus_g], pg_g), (balQ[bus_g], qg_g)
+ *     line-balance  4 x B : (balP[i],pf) (balQ[i],qf) (balP[j],pt) (balQ[j],qt)
+ *     ref           1     : (ref, va[ref_bus])
+ *     flows        20 x B : local = kind*5 + {own, vm_i, vm_j, va_i, va_j},
+ *                           kind in {pf, qf, pt, qt}
+ *     thermal       4 x B : (thf,pf) (thf,qf) (tht,pt) (tht,qt)
+ *     angle         2 x B : (ang, va_i) (ang, va_j)
+ *   then the ramp block at T*(2G+30B+1): (t-1)*2G + local*G + g with
+ *   local 0 = (ramp, pg_t), 1 = (ramp, pg_{t-1}).
+ *  H COO (lower, row >= col, duplicates kept), per period t (offset
+ *   t*(G+40B)): objective G x (pg,pg); flows 36 x B with local = kind*9 + p
+ *   over the row-major lower triangle of (vm_i, vm_j, va_i, va_j) without
+ *   its structural zero ((vm_j,vm_j) for pf/qf, (vm_i,vm_i) for pt/qt);
+ *   thermal 4 x B: (pf,pf) (qf,qf) (pt,pt) (qt,qt).
+ *  K CSR: rows in x order, lower triangle, strictly ascending columns,
+ *   duplicates merged, diagonal always present.
+ */
+#ifndef OPF_H
+#define OPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  OPF_OK = 0,
+  OPF_EINVAL = -1, /* bad descriptor, NULL required pointer, misuse          */
+  OPF_ERANGE = -2, /* a count or index does not fit the index types         */
+  OPF_ENOMEM = -3, /* device or host allocation failed                      */
+  OPF_EHIP = -4,   /* HIP runtime error (message holds hipGetErrorString)   */
+  OPF_ENODEV = -5  /* the call needs a device but the model is host-only    */
+};
+
+typedef struct opf_model opf_model;
+
+/* One instance, as HOST arrays (copied at creation; the caller keeps
+ * ownership).  Sec. II, eq. (1): buses N, lines B with pi-model data,
+ * generators G with quadratic cost c2 p^2 + c1 p + c0 (eq. (1a)) and bounds
+ * (eq. (1g)-(1h), (1k)), voltage bounds (eq. (1i)), line rating (eq. (1f)),
+ * angle-difference limits (eq. (1j)) and the per-period bus load profile
+ * (eq. (1b)-(1c)).  Multiple lines between one bus pair and several
+ * generators per bus are allowed. */
+typedef struct {
+  int32_t nbus, nbranch, ngen, nperiod, ref_bus; /* N>=1, B>=0, G>=1, T>=1    */
+  const double *vmin, *vmax;                     /* [N]                       */
+  const int32_t *f_bus, *t_bus;                  /* [B], in [0,N), f != t     */
+  const double *r, *x, *b_charge;                /* [B] series r + jx, charging */
+  const double *rate, *angmin, *angmax;          /* [B]                       */
+  const double *tap, *shift;                     /* [B] or NULL => 1, 0 (rad) */
+  const int32_t *gen_bus;                        /* [G], in [0,N)             */
+  const double *c2, *c1, *c0;                    /* [G]; c0 may be NULL => 0  */
+  const double *pmin, *pmax, *qmin, *qmax, *ramp;/* [G]                       */
+  const double *pd, *qd;                         /* [T*N], pd[t*N + n]        */
+} opf_instance_desc;
+
+typedef struct {
+  int64_t n, m, nnz_jac, nnz_hess, nnz_kkt; /* totals over all instances      */
+  int32_t ninst;
+} opf_dims;
+
+/* Arguments of one whole evaluation sweep.  Device pointers; an output left
+ * NULL is not computed (its inputs may then be NULL too).  kvals needs
+ * jvals and hvals (the sweep computes them first). */
+typedef struct {
+  const double *x;      /* [n]                                             */
+  const double *lambda; /* [m] multipliers of the Hessian                  */
+  double sigma;         /* objective weight of the Hessian                 */
+  const double *v;      /* [m] vector of the J^T v product                  */
+  const double *diag_x; /* [n] or NULL: diagonal added to K                */
+  const double *dcon;   /* [m] row weights D of K                          */
+  double *f;            /* [ninst] objective per instance                  */
+  double *grad;         /* [n]                                             */
+  double *c;            /* [m]                                             */
+  double *jvals;        /* [nnz_jac]                                       */
+  double *hvals;        /* [nnz_hess]                                      */
+  double *jtv;          /* [n]                                             */
+  double *kvals;        /* [nnz_kkt]                                       */
+} opf_sweep_args;
+
+/* Checks a descriptor array on the host (no device needed): sizes, index
+ * ranges, f != t, NULL pointers, finite admittances, int32 index limits.
+ * Returns OPF_OK, OPF_EINVAL or OPF_ERANGE. */
+int opf_validate(const opf_instance_desc *desc, int32_t ninst);
+
+/* Builds a model of ninst instances.  device >= 0: element tables, the
+ * per-period symbolic plans (Sec. III-A: sparsity analysed once per pattern
+ * and expanded over the data) and scratch are uploaded to that HIP device.
+ * device < 0: host-only model, only dims / offsets / opf_kkt_structure
+ * (into HOST arrays) are available; evaluation calls return OPF_ENODEV.
+ * *out receives the model (NULL on failure). */
+int opf_model_create(const opf_instance_desc *desc, int32_t ninst, int device,
+                     opf_model **out);
+void opf_model_destroy(opf_model *model); /* NULL is a no-op */
+
+int opf_model_dims(const opf_model *model, opf_dims *dims); /* host out */
+
+/* Host arrays of ninst+1 entries each (any may be NULL): starting offsets of
+ * each instance in x, c, J, H and K (the last entry is the total). */
+int opf_instance_offsets(const opf_model *model, int64_t *x_off, int64_t *c_off,
+                         int64_t *j_off, int64_t *h_off, int64_t *k_off);
+
+/* Stream for all later calls on this model (a hipStream_t; NULL = the null
+ * stream). */
+int opf_set_stream(opf_model *model, void *hip_stream);
+
+/* Variable and row bounds (eq. (1f)-(1k); flows, angles unbounded = +-inf,
+ * equality rows [0,0], ref row [0,0]).  Device [n], [n], [m], [m]. */
+int opf_bounds(const opf_model *model, double *lvar, double *uvar, double *lcon,
+               double *ucon);
+
+/* COO index arrays of J ([nnz_jac] each) and of the lower Hessian
+ * ([nnz_hess] each, row >= col), canonical order (Sec. III-A). Device. */
+int opf_jac_structure(const opf_model *model, int32_t *rows, int32_t *cols);
+int opf_hess_structure(const opf_model *model, int32_t *rows, int32_t *cols);
+
+/* CSR pattern of the lower triangle of K (Sec. III-B, M_cond; the optional
+ * compressed form of Sec. III-A): rowptr [n+1], colind [nnz_kkt].  Device
+ * arrays for a device model, HOST arrays for a host-only model. */
+int opf_kkt_structure(const opf_model *model, int64_t *rowptr, int32_t *colind);
+
+/* f = sum_t sum_g c2 pg^2 + c1 pg + c0 (eq. (1a)); f: device [ninst].
+ * Deterministic two-pass reduction. */
+int opf_eval_obj(opf_model *model, const double *x, double *f);
+/* grad f (eq. (1a)): [n], zero outside the pg entries. */
+int opf_eval_grad(opf_model *model, const double *x, double *g);
+/* All rows c(x) in canonical order (eq. (1b)-(1f), (1j), (1k), ref). [m] */
+int opf_eval_cons(opf_model *model, const double *x, double *c);
+/* Jacobian values in the canonical COO order. [nnz_jac] */
+int opf_eval_jac(opf_model *model, const double *x, double *jvals);
+/* Lower COO values of sigma Hess f + sum_i lambda_i Hess c_i (Sec. III-B:
+ * W, the Hessian of the Lagrangian; an IPM written with p_x = grad f -
+ * A^T y passes lambda = -y). [nnz_hess] */
+int opf_eval_hess(opf_model *model, const double *x, const double *lambda,
+                  double sigma, double *hvals);
+/* Matrix-free J(x)^T v (the A^T y term of p_x, Sec. III-B). [n] */
+int opf_jtprod(opf_model *model, const double *x, const double *v, double *jtv);
+/* Replace the load profile by device arrays pd, qd (concatenation over
+ * instances of [T*N] each). */
+int opf_set_load(opf_model *model, const double *pd, const double *qd);
+/* d(lambda^T c)/d(pd, qd) = (-lambda_balP, -lambda_balQ) (the load enters
+ * eq. (1b)-(1c) with coefficient -1), each the concatenation of [T*N]. */
+int opf_load_adjoint(opf_model *model, const double *lambda, double *gpd,
+                     double *gqd);
+/* K = lower(H + diag(diag_x) + J^T diag(dcon) J) into the fixed CSR of
+ * opf_kkt_structure (Sec. III-B: M_cond with diag_x = delta_w + Sigma_x and
+ * dcon = D supplied by the caller).  hvals / jvals as produced by
+ * opf_eval_hess / opf_eval_jac; diag_x may be NULL (= 0).  Every slot is
+ * written by exactly one thread: no atomics, bitwise reproducible. */
+int opf_assemble_condensed(opf_model *model, const double *hvals,
+                           const double *jvals, const double *diag_x,
+                           const double *dcon, double *kvals);
+
+/* Every requested output of one iteration's evaluation, enqueued as
+ * persistent tile-list kernels covering all instances. */
+int opf_sweep(opf_model *model, const opf_sweep_args *args);
+/* The same sweep recorded once into a HIP graph (re-recorded when the
+ * argument set changes) and replayed with a single graph launch. */
+int opf_sweep_graph(opf_model *model, const opf_sweep_args *args);
+
+/* Chooses tile shapes (lines / buses / generators per tile, periods per
+ * tile, persistent grid size) per kernel by timing candidates on the device.
+ * cache_path (host string or NULL): JSON file read for a previous result
+ * for this model shape and written after tuning. */
+int opf_autotune(opf_model *model, const char *cache_path);
+
+/* Last error message of the calling thread ("" if none). */
+const char *opf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OPF_H */

@@ -1,0 +1,272 @@
+"""ctypes binding of libopf (include/opf.h).
+
+Argument marshalling only: every computation runs in the HIP library.  The
+functions keep the C names; :class:`Model` adds ownership of the handle and
+accepts torch tensors (device arrays) for the evaluation calls.  Importing
+this module loads ``libopf.so`` from the package directory and raises if it
+is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libopf.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "opf.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2405_14032_amd/build_lib.py "
+                      "(or __graft_entry__.build())")
+lib = C.CDLL(LIB_PATH)
+
+OPF_OK, OPF_EINVAL, OPF_ERANGE, OPF_ENOMEM, OPF_EHIP, OPF_ENODEV = 0, -1, -2, -3, -4, -5
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+
+
+class opf_instance_desc(C.Structure):
+    _fields_ = [
+        ("nbus", C.c_int32), ("nbranch", C.c_int32), ("ngen", C.c_int32),
+        ("nperiod", C.c_int32), ("ref_bus", C.c_int32),
+        ("vmin", _dp), ("vmax", _dp),
+        ("f_bus", _ip), ("t_bus", _ip),
+        ("r", _dp), ("x", _dp), ("b_charge", _dp),
+        ("rate", _dp), ("angmin", _dp), ("angmax", _dp),
+        ("tap", _dp), ("shift", _dp),
+        ("gen_bus", _ip),
+        ("c2", _dp), ("c1", _dp), ("c0", _dp),
+        ("pmin", _dp), ("pmax", _dp), ("qmin", _dp), ("qmax", _dp), ("ramp", _dp),
+        ("pd", _dp), ("qd", _dp),
+    ]
+
+
+class opf_dims(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("nnz_jac", C.c_int64),
+                ("nnz_hess", C.c_int64), ("nnz_kkt", C.c_int64), ("ninst", C.c_int32)]
+
+
+class opf_sweep_args(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("lambda_", C.c_void_p), ("sigma", C.c_double),
+                ("v", C.c_void_p), ("diag_x", C.c_void_p), ("dcon", C.c_void_p),
+                ("f", C.c_void_p), ("grad", C.c_void_p), ("c", C.c_void_p),
+                ("jvals", C.c_void_p), ("hvals", C.c_void_p), ("jtv", C.c_void_p),
+                ("kvals", C.c_void_p)]
+
+
+_vp = C.c_void_p
+_SIGS = {
+    "opf_validate": (C.c_int, [C.POINTER(opf_instance_desc), C.c_int32]),
+    "opf_model_create": (C.c_int, [C.POINTER(opf_instance_desc), C.c_int32, C.c_int, C.POINTER(_vp)]),
+    "opf_model_destroy": (None, [_vp]),
+    "opf_model_dims": (C.c_int, [_vp, C.POINTER(opf_dims)]),
+    "opf_instance_offsets": (C.c_int, [_vp, _lp, _lp, _lp, _lp, _lp]),
+    "opf_set_stream": (C.c_int, [_vp, _vp]),
+    "opf_bounds": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "opf_jac_structure": (C.c_int, [_vp, _vp, _vp]),
+    "opf_hess_structure": (C.c_int, [_vp, _vp, _vp]),
+    "opf_kkt_structure": (C.c_int, [_vp, _vp, _vp]),
+    "opf_eval_obj": (C.c_int, [_vp, _vp, _vp]),
+    "opf_eval_grad": (C.c_int, [_vp, _vp, _vp]),
+    "opf_eval_cons": (C.c_int, [_vp, _vp, _vp]),
+    "opf_eval_jac": (C.c_int, [_vp, _vp, _vp]),
+    "opf_eval_hess": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp]),
+    "opf_jtprod": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "opf_set_load": (C.c_int, [_vp, _vp, _vp]),
+    "opf_load_adjoint": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "opf_assemble_condensed": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "opf_sweep": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
+    "opf_sweep_graph": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
+    "opf_autotune": (C.c_int, [_vp, C.c_char_p]),
+    "opf_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+
+def header_symbols(path: str = HEADER) -> list[str]:
+    """Function names declared in include/opf.h."""
+    text = open(path).read()
+    return sorted(set(re.findall(r"\b(opf_[a-z_]+)\s*\(", text)))
+
+
+class OpfError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = lib.opf_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+def check(code: int, where: str) -> None:
+    if code != OPF_OK:
+        raise OpfError(code, where)
+
+
+# ---------------------------------------------------------------- descriptors
+_DOUBLE_FIELDS = ["vmin", "vmax", "r", "x", "b_charge", "rate", "angmin", "angmax", "tap", "shift",
+                  "c2", "c1", "c0", "pmin", "pmax", "qmin", "qmax", "ramp", "pd", "qd"]
+_INT_FIELDS = ["f_bus", "t_bus", "gen_bus"]
+
+
+def make_desc(net, keep: list) -> opf_instance_desc:
+    """Fill a descriptor from an object with the Network attributes (host
+    numpy arrays); ``keep`` receives the contiguous copies that must outlive
+    the call."""
+    d = opf_instance_desc()
+    d.nbus, d.nbranch, d.ngen, d.nperiod = int(net.N), int(net.B), int(net.G), int(net.T)
+    d.ref_bus = int(net.ref_bus)
+    for name in _DOUBLE_FIELDS:
+        val = getattr(net, name, None)
+        if val is None:
+            setattr(d, name, None)
+            continue
+        arr = np.ascontiguousarray(np.asarray(val, dtype=np.float64).reshape(-1))
+        keep.append(arr)
+        setattr(d, name, arr.ctypes.data_as(_dp))
+    for name in _INT_FIELDS:
+        arr = np.ascontiguousarray(np.asarray(getattr(net, name), dtype=np.int32).reshape(-1))
+        keep.append(arr)
+        setattr(d, name, arr.ctypes.data_as(_ip))
+    return d
+
+
+def make_descs(nets) -> tuple:
+    keep: list = []
+    arr = (opf_instance_desc * len(nets))()
+    for k, net in enumerate(nets):
+        arr[k] = make_desc(net, keep)
+    return arr, keep
+
+
+def validate(nets) -> int:
+    descs, keep = make_descs(nets)
+    return opf_validate(descs, len(nets))
+
+
+def _ptr(t) -> int | None:
+    """Device address of a torch tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+class Model:
+    """Owns an opf_model handle.  device >= 0 puts it on that HIP device;
+    device < 0 makes a host-only model (dims, offsets, host KKT pattern)."""
+
+    def __init__(self, nets, device: int = 0):
+        if not isinstance(nets, (list, tuple)):
+            nets = [nets]
+        self.nets = list(nets)
+        descs, keep = make_descs(self.nets)
+        h = _vp()
+        check(opf_model_create(descs, len(self.nets), int(device), C.byref(h)), "opf_model_create")
+        self.h = h
+        self.device = device
+        d = opf_dims()
+        check(opf_model_dims(self.h, C.byref(d)), "opf_model_dims")
+        self.n, self.m = d.n, d.m
+        self.nnz_jac, self.nnz_hess, self.nnz_kkt = d.nnz_jac, d.nnz_hess, d.nnz_kkt
+        self.ninst = d.ninst
+        k = self.ninst + 1
+        offs = [np.zeros(k, dtype=np.int64) for _ in range(5)]
+        check(opf_instance_offsets(self.h, *[o.ctypes.data_as(_lp) for o in offs]), "opf_instance_offsets")
+        self.x_off, self.c_off, self.j_off, self.h_off, self.k_off = offs
+        self._stream = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            opf_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # stream -----------------------------------------------------------------
+    def set_stream(self, stream_handle: int | None):
+        check(opf_set_stream(self.h, stream_handle), "opf_set_stream")
+        self._stream = stream_handle
+
+    def use_current_torch_stream(self):
+        import torch
+        self.set_stream(torch.cuda.current_stream().cuda_stream)
+
+    # structure --------------------------------------------------------------
+    def bounds(self, lv, uv, lc, uc):
+        check(opf_bounds(self.h, _ptr(lv), _ptr(uv), _ptr(lc), _ptr(uc)), "opf_bounds")
+
+    def jac_structure(self, rows, cols):
+        check(opf_jac_structure(self.h, _ptr(rows), _ptr(cols)), "opf_jac_structure")
+
+    def hess_structure(self, rows, cols):
+        check(opf_hess_structure(self.h, _ptr(rows), _ptr(cols)), "opf_hess_structure")
+
+    def kkt_structure(self, rowptr, colind):
+        check(opf_kkt_structure(self.h, _ptr(rowptr), _ptr(colind)), "opf_kkt_structure")
+
+    def kkt_structure_host(self):
+        """Host-only models: the K pattern as numpy arrays."""
+        rp = np.zeros(self.n + 1, dtype=np.int64)
+        ci = np.zeros(self.nnz_kkt, dtype=np.int32)
+        check(opf_kkt_structure(self.h, rp.ctypes.data, ci.ctypes.data), "opf_kkt_structure")
+        return rp, ci
+
+    # evaluation -------------------------------------------------------------
+    def eval_obj(self, x, f):
+        check(opf_eval_obj(self.h, _ptr(x), _ptr(f)), "opf_eval_obj")
+
+    def eval_grad(self, x, g):
+        check(opf_eval_grad(self.h, _ptr(x), _ptr(g)), "opf_eval_grad")
+
+    def eval_cons(self, x, c):
+        check(opf_eval_cons(self.h, _ptr(x), _ptr(c)), "opf_eval_cons")
+
+    def eval_jac(self, x, jv):
+        check(opf_eval_jac(self.h, _ptr(x), _ptr(jv)), "opf_eval_jac")
+
+    def eval_hess(self, x, lam, sigma, hv):
+        check(opf_eval_hess(self.h, _ptr(x), _ptr(lam), float(sigma), _ptr(hv)), "opf_eval_hess")
+
+    def jtprod(self, x, v, out):
+        check(opf_jtprod(self.h, _ptr(x), _ptr(v), _ptr(out)), "opf_jtprod")
+
+    def set_load(self, pd, qd):
+        check(opf_set_load(self.h, _ptr(pd), _ptr(qd)), "opf_set_load")
+
+    def load_adjoint(self, lam, gpd, gqd):
+        check(opf_load_adjoint(self.h, _ptr(lam), _ptr(gpd), _ptr(gqd)), "opf_load_adjoint")
+
+    def assemble_condensed(self, hv, jv, diag_x, dcon, kv):
+        check(opf_assemble_condensed(self.h, _ptr(hv), _ptr(jv), _ptr(diag_x), _ptr(dcon), _ptr(kv)),
+              "opf_assemble_condensed")
+
+    @staticmethod
+    def sweep_args(x=None, lam=None, sigma=1.0, v=None, diag_x=None, dcon=None, f=None, grad=None, c=None,
+                   jvals=None, hvals=None, jtv=None, kvals=None) -> opf_sweep_args:
+        a = opf_sweep_args()
+        a.x, a.lambda_, a.sigma, a.v = _ptr(x), _ptr(lam), float(sigma), _ptr(v)
+        a.diag_x, a.dcon, a.f, a.grad, a.c = _ptr(diag_x), _ptr(dcon), _ptr(f), _ptr(grad), _ptr(c)
+        a.jvals, a.hvals, a.jtv, a.kvals = _ptr(jvals), _ptr(hvals), _ptr(jtv), _ptr(kvals)
+        return a
+
+    def sweep(self, args: opf_sweep_args):
+        check(opf_sweep(self.h, C.byref(args)), "opf_sweep")
+
+    def sweep_graph(self, args: opf_sweep_args):
+        check(opf_sweep_graph(self.h, C.byref(args)), "opf_sweep_graph")
+
+    def autotune(self, cache_path: str | None = None):
+        check(opf_autotune(self.h, cache_path.encode() if cache_path else None), "opf_autotune")

@@ -1,0 +1,965 @@
+// C ABI of libopf: model lifetime, tile lists, entry points, the graph-
+// replayed sweep and the autotuner.  Every entry point returns a status code
+// and never lets a C++ exception escape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/opf.h"
+#include "opf_device.h"
+#include "opf_host.h"
+
+using namespace opf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define OPF_HIP(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return fail(OPF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Kernel families, each with its own tile list and launch shape.
+enum Op {
+  OP_JAC,
+  OP_HESS,
+  OP_CONS,
+  OP_GRAD,
+  OP_OBJ,
+  OP_JTA,
+  OP_JTB,
+  OP_KKA,
+  OP_KKB,
+  OP_JSTR,
+  OP_HSTR,
+  OP_KSTR,
+  OP_BOUNDS,
+  OP_LADJ,
+  OP_COUNT
+};
+
+const char* kOpName[OP_COUNT] = {"jac", "hess", "cons", "grad", "obj", "jt_a", "jt_b",
+                                 "kkt_a", "kkt_b", "jac_struct", "hess_struct", "kkt_struct",
+                                 "bounds", "load_adjoint"};
+
+struct Shape {
+  int block = 256;  // elements per tile = threads per block
+  int ppt = 1;      // periods per tile
+  int grid = 0;     // 0: one block per tile; > 0: persistent grid size
+};
+
+struct TileList {
+  Shape shape;
+  Tile* d = nullptr;
+  int n = 0;
+  int cap = 0;
+  std::vector<int32_t> inst_begin;  // first tile of each instance (+ total)
+};
+
+}  // namespace
+
+struct opf_model {
+  int device = -1;
+  int n_cu = 256;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::vector<InstHost> inst;
+  int64_t n = 0, m = 0, nnzj = 0, nnzh = 0, nnzk = 0;
+  char* arena = nullptr;
+  InstDev* d_inst = nullptr;
+  std::vector<InstDev> h_dev;  // host mirror of d_inst
+  double* scratch = nullptr;
+  double* obj_partial = nullptr;
+  int obj_partial_cap = 0;
+  int32_t* d_obj_begin = nullptr;
+  TileList lists[OP_COUNT];
+  // graph-replayed sweep
+  hipGraphExec_t gexec = nullptr;
+  opf_sweep_args gargs;
+  bool gvalid = false;
+};
+
+namespace {
+
+bool host_only(const opf_model* M) { return M->device < 0; }
+
+// Element classes of each op (in launch order inside one list).
+std::vector<int> kinds_of(int op) {
+  switch (op) {
+    case OP_JAC:
+    case OP_HESS:
+    case OP_JTA:
+    case OP_KKA:
+    case OP_JSTR:
+    case OP_HSTR:
+      return {TK_BRANCH, TK_GEN};
+    case OP_CONS:
+      return {TK_BRANCH, TK_BUS, TK_GEN};
+    case OP_GRAD:
+      return {TK_VAR};
+    case OP_OBJ:
+      return {TK_GEN};
+    case OP_JTB:
+    case OP_KKB:
+    case OP_LADJ:
+      return {TK_BUS};
+    case OP_KSTR:
+      return {TK_KROW};
+    case OP_BOUNDS:
+      return {TK_VAR, TK_CON, TK_GEN};
+  }
+  return {};
+}
+
+int64_t count_of(const InstHost& I, int kind) {
+  switch (kind) {
+    case TK_BRANCH:
+      return I.B;
+    case TK_GEN:
+      return I.G;
+    case TK_BUS:
+      return I.N;
+    case TK_VAR:
+    case TK_KROW:
+      return I.n_p;
+    case TK_CON:
+      return I.m_p;
+  }
+  return 0;
+}
+
+std::vector<Tile> make_tiles(const opf_model* M, int op, const Shape& s, std::vector<int32_t>& begin) {
+  std::vector<Tile> out;
+  begin.assign(M->inst.size() + 1, 0);
+  for (size_t k = 0; k < M->inst.size(); ++k) {
+    begin[k] = (int32_t)out.size();
+    const InstHost& I = M->inst[k];
+    for (int kind : kinds_of(op)) {
+      const int64_t cnt = count_of(I, kind);
+      for (int32_t t0 = 0; t0 < I.T; t0 += s.ppt) {
+        const int32_t t1 = std::min<int32_t>(I.T, t0 + s.ppt);
+        for (int64_t e0 = 0; e0 < cnt; e0 += s.block) {
+          Tile tl;
+          tl.inst = (int32_t)k;
+          tl.kind = kind;
+          tl.e0 = (int32_t)e0;
+          tl.e1 = (int32_t)std::min<int64_t>(cnt, e0 + s.block);
+          tl.t0 = t0;
+          tl.t1 = t1;
+          out.push_back(tl);
+        }
+      }
+    }
+  }
+  begin[M->inst.size()] = (int32_t)out.size();
+  return out;
+}
+
+int set_shape(opf_model* M, int op, const Shape& s) {
+  TileList& L = M->lists[op];
+  std::vector<int32_t> begin;
+  std::vector<Tile> tiles = make_tiles(M, op, s, begin);
+  if (tiles.size() > (size_t)0x7fffffff) return fail(OPF_ERANGE, "tile list too long");
+  if ((int)tiles.size() > L.cap) {
+    if (L.d) OPF_HIP(hipFree(L.d));
+    L.d = nullptr;
+    L.cap = 0;
+    if (hipMalloc(&L.d, std::max<size_t>(1, tiles.size()) * sizeof(Tile)) != hipSuccess) {
+      L.d = nullptr;
+      return fail(OPF_ENOMEM, std::string("tile list allocation failed for ") + kOpName[op]);
+    }
+    L.cap = (int)tiles.size();
+  }
+  if (!tiles.empty())
+    OPF_HIP(hipMemcpy(L.d, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  L.n = (int)tiles.size();
+  L.shape = s;
+  L.inst_begin = begin;
+  if (op == OP_OBJ) {
+    if (L.n > M->obj_partial_cap) {
+      if (M->obj_partial) OPF_HIP(hipFree(M->obj_partial));
+      M->obj_partial = nullptr;
+      if (hipMalloc(&M->obj_partial, std::max(1, L.n) * sizeof(double)) != hipSuccess)
+        return fail(OPF_ENOMEM, "objective partial buffer allocation failed");
+      M->obj_partial_cap = L.n;
+    }
+    OPF_HIP(hipMemcpy(M->d_obj_begin, begin.data(), begin.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  M->gvalid = false;
+  return OPF_OK;
+}
+
+Launch launch_of(const opf_model* M, int op) {
+  const TileList& L = M->lists[op];
+  Launch l;
+  l.insts = M->d_inst;
+  l.tiles = L.d;
+  l.ntiles = L.n;
+  l.block = L.shape.block;
+  l.grid = L.shape.grid > 0 ? std::min(L.shape.grid, L.n) : 0;
+  l.stream = M->stream;
+  return l;
+}
+
+// Simple bump allocator over one device allocation.
+struct Arena {
+  size_t size = 0;
+  size_t take(size_t bytes) {
+    size_t at = size;
+    size += (bytes + 255) & ~size_t(255);
+    return at;
+  }
+};
+
+int upload_model(opf_model* M) {
+  Arena a;
+  struct Place {
+    size_t f_bus, t_bus, gen_bus, adm, c2, c1, c0, pd, qd, bus_ptr, bus_adj, bgen_ptr, bgen, krow, kcol, ksrc;
+    size_t vmin, vmax, pmin, pmax, qmin, qmax, ramp, rate, angmin, angmax;
+  };
+  std::vector<Place> pl(M->inst.size());
+  for (size_t k = 0; k < M->inst.size(); ++k) {
+    const InstHost& I = M->inst[k];
+    Place& p = pl[k];
+    auto b4 = [](size_t n) { return n * 4; };
+    auto b8 = [](size_t n) { return n * 8; };
+    p.f_bus = a.take(b4(I.f_bus.size()));
+    p.t_bus = a.take(b4(I.t_bus.size()));
+    p.gen_bus = a.take(b4(I.gen_bus.size()));
+    p.adm = a.take(b8(I.adm.size()));
+    p.c2 = a.take(b8(I.c2.size()));
+    p.c1 = a.take(b8(I.c1.size()));
+    p.c0 = a.take(b8(I.c0.size()));
+    p.pd = a.take(b8(I.pd.size()));
+    p.qd = a.take(b8(I.qd.size()));
+    p.bus_ptr = a.take(b4(I.bus_ptr.size()));
+    p.bus_adj = a.take(b4(I.bus_adj.size()));
+    p.bgen_ptr = a.take(b4(I.bgen_ptr.size()));
+    p.bgen = a.take(b4(I.bgen.size()));
+    p.krow = a.take(b4(I.krow.size()));
+    p.kcol = a.take(b4(I.kcol.size()));
+    p.ksrc = a.take(b4(I.ksrc.size()));
+    p.vmin = a.take(b8(I.vmin.size()));
+    p.vmax = a.take(b8(I.vmax.size()));
+    p.pmin = a.take(b8(I.pmin.size()));
+    p.pmax = a.take(b8(I.pmax.size()));
+    p.qmin = a.take(b8(I.qmin.size()));
+    p.qmax = a.take(b8(I.qmax.size()));
+    p.ramp = a.take(b8(I.ramp.size()));
+    p.rate = a.take(b8(I.rate.size()));
+    p.angmin = a.take(b8(I.angmin.size()));
+    p.angmax = a.take(b8(I.angmax.size()));
+  }
+  const size_t inst_at = a.take(sizeof(InstDev) * M->inst.size());
+  std::vector<char> host(a.size, 0);
+  auto put = [&](size_t at, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(host.data() + at, src, bytes);
+  };
+  if (hipMalloc(&M->arena, std::max<size_t>(a.size, 256)) != hipSuccess) {
+    M->arena = nullptr;
+    return fail(OPF_ENOMEM, "device arena allocation failed");
+  }
+  std::vector<InstDev> dv(M->inst.size());
+  for (size_t k = 0; k < M->inst.size(); ++k) {
+    const InstHost& I = M->inst[k];
+    const Place& p = pl[k];
+#define PUT(field) put(p.field, I.field.data(), I.field.size() * sizeof(I.field[0]))
+    PUT(f_bus);
+    PUT(t_bus);
+    PUT(gen_bus);
+    PUT(adm);
+    PUT(c2);
+    PUT(c1);
+    PUT(c0);
+    PUT(pd);
+    PUT(qd);
+    PUT(bus_ptr);
+    PUT(bus_adj);
+    PUT(bgen_ptr);
+    PUT(bgen);
+    PUT(krow);
+    PUT(kcol);
+    PUT(ksrc);
+    PUT(vmin);
+    PUT(vmax);
+    PUT(pmin);
+    PUT(pmax);
+    PUT(qmin);
+    PUT(qmax);
+    PUT(ramp);
+    PUT(rate);
+    PUT(angmin);
+    PUT(angmax);
+#undef PUT
+    InstDev& d = dv[k];
+    std::memset(&d, 0, sizeof(d));
+    d.N = I.N;
+    d.B = I.B;
+    d.G = I.G;
+    d.T = I.T;
+    d.ref = I.ref;
+    d.n_p = I.n_p;
+    d.m_p = I.m_p;
+    d.nnzj_p = I.nnzj_p;
+    d.nnzh_p = I.nnzh_p;
+    d.nnzk_p = I.nnzk_p;
+    d.x_off = I.x_off;
+    d.c_off = I.c_off;
+    d.j_off = I.j_off;
+    d.h_off = I.h_off;
+    d.k_off = I.k_off;
+    d.ld_off = I.ld_off;
+    d.s_off = I.s_off;
+    char* base = M->arena;
+#define PTR(field, T) d.field = reinterpret_cast<T>(base + p.field)
+    PTR(f_bus, const int32_t*);
+    PTR(t_bus, const int32_t*);
+    PTR(gen_bus, const int32_t*);
+    PTR(adm, const double*);
+    PTR(c2, const double*);
+    PTR(c1, const double*);
+    PTR(c0, const double*);
+    PTR(pd, double*);
+    PTR(qd, double*);
+    PTR(bus_ptr, const int32_t*);
+    PTR(bus_adj, const int32_t*);
+    PTR(bgen_ptr, const int32_t*);
+    PTR(bgen, const int32_t*);
+    PTR(krow, const int32_t*);
+    PTR(kcol, const int32_t*);
+    PTR(ksrc, const int32_t*);
+    PTR(vmin, const double*);
+    PTR(vmax, const double*);
+    PTR(pmin, const double*);
+    PTR(pmax, const double*);
+    PTR(qmin, const double*);
+    PTR(qmax, const double*);
+    PTR(ramp, const double*);
+    PTR(rate, const double*);
+    PTR(angmin, const double*);
+    PTR(angmax, const double*);
+#undef PTR
+  }
+  put(inst_at, dv.data(), dv.size() * sizeof(InstDev));
+  M->h_dev = dv;
+  M->d_inst = reinterpret_cast<InstDev*>(M->arena + inst_at);
+  OPF_HIP(hipMemcpy(M->arena, host.data(), a.size, hipMemcpyHostToDevice));
+  return OPF_OK;
+}
+
+void release(opf_model* M) {
+  if (!M) return;
+  if (M->device >= 0) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != M->device) (void)hipSetDevice(M->device);
+    if (M->gexec) (void)hipGraphExecDestroy(M->gexec);
+    for (auto& L : M->lists)
+      if (L.d) (void)hipFree(L.d);
+    if (M->arena) (void)hipFree(M->arena);
+    if (M->scratch) (void)hipFree(M->scratch);
+    if (M->obj_partial) (void)hipFree(M->obj_partial);
+    if (M->d_obj_begin) (void)hipFree(M->d_obj_begin);
+    if (M->cap_stream) (void)hipStreamDestroy(M->cap_stream);
+    if (cur >= 0 && cur != M->device) (void)hipSetDevice(cur);
+  }
+  delete M;
+}
+
+// Makes the model's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (dev < 0) return;
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+      changed = hipSetDevice(dev) == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+#define OPF_CHECK_MODEL(M)                                                 \
+  do {                                                                     \
+    if (!(M)) return fail(OPF_EINVAL, "model is NULL");                    \
+    if (host_only(M)) return fail(OPF_ENODEV, "model is host-only");       \
+  } while (0)
+
+#define OPF_REQUIRE(p, name)                                               \
+  do {                                                                     \
+    if (!(p)) return fail(OPF_EINVAL, std::string(name) + " is NULL");     \
+  } while (0)
+
+#define OPF_LAUNCHED(expr, what)                                                              \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(OPF_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- enqueue helpers
+int enq_obj(opf_model* M, const double* x, double* f) {
+  OPF_LAUNCHED(launch_obj_partial(launch_of(M, OP_OBJ), x, M->obj_partial), "objective kernel");
+  OPF_LAUNCHED(launch_obj_final(M->d_obj_begin, (int)M->inst.size(), M->obj_partial, f, M->stream),
+               "objective reduction kernel");
+  return OPF_OK;
+}
+
+int enq_jt(opf_model* M, const double* x, const double* v, double* out) {
+  OPF_LAUNCHED(launch_jt_a(launch_of(M, OP_JTA), x, v, out, M->scratch), "J^T v line kernel");
+  OPF_LAUNCHED(launch_jt_b(launch_of(M, OP_JTB), v, out, M->scratch), "J^T v bus kernel");
+  return OPF_OK;
+}
+
+int enq_kkt(opf_model* M, const double* h, const double* j, const double* dx, const double* d, double* k) {
+  OPF_LAUNCHED(launch_kkt_a(launch_of(M, OP_KKA), h, j, dx, d, k, M->scratch), "condensed line kernel");
+  OPF_LAUNCHED(launch_kkt_b(launch_of(M, OP_KKB), j, dx, d, k, M->scratch), "condensed bus kernel");
+  return OPF_OK;
+}
+
+int check_sweep_args(const opf_sweep_args* a) {
+  if (!a) return fail(OPF_EINVAL, "sweep args are NULL");
+  const bool need_x = a->f || a->grad || a->c || a->jvals || a->hvals || a->jtv;
+  if (need_x && !a->x) return fail(OPF_EINVAL, "sweep: x is NULL");
+  if (a->hvals && !a->lambda) return fail(OPF_EINVAL, "sweep: lambda is NULL");
+  if (a->jtv && !a->v) return fail(OPF_EINVAL, "sweep: v is NULL");
+  if (a->kvals && (!a->jvals || !a->hvals || !a->dcon))
+    return fail(OPF_EINVAL, "sweep: kvals needs jvals, hvals and dcon");
+  return OPF_OK;
+}
+
+int enq_sweep(opf_model* M, const opf_sweep_args* a) {
+  if (a->jvals) OPF_LAUNCHED(launch_jac(launch_of(M, OP_JAC), a->x, a->jvals), "Jacobian kernel");
+  if (a->hvals)
+    OPF_LAUNCHED(launch_hess(launch_of(M, OP_HESS), a->x, a->lambda, a->sigma, a->hvals), "Hessian kernel");
+  if (a->c) OPF_LAUNCHED(launch_cons(launch_of(M, OP_CONS), a->x, a->c), "constraint kernel");
+  if (a->grad) OPF_LAUNCHED(launch_grad(launch_of(M, OP_GRAD), a->x, a->grad), "gradient kernel");
+  int rc;
+  if (a->f && (rc = enq_obj(M, a->x, a->f)) != OPF_OK) return rc;
+  if (a->jtv && (rc = enq_jt(M, a->x, a->v, a->jtv)) != OPF_OK) return rc;
+  if (a->kvals && (rc = enq_kkt(M, a->hvals, a->jvals, a->diag_x, a->dcon, a->kvals)) != OPF_OK) return rc;
+  return OPF_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+extern "C" {
+
+const char* opf_last_error(void) { return g_err.c_str(); }
+
+int opf_validate(const opf_instance_desc* desc, int32_t ninst) {
+  try {
+    std::string err;
+    int rc = validate_descs(desc, ninst, err);
+    if (rc != OPF_OK) return fail(rc, err);
+    return OPF_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(OPF_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(OPF_EINVAL, "unexpected host exception");
+  }
+}
+
+int opf_model_create(const opf_instance_desc* desc, int32_t ninst, int device, opf_model** out) {
+  if (!out) return fail(OPF_EINVAL, "out is NULL");
+  *out = nullptr;
+  opf_model* M = nullptr;
+  try {
+    std::string err;
+    int rc = validate_descs(desc, ninst, err);
+    if (rc != OPF_OK) return fail(rc, err);
+    if (const char* inj = std::getenv("OPF_TEST_FAIL_ALLOC")) {
+      if (std::strcmp(inj, "1") == 0) return fail(OPF_ENOMEM, "allocation failure injected by OPF_TEST_FAIL_ALLOC");
+    }
+    M = new opf_model();
+    M->device = device;
+    M->inst.resize(ninst);
+    for (int32_t k = 0; k < ninst; ++k) {
+      rc = build_instance(desc[k], M->inst[k], err);
+      if (rc != OPF_OK) {
+        release(M);
+        return fail(rc, "instance " + std::to_string(k) + ": " + err);
+      }
+    }
+    rc = assign_offsets(M->inst, err);
+    if (rc != OPF_OK) {
+      release(M);
+      return fail(rc, err);
+    }
+    for (const auto& I : M->inst) {
+      M->n += I.n;
+      M->m += I.m;
+      M->nnzj += I.nnzj;
+      M->nnzh += I.nnzh;
+      M->nnzk += I.nnzk;
+    }
+    if (device < 0) {
+      *out = M;
+      return OPF_OK;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+      release(M);
+      return fail(OPF_EINVAL, "device " + std::to_string(device) + " is not available");
+    }
+    DeviceGuard guard(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+      M->n_cu = prop.multiProcessorCount;
+    if ((rc = upload_model(M)) != OPF_OK) {
+      std::string e = g_err;
+      release(M);
+      return fail(rc, e);
+    }
+    size_t scr = 0;
+    for (const auto& I : M->inst) scr += 14ull * I.B * I.T;
+    if (hipMalloc(&M->scratch, std::max<size_t>(scr, 1) * sizeof(double)) != hipSuccess) {
+      M->scratch = nullptr;
+      release(M);
+      return fail(OPF_ENOMEM, "scratch allocation failed");
+    }
+    if (hipMalloc(&M->d_obj_begin, (ninst + 1) * sizeof(int32_t)) != hipSuccess) {
+      M->d_obj_begin = nullptr;
+      release(M);
+      return fail(OPF_ENOMEM, "allocation failed");
+    }
+    if (hipStreamCreateWithFlags(&M->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      M->cap_stream = nullptr;
+      release(M);
+      return fail(OPF_EHIP, "stream creation failed");
+    }
+    for (int op = 0; op < OP_COUNT; ++op) {
+      Shape s;
+      if ((rc = set_shape(M, op, s)) != OPF_OK) {
+        std::string e = g_err;
+        release(M);
+        return fail(rc, e);
+      }
+    }
+    *out = M;
+    return OPF_OK;
+  } catch (const std::bad_alloc&) {
+    release(M);
+    return fail(OPF_ENOMEM, "host allocation failed");
+  } catch (...) {
+    release(M);
+    return fail(OPF_EINVAL, "unexpected host exception");
+  }
+}
+
+void opf_model_destroy(opf_model* model) { release(model); }
+
+int opf_model_dims(const opf_model* M, opf_dims* d) {
+  if (!M || !d) return fail(OPF_EINVAL, "model or dims is NULL");
+  d->n = M->n;
+  d->m = M->m;
+  d->nnz_jac = M->nnzj;
+  d->nnz_hess = M->nnzh;
+  d->nnz_kkt = M->nnzk;
+  d->ninst = (int32_t)M->inst.size();
+  return OPF_OK;
+}
+
+int opf_instance_offsets(const opf_model* M, int64_t* x_off, int64_t* c_off, int64_t* j_off, int64_t* h_off,
+                         int64_t* k_off) {
+  if (!M) return fail(OPF_EINVAL, "model is NULL");
+  const size_t K = M->inst.size();
+  for (size_t k = 0; k < K; ++k) {
+    const InstHost& I = M->inst[k];
+    if (x_off) x_off[k] = I.x_off;
+    if (c_off) c_off[k] = I.c_off;
+    if (j_off) j_off[k] = I.j_off;
+    if (h_off) h_off[k] = I.h_off;
+    if (k_off) k_off[k] = I.k_off;
+  }
+  if (x_off) x_off[K] = M->n;
+  if (c_off) c_off[K] = M->m;
+  if (j_off) j_off[K] = M->nnzj;
+  if (h_off) h_off[K] = M->nnzh;
+  if (k_off) k_off[K] = M->nnzk;
+  return OPF_OK;
+}
+
+int opf_set_stream(opf_model* M, void* s) {
+  OPF_CHECK_MODEL(M);
+  M->stream = reinterpret_cast<hipStream_t>(s);
+  return OPF_OK;
+}
+
+int opf_bounds(const opf_model* M, double* lv, double* uv, double* lc, double* uc) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(lv && uv && lc && uc, "a bounds array");
+  DeviceGuard g(M->device);
+  OPF_LAUNCHED(launch_bounds(launch_of(M, OP_BOUNDS), lv, uv, lc, uc), "bounds kernel");
+  return OPF_OK;
+}
+
+int opf_jac_structure(const opf_model* M, int32_t* rows, int32_t* cols) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(rows && cols, "rows / cols");
+  DeviceGuard g(M->device);
+  OPF_LAUNCHED(launch_jac_struct(launch_of(M, OP_JSTR), rows, cols), "Jacobian structure kernel");
+  return OPF_OK;
+}
+
+int opf_hess_structure(const opf_model* M, int32_t* rows, int32_t* cols) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(rows && cols, "rows / cols");
+  DeviceGuard g(M->device);
+  OPF_LAUNCHED(launch_hess_struct(launch_of(M, OP_HSTR), rows, cols), "Hessian structure kernel");
+  return OPF_OK;
+}
+
+int opf_kkt_structure(const opf_model* M, int64_t* rowptr, int32_t* colind) {
+  if (!M) return fail(OPF_EINVAL, "model is NULL");
+  OPF_REQUIRE(rowptr && colind, "rowptr / colind");
+  try {
+    if (host_only(M)) {
+      kkt_structure_host(M->inst, rowptr, colind);
+      return OPF_OK;
+    }
+  } catch (...) {
+    return fail(OPF_EINVAL, "unexpected host exception");
+  }
+  DeviceGuard g(M->device);
+  OPF_LAUNCHED(launch_kkt_struct(launch_of(M, OP_KSTR), (int)M->inst.size(), rowptr, colind),
+               "condensed structure kernel");
+  return OPF_OK;
+}
+
+int opf_eval_obj(opf_model* M, const double* x, double* f) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(x && f, "x / f");
+  DeviceGuard g(M->device);
+  return enq_obj(M, x, f);
+}
+
+int opf_eval_grad(opf_model* M, const double* x, double* gr) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(x && gr, "x / g");
+  DeviceGuard g(M->device);
+  OPF_LAUNCHED(launch_grad(launch_of(M, OP_GRAD), x, gr), "gradient kernel");
+  return OPF_OK;
+}
+
+int opf_eval_cons(opf_model* M, const double* x, double* c) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(x && c, "x / c");
+  DeviceGuard g(M->device);
+  OPF_LAUNCHED(launch_cons(launch_of(M, OP_CONS), x, c), "constraint kernel");
+  return OPF_OK;
+}
+
+int opf_eval_jac(opf_model* M, const double* x, double* jv) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(x && jv, "x / jvals");
+  DeviceGuard g(M->device);
+  OPF_LAUNCHED(launch_jac(launch_of(M, OP_JAC), x, jv), "Jacobian kernel");
+  return OPF_OK;
+}
+
+int opf_eval_hess(opf_model* M, const double* x, const double* lam, double sigma, double* hv) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(x && lam && hv, "x / lambda / hvals");
+  DeviceGuard g(M->device);
+  OPF_LAUNCHED(launch_hess(launch_of(M, OP_HESS), x, lam, sigma, hv), "Hessian kernel");
+  return OPF_OK;
+}
+
+int opf_jtprod(opf_model* M, const double* x, const double* v, double* out) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(x && v && out, "x / v / jtv");
+  DeviceGuard g(M->device);
+  return enq_jt(M, x, v, out);
+}
+
+int opf_set_load(opf_model* M, const double* pd, const double* qd) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(pd && qd, "pd / qd");
+  DeviceGuard g(M->device);
+  for (size_t k = 0; k < M->inst.size(); ++k) {
+    const InstHost& I = M->inst[k];
+    const size_t bytes = (size_t)I.T * I.N * sizeof(double);
+    OPF_HIP(hipMemcpyAsync(M->h_dev[k].pd, pd + I.ld_off, bytes, hipMemcpyDeviceToDevice, M->stream));
+    OPF_HIP(hipMemcpyAsync(M->h_dev[k].qd, qd + I.ld_off, bytes, hipMemcpyDeviceToDevice, M->stream));
+  }
+  return OPF_OK;
+}
+
+int opf_load_adjoint(opf_model* M, const double* lam, double* gpd, double* gqd) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(lam && gpd && gqd, "lambda / gpd / gqd");
+  DeviceGuard g(M->device);
+  OPF_LAUNCHED(launch_load_adjoint(launch_of(M, OP_LADJ), lam, gpd, gqd), "load adjoint kernel");
+  return OPF_OK;
+}
+
+int opf_assemble_condensed(opf_model* M, const double* hv, const double* jv, const double* dx, const double* d,
+                           double* kv) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(hv && jv && d && kv, "hvals / jvals / dcon / kvals");
+  DeviceGuard g(M->device);
+  return enq_kkt(M, hv, jv, dx, d, kv);
+}
+
+int opf_sweep(opf_model* M, const opf_sweep_args* a) {
+  OPF_CHECK_MODEL(M);
+  int rc = check_sweep_args(a);
+  if (rc != OPF_OK) return rc;
+  DeviceGuard g(M->device);
+  return enq_sweep(M, a);
+}
+
+int opf_sweep_graph(opf_model* M, const opf_sweep_args* a) {
+  OPF_CHECK_MODEL(M);
+  int rc = check_sweep_args(a);
+  if (rc != OPF_OK) return rc;
+  DeviceGuard g(M->device);
+  if (!M->gvalid || std::memcmp(&M->gargs, a, sizeof(opf_sweep_args)) != 0) {
+    if (M->gexec) {
+      OPF_HIP(hipGraphExecDestroy(M->gexec));
+      M->gexec = nullptr;
+    }
+    M->gvalid = false;
+    hipStream_t keep = M->stream;
+    M->stream = M->cap_stream;
+    OPF_HIP(hipStreamBeginCapture(M->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = enq_sweep(M, a);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(M->cap_stream, &graph);
+    M->stream = keep;
+    if (rc != OPF_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(OPF_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&M->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      M->gexec = nullptr;
+      return fail(OPF_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    M->gargs = *a;
+    M->gvalid = true;
+  }
+  OPF_HIP(hipGraphLaunch(M->gexec, M->stream));
+  return OPF_OK;
+}
+
+}  // extern "C"
+
+// ============================================================== autotuner
+namespace {
+
+std::string shape_key(const opf_model* M) {
+  std::ostringstream s;
+  s << "cu" << M->n_cu << "_k" << M->inst.size();
+  int64_t sn = 0, sb = 0, sg = 0, st = 0;
+  for (const auto& I : M->inst) {
+    sn += (int64_t)I.N * I.T;
+    sb += (int64_t)I.B * I.T;
+    sg += (int64_t)I.G * I.T;
+    st += I.T;
+  }
+  s << "_nt" << sn << "_bt" << sb << "_gt" << sg << "_t" << st;
+  return s.str();
+}
+
+// Minimal reader for the cache written below: one line per key,
+//   "key": {"op": [block, ppt, grid], ...}
+bool read_cache(const char* path, const std::string& key, std::vector<Shape>& shapes) {
+  if (!path) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  const std::string tag = "\"" + key + "\"";
+  while (std::getline(f, line)) {
+    if (line.find(tag) == std::string::npos) continue;
+    shapes.assign(OP_COUNT, Shape());
+    for (int op = 0; op < OP_COUNT; ++op) {
+      std::string name = std::string("\"") + kOpName[op] + "\": [";
+      size_t at = line.find(name);
+      if (at == std::string::npos) return false;
+      int b = 0, p = 0, g = 0;
+      if (std::sscanf(line.c_str() + at + name.size(), "%d, %d, %d", &b, &p, &g) != 3) return false;
+      if (b < 64 || b > 512 || (b & 63) || p < 1 || g < 0) return false;
+      shapes[op].block = b;
+      shapes[op].ppt = p;
+      shapes[op].grid = g;
+    }
+    return true;
+  }
+  return false;
+}
+
+void write_cache(const char* path, const std::string& key, const opf_model* M) {
+  if (!path) return;
+  std::vector<std::string> keep;
+  {
+    std::ifstream f(path);
+    std::string line;
+    const std::string tag = "\"" + key + "\"";
+    while (f && std::getline(f, line))
+      if (line.find("\": {") != std::string::npos && line.find(tag) == std::string::npos) keep.push_back(line);
+  }
+  std::ostringstream s;
+  s << "  \"" << key << "\": {";
+  for (int op = 0; op < OP_COUNT; ++op) {
+    const Shape& sh = M->lists[op].shape;
+    s << "\"" << kOpName[op] << "\": [" << sh.block << ", " << sh.ppt << ", " << sh.grid << "]"
+      << (op + 1 < OP_COUNT ? ", " : "");
+  }
+  s << "}";
+  keep.push_back(s.str());
+  std::ofstream o(path);
+  o << "{\n";
+  for (size_t i = 0; i < keep.size(); ++i) {
+    std::string l = keep[i];
+    while (!l.empty() && (l.back() == ',' || l.back() == ' ')) l.pop_back();
+    o << l << (i + 1 < keep.size() ? ",\n" : "\n");
+  }
+  o << "}\n";
+}
+
+}  // namespace
+
+extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
+  OPF_CHECK_MODEL(M);
+  DeviceGuard guard(M->device);
+  const std::string key = shape_key(M);
+  std::vector<Shape> cached;
+  int rc;
+  if (read_cache(cache_path, key, cached)) {
+    for (int op = 0; op < OP_COUNT; ++op)
+      if ((rc = set_shape(M, op, cached[op])) != OPF_OK) return rc;
+    return OPF_OK;
+  }
+  // scratch inputs / outputs for timing (contents only need to be finite)
+  const size_t n = M->n, m = M->m;
+  double *x = nullptr, *lam = nullptr, *dx = nullptr, *d = nullptr, *out_n = nullptr, *out_m = nullptr;
+  double *jv = nullptr, *hv = nullptr, *kv = nullptr;
+  auto cleanup = [&]() {
+    for (double* p : {x, lam, dx, d, out_n, out_m, jv, hv, kv})
+      if (p) (void)hipFree(p);
+  };
+  if (hipMalloc(&x, n * 8) != hipSuccess || hipMalloc(&lam, m * 8) != hipSuccess ||
+      hipMalloc(&dx, n * 8) != hipSuccess || hipMalloc(&d, m * 8) != hipSuccess ||
+      hipMalloc(&out_n, n * 8) != hipSuccess || hipMalloc(&out_m, m * 8) != hipSuccess ||
+      hipMalloc(&jv, M->nnzj * 8) != hipSuccess || hipMalloc(&hv, M->nnzh * 8) != hipSuccess ||
+      hipMalloc(&kv, M->nnzk * 8) != hipSuccess) {
+    cleanup();
+    return fail(OPF_ENOMEM, "autotune buffers");
+  }
+  {
+    std::vector<double> hx(n, 1.0), hm(m, 0.5);
+    if (hipMemcpy(x, hx.data(), n * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dx, hx.data(), n * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(lam, hm.data(), m * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d, hm.data(), m * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      cleanup();
+      return fail(OPF_EHIP, "autotune upload");
+    }
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  auto run = [&](int op) -> hipError_t {
+    switch (op) {
+      case OP_JAC:
+        return launch_jac(launch_of(M, op), x, jv);
+      case OP_HESS:
+        return launch_hess(launch_of(M, op), x, lam, 1.0, hv);
+      case OP_CONS:
+        return launch_cons(launch_of(M, op), x, out_m);
+      case OP_GRAD:
+        return launch_grad(launch_of(M, op), x, out_n);
+      case OP_OBJ:
+        return launch_obj_partial(launch_of(M, op), x, M->obj_partial);
+      case OP_JTA:
+        return launch_jt_a(launch_of(M, op), x, lam, out_n, M->scratch);
+      case OP_JTB:
+        return launch_jt_b(launch_of(M, op), lam, out_n, M->scratch);
+      case OP_KKA:
+        return launch_kkt_a(launch_of(M, op), hv, jv, dx, d, kv, M->scratch);
+      case OP_KKB:
+        return launch_kkt_b(launch_of(M, op), jv, dx, d, kv, M->scratch);
+    }
+    return hipSuccess;
+  };
+  // fill J and H once so the condensed candidates read finite data
+  (void)run(OP_JAC);
+  (void)run(OP_HESS);
+  const int tuned[] = {OP_JAC, OP_HESS, OP_CONS, OP_GRAD, OP_OBJ, OP_JTA, OP_JTB, OP_KKA, OP_KKB};
+  const int blocks[] = {64, 128, 256, 512};
+  const int ppts[] = {1, 2, 4, 8};
+  rc = OPF_OK;
+  for (int op : tuned) {
+    Shape best = M->lists[op].shape;
+    float best_ms = 1e30f;
+    for (int b : blocks) {
+      if (op == OP_OBJ && b > 512) continue;
+      for (int p : ppts) {
+        for (int gm = 0; gm < 2; ++gm) {
+          Shape s;
+          s.block = b;
+          s.ppt = p;
+          s.grid = gm == 0 ? 0 : M->n_cu * (2048 / b);
+          if ((rc = set_shape(M, op, s)) != OPF_OK) break;
+          if (gm == 1 && M->lists[op].n <= s.grid) continue;  // same as one block per tile
+          hipError_t he = run(op);
+          if (he != hipSuccess) {
+            rc = fail(OPF_EHIP, std::string("autotune launch: ") + hipGetErrorString(he));
+            break;
+          }
+          float ms_min = 1e30f;
+          for (int rep = 0; rep < 3; ++rep) {
+            (void)hipEventRecord(e0, M->stream);
+            (void)run(op);
+            (void)hipEventRecord(e1, M->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms_min = std::min(ms_min, ms);
+          }
+          if (ms_min < best_ms) {
+            best_ms = ms_min;
+            best = s;
+          }
+        }
+        if (rc != OPF_OK) break;
+      }
+      if (rc != OPF_OK) break;
+    }
+    if (rc != OPF_OK) break;
+    if ((rc = set_shape(M, op, best)) != OPF_OK) break;
+  }
+  (void)hipStreamSynchronize(M->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  cleanup();
+  if (rc != OPF_OK) return rc;
+  // structure / bounds / adjoint kernels follow their evaluation siblings
+  set_shape(M, OP_JSTR, M->lists[OP_JAC].shape);
+  set_shape(M, OP_HSTR, M->lists[OP_HESS].shape);
+  set_shape(M, OP_LADJ, M->lists[OP_JTB].shape);
+  write_cache(cache_path, key, M);
+  return OPF_OK;
+}

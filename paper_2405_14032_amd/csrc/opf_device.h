@@ -1,0 +1,85 @@
+// Device-visible instance descriptor, tile list entries and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace opf {
+
+// One instance as the kernels see it: sizes, concatenation offsets and
+// device pointers into the model's arena.  Lives in device memory (an array
+// over instances) and is read with uniform loads.
+struct InstDev {
+  int32_t N, B, G, T, ref, pad;
+  int64_t n_p, m_p, nnzj_p, nnzh_p, nnzk_p;
+  int64_t x_off, c_off, j_off, h_off, k_off, ld_off, s_off;
+  const int32_t *f_bus, *t_bus, *gen_bus;
+  const double* adm;  // [8][B]: Gff Bff Gft Bft Gtf Btf Gtt Btt
+  const double *c2, *c1, *c0;
+  double *pd, *qd;  // [T][N]
+  const int32_t *bus_ptr, *bus_adj, *bgen_ptr, *bgen;
+  const int32_t *krow, *kcol, *ksrc;
+  const double *vmin, *vmax, *pmin, *pmax, *qmin, *qmax, *ramp, *rate, *angmin, *angmax;
+};
+
+// Element classes a tile can cover.
+enum TileKind : int32_t {
+  TK_BRANCH = 0,  // lines
+  TK_GEN = 1,     // generators
+  TK_BUS = 2,     // buses
+  TK_VAR = 3,     // local variable slots of a period block
+  TK_CON = 4,     // local constraint rows of a period block
+  TK_KROW = 5     // local rows of the condensed-matrix template
+};
+
+// A tile: elements [e0, e1) of one kind of one instance over periods
+// [t0, t1).  Thread threadIdx.x owns element e0 + threadIdx.x and walks the
+// periods; e1 - e0 <= blockDim.x.
+struct Tile {
+  int32_t inst, kind, e0, e1, t0, t1;
+};
+
+// Start of period t's block of K inside one instance (device twin of the
+// host helper in opf_host.h): periods t >= 1 carry G extra ramp-pair slots.
+__device__ __forceinline__ int64_t kkt_period_offset_dev(int64_t nnzk_p, int32_t G, int32_t t) {
+  return (int64_t)t * nnzk_p + (t >= 1 ? (int64_t)(t - 1) * G : 0);
+}
+
+// Scratch doubles per line and period: 10 for the condensed assembly's
+// line -> bus hand-off, 4 for the J^T v line -> bus hand-off.
+constexpr int kScratchKkt = 10;
+constexpr int kScratchJt = 4;
+
+// Kernel launchers (opf_kernels.hip).  Each takes the device instance
+// array, a device tile list and a launch shape; returns the HIP error of the
+// launch.
+struct Launch {
+  const InstDev* insts;
+  const Tile* tiles;
+  int ntiles;
+  int block;
+  int grid;
+  hipStream_t stream;
+};
+
+hipError_t launch_jac(const Launch& L, const double* x, double* jv);
+hipError_t launch_hess(const Launch& L, const double* x, const double* lam, double sigma, double* hv);
+hipError_t launch_cons(const Launch& L, const double* x, double* c);
+hipError_t launch_grad(const Launch& L, const double* x, double* g);
+hipError_t launch_obj_partial(const Launch& L, const double* x, double* partial);
+hipError_t launch_obj_final(const int32_t* inst_tile_begin, int ninst, const double* partial, double* f,
+                            hipStream_t s);
+hipError_t launch_jt_a(const Launch& L, const double* x, const double* v, double* out, double* scratch);
+hipError_t launch_jt_b(const Launch& L, const double* v, double* out, const double* scratch);
+hipError_t launch_kkt_a(const Launch& L, const double* h, const double* j, const double* dx, const double* d,
+                        double* k, double* scratch);
+hipError_t launch_kkt_b(const Launch& L, const double* j, const double* dx, const double* d, double* k,
+                        const double* scratch);
+hipError_t launch_jac_struct(const Launch& L, int32_t* rows, int32_t* cols);
+hipError_t launch_hess_struct(const Launch& L, int32_t* rows, int32_t* cols);
+hipError_t launch_kkt_struct(const Launch& L, int ninst, int64_t* rowptr, int32_t* colind);
+hipError_t launch_bounds(const Launch& L, double* lv, double* uv, double* lc, double* uc);
+hipError_t launch_load_adjoint(const Launch& L, const double* lam, double* gpd, double* gqd);
+
+}  // namespace opf

@@ -1,0 +1,974 @@
+// HIP kernels for gfx950 (FP64): per-iteration evaluation of the
+// multi-period AC OPF model (Sec. II, eq. (1a)-(1k)), its sparse derivatives
+// in per-pattern COO form (Sec. III-A) and the condensed KKT matrix of the
+// lifted-KKT interior-point method (Sec. III-B).
+//
+// Execution model: every kernel walks a tile list.  A tile covers a range
+// of elements of one class (lines, generators, buses, ...) of one instance
+// over a range of periods; lane e of the block owns element e0 + e and
+// walks the tile's periods, so consecutive lanes touch consecutive entries
+// of every per-period SoA block (coalesced loads and stores).  The grid is
+// either one block per tile or a persistent grid that strides over the list.
+// Consecutive tiles go to the same XCD (the remap below), so each XCD's L2
+// serves a contiguous run of periods.  No kernel uses atomics: each output
+// slot has exactly one owning lane, which makes results bitwise
+// reproducible.
+//
+// The flow physics is the pi-model in expanded real trigonometric form: for
+// line l = (i -> j), delta = va_i - va_j, c = cos delta, s = sin delta and
+// each of the four flows (pf, qf at the from end, pt, qt at the to end)
+//   phi_k = S_k V_o^2 + V_i V_j (alpha_k c + beta_k s),   o = i or j,
+// with (S, alpha, beta) = (Gff, Gft, Bft), (-Bff, -Bft, Gft),
+// (Gtt, Gtf, -Btf), (-Btt, -Btf, -Gtf) from the admittances Y = G + jB.
+// With w = alpha c + beta s and u = dw/d delta = beta c - alpha s:
+//   dphi/dV_i = 2 S V_i [o=i] + V_j w,  dphi/dV_j = 2 S V_j [o=j] + V_i w,
+//   dphi/dtheta_i = V_i V_j u = -dphi/dtheta_j,
+//   d2phi: (Vi,Vi) 2S[o=i], (Vj,Vi) w, (Vj,Vj) 2S[o=j], (ti,Vi) V_j u,
+//   (ti,Vj) V_i u, (ti,ti) -V_iV_j w, (tj,Vi) -V_j u, (tj,Vj) -V_i u,
+//   (tj,ti) V_iV_j w, (tj,tj) -V_iV_j w.
+#include "opf_device.h"
+
+namespace opf {
+namespace {
+
+// Tiles v = b, b + grid, ... of block b run on XCD b % 8; give each XCD a
+// contiguous run of the list (bijective on [0, ntiles)).
+__device__ __forceinline__ int remap_tile(int v, int ntiles) {
+  const int q = ntiles >> 3;
+  if (v < (q << 3)) return (v & 7) * q + (v >> 3);
+  return v;
+}
+
+struct Coef {
+  double S[4], al[4], be[4];
+};
+
+__device__ __forceinline__ void load_coef(const InstDev& I, int l, Coef& c) {
+  const int64_t B = I.B;
+  const double* a = I.adm;
+  const double gff = a[l], bff = a[B + l], gft = a[2 * B + l], bft = a[3 * B + l];
+  const double gtf = a[4 * B + l], btf = a[5 * B + l], gtt = a[6 * B + l], btt = a[7 * B + l];
+  c.S[0] = gff;
+  c.al[0] = gft;
+  c.be[0] = bft;
+  c.S[1] = -bff;
+  c.al[1] = -bft;
+  c.be[1] = gft;
+  c.S[2] = gtt;
+  c.al[2] = gtf;
+  c.be[2] = -btf;
+  c.S[3] = -btt;
+  c.al[3] = -btf;
+  c.be[3] = -gtf;
+}
+
+// Per-period block bases (local offsets inside one period).
+struct Bases {
+  int64_t N, B, G;
+  int64_t xFL;                                     // first flow variable
+  int64_t jBAL, jREF, jFLOW, jTH, jANG;            // J blocks
+  int64_t cREF, cFLOW, cTHF, cTHT, cANG;           // c blocks
+  int64_t hFLOW, hTH;                              // H blocks
+  __device__ __forceinline__ explicit Bases(const InstDev& I) {
+    N = I.N;
+    B = I.B;
+    G = I.G;
+    xFL = 2 * N + 2 * G;
+    jBAL = 2 * G;
+    jREF = 2 * G + 4 * B;
+    jFLOW = jREF + 1;
+    jTH = jFLOW + 20 * B;
+    jANG = jTH + 4 * B;
+    cREF = 2 * N;
+    cFLOW = 2 * N + 1;
+    cTHF = cFLOW + 4 * B;
+    cTHT = cTHF + B;
+    cANG = cTHT + B;
+    hFLOW = G;
+    hTH = G + 36 * B;
+  }
+};
+
+// ---------------------------------------------------------------- Jacobian
+__device__ void jac_branch(const InstDev& I, int l, int t0, int t1, const double* __restrict__ x,
+                           double* __restrict__ jv) {
+  const Bases b(I);
+  Coef cf;
+  load_coef(I, l, cf);
+  const int64_t B = b.B;
+  const int i = I.f_bus[l], j = I.t_bus[l];
+  for (int t = t0; t < t1; ++t) {
+    const double* xp = x + I.x_off + (int64_t)t * I.n_p;
+    double* jp = jv + I.j_off + (int64_t)t * I.nnzj_p;
+    const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
+    double fl[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fl[k] = xp[b.xFL + k * B + l];
+    double s, c;
+    sincos(ti - tj, &s, &c);
+    const double vv = vi * vj;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double w = cf.al[k] * c + cf.be[k] * s;
+      const double u = cf.be[k] * c - cf.al[k] * s;
+      const double dvi = (k < 2 ? 2.0 * cf.S[k] * vi : 0.0) + vj * w;
+      const double dvj = (k < 2 ? 0.0 : 2.0 * cf.S[k] * vj) + vi * w;
+      const double dti = vv * u;
+      double* q = jp + b.jFLOW + (int64_t)(k * 5) * B + l;
+      q[0] = 1.0;
+      q[B] = -dvi;
+      q[2 * B] = -dvj;
+      q[3 * B] = -dti;
+      q[4 * B] = dti;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      jp[b.jBAL + k * B + l] = -1.0;
+      jp[b.jTH + k * B + l] = 2.0 * fl[k];
+    }
+    jp[b.jANG + l] = 1.0;
+    jp[b.jANG + B + l] = -1.0;
+  }
+}
+
+__device__ void jac_gen(const InstDev& I, int g, int t0, int t1, double* __restrict__ jv) {
+  const Bases b(I);
+  for (int t = t0; t < t1; ++t) {
+    double* jp = jv + I.j_off + (int64_t)t * I.nnzj_p;
+    jp[g] = 1.0;
+    jp[b.G + g] = 1.0;
+    if (g == 0) jp[b.jREF] = 1.0;
+    if (t >= 1) {
+      double* jr = jv + I.j_off + (int64_t)I.T * I.nnzj_p + (int64_t)(t - 1) * 2 * b.G;
+      jr[g] = 1.0;
+      jr[b.G + g] = -1.0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(512) k_jac(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                             int ntiles, const double* __restrict__ x, double* __restrict__ jv) {
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    if (e >= tl.e1) continue;
+    if (tl.kind == TK_BRANCH)
+      jac_branch(I, e, tl.t0, tl.t1, x, jv);
+    else
+      jac_gen(I, e, tl.t0, tl.t1, jv);
+  }
+}
+
+// ---------------------------------------------------------------- Hessian
+__device__ void hess_branch(const InstDev& I, int l, int t0, int t1, const double* __restrict__ x,
+                            const double* __restrict__ lam, double* __restrict__ hv) {
+  const Bases b(I);
+  Coef cf;
+  load_coef(I, l, cf);
+  const int64_t B = b.B;
+  const int i = I.f_bus[l], j = I.t_bus[l];
+  for (int t = t0; t < t1; ++t) {
+    const double* xp = x + I.x_off + (int64_t)t * I.n_p;
+    const double* lp = lam + I.c_off + (int64_t)t * I.m_p;
+    double* hp = hv + I.h_off + (int64_t)t * I.nnzh_p;
+    const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
+    double s, c;
+    sincos(ti - tj, &s, &c);
+    const double vv = vi * vj;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double ck = -lp[b.cFLOW + k * B + l];
+      const double w = cf.al[k] * c + cf.be[k] * s;
+      const double u = cf.be[k] * c - cf.al[k] * s;
+      double* q = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
+      if (k < 2) {
+        q[0] = ck * (2.0 * cf.S[k]);
+        q[B] = ck * w;
+      } else {
+        q[0] = ck * w;
+        q[B] = ck * (2.0 * cf.S[k]);
+      }
+      q[2 * B] = ck * (vj * u);
+      q[3 * B] = ck * (vi * u);
+      q[4 * B] = -ck * (vv * w);
+      q[5 * B] = -ck * (vj * u);
+      q[6 * B] = -ck * (vi * u);
+      q[7 * B] = ck * (vv * w);
+      q[8 * B] = -ck * (vv * w);
+    }
+    const double lf = 2.0 * lp[b.cTHF + l], lt = 2.0 * lp[b.cTHT + l];
+    hp[b.hTH + l] = lf;
+    hp[b.hTH + B + l] = lf;
+    hp[b.hTH + 2 * B + l] = lt;
+    hp[b.hTH + 3 * B + l] = lt;
+  }
+}
+
+__global__ void __launch_bounds__(512) k_hess(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                              int ntiles, const double* __restrict__ x,
+                                              const double* __restrict__ lam, double sigma,
+                                              double* __restrict__ hv) {
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    if (e >= tl.e1) continue;
+    if (tl.kind == TK_BRANCH) {
+      hess_branch(I, e, tl.t0, tl.t1, x, lam, hv);
+    } else {
+      const double h = 2.0 * sigma * I.c2[e];
+      for (int t = tl.t0; t < tl.t1; ++t) hv[I.h_off + (int64_t)t * I.nnzh_p + e] = h;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- constraints
+__device__ void cons_branch(const InstDev& I, int l, int t0, int t1, const double* __restrict__ x,
+                            double* __restrict__ cv) {
+  const Bases b(I);
+  Coef cf;
+  load_coef(I, l, cf);
+  const int64_t B = b.B;
+  const int i = I.f_bus[l], j = I.t_bus[l];
+  for (int t = t0; t < t1; ++t) {
+    const double* xp = x + I.x_off + (int64_t)t * I.n_p;
+    double* cp = cv + I.c_off + (int64_t)t * I.m_p;
+    const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
+    double fl[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fl[k] = xp[b.xFL + k * B + l];
+    double s, c;
+    sincos(ti - tj, &s, &c);
+    const double vv = vi * vj;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double w = cf.al[k] * c + cf.be[k] * s;
+      const double vo = k < 2 ? vi : vj;
+      cp[b.cFLOW + k * B + l] = fl[k] - (cf.S[k] * vo * vo + vv * w);
+    }
+    cp[b.cTHF + l] = fl[0] * fl[0] + fl[1] * fl[1];
+    cp[b.cTHT + l] = fl[2] * fl[2] + fl[3] * fl[3];
+    cp[b.cANG + l] = ti - tj;
+  }
+}
+
+__device__ void cons_bus(const InstDev& I, int n, int t0, int t1, const double* __restrict__ x,
+                         double* __restrict__ cv) {
+  const Bases b(I);
+  const int64_t B = b.B;
+  const int q0 = I.bus_ptr[n], q1 = I.bus_ptr[n + 1];
+  const int g0 = I.bgen_ptr[n], g1 = I.bgen_ptr[n + 1];
+  for (int t = t0; t < t1; ++t) {
+    const double* xp = x + I.x_off + (int64_t)t * I.n_p;
+    double* cp = cv + I.c_off + (int64_t)t * I.m_p;
+    double bp = 0.0, bq = 0.0;
+    for (int q = g0; q < g1; ++q) {
+      const int g = I.bgen[q];
+      bp += xp[2 * b.N + g];
+      bq += xp[2 * b.N + b.G + g];
+    }
+    for (int q = q0; q < q1; ++q) {
+      const int a = I.bus_adj[q];
+      const int64_t l = a >> 1;
+      const int64_t kp = (a & 1) ? 2 : 0;
+      bp -= xp[b.xFL + kp * B + l];
+      bq -= xp[b.xFL + (kp + 1) * B + l];
+    }
+    bp -= I.pd[(int64_t)t * b.N + n];
+    bq -= I.qd[(int64_t)t * b.N + n];
+    cp[n] = bp;
+    cp[b.N + n] = bq;
+    if (n == I.ref) cp[b.cREF] = xp[b.N + n];
+  }
+}
+
+__global__ void __launch_bounds__(512) k_cons(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                              int ntiles, const double* __restrict__ x, double* __restrict__ cv) {
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    if (e >= tl.e1) continue;
+    if (tl.kind == TK_BRANCH) {
+      cons_branch(I, e, tl.t0, tl.t1, x, cv);
+    } else if (tl.kind == TK_BUS) {
+      cons_bus(I, e, tl.t0, tl.t1, x, cv);
+    } else {
+      const int64_t pg = 2LL * I.N + e;
+      for (int t = tl.t0 < 1 ? 1 : tl.t0; t < tl.t1; ++t) {
+        const double* xp = x + I.x_off + (int64_t)t * I.n_p;
+        cv[I.c_off + (int64_t)I.T * I.m_p + (int64_t)(t - 1) * I.G + e] = xp[pg] - xp[pg - I.n_p];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- gradient
+__global__ void __launch_bounds__(512) k_grad(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                              int ntiles, const double* __restrict__ x, double* __restrict__ gv) {
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    if (e >= tl.e1) continue;
+    const int64_t PG = 2LL * I.N;
+    const bool is_pg = e >= PG && e < PG + I.G;
+    const double c2 = is_pg ? I.c2[e - PG] : 0.0, c1 = is_pg ? I.c1[e - PG] : 0.0;
+    for (int t = tl.t0; t < tl.t1; ++t) {
+      const int64_t idx = I.x_off + (int64_t)t * I.n_p + e;
+      gv[idx] = is_pg ? 2.0 * c2 * x[idx] + c1 : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- objective
+// Pass 1: per tile, a fixed-order block tree sum of c2 p^2 + c1 p + c0.
+__global__ void __launch_bounds__(512) k_obj_partial(const InstDev* __restrict__ insts,
+                                                     const Tile* __restrict__ tiles, int ntiles,
+                                                     const double* __restrict__ x, double* __restrict__ partial) {
+  __shared__ double red[512];
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const int ti = remap_tile(v, ntiles);
+    const Tile tl = tiles[ti];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    double acc = 0.0;
+    if (e < tl.e1) {
+      const double c2 = I.c2[e], c1 = I.c1[e], c0 = I.c0[e];
+      for (int t = tl.t0; t < tl.t1; ++t) {
+        const double p = x[I.x_off + (int64_t)t * I.n_p + 2LL * I.N + e];
+        acc += c2 * p * p + c1 * p + c0;
+      }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[ti] = red[0];
+    __syncthreads();
+  }
+}
+
+// Pass 2: one block per instance sums that instance's tile partials in a
+// fixed order (strided per lane, then a tree).
+__global__ void __launch_bounds__(256) k_obj_final(const int32_t* __restrict__ begin,
+                                                   const double* __restrict__ partial, double* __restrict__ f) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  const int a = begin[k], z = begin[k + 1];
+  double acc = 0.0;
+  for (int q = a + (int)threadIdx.x; q < z; q += blockDim.x) acc += partial[q];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) f[k] = red[0];
+}
+
+// ---------------------------------------------------------------- J^T v
+// Phase A: lines write their four flow-variable outputs and hand the bus
+// contributions (vm_i, vm_j, va_i, va_j) to a per-line scratch record;
+// generators write pg / qg.  Phase B: buses gather their incident records.
+__device__ void jt_branch(const InstDev& I, int l, int t0, int t1, const double* __restrict__ x,
+                          const double* __restrict__ vv_, double* __restrict__ out, double* __restrict__ scr) {
+  const Bases b(I);
+  Coef cf;
+  load_coef(I, l, cf);
+  const int64_t B = b.B;
+  const int i = I.f_bus[l], j = I.t_bus[l];
+  for (int t = t0; t < t1; ++t) {
+    const double* xp = x + I.x_off + (int64_t)t * I.n_p;
+    const double* vp = vv_ + I.c_off + (int64_t)t * I.m_p;
+    double* op = out + I.x_off + (int64_t)t * I.n_p;
+    const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
+    double fl[4], vk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      fl[k] = xp[b.xFL + k * B + l];
+      vk[k] = vp[b.cFLOW + k * B + l];
+    }
+    const double vtf = vp[b.cTHF + l], vtt = vp[b.cTHT + l], vang = vp[b.cANG + l];
+    double s, c;
+    sincos(ti - tj, &s, &c);
+    const double vv = vi * vj;
+    double svi = 0.0, svj = 0.0, sti = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double w = cf.al[k] * c + cf.be[k] * s;
+      const double u = cf.be[k] * c - cf.al[k] * s;
+      const double dvi = (k < 2 ? 2.0 * cf.S[k] * vi : 0.0) + vj * w;
+      const double dvj = (k < 2 ? 0.0 : 2.0 * cf.S[k] * vj) + vi * w;
+      svi -= vk[k] * dvi;
+      svj -= vk[k] * dvj;
+      sti -= vk[k] * (vv * u);
+    }
+    op[b.xFL + l] = vk[0] + vtf * (2.0 * fl[0]) - vp[i];
+    op[b.xFL + B + l] = vk[1] + vtf * (2.0 * fl[1]) - vp[b.N + i];
+    op[b.xFL + 2 * B + l] = vk[2] + vtt * (2.0 * fl[2]) - vp[j];
+    op[b.xFL + 3 * B + l] = vk[3] + vtt * (2.0 * fl[3]) - vp[b.N + j];
+    double* r = scr + I.s_off + (int64_t)kScratchKkt * I.B * I.T + ((int64_t)t * B + l) * kScratchJt;
+    r[0] = svi;
+    r[1] = svj;
+    r[2] = sti + vang;
+    r[3] = -sti - vang;
+  }
+}
+
+__device__ void jt_gen(const InstDev& I, int g, int t0, int t1, const double* __restrict__ vv_,
+                       double* __restrict__ out) {
+  const int64_t N = I.N, G = I.G;
+  const int n = I.gen_bus[g];
+  const double* vr = vv_ + I.c_off + (int64_t)I.T * I.m_p;
+  for (int t = t0; t < t1; ++t) {
+    const double* vp = vv_ + I.c_off + (int64_t)t * I.m_p;
+    double* op = out + I.x_off + (int64_t)t * I.n_p;
+    double a = vp[n];
+    if (t >= 1) a += vr[(int64_t)(t - 1) * G + g];
+    if (t + 1 < I.T) a -= vr[(int64_t)t * G + g];
+    op[2 * N + g] = a;
+    op[2 * N + G + g] = vp[N + n];
+  }
+}
+
+__global__ void __launch_bounds__(512) k_jt_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                              int ntiles, const double* __restrict__ x,
+                                              const double* __restrict__ v, double* __restrict__ out,
+                                              double* __restrict__ scr) {
+  for (int q = blockIdx.x; q < ntiles; q += gridDim.x) {
+    const Tile tl = tiles[remap_tile(q, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    if (e >= tl.e1) continue;
+    if (tl.kind == TK_BRANCH)
+      jt_branch(I, e, tl.t0, tl.t1, x, v, out, scr);
+    else
+      jt_gen(I, e, tl.t0, tl.t1, v, out);
+  }
+}
+
+__global__ void __launch_bounds__(512) k_jt_b(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                              int ntiles, const double* __restrict__ v, double* __restrict__ out,
+                                              const double* __restrict__ scr) {
+  for (int q = blockIdx.x; q < ntiles; q += gridDim.x) {
+    const Tile tl = tiles[remap_tile(q, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int n = tl.e0 + (int)threadIdx.x;
+    if (n >= tl.e1) continue;
+    const int q0 = I.bus_ptr[n], q1 = I.bus_ptr[n + 1];
+    for (int t = tl.t0; t < tl.t1; ++t) {
+      const double* rs = scr + I.s_off + (int64_t)kScratchKkt * I.B * I.T + (int64_t)t * I.B * kScratchJt;
+      double svm = 0.0, sva = 0.0;
+      for (int a = q0; a < q1; ++a) {
+        const int ad = I.bus_adj[a];
+        const double* r = rs + (int64_t)(ad >> 1) * kScratchJt;
+        if (ad & 1) {
+          svm += r[1];
+          sva += r[3];
+        } else {
+          svm += r[0];
+          sva += r[2];
+        }
+      }
+      if (n == I.ref) sva += v[I.c_off + (int64_t)t * I.m_p + 2LL * I.N];
+      double* op = out + I.x_off + (int64_t)t * I.n_p;
+      op[n] = svm;
+      op[I.N + n] = sva;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- condensed
+// K = lower(H + diag(diag_x) + J^T diag(d) J) on the fixed CSR.
+//
+// Phase A (lines): a line owns the four flow-variable rows of K; their
+// slots are the four bus-variable pairs (one flow row each), the lower
+// members of the balance row the flow enters, the thermal partner, and the
+// diagonal.  It also reduces its own contributions to the ten bus-variable
+// slots it touches (end-local pairs at i and j, four cross pairs) into a
+// scratch record.  Generators own the pg / qg rows (balance partners, the
+// ramp pair of t >= 1, diagonal).
+// Phase B (buses): a bus owns its vm and va rows and sums the scratch
+// records of its incident lines per neighbour (merging parallel lines).
+__device__ void kkt_branch(const InstDev& I, int l, int t0, int t1, const double* __restrict__ H,
+                           const double* __restrict__ J, const double* __restrict__ DX,
+                           const double* __restrict__ D, double* __restrict__ K, double* __restrict__ scr) {
+  const Bases b(I);
+  const int64_t B = b.B, N = b.N, G = b.G;
+  const int i = I.f_bus[l], j = I.t_bus[l];
+  const bool ilo = i < j;
+  int rs[4], re[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    rs[k] = I.krow[b.xFL + k * B + l];
+    re[k] = I.krow[b.xFL + k * B + l + 1];
+  }
+  for (int t = t0; t < t1; ++t) {
+    const double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
+    const double* hp = H + I.h_off + (int64_t)t * I.nnzh_p;
+    const double* dp = D + I.c_off + (int64_t)t * I.m_p;
+    double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t) + (t >= 1 ? G : 0);
+    double Jf[4][5], df[4], Jb[4], Jt[4], Hth[4], dbal[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int a = 0; a < 5; ++a) Jf[k][a] = jp[b.jFLOW + (int64_t)(k * 5 + a) * B + l];
+      df[k] = dp[b.cFLOW + k * B + l];
+      Jb[k] = jp[b.jBAL + k * B + l];
+      Jt[k] = jp[b.jTH + k * B + l];
+      Hth[k] = hp[b.hTH + k * B + l];
+    }
+    dbal[0] = dp[i];
+    dbal[1] = dp[N + i];
+    dbal[2] = dp[j];
+    dbal[3] = dp[N + j];
+    const double dth[2] = {dp[b.cTHF + l], dp[b.cTHT + l]};
+    const double dang = dp[b.cANG + l];
+    const double Ja0 = jp[b.jANG + l], Ja1 = jp[b.jANG + B + l];
+    // flow-variable rows
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double pk = df[k] * Jf[k][0];
+      double* row = kb + rs[k];
+      if (ilo) {
+        row[0] = pk * Jf[k][1];
+        row[1] = pk * Jf[k][2];
+        row[2] = pk * Jf[k][3];
+        row[3] = pk * Jf[k][4];
+      } else {
+        row[0] = pk * Jf[k][2];
+        row[1] = pk * Jf[k][1];
+        row[2] = pk * Jf[k][4];
+        row[3] = pk * Jf[k][3];
+      }
+      const double pb = dbal[k] * Jb[k];
+      for (int p = rs[k] + 4; p < re[k] - 1; ++p) {
+        const int src = I.ksrc[p];
+        kb[p] = ((k & 1) && src < 0) ? dth[k >> 1] * Jt[k ^ 1] * Jt[k] : pb * jp[src];
+      }
+      const double dxv = DX ? DX[I.x_off + (int64_t)t * I.n_p + b.xFL + k * B + l] : 0.0;
+      kb[re[k] - 1] = dxv + pk * Jf[k][0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jb[k] + Hth[k];
+    }
+    // bus-variable contributions: P[a][b] = sum_k d_k J_k,a J_k,b + angle + H
+    double q[10];
+    q[0] = q[1] = q[2] = q[3] = q[4] = q[5] = q[6] = q[7] = q[8] = q[9] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double* hf = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
+      const double a1 = Jf[k][1], a2 = Jf[k][2], a3 = Jf[k][3], a4 = Jf[k][4];
+      const double d1 = df[k] * a1, d2 = df[k] * a2, d3 = df[k] * a3, d4 = df[k] * a4;
+      // local H order: from end (0,0)(1,0)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3);
+      // to end (1,0)(1,1)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3)
+      const double h0 = hf[0], h1 = hf[B];
+      if (k < 2) {
+        q[0] += d1 * a1 + h0;
+        q[3] += d2 * a2;
+        q[6] += d2 * a1 + h1;
+      } else {
+        q[0] += d1 * a1;
+        q[3] += d2 * a2 + h1;
+        q[6] += d2 * a1 + h0;
+      }
+      q[1] += d3 * a1 + hf[2 * B];
+      q[7] += d3 * a2 + hf[3 * B];
+      q[2] += d3 * a3 + hf[4 * B];
+      q[8] += d4 * a1 + hf[5 * B];
+      q[4] += d4 * a2 + hf[6 * B];
+      q[9] += d4 * a3 + hf[7 * B];
+      q[5] += d4 * a4 + hf[8 * B];
+    }
+    q[2] += dang * Ja0 * Ja0;
+    q[5] += dang * Ja1 * Ja1;
+    q[9] += dang * Ja1 * Ja0;
+    double* r = scr + I.s_off + ((int64_t)t * B + l) * kScratchKkt;
+#pragma unroll
+    for (int a = 0; a < 10; ++a) r[a] = q[a];
+  }
+}
+
+__device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, const double* __restrict__ H,
+                        const double* __restrict__ J, const double* __restrict__ DX, const double* __restrict__ D,
+                        double* __restrict__ K) {
+  const int64_t N = I.N, G = I.G;
+  const int n = I.gen_bus[g];
+  const int64_t rp = 2 * N + g, rq = 2 * N + G + g;
+  const int ps = I.krow[rp], pe = I.krow[rp + 1], qs = I.krow[rq], qe = I.krow[rq + 1];
+  const double* jr = J + I.j_off + (int64_t)I.T * I.nnzj_p;   // ramp block of J
+  const double* dr = D + I.c_off + (int64_t)I.T * I.m_p;       // ramp rows of D
+  for (int t = t0; t < t1; ++t) {
+    const double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
+    const double* dp = D + I.c_off + (int64_t)t * I.m_p;
+    double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
+    const double Jgp = jp[g], Jgq = jp[G + g];
+    const double pbp = dp[n] * Jgp, pbq = dp[N + n] * Jgq;
+    const int64_t xo = I.x_off + (int64_t)t * I.n_p;
+    double diag = (DX ? DX[xo + rp] : 0.0) + pbp * Jgp + H[I.h_off + (int64_t)t * I.nnzh_p + g];
+    const int sp = t >= 1 ? g + 1 : 0, sq = t >= 1 ? (int)G : 0;
+    if (t >= 1) {
+      const double* jt = jr + (int64_t)(t - 1) * 2 * G;
+      const double d = dr[(int64_t)(t - 1) * G + g];
+      const double j0 = jt[g], j1 = jt[G + g];
+      kb[ps + g] = d * j0 * j1;
+      diag += d * j0 * j0;
+    }
+    if (t + 1 < I.T) {
+      const double j1 = jr[(int64_t)t * 2 * G + G + g];
+      diag += dr[(int64_t)t * G + g] * j1 * j1;
+    }
+    for (int p = ps; p < pe - 1; ++p) kb[p + sp] = pbp * jp[I.ksrc[p]];
+    kb[pe - 1 + sp] = diag;
+    for (int p = qs; p < qe - 1; ++p) kb[p + sq] = pbq * jp[I.ksrc[p]];
+    kb[qe - 1 + sq] = (DX ? DX[xo + rq] : 0.0) + pbq * Jgq;
+  }
+}
+
+__global__ void __launch_bounds__(512) k_kkt_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                               int ntiles, const double* __restrict__ H,
+                                               const double* __restrict__ J, const double* __restrict__ DX,
+                                               const double* __restrict__ D, double* __restrict__ K,
+                                               double* __restrict__ scr) {
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    if (e >= tl.e1) continue;
+    if (tl.kind == TK_BRANCH)
+      kkt_branch(I, e, tl.t0, tl.t1, H, J, DX, D, K, scr);
+    else
+      kkt_gen(I, e, tl.t0, tl.t1, H, J, DX, D, K);
+  }
+}
+
+__global__ void __launch_bounds__(512) k_kkt_b(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                               int ntiles, const double* __restrict__ J,
+                                               const double* __restrict__ DX, const double* __restrict__ D,
+                                               double* __restrict__ K, const double* __restrict__ scr) {
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int n = tl.e0 + (int)threadIdx.x;
+    if (n >= tl.e1) continue;
+    const int64_t N = I.N;
+    const int q0 = I.bus_ptr[n], q1 = I.bus_ptr[n + 1];
+    const int vmr = I.krow[n], var = I.krow[N + n];
+    const int clo = I.krow[n + 1] - vmr - 1;
+    const int lva = I.krow[N + n + 1] - var;
+    const int call = lva - clo - 2;
+    for (int t = tl.t0; t < tl.t1; ++t) {
+      const double* rs = scr + I.s_off + (int64_t)t * I.B * kScratchKkt;
+      double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
+      // same-bus sums over every incident line end
+      double svm = 0.0, svavm = 0.0, sva = 0.0;
+      for (int a = q0; a < q1; ++a) {
+        const int ad = I.bus_adj[a];
+        const double* r = rs + (int64_t)(ad >> 1) * kScratchKkt + ((ad & 1) ? 3 : 0);
+        svm += r[0];
+        svavm += r[1];
+        sva += r[2];
+      }
+      // cross slots, one per distinct neighbour (parallel lines merged)
+      int gi = 0, prev = -1;
+      double cvm = 0.0, cvavm = 0.0, cva = 0.0;
+      for (int a = q0; a <= q1; ++a) {
+        int m = -1, ad = 0;
+        if (a < q1) {
+          ad = I.bus_adj[a];
+          m = (ad & 1) ? I.f_bus[ad >> 1] : I.t_bus[ad >> 1];
+        }
+        if (prev >= 0 && m != prev) {
+          if (prev < n) {
+            kb[vmr + gi] = cvm;
+            kb[var + gi] = cvavm;
+            kb[var + call + 1 + gi] = cva;
+          } else {
+            kb[var + gi + 1] = cvavm;
+          }
+          ++gi;
+          cvm = cvavm = cva = 0.0;
+        }
+        if (a == q1) break;
+        prev = m;
+        const double* r = rs + (int64_t)(ad >> 1) * kScratchKkt;
+        cvm += r[6];
+        cvavm += (ad & 1) ? r[8] : r[7];
+        cva += r[9];
+      }
+      const int64_t xo = I.x_off + (int64_t)t * I.n_p;
+      double dref = 0.0;
+      if (n == I.ref) {
+        const double jr = J[I.j_off + (int64_t)t * I.nnzj_p + 2LL * I.G + 4LL * I.B];
+        dref = D[I.c_off + (int64_t)t * I.m_p + 2 * N] * jr * jr;
+      }
+      kb[vmr + clo] = (DX ? DX[xo + n] : 0.0) + svm;
+      if (q1 > q0) kb[var + clo] = svavm;  // (va_n, vm_n) exists only with an incident line
+      kb[var + lva - 1] = (DX ? DX[xo + N + n] : 0.0) + sva + dref;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- structure
+__global__ void __launch_bounds__(512) k_jac_struct(const InstDev* __restrict__ insts,
+                                                    const Tile* __restrict__ tiles, int ntiles,
+                                                    int32_t* __restrict__ rows, int32_t* __restrict__ cols) {
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    if (e >= tl.e1) continue;
+    const Bases b(I);
+    const int64_t B = b.B, N = b.N, G = b.G;
+    for (int t = tl.t0; t < tl.t1; ++t) {
+      const int64_t jo = I.j_off + (int64_t)t * I.nnzj_p;
+      const int32_t cr = (int32_t)(I.c_off + (int64_t)t * I.m_p);
+      const int32_t xc = (int32_t)(I.x_off + (int64_t)t * I.n_p);
+      if (tl.kind == TK_BRANCH) {
+        const int l = e, i = I.f_bus[l], j = I.t_bus[l];
+        const int32_t fl = xc + (int32_t)b.xFL + l;
+        const int32_t brow[4] = {cr + i, cr + (int32_t)N + i, cr + j, cr + (int32_t)N + j};
+        const int32_t bus[4] = {xc + i, xc + j, xc + (int32_t)N + i, xc + (int32_t)N + j};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          rows[jo + b.jBAL + k * B + l] = brow[k];
+          cols[jo + b.jBAL + k * B + l] = fl + (int32_t)(k * B);
+          const int32_t r = cr + (int32_t)(b.cFLOW + k * B) + l;
+          const int64_t q = jo + b.jFLOW + (int64_t)(k * 5) * B + l;
+          rows[q] = r;
+          cols[q] = fl + (int32_t)(k * B);
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            rows[q + (a + 1) * B] = r;
+            cols[q + (a + 1) * B] = bus[a];
+          }
+          rows[jo + b.jTH + k * B + l] = cr + (int32_t)((k < 2 ? b.cTHF : b.cTHT)) + l;
+          cols[jo + b.jTH + k * B + l] = fl + (int32_t)(k * B);
+        }
+        rows[jo + b.jANG + l] = cr + (int32_t)b.cANG + l;
+        cols[jo + b.jANG + l] = bus[2];
+        rows[jo + b.jANG + B + l] = cr + (int32_t)b.cANG + l;
+        cols[jo + b.jANG + B + l] = bus[3];
+      } else {
+        const int g = e, n = I.gen_bus[g];
+        rows[jo + g] = cr + n;
+        cols[jo + g] = xc + (int32_t)(2 * N) + g;
+        rows[jo + G + g] = cr + (int32_t)N + n;
+        cols[jo + G + g] = xc + (int32_t)(2 * N + G) + g;
+        if (g == 0) {
+          rows[jo + b.jREF] = cr + (int32_t)b.cREF;
+          cols[jo + b.jREF] = xc + (int32_t)N + I.ref;
+        }
+        if (t >= 1) {
+          const int64_t q = I.j_off + (int64_t)I.T * I.nnzj_p + (int64_t)(t - 1) * 2 * G;
+          const int32_t rr = (int32_t)(I.c_off + (int64_t)I.T * I.m_p + (int64_t)(t - 1) * G) + g;
+          rows[q + g] = rr;
+          cols[q + g] = xc + (int32_t)(2 * N) + g;
+          rows[q + G + g] = rr;
+          cols[q + G + g] = xc - (int32_t)I.n_p + (int32_t)(2 * N) + g;
+        }
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(512) k_hess_struct(const InstDev* __restrict__ insts,
+                                                     const Tile* __restrict__ tiles, int ntiles,
+                                                     int32_t* __restrict__ rows, int32_t* __restrict__ cols) {
+  // (a, b) pairs of the local variable list (vm_i, vm_j, va_i, va_j)
+  const int pf_a[9] = {0, 1, 2, 2, 2, 3, 3, 3, 3}, pf_b[9] = {0, 0, 0, 1, 2, 0, 1, 2, 3};
+  const int pt_a[9] = {1, 1, 2, 2, 2, 3, 3, 3, 3}, pt_b[9] = {0, 1, 0, 1, 2, 0, 1, 2, 3};
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    if (e >= tl.e1) continue;
+    const Bases b(I);
+    const int64_t B = b.B, N = b.N;
+    for (int t = tl.t0; t < tl.t1; ++t) {
+      const int64_t ho = I.h_off + (int64_t)t * I.nnzh_p;
+      const int32_t xc = (int32_t)(I.x_off + (int64_t)t * I.n_p);
+      if (tl.kind == TK_BRANCH) {
+        const int l = e, i = I.f_bus[l], j = I.t_bus[l];
+        const int32_t bus[4] = {xc + i, xc + j, xc + (int32_t)N + i, xc + (int32_t)N + j};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+          for (int p = 0; p < 9; ++p) {
+            const int32_t ra = bus[k < 2 ? pf_a[p] : pt_a[p]], rb = bus[k < 2 ? pf_b[p] : pt_b[p]];
+            const int64_t q = ho + b.hFLOW + (int64_t)(k * 9 + p) * B + l;
+            rows[q] = ra > rb ? ra : rb;
+            cols[q] = ra > rb ? rb : ra;
+          }
+          const int32_t fv = xc + (int32_t)(b.xFL + k * B) + l;
+          rows[ho + b.hTH + k * B + l] = fv;
+          cols[ho + b.hTH + k * B + l] = fv;
+        }
+      } else {
+        const int32_t pv = xc + (int32_t)(2 * N) + e;
+        rows[ho + e] = pv;
+        cols[ho + e] = pv;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(512) k_kkt_struct(const InstDev* __restrict__ insts,
+                                                    const Tile* __restrict__ tiles, int ntiles, int ninst,
+                                                    int64_t* __restrict__ rowptr, int32_t* __restrict__ colind) {
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int r = tl.e0 + (int)threadIdx.x;
+    if (r >= tl.e1) continue;
+    const int64_t PG = 2LL * I.N;
+    const int rs = I.krow[r], re = I.krow[r + 1];
+    for (int t = tl.t0; t < tl.t1; ++t) {
+      const int64_t kp = I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
+      const int64_t xb = I.x_off + (int64_t)t * I.n_p;
+      int64_t shift = 0;
+      bool ramp = false;
+      if (t >= 1) {
+        if (r >= PG && r < PG + I.G) {
+          shift = r - PG + 1;
+          ramp = true;
+        } else if (r >= PG + I.G) {
+          shift = I.G;
+        }
+      }
+      int64_t pos = kp + rs + shift - (ramp ? 1 : 0);
+      rowptr[xb + r] = pos;
+      if (ramp) colind[pos++] = (int32_t)(xb - I.n_p + r);
+      for (int p = rs; p < re; ++p) colind[pos++] = (int32_t)(xb + I.kcol[p]);
+      if (tl.inst == ninst - 1 && r == I.n_p - 1 && t == I.T - 1) rowptr[I.x_off + (int64_t)I.T * I.n_p] = pos;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- bounds
+__global__ void __launch_bounds__(512) k_bounds(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                                int ntiles, double* __restrict__ lv, double* __restrict__ uv,
+                                                double* __restrict__ lc, double* __restrict__ uc) {
+  const double inf = __builtin_huge_val();
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    if (e >= tl.e1) continue;
+    const Bases b(I);
+    const int64_t N = b.N, G = b.G, B = b.B;
+    for (int t = tl.t0; t < tl.t1; ++t) {
+      if (tl.kind == TK_VAR) {
+        double lo = -inf, hi = inf;
+        if (e < N) {
+          lo = I.vmin[e];
+          hi = I.vmax[e];
+        } else if (e >= 2 * N && e < 2 * N + G) {
+          lo = I.pmin[e - 2 * N];
+          hi = I.pmax[e - 2 * N];
+        } else if (e >= 2 * N + G && e < 2 * N + 2 * G) {
+          lo = I.qmin[e - 2 * N - G];
+          hi = I.qmax[e - 2 * N - G];
+        }
+        const int64_t q = I.x_off + (int64_t)t * I.n_p + e;
+        lv[q] = lo;
+        uv[q] = hi;
+      } else if (tl.kind == TK_CON) {
+        double lo = 0.0, hi = 0.0;
+        if (e >= b.cTHF && e < b.cANG) {
+          const int64_t l = e - (e >= b.cTHT ? b.cTHT : b.cTHF);
+          lo = -inf;
+          hi = I.rate[l] * I.rate[l];
+        } else if (e >= b.cANG) {
+          lo = I.angmin[e - b.cANG];
+          hi = I.angmax[e - b.cANG];
+        }
+        (void)B;
+        const int64_t q = I.c_off + (int64_t)t * I.m_p + e;
+        lc[q] = lo;
+        uc[q] = hi;
+      } else if (t >= 1) {
+        const int64_t q = I.c_off + (int64_t)I.T * I.m_p + (int64_t)(t - 1) * G + e;
+        lc[q] = -I.ramp[e];
+        uc[q] = I.ramp[e];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- load adjoint
+__global__ void __launch_bounds__(512) k_load_adj(const InstDev* __restrict__ insts,
+                                                  const Tile* __restrict__ tiles, int ntiles,
+                                                  const double* __restrict__ lam, double* __restrict__ gpd,
+                                                  double* __restrict__ gqd) {
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int n = tl.e0 + (int)threadIdx.x;
+    if (n >= tl.e1) continue;
+    for (int t = tl.t0; t < tl.t1; ++t) {
+      const double* lp = lam + I.c_off + (int64_t)t * I.m_p;
+      const int64_t q = I.ld_off + (int64_t)t * I.N + n;
+      gpd[q] = -lp[n];
+      gqd[q] = -lp[I.N + n];
+    }
+  }
+}
+
+dim3 grid_of(const Launch& L) { return dim3((unsigned)(L.grid > 0 ? L.grid : L.ntiles)); }
+
+}  // namespace
+
+#define OPF_LAUNCH(kernel, L, ...)                                                              \
+  do {                                                                                          \
+    if ((L).ntiles <= 0) return hipSuccess;                                                     \
+    hipLaunchKernelGGL(kernel, grid_of(L), dim3((unsigned)(L).block), 0, (L).stream, (L).insts, \
+                       (L).tiles, (L).ntiles, __VA_ARGS__);                                     \
+    return hipGetLastError();                                                                   \
+  } while (0)
+
+hipError_t launch_jac(const Launch& L, const double* x, double* jv) { OPF_LAUNCH(k_jac, L, x, jv); }
+hipError_t launch_hess(const Launch& L, const double* x, const double* lam, double sigma, double* hv) {
+  OPF_LAUNCH(k_hess, L, x, lam, sigma, hv);
+}
+hipError_t launch_cons(const Launch& L, const double* x, double* c) { OPF_LAUNCH(k_cons, L, x, c); }
+hipError_t launch_grad(const Launch& L, const double* x, double* g) { OPF_LAUNCH(k_grad, L, x, g); }
+hipError_t launch_obj_partial(const Launch& L, const double* x, double* partial) {
+  OPF_LAUNCH(k_obj_partial, L, x, partial);
+}
+hipError_t launch_obj_final(const int32_t* begin, int ninst, const double* partial, double* f, hipStream_t s) {
+  hipLaunchKernelGGL(k_obj_final, dim3((unsigned)ninst), dim3(256), 0, s, begin, partial, f);
+  return hipGetLastError();
+}
+hipError_t launch_jt_a(const Launch& L, const double* x, const double* v, double* out, double* scratch) {
+  OPF_LAUNCH(k_jt_a, L, x, v, out, scratch);
+}
+hipError_t launch_jt_b(const Launch& L, const double* v, double* out, const double* scratch) {
+  OPF_LAUNCH(k_jt_b, L, v, out, scratch);
+}
+hipError_t launch_kkt_a(const Launch& L, const double* h, const double* j, const double* dx, const double* d,
+                        double* k, double* scratch) {
+  OPF_LAUNCH(k_kkt_a, L, h, j, dx, d, k, scratch);
+}
+hipError_t launch_kkt_b(const Launch& L, const double* j, const double* dx, const double* d, double* k,
+                        const double* scratch) {
+  OPF_LAUNCH(k_kkt_b, L, j, dx, d, k, scratch);
+}
+hipError_t launch_jac_struct(const Launch& L, int32_t* rows, int32_t* cols) {
+  OPF_LAUNCH(k_jac_struct, L, rows, cols);
+}
+hipError_t launch_hess_struct(const Launch& L, int32_t* rows, int32_t* cols) {
+  OPF_LAUNCH(k_hess_struct, L, rows, cols);
+}
+hipError_t launch_kkt_struct(const Launch& L, int ninst, int64_t* rowptr, int32_t* colind) {
+  OPF_LAUNCH(k_kkt_struct, L, ninst, rowptr, colind);
+}
+hipError_t launch_bounds(const Launch& L, double* lv, double* uv, double* lc, double* uc) {
+  OPF_LAUNCH(k_bounds, L, lv, uv, lc, uc);
+}
+hipError_t launch_load_adjoint(const Launch& L, const double* lam, double* gpd, double* gqd) {
+  OPF_LAUNCH(k_load_adj, L, lam, gpd, gqd);
+}
+
+}  // namespace opf

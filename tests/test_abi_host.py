@@ -1,0 +1,167 @@
+"""The C ABI on the host: symbols, validation, error paths, host-only models
+and the symbolic condensed-matrix pattern against the oracle (no GPU)."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+from oracle import opf_oracle as O
+from paper_2405_14032_amd import synth
+
+import pins
+
+capi = pytest.importorskip("paper_2405_14032_amd.capi")
+
+
+def test_library_exports_every_header_symbol():
+    names = capi.header_symbols()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(capi.lib, name), name
+
+
+def _one(net):
+    descs, keep = capi.make_descs([net])
+    return descs, keep
+
+
+def test_validate_accepts_synthetic_configs():
+    for name in ("tiny", "mid"):
+        assert capi.validate([synth.config_network(name)]) == capi.OPF_OK
+
+
+@pytest.mark.parametrize("mutation,code", [
+    ("bad_bus", capi.OPF_EINVAL),
+    ("self_loop", capi.OPF_EINVAL),
+    ("no_bus", capi.OPF_EINVAL),
+    ("no_period", capi.OPF_EINVAL),
+    ("bad_gen_bus", capi.OPF_EINVAL),
+    ("bad_ref", capi.OPF_EINVAL),
+    ("zero_impedance", capi.OPF_EINVAL),
+    ("null_array", capi.OPF_EINVAL),
+    ("overflow", capi.OPF_ERANGE),
+])
+def test_validate_rejects(mutation, code):
+    net = synth.config_network("tiny")
+    descs, keep = _one(net)
+    d = descs[0]
+    if mutation == "bad_bus":
+        arr = np.array(net.f_bus, dtype=np.int32)
+        arr[3] = net.N
+        keep.append(arr)
+        d.f_bus = arr.ctypes.data_as(C.POINTER(C.c_int32))
+    elif mutation == "self_loop":
+        arr = np.array(net.t_bus, dtype=np.int32)
+        arr[2] = net.f_bus[2]
+        keep.append(arr)
+        d.t_bus = arr.ctypes.data_as(C.POINTER(C.c_int32))
+    elif mutation == "no_bus":
+        d.nbus = 0
+    elif mutation == "no_period":
+        d.nperiod = 0
+    elif mutation == "bad_gen_bus":
+        arr = np.array(net.gen_bus, dtype=np.int32)
+        arr[0] = -1
+        keep.append(arr)
+        d.gen_bus = arr.ctypes.data_as(C.POINTER(C.c_int32))
+    elif mutation == "bad_ref":
+        d.ref_bus = net.N
+    elif mutation == "zero_impedance":
+        r = np.array(net.r)
+        x = np.array(net.x)
+        r[1] = 0.0
+        x[1] = 0.0
+        keep += [r, x]
+        d.r = r.ctypes.data_as(C.POINTER(C.c_double))
+        d.x = x.ctypes.data_as(C.POINTER(C.c_double))
+    elif mutation == "null_array":
+        d.pd = None
+    elif mutation == "overflow":
+        d.nbus = 1 << 28
+        d.nperiod = 1 << 10
+    assert capi.opf_validate(descs, 1) == code
+    assert len(capi.opf_last_error()) > 0
+    h = C.c_void_p()
+    assert capi.opf_model_create(descs, 1, -1, C.byref(h)) == code
+    assert not h.value
+
+
+def test_injected_allocation_failure(monkeypatch):
+    net = synth.config_network("tiny")
+    descs, keep = _one(net)
+    monkeypatch.setenv("OPF_TEST_FAIL_ALLOC", "1")
+    h = C.c_void_p()
+    assert capi.opf_model_create(descs, 1, -1, C.byref(h)) == capi.OPF_ENOMEM
+    assert b"injected" in capi.opf_last_error()
+
+
+def test_host_only_model_dims_and_offsets():
+    nets = [synth.config_network("tiny"), synth.make_network(30, 45, 7, 5, 99)]
+    M = capi.Model(nets, device=-1)
+    tot = {"n": 0, "m": 0, "nnz_jac": 0, "nnz_hess": 0}
+    for k, net in enumerate(nets):
+        d = O.dims(net.N, net.B, net.G, net.T)
+        assert M.x_off[k] == tot["n"] and M.c_off[k] == tot["m"]
+        assert M.j_off[k] == tot["nnz_jac"] and M.h_off[k] == tot["nnz_hess"]
+        for key in tot:
+            tot[key] += d[key]
+    assert (M.n, M.m, M.nnz_jac, M.nnz_hess) == (tot["n"], tot["m"], tot["nnz_jac"], tot["nnz_hess"])
+    assert M.nnz_kkt == sum(pins.nnz_kkt_closed_form(net) for net in nets)
+
+
+def test_host_only_model_refuses_evaluation():
+    M = capi.Model([synth.config_network("tiny")], device=-1)
+    assert capi.opf_eval_jac(M.h, None, None) == capi.OPF_ENODEV
+    assert capi.opf_eval_jac(None, None, None) == capi.OPF_EINVAL
+
+
+def _oracle_pattern(net, seed=1):
+    pt = synth.make_point(net, seed)
+    L = O.Layout(net)
+    rp, ci, _, _ = O.condensed(L.n, O.jacobian(net, pt.x), O.hessian(net, pt.x, pt.lam), pt.diag_x, pt.dcon)
+    return rp, ci
+
+
+@pytest.mark.parametrize("shape", [(14, 20, 5, 4, 1), (200, 300, 40, 3, 5), (60, 90, 12, 1, 6), (2, 1, 1, 2, 7)])
+def test_host_kkt_pattern_matches_oracle(shape):
+    N, B, G, T, seed = shape
+    net = synth.make_network(N, B, G, T, seed)
+    M = capi.Model([net], device=-1)
+    rp, ci = M.kkt_structure_host()
+    orp, oci = _oracle_pattern(net, seed)
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(ci.astype(np.int64), oci)
+
+
+def test_host_kkt_pattern_parallel_lines_and_shared_generator_bus():
+    # two parallel lines (0-1), an anti-parallel one (1-0), two generators on
+    # bus 1: the pattern merges them like the oracle's sort-and-reduce
+    net = pins.manual_network(4, [0, 0, 1, 1, 2], [1, 1, 0, 2, 3], [0.01] * 5, [0.1, 0.2, 0.15, 0.1, 0.3],
+                              [0.02] * 5, [1, 1, 3], T=3)
+    M = capi.Model([net], device=-1)
+    rp, ci = M.kkt_structure_host()
+    orp, oci = _oracle_pattern(net)
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(ci.astype(np.int64), oci)
+
+
+def test_host_kkt_pattern_batched_concatenation():
+    nets = [synth.make_network(20, 30, 4, 3, 11), synth.make_network(15, 22, 3, 5, 12)]
+    M = capi.Model(nets, device=-1)
+    rp, ci = M.kkt_structure_host()
+    for k, net in enumerate(nets):
+        orp, oci = _oracle_pattern(net)
+        a, b = M.x_off[k], M.x_off[k + 1]
+        assert np.array_equal(rp[a:b + 1] - M.k_off[k], orp)
+        assert np.array_equal(ci[M.k_off[k]:M.k_off[k + 1]].astype(np.int64) - a, oci)
+
+
+def test_host_kkt_pattern_isolated_bus():
+    # a bus with no line has no (va, vm) pair: its va row is the diagonal only
+    net = pins.manual_network(1, [], [], [], [], [], [0], T=3, pd=np.full((3, 1), 0.4))
+    M = capi.Model([net], device=-1)
+    rp, ci = M.kkt_structure_host()
+    orp, oci = _oracle_pattern(net)
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(ci.astype(np.int64), oci)
