@@ -18,6 +18,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libopf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "opf.h")
 
+# libopf must share one HIP runtime instance with torch (stream handles and
+# device pointers are per runtime).  torch ships its own libamdhip64 with
+# the same soname, so load torch first: the dynamic loader then resolves
+# libopf's dependency to the runtime torch already mapped.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2405_14032_amd/build_lib.py "
                       "(or __graft_entry__.build())")
