@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--tune-cache", default=TUNE_CACHE)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="skip the batched and adjoint legs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the evaluation path has no "
@@ -292,6 +294,13 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     res = bench_plain(torch, dev, args)
     log(f"plain sweep: {res['ms_per_step']:.3f} ms/step")
     line = {"metric": METRIC, "value": res["value"], "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,

@@ -70,7 +70,12 @@ struct TileList {
   int n = 0;
   int cap = 0;
   std::vector<int32_t> inst_begin;  // first tile of each instance (+ total)
+  int lds_cap = 0;                  // LDS segment capacity (doubles), staged kernels
+  size_t smem = 0;                  // dynamic LDS bytes per block
 };
+
+// Largest dynamic LDS a block of the staged kernels may ask for.
+constexpr size_t kMaxSmem = 64 * 1024;
 
 }  // namespace
 
@@ -171,11 +176,44 @@ std::vector<Tile> make_tiles(const opf_model* M, int op, const Shape& s, std::ve
   return out;
 }
 
+// LDS needs of the staged condensed kernels for a tile list: the longest
+// contiguous K row segment a tile writes (per flow kind for the line phase,
+// vm + va rows for the bus phase).
+int lds_needs(const opf_model* M, int op, const std::vector<Tile>& tiles, const Shape& s, int& cap,
+              size_t& smem) {
+  cap = 0;
+  smem = 0;
+  if (op != OP_KKA && op != OP_KKB) return OPF_OK;
+  if (op == OP_KKA && s.block > 256) return fail(OPF_EINVAL, "condensed line kernel: block > 256");
+  int cap2 = 0;
+  for (const Tile& tl : tiles) {
+    const InstHost& I = M->inst[tl.inst];
+    if (op == OP_KKA && tl.kind == TK_BRANCH) {
+      const int64_t FL = 2LL * I.N + 2LL * I.G;
+      for (int k = 0; k < 4; ++k)
+        cap = std::max<int>(cap, I.krow[FL + (int64_t)k * I.B + tl.e1] - I.krow[FL + (int64_t)k * I.B + tl.e0]);
+    } else if (op == OP_KKB) {
+      cap = std::max<int>(cap, I.krow[tl.e1] - I.krow[tl.e0]);
+      cap2 = std::max<int>(cap2, I.krow[I.N + tl.e1] - I.krow[I.N + tl.e0]);
+    }
+  }
+  smem = op == OP_KKA ? ((size_t)cap + (size_t)s.block * kScratchKkt) * sizeof(double)
+                      : ((size_t)cap + (size_t)cap2) * sizeof(double);
+  if (smem > kMaxSmem) return fail(OPF_EINVAL, std::string("tile shape needs too much LDS for ") + kOpName[op]);
+  return OPF_OK;
+}
+
 int set_shape(opf_model* M, int op, const Shape& s) {
   TileList& L = M->lists[op];
   std::vector<int32_t> begin;
   std::vector<Tile> tiles = make_tiles(M, op, s, begin);
   if (tiles.size() > (size_t)0x7fffffff) return fail(OPF_ERANGE, "tile list too long");
+  int lds_cap = 0;
+  size_t smem = 0;
+  int rc0 = lds_needs(M, op, tiles, s, lds_cap, smem);
+  if (rc0 != OPF_OK) return rc0;
+  L.lds_cap = lds_cap;
+  L.smem = smem;
   if ((int)tiles.size() > L.cap) {
     if (L.d) OPF_HIP(hipFree(L.d));
     L.d = nullptr;
@@ -214,6 +252,8 @@ Launch launch_of(const opf_model* M, int op) {
   l.block = L.shape.block;
   l.grid = L.shape.grid > 0 ? std::min(L.shape.grid, L.n) : 0;
   l.stream = M->stream;
+  l.cap0 = L.lds_cap;
+  l.smem = L.smem;
   return l;
 }
 
@@ -230,7 +270,7 @@ struct Arena {
 int upload_model(opf_model* M) {
   Arena a;
   struct Place {
-    size_t f_bus, t_bus, gen_bus, adm, c2, c1, c0, pd, qd, bus_ptr, bus_adj, bgen_ptr, bgen, krow, kcol, ksrc;
+    size_t f_bus, t_bus, gen_bus, adm, c2, c1, c0, pd, qd, bus_ptr, bus_adj, bus_nb, bgen_ptr, bgen, krow, kcol, ksrc;
     size_t vmin, vmax, pmin, pmax, qmin, qmax, ramp, rate, angmin, angmax;
   };
   std::vector<Place> pl(M->inst.size());
@@ -250,6 +290,7 @@ int upload_model(opf_model* M) {
     p.qd = a.take(b8(I.qd.size()));
     p.bus_ptr = a.take(b4(I.bus_ptr.size()));
     p.bus_adj = a.take(b4(I.bus_adj.size()));
+    p.bus_nb = a.take(b4(I.bus_nb.size()));
     p.bgen_ptr = a.take(b4(I.bgen_ptr.size()));
     p.bgen = a.take(b4(I.bgen.size()));
     p.krow = a.take(b4(I.krow.size()));
@@ -291,6 +332,7 @@ int upload_model(opf_model* M) {
     PUT(qd);
     PUT(bus_ptr);
     PUT(bus_adj);
+    PUT(bus_nb);
     PUT(bgen_ptr);
     PUT(bgen);
     PUT(krow);
@@ -339,6 +381,7 @@ int upload_model(opf_model* M) {
     PTR(qd, double*);
     PTR(bus_ptr, const int32_t*);
     PTR(bus_adj, const int32_t*);
+    PTR(bus_nb, const int32_t*);
     PTR(bgen_ptr, const int32_t*);
     PTR(bgen, const int32_t*);
     PTR(krow, const int32_t*);
@@ -848,9 +891,11 @@ extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
   std::vector<Shape> cached;
   int rc;
   if (read_cache(cache_path, key, cached)) {
-    for (int op = 0; op < OP_COUNT; ++op)
-      if ((rc = set_shape(M, op, cached[op])) != OPF_OK) return rc;
-    return OPF_OK;
+    bool ok = true;
+    for (int op = 0; op < OP_COUNT && ok; ++op) ok = set_shape(M, op, cached[op]) == OPF_OK;
+    if (ok) return OPF_OK;
+    for (int op = 0; op < OP_COUNT; ++op)  // stale entry: back to defaults, then tune
+      if ((rc = set_shape(M, op, Shape())) != OPF_OK) return rc;
   }
   // scratch inputs / outputs for timing (contents only need to be finite)
   const size_t n = M->n, m = M->m;
@@ -922,7 +967,10 @@ extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
           s.block = b;
           s.ppt = p;
           s.grid = gm == 0 ? 0 : M->n_cu * (2048 / b);
-          if ((rc = set_shape(M, op, s)) != OPF_OK) break;
+          if ((op == OP_KKA && b > 256) || (rc = set_shape(M, op, s)) != OPF_OK) {
+            rc = OPF_OK;  // infeasible shape (block or LDS limit): skip it
+            continue;
+          }
           if (gm == 1 && M->lists[op].n <= s.grid) continue;  // same as one block per tile
           hipError_t he = run(op);
           if (he != hipSuccess) {

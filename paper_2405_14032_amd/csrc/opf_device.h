@@ -18,7 +18,7 @@ struct InstDev {
   const double* adm;  // [8][B]: Gff Bff Gft Bft Gtf Btf Gtt Btt
   const double *c2, *c1, *c0;
   double *pd, *qd;  // [T][N]
-  const int32_t *bus_ptr, *bus_adj, *bgen_ptr, *bgen;
+  const int32_t *bus_ptr, *bus_adj, *bus_nb, *bgen_ptr, *bgen;
   const int32_t *krow, *kcol, *ksrc;
   const double *vmin, *vmax, *pmin, *pmax, *qmin, *qmax, *ramp, *rate, *angmin, *angmax;
 };
@@ -61,6 +61,8 @@ struct Launch {
   int block;
   int grid;
   hipStream_t stream;
+  int cap0 = 0;     // LDS segment capacity (doubles) of the staged kernels
+  size_t smem = 0;  // dynamic LDS bytes
 };
 
 hipError_t launch_jac(const Launch& L, const double* x, double* jv);

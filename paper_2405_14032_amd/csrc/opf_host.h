@@ -35,7 +35,7 @@ struct InstHost {
   std::vector<double> vmin, vmax, pmin, pmax, qmin, qmax, ramp, rate, angmin, angmax;
   // bus incidence, entries (l << 1 | end) sorted by (neighbour bus, l);
   // end 0: the bus is the line's from end, 1: its to end
-  std::vector<int32_t> bus_ptr, bus_adj;
+  std::vector<int32_t> bus_ptr, bus_adj, bus_nb;  // bus_nb: neighbour bus of each entry
   // generators at each bus, ascending
   std::vector<int32_t> bgen_ptr, bgen;
   // condensed-matrix template of one period (t = 0 layout): CSR over the

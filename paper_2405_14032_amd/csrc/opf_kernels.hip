@@ -485,111 +485,27 @@ __global__ void __launch_bounds__(512) k_jt_b(const InstDev* __restrict__ insts,
 // ---------------------------------------------------------------- condensed
 // K = lower(H + diag(diag_x) + J^T diag(d) J) on the fixed CSR.
 //
-// Phase A (lines): a line owns the four flow-variable rows of K; their
-// slots are the four bus-variable pairs (one flow row each), the lower
-// members of the balance row the flow enters, the thermal partner, and the
-// diagonal.  It also reduces its own contributions to the ten bus-variable
-// slots it touches (end-local pairs at i and j, four cross pairs) into a
-// scratch record.  Generators own the pg / qg rows (balance partners, the
-// ramp pair of t >= 1, diagonal).
-// Phase B (buses): a bus owns its vm and va rows and sums the scratch
-// records of its incident lines per neighbour (merging parallel lines).
-__device__ void kkt_branch(const InstDev& I, int l, int t0, int t1, const double* __restrict__ H,
-                           const double* __restrict__ J, const double* __restrict__ DX,
-                           const double* __restrict__ D, double* __restrict__ K, double* __restrict__ scr) {
-  const Bases b(I);
-  const int64_t B = b.B, N = b.N, G = b.G;
-  const int i = I.f_bus[l], j = I.t_bus[l];
-  const bool ilo = i < j;
-  int rs[4], re[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    rs[k] = I.krow[b.xFL + k * B + l];
-    re[k] = I.krow[b.xFL + k * B + l + 1];
-  }
-  for (int t = t0; t < t1; ++t) {
-    const double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
-    const double* hp = H + I.h_off + (int64_t)t * I.nnzh_p;
-    const double* dp = D + I.c_off + (int64_t)t * I.m_p;
-    double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t) + (t >= 1 ? G : 0);
-    double Jf[4][5], df[4], Jb[4], Jt[4], Hth[4], dbal[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-#pragma unroll
-      for (int a = 0; a < 5; ++a) Jf[k][a] = jp[b.jFLOW + (int64_t)(k * 5 + a) * B + l];
-      df[k] = dp[b.cFLOW + k * B + l];
-      Jb[k] = jp[b.jBAL + k * B + l];
-      Jt[k] = jp[b.jTH + k * B + l];
-      Hth[k] = hp[b.hTH + k * B + l];
-    }
-    dbal[0] = dp[i];
-    dbal[1] = dp[N + i];
-    dbal[2] = dp[j];
-    dbal[3] = dp[N + j];
-    const double dth[2] = {dp[b.cTHF + l], dp[b.cTHT + l]};
-    const double dang = dp[b.cANG + l];
-    const double Ja0 = jp[b.jANG + l], Ja1 = jp[b.jANG + B + l];
-    // flow-variable rows
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double pk = df[k] * Jf[k][0];
-      double* row = kb + rs[k];
-      if (ilo) {
-        row[0] = pk * Jf[k][1];
-        row[1] = pk * Jf[k][2];
-        row[2] = pk * Jf[k][3];
-        row[3] = pk * Jf[k][4];
-      } else {
-        row[0] = pk * Jf[k][2];
-        row[1] = pk * Jf[k][1];
-        row[2] = pk * Jf[k][4];
-        row[3] = pk * Jf[k][3];
-      }
-      const double pb = dbal[k] * Jb[k];
-      for (int p = rs[k] + 4; p < re[k] - 1; ++p) {
-        const int src = I.ksrc[p];
-        kb[p] = ((k & 1) && src < 0) ? dth[k >> 1] * Jt[k ^ 1] * Jt[k] : pb * jp[src];
-      }
-      const double dxv = DX ? DX[I.x_off + (int64_t)t * I.n_p + b.xFL + k * B + l] : 0.0;
-      kb[re[k] - 1] = dxv + pk * Jf[k][0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jb[k] + Hth[k];
-    }
-    // bus-variable contributions: P[a][b] = sum_k d_k J_k,a J_k,b + angle + H
-    double q[10];
-    q[0] = q[1] = q[2] = q[3] = q[4] = q[5] = q[6] = q[7] = q[8] = q[9] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double* hf = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
-      const double a1 = Jf[k][1], a2 = Jf[k][2], a3 = Jf[k][3], a4 = Jf[k][4];
-      const double d1 = df[k] * a1, d2 = df[k] * a2, d3 = df[k] * a3, d4 = df[k] * a4;
-      // local H order: from end (0,0)(1,0)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3);
-      // to end (1,0)(1,1)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3)
-      const double h0 = hf[0], h1 = hf[B];
-      if (k < 2) {
-        q[0] += d1 * a1 + h0;
-        q[3] += d2 * a2;
-        q[6] += d2 * a1 + h1;
-      } else {
-        q[0] += d1 * a1;
-        q[3] += d2 * a2 + h1;
-        q[6] += d2 * a1 + h0;
-      }
-      q[1] += d3 * a1 + hf[2 * B];
-      q[7] += d3 * a2 + hf[3 * B];
-      q[2] += d3 * a3 + hf[4 * B];
-      q[8] += d4 * a1 + hf[5 * B];
-      q[4] += d4 * a2 + hf[6 * B];
-      q[9] += d4 * a3 + hf[7 * B];
-      q[5] += d4 * a4 + hf[8 * B];
-    }
-    q[2] += dang * Ja0 * Ja0;
-    q[5] += dang * Ja1 * Ja1;
-    q[9] += dang * Ja1 * Ja0;
-    double* r = scr + I.s_off + ((int64_t)t * B + l) * kScratchKkt;
-#pragma unroll
-    for (int a = 0; a < 10; ++a) r[a] = q[a];
-  }
-}
-
+// Line phase: a block owns the four flow-variable rows of K of its lines,
+// one kind at a time.  Those rows are contiguous in K (rows are in x order),
+// so the block first builds the kind's row segment in LDS (owner lane per
+// row: the four bus-variable pairs of its flow row, the thermal partner,
+// the diagonal, and for every balance-row partner the factor d_bal * J_bal)
+// and then streams the segment to HBM with consecutive lanes on consecutive
+// slots; in that pass a lane whose slot is a balance partner multiplies by
+// the partner's J entry (one independent gather per lane).  Each line also
+// reduces its own contributions to the bus-variable slots it touches into a
+// 10-value hand-off record, staged in LDS and stored contiguously.
+// Generators own the pg / qg rows (balance partners, the ramp pair of
+// t >= 1, diagonal).
+// Bus phase: a bus owns its vm and va rows; one pass over its incident line
+// ends (sorted by neighbour) sums the records, merging parallel lines, into
+// an LDS copy of the block's row segments, streamed out the same way.
+//
+// Hand-off record of a line and period, laid out so that each end reads six
+// consecutive values (end i: [0, 6), end j: [4, 10)):
+//   [0] (vm_i,vm_i)  [1] (va_i,vm_i)  [2] (va_i,va_i)  [3] (va_i,vm_j)
+//   [4] (vm_j,vm_i)  [5] (va_j,va_i)
+//   [6] (vm_j,vm_j)  [7] (va_j,vm_j)  [8] (va_j,va_j)  [9] (va_j,vm_i)
 __device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, const double* __restrict__ H,
                         const double* __restrict__ J, const double* __restrict__ DX, const double* __restrict__ D,
                         double* __restrict__ K) {
@@ -626,86 +542,235 @@ __device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, const double* _
   }
 }
 
-__global__ void __launch_bounds__(512) k_kkt_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
-                                               int ntiles, const double* __restrict__ H,
-                                               const double* __restrict__ J, const double* __restrict__ DX,
-                                               const double* __restrict__ D, double* __restrict__ K,
-                                               double* __restrict__ scr) {
-  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
-    const Tile tl = tiles[remap_tile(v, ntiles)];
-    const InstDev& I = insts[tl.inst];
-    const int e = tl.e0 + (int)threadIdx.x;
-    if (e >= tl.e1) continue;
-    if (tl.kind == TK_BRANCH)
-      kkt_branch(I, e, tl.t0, tl.t1, H, J, DX, D, K, scr);
-    else
-      kkt_gen(I, e, tl.t0, tl.t1, H, J, DX, D, K);
+__device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __restrict__ H,
+                              const double* __restrict__ J, const double* __restrict__ DX,
+                              const double* __restrict__ D, double* __restrict__ K, double* __restrict__ scr,
+                              double* __restrict__ seg, double* __restrict__ rec) {
+  const Bases b(I);
+  const int64_t B = b.B, N = b.N, G = b.G;
+  const int tid = (int)threadIdx.x;
+  const int l = tl.e0 + tid;
+  const bool act = l < tl.e1;
+  const int nl = tl.e1 - tl.e0;
+  int sb[4], se[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    sb[k] = I.krow[b.xFL + k * B + tl.e0];
+    se[k] = I.krow[b.xFL + k * B + tl.e1];
+  }
+  int i = 0, j = 0, rs[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0};
+  if (act) {
+    i = I.f_bus[l];
+    j = I.t_bus[l];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      rs[k] = I.krow[b.xFL + k * B + l] - sb[k];
+      re[k] = I.krow[b.xFL + k * B + l + 1] - sb[k];
+    }
+  }
+  const bool ilo = i < j;
+  for (int t = tl.t0; t < tl.t1; ++t) {
+    const double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
+    double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t) + (t >= 1 ? G : 0);
+    double Jf[4][5], df[4], Jb[4], Jt[4], Hth[4], dbal[4], dth[2];
+    if (act) {
+      const double* hp = H + I.h_off + (int64_t)t * I.nnzh_p;
+      const double* dp = D + I.c_off + (int64_t)t * I.m_p;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) Jf[k][a] = jp[b.jFLOW + (int64_t)(k * 5 + a) * B + l];
+        df[k] = dp[b.cFLOW + k * B + l];
+        Jb[k] = jp[b.jBAL + k * B + l];
+        Jt[k] = jp[b.jTH + k * B + l];
+        Hth[k] = hp[b.hTH + k * B + l];
+      }
+      dbal[0] = dp[i];
+      dbal[1] = dp[N + i];
+      dbal[2] = dp[j];
+      dbal[3] = dp[N + j];
+      dth[0] = dp[b.cTHF + l];
+      dth[1] = dp[b.cTHT + l];
+      const double dang = dp[b.cANG + l];
+      const double Ja0 = jp[b.jANG + l], Ja1 = jp[b.jANG + B + l];
+      // bus-variable contributions: sum_k d_k J_k,a J_k,b + angle + H
+      double q[10];
+#pragma unroll
+      for (int a = 0; a < 10; ++a) q[a] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double* hf = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
+        const double a1 = Jf[k][1], a2 = Jf[k][2], a3 = Jf[k][3], a4 = Jf[k][4];
+        const double d1 = df[k] * a1, d2 = df[k] * a2, d3 = df[k] * a3, d4 = df[k] * a4;
+        // local H order: from end (0,0)(1,0)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3);
+        // to end (1,0)(1,1)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3)
+        const double h0 = hf[0], h1 = hf[B];
+        if (k < 2) {
+          q[0] += d1 * a1 + h0;
+          q[6] += d2 * a2;
+          q[4] += d2 * a1 + h1;
+        } else {
+          q[0] += d1 * a1;
+          q[6] += d2 * a2 + h1;
+          q[4] += d2 * a1 + h0;
+        }
+        q[1] += d3 * a1 + hf[2 * B];
+        q[3] += d3 * a2 + hf[3 * B];
+        q[2] += d3 * a3 + hf[4 * B];
+        q[9] += d4 * a1 + hf[5 * B];
+        q[7] += d4 * a2 + hf[6 * B];
+        q[5] += d4 * a3 + hf[7 * B];
+        q[8] += d4 * a4 + hf[8 * B];
+      }
+      q[2] += dang * Ja0 * Ja0;
+      q[8] += dang * Ja1 * Ja1;
+      q[5] += dang * Ja1 * Ja0;
+#pragma unroll
+      for (int a = 0; a < 10; ++a) rec[tid * kScratchKkt + a] = q[a];
+    }
+    // flow-variable rows, one kind at a time through LDS
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (act) {
+        const double pk = df[k] * Jf[k][0];
+        double* row = seg + rs[k];
+        if (ilo) {
+          row[0] = pk * Jf[k][1];
+          row[1] = pk * Jf[k][2];
+          row[2] = pk * Jf[k][3];
+          row[3] = pk * Jf[k][4];
+        } else {
+          row[0] = pk * Jf[k][2];
+          row[1] = pk * Jf[k][1];
+          row[2] = pk * Jf[k][4];
+          row[3] = pk * Jf[k][3];
+        }
+        const double pb = dbal[k] * Jb[k];
+        for (int p = rs[k] + 4; p < re[k] - 1; ++p) {
+          // balance partners carry the factor, the thermal partner its value
+          seg[p] = ((k & 1) && I.ksrc[sb[k] + p] < 0) ? dth[k >> 1] * Jt[k ^ 1] * Jt[k] : pb;
+        }
+        const double dxv = DX ? DX[I.x_off + (int64_t)t * I.n_p + b.xFL + k * B + l] : 0.0;
+        seg[re[k] - 1] = dxv + pk * Jf[k][0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jb[k] + Hth[k];
+      }
+      __syncthreads();
+      const int len = se[k] - sb[k];
+      for (int p = tid; p < len; p += (int)blockDim.x) {
+        const int src = I.ksrc[sb[k] + p];
+        double v = seg[p];
+        if (src >= 0) v *= jp[src];
+        kb[sb[k] + p] = v;
+      }
+      __syncthreads();
+    }
+    double* dst = scr + I.s_off + ((int64_t)t * B + tl.e0) * kScratchKkt;
+    for (int p = tid; p < nl * kScratchKkt; p += (int)blockDim.x) dst[p] = rec[p];
+    __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(512) k_kkt_b(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
-                                               int ntiles, const double* __restrict__ J,
-                                               const double* __restrict__ DX, const double* __restrict__ D,
-                                               double* __restrict__ K, const double* __restrict__ scr) {
+// Dynamic LDS: seg[cap_seg] then rec[blockDim * 10] (doubles).
+__global__ void __launch_bounds__(256) k_kkt_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                               int ntiles, int cap_seg, const double* __restrict__ H,
+                                               const double* __restrict__ J, const double* __restrict__ DX,
+                                               const double* __restrict__ D, double* __restrict__ K,
+                                               double* __restrict__ scr) {
+  extern __shared__ double lds[];
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile tl = tiles[remap_tile(v, ntiles)];
     const InstDev& I = insts[tl.inst];
-    const int n = tl.e0 + (int)threadIdx.x;
-    if (n >= tl.e1) continue;
+    if (tl.kind == TK_BRANCH) {
+      kkt_line_tile(I, tl, H, J, DX, D, K, scr, lds, lds + cap_seg);
+    } else {
+      const int e = tl.e0 + (int)threadIdx.x;
+      if (e < tl.e1) kkt_gen(I, e, tl.t0, tl.t1, H, J, DX, D, K);
+    }
+  }
+}
+
+// Dynamic LDS: vm-row segment [cap_vm] then va-row segment [cap_va].
+__global__ void __launch_bounds__(512) k_kkt_b(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                               int ntiles, int cap_vm, const double* __restrict__ J,
+                                               const double* __restrict__ DX, const double* __restrict__ D,
+                                               double* __restrict__ K, const double* __restrict__ scr) {
+  extern __shared__ double lds[];
+  double* svm = lds;
+  double* sva = lds + cap_vm;
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
     const int64_t N = I.N;
-    const int q0 = I.bus_ptr[n], q1 = I.bus_ptr[n + 1];
-    const int vmr = I.krow[n], var = I.krow[N + n];
-    const int clo = I.krow[n + 1] - vmr - 1;
-    const int lva = I.krow[N + n + 1] - var;
-    const int call = lva - clo - 2;
+    const int tid = (int)threadIdx.x;
+    const int n = tl.e0 + tid;
+    const bool act = n < tl.e1;
+    const int b0 = I.krow[tl.e0], b1 = I.krow[tl.e1];
+    const int a0 = I.krow[N + tl.e0], a1 = I.krow[N + tl.e1];
+    int q0 = 0, q1 = 0, vmr = 0, var = 0, clo = 0, lva = 0, call = 0;
+    if (act) {
+      q0 = I.bus_ptr[n];
+      q1 = I.bus_ptr[n + 1];
+      vmr = I.krow[n] - b0;
+      var = I.krow[N + n] - a0;
+      clo = I.krow[n + 1] - I.krow[n] - 1;
+      lva = I.krow[N + n + 1] - I.krow[N + n];
+      call = lva - clo - 2;
+    }
     for (int t = tl.t0; t < tl.t1; ++t) {
-      const double* rs = scr + I.s_off + (int64_t)t * I.B * kScratchKkt;
       double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
-      // same-bus sums over every incident line end
-      double svm = 0.0, svavm = 0.0, sva = 0.0;
-      for (int a = q0; a < q1; ++a) {
-        const int ad = I.bus_adj[a];
-        const double* r = rs + (int64_t)(ad >> 1) * kScratchKkt + ((ad & 1) ? 3 : 0);
-        svm += r[0];
-        svavm += r[1];
-        sva += r[2];
-      }
-      // cross slots, one per distinct neighbour (parallel lines merged)
-      int gi = 0, prev = -1;
-      double cvm = 0.0, cvavm = 0.0, cva = 0.0;
-      for (int a = q0; a <= q1; ++a) {
-        int m = -1, ad = 0;
-        if (a < q1) {
-          ad = I.bus_adj[a];
-          m = (ad & 1) ? I.f_bus[ad >> 1] : I.t_bus[ad >> 1];
-        }
-        if (prev >= 0 && m != prev) {
-          if (prev < n) {
-            kb[vmr + gi] = cvm;
-            kb[var + gi] = cvavm;
-            kb[var + call + 1 + gi] = cva;
-          } else {
-            kb[var + gi + 1] = cvavm;
+      if (act) {
+        const double* rs = scr + I.s_off + (int64_t)t * I.B * kScratchKkt;
+        double svm_s = 0.0, svavm_s = 0.0, sva_s = 0.0;
+        double cvm = 0.0, cvavm = 0.0, cva = 0.0;
+        int gi = 0, prev = -1;
+        for (int a = q0; a < q1; ++a) {
+          const int ad = I.bus_adj[a];
+          const int m = I.bus_nb[a];
+          if (prev >= 0 && m != prev) {
+            if (prev < n) {
+              svm[vmr + gi] = cvm;
+              sva[var + gi] = cvavm;
+              sva[var + call + 1 + gi] = cva;
+            } else {
+              sva[var + gi + 1] = cvavm;
+            }
+            ++gi;
+            cvm = cvavm = cva = 0.0;
           }
-          ++gi;
-          cvm = cvavm = cva = 0.0;
+          prev = m;
+          const int e = ad & 1;
+          const double* r = rs + (int64_t)(ad >> 1) * kScratchKkt + 4 * e;
+          const double* own = r + (e ? 2 : 0);
+          const double* sh = r + (e ? 0 : 4);
+          svm_s += own[0];
+          svavm_s += own[1];
+          sva_s += own[2];
+          cvavm += own[3];
+          cvm += sh[0];
+          cva += sh[1];
         }
-        if (a == q1) break;
-        prev = m;
-        const double* r = rs + (int64_t)(ad >> 1) * kScratchKkt;
-        cvm += r[6];
-        cvavm += (ad & 1) ? r[8] : r[7];
-        cva += r[9];
+        if (prev >= 0) {
+          if (prev < n) {
+            svm[vmr + gi] = cvm;
+            sva[var + gi] = cvavm;
+            sva[var + call + 1 + gi] = cva;
+          } else {
+            sva[var + gi + 1] = cvavm;
+          }
+        }
+        const int64_t xo = I.x_off + (int64_t)t * I.n_p;
+        double dref = 0.0;
+        if (n == I.ref) {
+          const double jr = J[I.j_off + (int64_t)t * I.nnzj_p + 2LL * I.G + 4LL * I.B];
+          dref = D[I.c_off + (int64_t)t * I.m_p + 2 * N] * jr * jr;
+        }
+        svm[vmr + clo] = (DX ? DX[xo + n] : 0.0) + svm_s;
+        if (q1 > q0) sva[var + clo] = svavm_s;  // (va_n, vm_n) exists only with an incident line
+        sva[var + lva - 1] = (DX ? DX[xo + N + n] : 0.0) + sva_s + dref;
       }
-      const int64_t xo = I.x_off + (int64_t)t * I.n_p;
-      double dref = 0.0;
-      if (n == I.ref) {
-        const double jr = J[I.j_off + (int64_t)t * I.nnzj_p + 2LL * I.G + 4LL * I.B];
-        dref = D[I.c_off + (int64_t)t * I.m_p + 2 * N] * jr * jr;
-      }
-      kb[vmr + clo] = (DX ? DX[xo + n] : 0.0) + svm;
-      if (q1 > q0) kb[var + clo] = svavm;  // (va_n, vm_n) exists only with an incident line
-      kb[var + lva - 1] = (DX ? DX[xo + N + n] : 0.0) + sva + dref;
+      __syncthreads();
+      for (int p = tid; p < b1 - b0; p += (int)blockDim.x) kb[b0 + p] = svm[p];
+      for (int p = tid; p < a1 - a0; p += (int)blockDim.x) kb[a0 + p] = sva[p];
+      __syncthreads();
     }
   }
 }
@@ -949,11 +1014,17 @@ hipError_t launch_jt_b(const Launch& L, const double* v, double* out, const doub
 }
 hipError_t launch_kkt_a(const Launch& L, const double* h, const double* j, const double* dx, const double* d,
                         double* k, double* scratch) {
-  OPF_LAUNCH(k_kkt_a, L, h, j, dx, d, k, scratch);
+  if (L.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kkt_a, grid_of(L), dim3((unsigned)L.block), L.smem, L.stream, L.insts, L.tiles, L.ntiles,
+                     L.cap0, h, j, dx, d, k, scratch);
+  return hipGetLastError();
 }
 hipError_t launch_kkt_b(const Launch& L, const double* j, const double* dx, const double* d, double* k,
                         const double* scratch) {
-  OPF_LAUNCH(k_kkt_b, L, j, dx, d, k, scratch);
+  if (L.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kkt_b, grid_of(L), dim3((unsigned)L.block), L.smem, L.stream, L.insts, L.tiles, L.ntiles,
+                     L.cap0, j, dx, d, k, scratch);
+  return hipGetLastError();
 }
 hipError_t launch_jac_struct(const Launch& L, int32_t* rows, int32_t* cols) {
   OPF_LAUNCH(k_jac_struct, L, rows, cols);

@@ -171,10 +171,15 @@ int build_instance(const opf_instance_desc& d, InstHost& I, std::string& err) {
   }
   I.bus_ptr.assign(N + 1, 0);
   I.bus_adj.clear();
+  I.bus_nb.clear();
   I.bus_adj.reserve(2 * (size_t)B);
+  I.bus_nb.reserve(2 * (size_t)B);
   for (int32_t n = 0; n < N; ++n) {
     std::sort(inc[n].begin(), inc[n].end());
-    for (auto& e : inc[n]) I.bus_adj.push_back(e.second);
+    for (auto& e : inc[n]) {
+      I.bus_adj.push_back(e.second);
+      I.bus_nb.push_back(e.first);
+    }
     I.bus_ptr[n + 1] = (int32_t)I.bus_adj.size();
   }
   std::vector<std::vector<int32_t>> gat(N);
