@@ -197,7 +197,7 @@ int lds_needs(const opf_model* M, int op, const std::vector<Tile>& tiles, const 
       cap2 = std::max<int>(cap2, I.krow[I.N + tl.e1] - I.krow[I.N + tl.e0]);
     }
   }
-  smem = op == OP_KKA ? ((size_t)cap + (size_t)s.block * kScratchKkt) * sizeof(double)
+  smem = op == OP_KKA ? std::max((size_t)cap, (size_t)s.block * kScratchKkt) * sizeof(double)
                       : ((size_t)cap + (size_t)cap2) * sizeof(double);
   if (smem > kMaxSmem) return fail(OPF_EINVAL, std::string("tile shape needs too much LDS for ") + kOpName[op]);
   return OPF_OK;

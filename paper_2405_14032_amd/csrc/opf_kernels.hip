@@ -542,10 +542,40 @@ __device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, const double* _
   }
 }
 
+// Streams a K row segment from LDS to HBM with consecutive lanes on
+// consecutive slots.  A slot whose template source is a J entry (a balance
+// partner) holds the factor d_bal * J_bal and is multiplied by that entry;
+// four slots per lane are handled per step so their template loads and J
+// gathers are in flight together.
+__device__ __forceinline__ void stream_segment(const double* __restrict__ seg, const int32_t* __restrict__ src,
+                                               const double* __restrict__ jp, double* __restrict__ dst,
+                                               int len) {
+  constexpr int U = 4;
+  const int bd = (int)blockDim.x;
+  for (int p0 = (int)threadIdx.x; p0 < len; p0 += U * bd) {
+    int sr[U];
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * bd;
+      sr[u] = p < len ? src[p] : -2;
+      v[u] = p < len ? seg[p] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (sr[u] >= 0) v[u] *= jp[sr[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * bd;
+      if (p < len) dst[p] = v[u];
+    }
+  }
+}
+
 __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __restrict__ H,
                               const double* __restrict__ J, const double* __restrict__ DX,
                               const double* __restrict__ D, double* __restrict__ K, double* __restrict__ scr,
-                              double* __restrict__ seg, double* __restrict__ rec) {
+                              double* __restrict__ seg) {
   const Bases b(I);
   const int64_t B = b.B, N = b.N, G = b.G;
   const int tid = (int)threadIdx.x;
@@ -572,7 +602,7 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
   for (int t = tl.t0; t < tl.t1; ++t) {
     const double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
     double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t) + (t >= 1 ? G : 0);
-    double Jf[4][5], df[4], Jb[4], Jt[4], Hth[4], dbal[4], dth[2];
+    double Jf[4][5], df[4], Jb[4], Jt[4], Hth[4], dbal[4], dth[2], q[10];
     if (act) {
       const double* hp = H + I.h_off + (int64_t)t * I.nnzh_p;
       const double* dp = D + I.c_off + (int64_t)t * I.m_p;
@@ -594,7 +624,6 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
       const double dang = dp[b.cANG + l];
       const double Ja0 = jp[b.jANG + l], Ja1 = jp[b.jANG + B + l];
       // bus-variable contributions: sum_k d_k J_k,a J_k,b + angle + H
-      double q[10];
 #pragma unroll
       for (int a = 0; a < 10; ++a) q[a] = 0.0;
 #pragma unroll
@@ -625,8 +654,6 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
       q[2] += dang * Ja0 * Ja0;
       q[8] += dang * Ja1 * Ja1;
       q[5] += dang * Ja1 * Ja0;
-#pragma unroll
-      for (int a = 0; a < 10; ++a) rec[tid * kScratchKkt + a] = q[a];
     }
     // flow-variable rows, one kind at a time through LDS
 #pragma unroll
@@ -654,22 +681,22 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
         seg[re[k] - 1] = dxv + pk * Jf[k][0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jb[k] + Hth[k];
       }
       __syncthreads();
-      const int len = se[k] - sb[k];
-      for (int p = tid; p < len; p += (int)blockDim.x) {
-        const int src = I.ksrc[sb[k] + p];
-        double v = seg[p];
-        if (src >= 0) v *= jp[src];
-        kb[sb[k] + p] = v;
-      }
+      stream_segment(seg, I.ksrc + sb[k], jp, kb + sb[k], se[k] - sb[k]);
       __syncthreads();
     }
+    // hand-off records through the (now free) segment buffer
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < kScratchKkt; ++a) seg[tid * kScratchKkt + a] = q[a];
+    }
+    __syncthreads();
     double* dst = scr + I.s_off + ((int64_t)t * B + tl.e0) * kScratchKkt;
-    for (int p = tid; p < nl * kScratchKkt; p += (int)blockDim.x) dst[p] = rec[p];
+    for (int p = tid; p < nl * kScratchKkt; p += (int)blockDim.x) dst[p] = seg[p];
     __syncthreads();
   }
 }
 
-// Dynamic LDS: seg[cap_seg] then rec[blockDim * 10] (doubles).
+// Dynamic LDS: seg[max(cap_seg, blockDim * 10)] doubles.
 __global__ void __launch_bounds__(256) k_kkt_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
                                                int ntiles, int cap_seg, const double* __restrict__ H,
                                                const double* __restrict__ J, const double* __restrict__ DX,
@@ -680,7 +707,7 @@ __global__ void __launch_bounds__(256) k_kkt_a(const InstDev* __restrict__ insts
     const Tile tl = tiles[remap_tile(v, ntiles)];
     const InstDev& I = insts[tl.inst];
     if (tl.kind == TK_BRANCH) {
-      kkt_line_tile(I, tl, H, J, DX, D, K, scr, lds, lds + cap_seg);
+      kkt_line_tile(I, tl, H, J, DX, D, K, scr, lds);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
       if (e < tl.e1) kkt_gen(I, e, tl.t0, tl.t1, H, J, DX, D, K);
@@ -722,31 +749,49 @@ __global__ void __launch_bounds__(512) k_kkt_b(const InstDev* __restrict__ insts
         double svm_s = 0.0, svavm_s = 0.0, sva_s = 0.0;
         double cvm = 0.0, cvavm = 0.0, cva = 0.0;
         int gi = 0, prev = -1;
-        for (int a = q0; a < q1; ++a) {
-          const int ad = I.bus_adj[a];
-          const int m = I.bus_nb[a];
-          if (prev >= 0 && m != prev) {
-            if (prev < n) {
-              svm[vmr + gi] = cvm;
-              sva[var + gi] = cvavm;
-              sva[var + call + 1 + gi] = cva;
-            } else {
-              sva[var + gi + 1] = cvavm;
-            }
-            ++gi;
-            cvm = cvavm = cva = 0.0;
+        constexpr int U = 4;
+        for (int a0 = q0; a0 < q1; a0 += U) {
+          // issue the incidence loads and record gathers of up to U ends together
+          int ad[U], nb[U];
+          double r[U][6];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const bool ok = a0 + u < q1;
+            ad[u] = ok ? I.bus_adj[a0 + u] : 0;
+            nb[u] = ok ? I.bus_nb[a0 + u] : -1;
           }
-          prev = m;
-          const int e = ad & 1;
-          const double* r = rs + (int64_t)(ad >> 1) * kScratchKkt + 4 * e;
-          const double* own = r + (e ? 2 : 0);
-          const double* sh = r + (e ? 0 : 4);
-          svm_s += own[0];
-          svavm_s += own[1];
-          sva_s += own[2];
-          cvavm += own[3];
-          cvm += sh[0];
-          cva += sh[1];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const double* rp = rs + (int64_t)(ad[u] >> 1) * kScratchKkt + 4 * (ad[u] & 1);
+#pragma unroll
+            for (int w = 0; w < 6; ++w) r[u][w] = nb[u] >= 0 ? rp[w] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (nb[u] < 0) break;
+            const int m = nb[u];
+            if (prev >= 0 && m != prev) {
+              if (prev < n) {
+                svm[vmr + gi] = cvm;
+                sva[var + gi] = cvavm;
+                sva[var + call + 1 + gi] = cva;
+              } else {
+                sva[var + gi + 1] = cvavm;
+              }
+              ++gi;
+              cvm = cvavm = cva = 0.0;
+            }
+            prev = m;
+            // own-end values at [0,4) of end i's window, [2,6) of end j's;
+            // the shared cross pair at [4,6) for end i, [0,2) for end j
+            const bool ej = ad[u] & 1;
+            svm_s += ej ? r[u][2] : r[u][0];
+            svavm_s += ej ? r[u][3] : r[u][1];
+            sva_s += ej ? r[u][4] : r[u][2];
+            cvavm += ej ? r[u][5] : r[u][3];
+            cvm += ej ? r[u][0] : r[u][4];
+            cva += ej ? r[u][1] : r[u][5];
+          }
         }
         if (prev >= 0) {
           if (prev < n) {
