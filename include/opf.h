@@ -192,8 +192,19 @@ int opf_assemble_condensed(opf_model *model, const double *hvals,
                            const double *jvals, const double *diag_x,
                            const double *dcon, double *kvals);
 
+/* Jacobian, Hessian and condensed matrix in one pass over x: the values of
+ * opf_eval_jac, opf_eval_hess and opf_assemble_condensed (bitwise identical
+ * to those three calls), with K built from the J / H values while they are
+ * in registers instead of reading them back (the per-pattern evaluation of
+ * Sec. III-A feeding the condensation of Sec. III-B directly).  diag_x may
+ * be NULL. */
+int opf_eval_jhk(opf_model *model, const double *x, const double *lambda,
+                 double sigma, const double *diag_x, const double *dcon,
+                 double *jvals, double *hvals, double *kvals);
+
 /* Every requested output of one iteration's evaluation, enqueued as
- * persistent tile-list kernels covering all instances. */
+ * persistent tile-list kernels covering all instances; when jvals, hvals and
+ * kvals are all requested the fused pass of opf_eval_jhk is used. */
 int opf_sweep(opf_model *model, const opf_sweep_args *args);
 /* The same sweep recorded once into a HIP graph (re-recorded when the
  * argument set changes) and replayed with a single graph launch. */

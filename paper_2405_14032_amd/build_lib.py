@@ -22,6 +22,9 @@ def build(verbose: bool = False) -> str:
         hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
         # no packed-FP32 instructions anywhere in the device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # contraction decided per source expression, so every kernel that
+        # shares an expression rounds it identically
+        "-ffp-contract=on",
         "-Wall", "-Wno-unused-result",
         "-o", LIB + ".tmp",
     ] + [os.path.join(HERE, s) for s in SOURCES]

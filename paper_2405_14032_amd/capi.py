@@ -86,6 +86,7 @@ _SIGS = {
     "opf_set_load": (C.c_int, [_vp, _vp, _vp]),
     "opf_load_adjoint": (C.c_int, [_vp, _vp, _vp, _vp]),
     "opf_assemble_condensed": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "opf_eval_jhk": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _vp, _vp, _vp, _vp]),
     "opf_sweep": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
     "opf_sweep_graph": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
     "opf_autotune": (C.c_int, [_vp, C.c_char_p]),
@@ -258,6 +259,10 @@ class Model:
     def assemble_condensed(self, hv, jv, diag_x, dcon, kv):
         check(opf_assemble_condensed(self.h, _ptr(hv), _ptr(jv), _ptr(diag_x), _ptr(dcon), _ptr(kv)),
               "opf_assemble_condensed")
+
+    def eval_jhk(self, x, lam, sigma, diag_x, dcon, jv, hv, kv):
+        check(opf_eval_jhk(self.h, _ptr(x), _ptr(lam), float(sigma), _ptr(diag_x), _ptr(dcon), _ptr(jv),
+                           _ptr(hv), _ptr(kv)), "opf_eval_jhk")
 
     @staticmethod
     def sweep_args(x=None, lam=None, sigma=1.0, v=None, diag_x=None, dcon=None, f=None, grad=None, c=None,

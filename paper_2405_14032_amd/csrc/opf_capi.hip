@@ -51,12 +51,15 @@ enum Op {
   OP_KSTR,
   OP_BOUNDS,
   OP_LADJ,
+  OP_JHKA,
+  OP_SWA,
+  OP_SWB,
   OP_COUNT
 };
 
 const char* kOpName[OP_COUNT] = {"jac", "hess", "cons", "grad", "obj", "jt_a", "jt_b",
                                  "kkt_a", "kkt_b", "jac_struct", "hess_struct", "kkt_struct",
-                                 "bounds", "load_adjoint"};
+                                 "bounds", "load_adjoint", "jhk_a", "sweep_a", "sweep_b"};
 
 struct Shape {
   int block = 256;  // elements per tile = threads per block
@@ -111,6 +114,8 @@ std::vector<int> kinds_of(int op) {
     case OP_HESS:
     case OP_JTA:
     case OP_KKA:
+    case OP_JHKA:
+    case OP_SWA:
     case OP_JSTR:
     case OP_HSTR:
       return {TK_BRANCH, TK_GEN};
@@ -122,6 +127,7 @@ std::vector<int> kinds_of(int op) {
       return {TK_GEN};
     case OP_JTB:
     case OP_KKB:
+    case OP_SWB:
     case OP_LADJ:
       return {TK_BUS};
     case OP_KSTR:
@@ -183,22 +189,23 @@ int lds_needs(const opf_model* M, int op, const std::vector<Tile>& tiles, const 
               size_t& smem) {
   cap = 0;
   smem = 0;
-  if (op != OP_KKA && op != OP_KKB) return OPF_OK;
-  if (op == OP_KKA && s.block > 256) return fail(OPF_EINVAL, "condensed line kernel: block > 256");
+  const bool line = op == OP_KKA || op == OP_JHKA || op == OP_SWA;
+  if (!line && op != OP_KKB && op != OP_SWB) return OPF_OK;
+  if (line && s.block > 256) return fail(OPF_EINVAL, "condensed line kernel: block > 256");
   int cap2 = 0;
   for (const Tile& tl : tiles) {
     const InstHost& I = M->inst[tl.inst];
-    if (op == OP_KKA && tl.kind == TK_BRANCH) {
+    if (line && tl.kind == TK_BRANCH) {
       const int64_t FL = 2LL * I.N + 2LL * I.G;
       for (int k = 0; k < 4; ++k)
         cap = std::max<int>(cap, I.krow[FL + (int64_t)k * I.B + tl.e1] - I.krow[FL + (int64_t)k * I.B + tl.e0]);
-    } else if (op == OP_KKB) {
+    } else if (!line) {
       cap = std::max<int>(cap, I.krow[tl.e1] - I.krow[tl.e0]);
       cap2 = std::max<int>(cap2, I.krow[I.N + tl.e1] - I.krow[I.N + tl.e0]);
     }
   }
-  smem = op == OP_KKA ? std::max((size_t)cap, (size_t)s.block * kScratchKkt) * sizeof(double)
-                      : ((size_t)cap + (size_t)cap2) * sizeof(double);
+  smem = line ? std::max((size_t)cap, (size_t)s.block * kScratchKkt) * sizeof(double)
+               : ((size_t)cap + (size_t)cap2) * sizeof(double);
   if (smem > kMaxSmem) return fail(OPF_EINVAL, std::string("tile shape needs too much LDS for ") + kOpName[op]);
   return OPF_OK;
 }
@@ -477,6 +484,14 @@ int enq_kkt(opf_model* M, const double* h, const double* j, const double* dx, co
   return OPF_OK;
 }
 
+int enq_jhk(opf_model* M, const double* x, const double* lam, double sigma, const double* dx, const double* d,
+            double* j, double* h, double* k) {
+  OPF_LAUNCHED(launch_jhk_a(launch_of(M, OP_JHKA), x, lam, sigma, h, j, dx, d, k, M->scratch),
+               "fused J/H/condensed line kernel");
+  OPF_LAUNCHED(launch_kkt_b(launch_of(M, OP_KKB), j, dx, d, k, M->scratch), "condensed bus kernel");
+  return OPF_OK;
+}
+
 int check_sweep_args(const opf_sweep_args* a) {
   if (!a) return fail(OPF_EINVAL, "sweep args are NULL");
   const bool need_x = a->f || a->grad || a->c || a->jvals || a->hvals || a->jtv;
@@ -489,15 +504,33 @@ int check_sweep_args(const opf_sweep_args* a) {
 }
 
 int enq_sweep(opf_model* M, const opf_sweep_args* a) {
-  if (a->jvals) OPF_LAUNCHED(launch_jac(launch_of(M, OP_JAC), a->x, a->jvals), "Jacobian kernel");
-  if (a->hvals)
-    OPF_LAUNCHED(launch_hess(launch_of(M, OP_HESS), a->x, a->lambda, a->sigma, a->hvals), "Hessian kernel");
+  int rc;
+  // every per-element output requested: two fused passes (lines and
+  // generators, then buses) plus the objective reduction
+  if (a->grad && a->c && a->jvals && a->hvals && a->jtv && a->kvals) {
+    OPF_LAUNCHED(launch_sweep_a(launch_of(M, OP_SWA), a->x, a->lambda, a->sigma, a->v, a->hvals, a->jvals, a->diag_x,
+                                a->dcon, a->kvals, a->c, a->jtv, a->grad, M->scratch),
+                 "sweep line kernel");
+    OPF_LAUNCHED(launch_sweep_b(launch_of(M, OP_SWB), a->x, a->v, a->jvals, a->diag_x, a->dcon, a->kvals, a->c,
+                                a->jtv, a->grad, M->scratch),
+                 "sweep bus kernel");
+    if (a->f && (rc = enq_obj(M, a->x, a->f)) != OPF_OK) return rc;
+    return OPF_OK;
+  }
+  // J, H and K together: the fused pass (K from the J / H values in registers)
+  const bool fused = a->jvals && a->hvals && a->kvals;
+  if (fused) {
+    if ((rc = enq_jhk(M, a->x, a->lambda, a->sigma, a->diag_x, a->dcon, a->jvals, a->hvals, a->kvals)) != OPF_OK)
+      return rc;
+  } else {
+    if (a->jvals) OPF_LAUNCHED(launch_jac(launch_of(M, OP_JAC), a->x, a->jvals), "Jacobian kernel");
+    if (a->hvals)
+      OPF_LAUNCHED(launch_hess(launch_of(M, OP_HESS), a->x, a->lambda, a->sigma, a->hvals), "Hessian kernel");
+  }
   if (a->c) OPF_LAUNCHED(launch_cons(launch_of(M, OP_CONS), a->x, a->c), "constraint kernel");
   if (a->grad) OPF_LAUNCHED(launch_grad(launch_of(M, OP_GRAD), a->x, a->grad), "gradient kernel");
-  int rc;
   if (a->f && (rc = enq_obj(M, a->x, a->f)) != OPF_OK) return rc;
   if (a->jtv && (rc = enq_jt(M, a->x, a->v, a->jtv)) != OPF_OK) return rc;
-  if (a->kvals && (rc = enq_kkt(M, a->hvals, a->jvals, a->diag_x, a->dcon, a->kvals)) != OPF_OK) return rc;
   return OPF_OK;
 }
 
@@ -763,6 +796,14 @@ int opf_assemble_condensed(opf_model* M, const double* hv, const double* jv, con
   return enq_kkt(M, hv, jv, dx, d, kv);
 }
 
+int opf_eval_jhk(opf_model* M, const double* x, const double* lam, double sigma, const double* dx, const double* d,
+                 double* jv, double* hv, double* kv) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(x && lam && d && jv && hv && kv, "x / lambda / dcon / jvals / hvals / kvals");
+  DeviceGuard g(M->device);
+  return enq_jhk(M, x, lam, sigma, dx, d, jv, hv, kv);
+}
+
 int opf_sweep(opf_model* M, const opf_sweep_args* a) {
   OPF_CHECK_MODEL(M);
   int rc = check_sweep_args(a);
@@ -899,15 +940,17 @@ extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
   }
   // scratch inputs / outputs for timing (contents only need to be finite)
   const size_t n = M->n, m = M->m;
-  double *x = nullptr, *lam = nullptr, *dx = nullptr, *d = nullptr, *out_n = nullptr, *out_m = nullptr;
+  double *x = nullptr, *lam = nullptr, *dx = nullptr, *d = nullptr, *out_n = nullptr, *out_m = nullptr,
+         *dx_out = nullptr;
   double *jv = nullptr, *hv = nullptr, *kv = nullptr;
   auto cleanup = [&]() {
-    for (double* p : {x, lam, dx, d, out_n, out_m, jv, hv, kv})
+    for (double* p : {x, lam, dx, d, out_n, out_m, dx_out, jv, hv, kv})
       if (p) (void)hipFree(p);
   };
   if (hipMalloc(&x, n * 8) != hipSuccess || hipMalloc(&lam, m * 8) != hipSuccess ||
       hipMalloc(&dx, n * 8) != hipSuccess || hipMalloc(&d, m * 8) != hipSuccess ||
       hipMalloc(&out_n, n * 8) != hipSuccess || hipMalloc(&out_m, m * 8) != hipSuccess ||
+      hipMalloc(&dx_out, n * 8) != hipSuccess ||
       hipMalloc(&jv, M->nnzj * 8) != hipSuccess || hipMalloc(&hv, M->nnzh * 8) != hipSuccess ||
       hipMalloc(&kv, M->nnzk * 8) != hipSuccess) {
     cleanup();
@@ -946,13 +989,21 @@ extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
         return launch_kkt_a(launch_of(M, op), hv, jv, dx, d, kv, M->scratch);
       case OP_KKB:
         return launch_kkt_b(launch_of(M, op), jv, dx, d, kv, M->scratch);
+      case OP_JHKA:
+        return launch_jhk_a(launch_of(M, op), x, lam, 1.0, hv, jv, dx, d, kv, M->scratch);
+      case OP_SWA:
+        return launch_sweep_a(launch_of(M, op), x, lam, 1.0, lam, hv, jv, dx, d, kv, out_m, out_n, dx_out,
+                              M->scratch);
+      case OP_SWB:
+        return launch_sweep_b(launch_of(M, op), x, lam, jv, dx, d, kv, out_m, out_n, dx_out, M->scratch);
     }
     return hipSuccess;
   };
   // fill J and H once so the condensed candidates read finite data
   (void)run(OP_JAC);
   (void)run(OP_HESS);
-  const int tuned[] = {OP_JAC, OP_HESS, OP_CONS, OP_GRAD, OP_OBJ, OP_JTA, OP_JTB, OP_KKA, OP_KKB};
+  const int tuned[] = {OP_JAC, OP_HESS, OP_CONS, OP_GRAD, OP_OBJ, OP_JTA, OP_JTB, OP_KKA, OP_KKB, OP_JHKA,
+                       OP_SWA, OP_SWB};
   const int blocks[] = {64, 128, 256, 512};
   const int ppts[] = {1, 2, 4, 8};
   rc = OPF_OK;
@@ -967,7 +1018,8 @@ extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
           s.block = b;
           s.ppt = p;
           s.grid = gm == 0 ? 0 : M->n_cu * (2048 / b);
-          if ((op == OP_KKA && b > 256) || (rc = set_shape(M, op, s)) != OPF_OK) {
+          if (((op == OP_KKA || op == OP_JHKA || op == OP_SWA) && b > 256) ||
+              (rc = set_shape(M, op, s)) != OPF_OK) {
             rc = OPF_OK;  // infeasible shape (block or LDS limit): skip it
             continue;
           }

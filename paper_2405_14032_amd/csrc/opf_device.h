@@ -76,6 +76,13 @@ hipError_t launch_jt_a(const Launch& L, const double* x, const double* v, double
 hipError_t launch_jt_b(const Launch& L, const double* v, double* out, const double* scratch);
 hipError_t launch_kkt_a(const Launch& L, const double* h, const double* j, const double* dx, const double* d,
                         double* k, double* scratch);
+hipError_t launch_jhk_a(const Launch& L, const double* x, const double* lam, double sigma, double* h, double* j,
+                        const double* dx, const double* d, double* k, double* scratch);
+hipError_t launch_sweep_a(const Launch& L, const double* x, const double* lam, double sigma, const double* v,
+                          double* h, double* j, const double* dx, const double* d, double* k, double* c, double* jtv,
+                          double* g, double* scratch);
+hipError_t launch_sweep_b(const Launch& L, const double* x, const double* v, const double* j, const double* dx,
+                          const double* d, double* k, double* c, double* jtv, double* g, const double* scratch);
 hipError_t launch_kkt_b(const Launch& L, const double* j, const double* dx, const double* d, double* k,
                         const double* scratch);
 hipError_t launch_jac_struct(const Launch& L, int32_t* rows, int32_t* cols);

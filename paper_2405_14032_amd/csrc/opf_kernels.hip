@@ -89,6 +89,73 @@ struct Bases {
   }
 };
 
+// First and second derivatives of flow kind k of one line at one period.
+// Jk: the flow row's J entries (own, vm_i, vm_j, va_i, va_j); h: the nine
+// lower-triangle Hessian entries of -ck * Hess(phi_k) in the local order of
+// the kind (ck = the row's multiplier).  Every kernel that produces J or H
+// values goes through this function, so separate and fused evaluations
+// give bitwise identical values.
+__device__ __forceinline__ double flow_w(const Coef& cf, int k, double s, double c) {
+  return cf.al[k] * c + cf.be[k] * s;
+}
+
+// phi_k = S_k V_o^2 + V_i V_j w_k, the flow the kind's definition row equates.
+__device__ __forceinline__ double flow_value(const Coef& cf, int k, double vi, double vj, double vv, double w) {
+  const double vo = k < 2 ? vi : vj;
+  return cf.S[k] * vo * vo + vv * w;
+}
+
+__device__ __forceinline__ void flow_kind(const Coef& cf, int k, double vi, double vj, double vv, double s,
+                                          double c, double ck, double Jk[5], double h[9]) {
+  const double w = flow_w(cf, k, s, c);
+  const double u = cf.be[k] * c - cf.al[k] * s;
+  const double dvi = (k < 2 ? 2.0 * cf.S[k] * vi : 0.0) + vj * w;
+  const double dvj = (k < 2 ? 0.0 : 2.0 * cf.S[k] * vj) + vi * w;
+  const double dti = vv * u;
+  Jk[0] = 1.0;
+  Jk[1] = -dvi;
+  Jk[2] = -dvj;
+  Jk[3] = -dti;
+  Jk[4] = dti;
+  if (k < 2) {
+    h[0] = ck * (2.0 * cf.S[k]);
+    h[1] = ck * w;
+  } else {
+    h[0] = ck * w;
+    h[1] = ck * (2.0 * cf.S[k]);
+  }
+  h[2] = ck * (vj * u);
+  h[3] = ck * (vi * u);
+  h[4] = -ck * (vv * w);
+  h[5] = -ck * (vj * u);
+  h[6] = -ck * (vi * u);
+  h[7] = ck * (vv * w);
+  h[8] = -ck * (vv * w);
+}
+
+// J^T v of one line at one period from its flow-row J entries Jf: the four
+// flow-variable outputs and the hand-off record of the bus-variable sums
+// (vm_i, vm_j, va_i, va_j).  vbal = v of the balance rows each flow enters.
+__device__ __forceinline__ void jt_line(const double vk[4], const double Jf[4][5], double vtf, double vtt,
+                                        double vang, const double fl[4], const double vbal[4], double out[4],
+                                        double rec[4]) {
+  double svi = 0.0, svj = 0.0, sti = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    svi += vk[k] * Jf[k][1];
+    svj += vk[k] * Jf[k][2];
+    sti += vk[k] * Jf[k][3];
+  }
+  out[0] = vk[0] + vtf * (2.0 * fl[0]) - vbal[0];
+  out[1] = vk[1] + vtf * (2.0 * fl[1]) - vbal[1];
+  out[2] = vk[2] + vtt * (2.0 * fl[2]) - vbal[2];
+  out[3] = vk[3] + vtt * (2.0 * fl[3]) - vbal[3];
+  rec[0] = svi;
+  rec[1] = svj;
+  rec[2] = sti + vang;
+  rec[3] = -sti - vang;
+}
+
 // ---------------------------------------------------------------- Jacobian
 __device__ void jac_branch(const InstDev& I, int l, int t0, int t1, const double* __restrict__ x,
                            double* __restrict__ jv) {
@@ -109,17 +176,11 @@ __device__ void jac_branch(const InstDev& I, int l, int t0, int t1, const double
     const double vv = vi * vj;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double w = cf.al[k] * c + cf.be[k] * s;
-      const double u = cf.be[k] * c - cf.al[k] * s;
-      const double dvi = (k < 2 ? 2.0 * cf.S[k] * vi : 0.0) + vj * w;
-      const double dvj = (k < 2 ? 0.0 : 2.0 * cf.S[k] * vj) + vi * w;
-      const double dti = vv * u;
+      double Jk[5], h[9];
+      flow_kind(cf, k, vi, vj, vv, s, c, 0.0, Jk, h);
       double* q = jp + b.jFLOW + (int64_t)(k * 5) * B + l;
-      q[0] = 1.0;
-      q[B] = -dvi;
-      q[2 * B] = -dvj;
-      q[3 * B] = -dti;
-      q[4 * B] = dti;
+#pragma unroll
+      for (int a = 0; a < 5; ++a) q[a * B] = Jk[a];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -178,24 +239,11 @@ __device__ void hess_branch(const InstDev& I, int l, int t0, int t1, const doubl
     const double vv = vi * vj;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double ck = -lp[b.cFLOW + k * B + l];
-      const double w = cf.al[k] * c + cf.be[k] * s;
-      const double u = cf.be[k] * c - cf.al[k] * s;
+      double Jk[5], h[9];
+      flow_kind(cf, k, vi, vj, vv, s, c, -lp[b.cFLOW + k * B + l], Jk, h);
       double* q = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
-      if (k < 2) {
-        q[0] = ck * (2.0 * cf.S[k]);
-        q[B] = ck * w;
-      } else {
-        q[0] = ck * w;
-        q[B] = ck * (2.0 * cf.S[k]);
-      }
-      q[2 * B] = ck * (vj * u);
-      q[3 * B] = ck * (vi * u);
-      q[4 * B] = -ck * (vv * w);
-      q[5 * B] = -ck * (vj * u);
-      q[6 * B] = -ck * (vi * u);
-      q[7 * B] = ck * (vv * w);
-      q[8 * B] = -ck * (vv * w);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) q[a * B] = h[a];
     }
     const double lf = 2.0 * lp[b.cTHF + l], lt = 2.0 * lp[b.cTHT + l];
     hp[b.hTH + l] = lf;
@@ -242,11 +290,7 @@ __device__ void cons_branch(const InstDev& I, int l, int t0, int t1, const doubl
     sincos(ti - tj, &s, &c);
     const double vv = vi * vj;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double w = cf.al[k] * c + cf.be[k] * s;
-      const double vo = k < 2 ? vi : vj;
-      cp[b.cFLOW + k * B + l] = fl[k] - (cf.S[k] * vo * vo + vv * w);
-    }
+    for (int k = 0; k < 4; ++k) cp[b.cFLOW + k * B + l] = fl[k] - flow_value(cf, k, vi, vj, vv, flow_w(cf, k, s, c));
     cp[b.cTHF + l] = fl[0] * fl[0] + fl[1] * fl[1];
     cp[b.cTHT + l] = fl[2] * fl[2] + fl[3] * fl[3];
     cp[b.cANG + l] = ti - tj;
@@ -386,53 +430,47 @@ __device__ void jt_branch(const InstDev& I, int l, int t0, int t1, const double*
     const double* vp = vv_ + I.c_off + (int64_t)t * I.m_p;
     double* op = out + I.x_off + (int64_t)t * I.n_p;
     const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
-    double fl[4], vk[4];
+    double fl[4], vk[4], Jf[4][5], h[9];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       fl[k] = xp[b.xFL + k * B + l];
       vk[k] = vp[b.cFLOW + k * B + l];
     }
-    const double vtf = vp[b.cTHF + l], vtt = vp[b.cTHT + l], vang = vp[b.cANG + l];
+    const double vbal[4] = {vp[i], vp[b.N + i], vp[j], vp[b.N + j]};
     double s, c;
     sincos(ti - tj, &s, &c);
     const double vv = vi * vj;
-    double svi = 0.0, svj = 0.0, sti = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double w = cf.al[k] * c + cf.be[k] * s;
-      const double u = cf.be[k] * c - cf.al[k] * s;
-      const double dvi = (k < 2 ? 2.0 * cf.S[k] * vi : 0.0) + vj * w;
-      const double dvj = (k < 2 ? 0.0 : 2.0 * cf.S[k] * vj) + vi * w;
-      svi -= vk[k] * dvi;
-      svj -= vk[k] * dvj;
-      sti -= vk[k] * (vv * u);
-    }
-    op[b.xFL + l] = vk[0] + vtf * (2.0 * fl[0]) - vp[i];
-    op[b.xFL + B + l] = vk[1] + vtf * (2.0 * fl[1]) - vp[b.N + i];
-    op[b.xFL + 2 * B + l] = vk[2] + vtt * (2.0 * fl[2]) - vp[j];
-    op[b.xFL + 3 * B + l] = vk[3] + vtt * (2.0 * fl[3]) - vp[b.N + j];
+    for (int k = 0; k < 4; ++k) flow_kind(cf, k, vi, vj, vv, s, c, 0.0, Jf[k], h);
+    double o4[4], rec[4];
+    jt_line(vk, Jf, vp[b.cTHF + l], vp[b.cTHT + l], vp[b.cANG + l], fl, vbal, o4, rec);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) op[b.xFL + k * B + l] = o4[k];
     double* r = scr + I.s_off + (int64_t)kScratchKkt * I.B * I.T + ((int64_t)t * B + l) * kScratchJt;
-    r[0] = svi;
-    r[1] = svj;
-    r[2] = sti + vang;
-    r[3] = -sti - vang;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) r[a] = rec[a];
   }
+}
+
+// J^T v on the generator variables of one period: pg enters its balance row
+// (+1) and the ramp rows of periods t (+1) and t + 1 (-1); qg its balance row.
+__device__ __forceinline__ void jt_gen_period(const InstDev& I, int g, int n, int t, const double* __restrict__ vv_,
+                                              double* __restrict__ out) {
+  const int64_t N = I.N, G = I.G;
+  const double* vr = vv_ + I.c_off + (int64_t)I.T * I.m_p;
+  const double* vp = vv_ + I.c_off + (int64_t)t * I.m_p;
+  double* op = out + I.x_off + (int64_t)t * I.n_p;
+  double a = vp[n];
+  if (t >= 1) a += vr[(int64_t)(t - 1) * G + g];
+  if (t + 1 < I.T) a -= vr[(int64_t)t * G + g];
+  op[2 * N + g] = a;
+  op[2 * N + G + g] = vp[N + n];
 }
 
 __device__ void jt_gen(const InstDev& I, int g, int t0, int t1, const double* __restrict__ vv_,
                        double* __restrict__ out) {
-  const int64_t N = I.N, G = I.G;
   const int n = I.gen_bus[g];
-  const double* vr = vv_ + I.c_off + (int64_t)I.T * I.m_p;
-  for (int t = t0; t < t1; ++t) {
-    const double* vp = vv_ + I.c_off + (int64_t)t * I.m_p;
-    double* op = out + I.x_off + (int64_t)t * I.n_p;
-    double a = vp[n];
-    if (t >= 1) a += vr[(int64_t)(t - 1) * G + g];
-    if (t + 1 < I.T) a -= vr[(int64_t)t * G + g];
-    op[2 * N + g] = a;
-    op[2 * N + G + g] = vp[N + n];
-  }
+  for (int t = t0; t < t1; ++t) jt_gen_period(I, g, n, t, vv_, out);
 }
 
 __global__ void __launch_bounds__(512) k_jt_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
@@ -506,47 +544,84 @@ __global__ void __launch_bounds__(512) k_jt_b(const InstDev* __restrict__ insts,
 //   [0] (vm_i,vm_i)  [1] (va_i,vm_i)  [2] (va_i,va_i)  [3] (va_i,vm_j)
 //   [4] (vm_j,vm_i)  [5] (va_j,va_i)
 //   [6] (vm_j,vm_j)  [7] (va_j,vm_j)  [8] (va_j,va_j)  [9] (va_j,vm_i)
-__device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, const double* __restrict__ H,
-                        const double* __restrict__ J, const double* __restrict__ DX, const double* __restrict__ D,
-                        double* __restrict__ K) {
+// Generator rows of K (pg: balance partners, the ramp pair of t >= 1, the
+// diagonal; qg: balance partners, diagonal).  FUSED: the generator's J and H
+// entries are produced here (structural constants and 2 sigma c2) and
+// written, and K uses those values; otherwise K reads them from J and H.
+template <bool FUSED>
+__device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, double sigma, double* __restrict__ H,
+                        double* __restrict__ J, const double* __restrict__ DX, const double* __restrict__ D,
+                        double* __restrict__ K, const double* __restrict__ X = nullptr,
+                        const double* __restrict__ V = nullptr, double* __restrict__ C = nullptr,
+                        double* __restrict__ JTV = nullptr, double* __restrict__ GR = nullptr) {
   const int64_t N = I.N, G = I.G;
   const int n = I.gen_bus[g];
   const int64_t rp = 2 * N + g, rq = 2 * N + G + g;
   const int ps = I.krow[rp], pe = I.krow[rp + 1], qs = I.krow[rq], qe = I.krow[rq + 1];
-  const double* jr = J + I.j_off + (int64_t)I.T * I.nnzj_p;   // ramp block of J
-  const double* dr = D + I.c_off + (int64_t)I.T * I.m_p;       // ramp rows of D
+  double* jr = J + I.j_off + (int64_t)I.T * I.nnzj_p;   // ramp block of J
+  const double* dr = D + I.c_off + (int64_t)I.T * I.m_p;  // ramp rows of D
+  const double hobj = 2.0 * sigma * I.c2[g];
   for (int t = t0; t < t1; ++t) {
-    const double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
+    double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
     const double* dp = D + I.c_off + (int64_t)t * I.m_p;
     double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
-    const double Jgp = jp[g], Jgq = jp[G + g];
+    double Jgp, Jgq, Hg;
+    if constexpr (FUSED) {
+      Jgp = 1.0;
+      Jgq = 1.0;
+      Hg = hobj;
+      jp[g] = Jgp;
+      jp[G + g] = Jgq;
+      if (g == 0) jp[2 * G + 4LL * I.B] = 1.0;  // reference-angle row
+      H[I.h_off + (int64_t)t * I.nnzh_p + g] = Hg;
+      if (t >= 1) {
+        double* jt = jr + (int64_t)(t - 1) * 2 * G;
+        jt[g] = 1.0;
+        jt[G + g] = -1.0;
+      }
+    } else {
+      Jgp = jp[g];
+      Jgq = jp[G + g];
+      Hg = H[I.h_off + (int64_t)t * I.nnzh_p + g];
+    }
     const double pbp = dp[n] * Jgp, pbq = dp[N + n] * Jgq;
     const int64_t xo = I.x_off + (int64_t)t * I.n_p;
-    double diag = (DX ? DX[xo + rp] : 0.0) + pbp * Jgp + H[I.h_off + (int64_t)t * I.nnzh_p + g];
+    double diag = (DX ? DX[xo + rp] : 0.0) + pbp * Jgp + Hg;
     const int sp = t >= 1 ? g + 1 : 0, sq = t >= 1 ? (int)G : 0;
     if (t >= 1) {
       const double* jt = jr + (int64_t)(t - 1) * 2 * G;
       const double d = dr[(int64_t)(t - 1) * G + g];
-      const double j0 = jt[g], j1 = jt[G + g];
+      const double j0 = FUSED ? 1.0 : jt[g], j1 = FUSED ? -1.0 : jt[G + g];
       kb[ps + g] = d * j0 * j1;
       diag += d * j0 * j0;
     }
     if (t + 1 < I.T) {
-      const double j1 = jr[(int64_t)t * 2 * G + G + g];
+      const double j1 = FUSED ? -1.0 : jr[(int64_t)t * 2 * G + G + g];
       diag += dr[(int64_t)t * G + g] * j1 * j1;
     }
-    for (int p = ps; p < pe - 1; ++p) kb[p + sp] = pbp * jp[I.ksrc[p]];
+    // balance partners of a generator row are generators (J = +1)
+    for (int p = ps; p < pe - 1; ++p) kb[p + sp] = pbp * (FUSED ? 1.0 : jp[I.ksrc[p]]);
     kb[pe - 1 + sp] = diag;
-    for (int p = qs; p < qe - 1; ++p) kb[p + sq] = pbq * jp[I.ksrc[p]];
+    for (int p = qs; p < qe - 1; ++p) kb[p + sq] = pbq * (FUSED ? 1.0 : jp[I.ksrc[p]]);
     kb[qe - 1 + sq] = (DX ? DX[xo + rq] : 0.0) + pbq * Jgq;
+    if constexpr (FUSED) {
+      // the rest of the sweep on this generator: ramp row, J^T v, gradient
+      if (C && t >= 1) C[I.c_off + (int64_t)I.T * I.m_p + (int64_t)(t - 1) * G + g] = X[xo + rp] - X[xo + rp - I.n_p];
+      if (JTV) jt_gen_period(I, g, n, t, V, JTV);
+      if (GR) {
+        GR[xo + rp] = 2.0 * I.c2[g] * X[xo + rp] + I.c1[g];
+        GR[xo + rq] = 0.0;
+      }
+    }
   }
 }
 
 // Streams a K row segment from LDS to HBM with consecutive lanes on
-// consecutive slots.  A slot whose template source is a J entry (a balance
-// partner) holds the factor d_bal * J_bal and is multiplied by that entry;
-// four slots per lane are handled per step so their template loads and J
-// gathers are in flight together.
+// consecutive slots.  GATHER: a slot whose template source is a J entry (a
+// balance partner) holds the factor d_bal * J_bal and is multiplied by that
+// entry; four slots per lane are handled per step so their template loads
+// and J gathers are in flight together.
+template <bool GATHER>
 __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, const int32_t* __restrict__ src,
                                                const double* __restrict__ jp, double* __restrict__ dst,
                                                int len) {
@@ -558,12 +633,14 @@ __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, c
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = p0 + u * bd;
-      sr[u] = p < len ? src[p] : -2;
+      sr[u] = (GATHER && p < len) ? src[p] : -2;
       v[u] = p < len ? seg[p] : 0.0;
     }
+    if (GATHER) {
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (sr[u] >= 0) v[u] *= jp[sr[u]];
+      for (int u = 0; u < U; ++u)
+        if (sr[u] >= 0) v[u] *= jp[sr[u]];
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = p0 + u * bd;
@@ -572,10 +649,17 @@ __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, c
   }
 }
 
-__device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __restrict__ H,
-                              const double* __restrict__ J, const double* __restrict__ DX,
-                              const double* __restrict__ D, double* __restrict__ K, double* __restrict__ scr,
-                              double* __restrict__ seg) {
+// One line tile of the condensed assembly.  FUSED: J and H of the lines are
+// evaluated from x and lambda here, written out, and used directly (the
+// partner J entries are the structural -1 / +1 of the balance rows);
+// otherwise J and H are read from the given arrays.
+template <bool FUSED>
+__device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __restrict__ X,
+                              const double* __restrict__ LAM, double* __restrict__ H, double* __restrict__ J,
+                              const double* __restrict__ DX, const double* __restrict__ D, double* __restrict__ K,
+                              double* __restrict__ scr, double* __restrict__ seg,
+                              const double* __restrict__ V = nullptr, double* __restrict__ C = nullptr,
+                              double* __restrict__ JTV = nullptr, double* __restrict__ GR = nullptr) {
   const Bases b(I);
   const int64_t B = b.B, N = b.N, G = b.G;
   const int tid = (int)threadIdx.x;
@@ -589,6 +673,7 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
     se[k] = I.krow[b.xFL + k * B + tl.e1];
   }
   int i = 0, j = 0, rs[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0};
+  Coef cf;
   if (act) {
     i = I.f_bus[l];
     j = I.t_bus[l];
@@ -597,24 +682,18 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
       rs[k] = I.krow[b.xFL + k * B + l] - sb[k];
       re[k] = I.krow[b.xFL + k * B + l + 1] - sb[k];
     }
+    if (FUSED) load_coef(I, l, cf);
   }
   const bool ilo = i < j;
   for (int t = tl.t0; t < tl.t1; ++t) {
-    const double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
+    double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
     double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t) + (t >= 1 ? G : 0);
     double Jf[4][5], df[4], Jb[4], Jt[4], Hth[4], dbal[4], dth[2], q[10];
     if (act) {
-      const double* hp = H + I.h_off + (int64_t)t * I.nnzh_p;
+      double* hp = H + I.h_off + (int64_t)t * I.nnzh_p;
       const double* dp = D + I.c_off + (int64_t)t * I.m_p;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-#pragma unroll
-        for (int a = 0; a < 5; ++a) Jf[k][a] = jp[b.jFLOW + (int64_t)(k * 5 + a) * B + l];
-        df[k] = dp[b.cFLOW + k * B + l];
-        Jb[k] = jp[b.jBAL + k * B + l];
-        Jt[k] = jp[b.jTH + k * B + l];
-        Hth[k] = hp[b.hTH + k * B + l];
-      }
+      for (int k = 0; k < 4; ++k) df[k] = dp[b.cFLOW + k * B + l];
       dbal[0] = dp[i];
       dbal[1] = dp[N + i];
       dbal[2] = dp[j];
@@ -622,38 +701,121 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
       dth[0] = dp[b.cTHF + l];
       dth[1] = dp[b.cTHT + l];
       const double dang = dp[b.cANG + l];
-      const double Ja0 = jp[b.jANG + l], Ja1 = jp[b.jANG + B + l];
+      double Ja0, Ja1;
+      double vi = 0.0, vj = 0.0, vv = 0.0, sn = 0.0, cs = 0.0, ti = 0.0, tj = 0.0, fl[4];
+      const double* lp = nullptr;
+      if constexpr (FUSED) {
+        const double* xp = X + I.x_off + (int64_t)t * I.n_p;
+        lp = LAM + I.c_off + (int64_t)t * I.m_p;
+        vi = xp[i];
+        vj = xp[j];
+        ti = xp[N + i];
+        tj = xp[N + j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fl[k] = xp[b.xFL + k * B + l];
+        sincos(ti - tj, &sn, &cs);
+        vv = vi * vj;
+        const double lf = 2.0 * lp[b.cTHF + l], lt = 2.0 * lp[b.cTHT + l];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          Jb[k] = -1.0;
+          Jt[k] = 2.0 * fl[k];
+          Hth[k] = k < 2 ? lf : lt;
+          jp[b.jBAL + k * B + l] = Jb[k];
+          jp[b.jTH + k * B + l] = Jt[k];
+          hp[b.hTH + k * B + l] = Hth[k];
+        }
+        Ja0 = 1.0;
+        Ja1 = -1.0;
+        jp[b.jANG + l] = Ja0;
+        jp[b.jANG + B + l] = Ja1;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+          for (int a = 0; a < 5; ++a) Jf[k][a] = jp[b.jFLOW + (int64_t)(k * 5 + a) * B + l];
+          Jb[k] = jp[b.jBAL + k * B + l];
+          Jt[k] = jp[b.jTH + k * B + l];
+          Hth[k] = hp[b.hTH + k * B + l];
+        }
+        Ja0 = jp[b.jANG + l];
+        Ja1 = jp[b.jANG + B + l];
+      }
       // bus-variable contributions: sum_k d_k J_k,a J_k,b + angle + H
 #pragma unroll
       for (int a = 0; a < 10; ++a) q[a] = 0.0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double* hf = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
+        double hf[9];
+        if constexpr (FUSED) {
+          flow_kind(cf, k, vi, vj, vv, sn, cs, -lp[b.cFLOW + k * B + l], Jf[k], hf);
+          double* jq = jp + b.jFLOW + (int64_t)(k * 5) * B + l;
+#pragma unroll
+          for (int a = 0; a < 5; ++a) jq[a * B] = Jf[k][a];
+          double* hq = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
+#pragma unroll
+          for (int a = 0; a < 9; ++a) hq[a * B] = hf[a];
+        } else {
+          const double* hq = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
+#pragma unroll
+          for (int a = 0; a < 9; ++a) hf[a] = hq[a * B];
+        }
         const double a1 = Jf[k][1], a2 = Jf[k][2], a3 = Jf[k][3], a4 = Jf[k][4];
         const double d1 = df[k] * a1, d2 = df[k] * a2, d3 = df[k] * a3, d4 = df[k] * a4;
         // local H order: from end (0,0)(1,0)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3);
         // to end (1,0)(1,1)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3)
-        const double h0 = hf[0], h1 = hf[B];
         if (k < 2) {
-          q[0] += d1 * a1 + h0;
+          q[0] += d1 * a1 + hf[0];
           q[6] += d2 * a2;
-          q[4] += d2 * a1 + h1;
+          q[4] += d2 * a1 + hf[1];
         } else {
           q[0] += d1 * a1;
-          q[6] += d2 * a2 + h1;
-          q[4] += d2 * a1 + h0;
+          q[6] += d2 * a2 + hf[1];
+          q[4] += d2 * a1 + hf[0];
         }
-        q[1] += d3 * a1 + hf[2 * B];
-        q[3] += d3 * a2 + hf[3 * B];
-        q[2] += d3 * a3 + hf[4 * B];
-        q[9] += d4 * a1 + hf[5 * B];
-        q[7] += d4 * a2 + hf[6 * B];
-        q[5] += d4 * a3 + hf[7 * B];
-        q[8] += d4 * a4 + hf[8 * B];
+        q[1] += d3 * a1 + hf[2];
+        q[3] += d3 * a2 + hf[3];
+        q[2] += d3 * a3 + hf[4];
+        q[9] += d4 * a1 + hf[5];
+        q[7] += d4 * a2 + hf[6];
+        q[5] += d4 * a3 + hf[7];
+        q[8] += d4 * a4 + hf[8];
       }
       q[2] += dang * Ja0 * Ja0;
       q[8] += dang * Ja1 * Ja1;
       q[5] += dang * Ja1 * Ja0;
+      if constexpr (FUSED) {
+        // the rest of the sweep on this line: its constraint rows, J^T v on
+        // its flow variables (bus sums through a hand-off record), gradient
+        const int64_t xo = I.x_off + (int64_t)t * I.n_p;
+        if (C) {
+          double* cp = C + I.c_off + (int64_t)t * I.m_p;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            cp[b.cFLOW + k * B + l] = fl[k] - flow_value(cf, k, vi, vj, vv, flow_w(cf, k, sn, cs));
+          cp[b.cTHF + l] = fl[0] * fl[0] + fl[1] * fl[1];
+          cp[b.cTHT + l] = fl[2] * fl[2] + fl[3] * fl[3];
+          cp[b.cANG + l] = ti - tj;
+        }
+        if (JTV) {
+          const double* vp = V + I.c_off + (int64_t)t * I.m_p;
+          double vk[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) vk[k] = vp[b.cFLOW + k * B + l];
+          const double vbal[4] = {vp[i], vp[N + i], vp[j], vp[N + j]};
+          double o4[4], rj[4];
+          jt_line(vk, Jf, vp[b.cTHF + l], vp[b.cTHT + l], vp[b.cANG + l], fl, vbal, o4, rj);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) JTV[xo + b.xFL + k * B + l] = o4[k];
+          double* r = scr + I.s_off + (int64_t)kScratchKkt * I.B * I.T + ((int64_t)t * B + l) * kScratchJt;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) r[a] = rj[a];
+        }
+        if (GR) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) GR[xo + b.xFL + k * B + l] = 0.0;
+        }
+      }
     }
     // flow-variable rows, one kind at a time through LDS
 #pragma unroll
@@ -674,14 +836,22 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
         }
         const double pb = dbal[k] * Jb[k];
         for (int p = rs[k] + 4; p < re[k] - 1; ++p) {
-          // balance partners carry the factor, the thermal partner its value
-          seg[p] = ((k & 1) && I.ksrc[sb[k] + p] < 0) ? dth[k >> 1] * Jt[k ^ 1] * Jt[k] : pb;
+          const int src = I.ksrc[sb[k] + p];
+          double v;
+          if ((k & 1) && src < 0) {
+            v = dth[k >> 1] * Jt[k ^ 1] * Jt[k];  // thermal partner
+          } else if (FUSED) {
+            v = pb * (src < 2 * G ? 1.0 : -1.0);  // balance partner: generator +1, line end -1
+          } else {
+            v = pb;  // factor; the stream-out multiplies by the partner's J entry
+          }
+          seg[p] = v;
         }
         const double dxv = DX ? DX[I.x_off + (int64_t)t * I.n_p + b.xFL + k * B + l] : 0.0;
         seg[re[k] - 1] = dxv + pk * Jf[k][0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jb[k] + Hth[k];
       }
       __syncthreads();
-      stream_segment(seg, I.ksrc + sb[k], jp, kb + sb[k], se[k] - sb[k]);
+      stream_segment<!FUSED>(seg, I.ksrc + sb[k], jp, kb + sb[k], se[k] - sb[k]);
       __syncthreads();
     }
     // hand-off records through the (now free) segment buffer
@@ -703,15 +873,214 @@ __global__ void __launch_bounds__(256) k_kkt_a(const InstDev* __restrict__ insts
                                                const double* __restrict__ D, double* __restrict__ K,
                                                double* __restrict__ scr) {
   extern __shared__ double lds[];
+  // read-only J / H in this form (the templates take writable pointers for
+  // the fused form, which writes them)
+  double* Hm = const_cast<double*>(H);
+  double* Jm = const_cast<double*>(J);
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile tl = tiles[remap_tile(v, ntiles)];
     const InstDev& I = insts[tl.inst];
     if (tl.kind == TK_BRANCH) {
-      kkt_line_tile(I, tl, H, J, DX, D, K, scr, lds);
+      kkt_line_tile<false>(I, tl, nullptr, nullptr, Hm, Jm, DX, D, K, scr, lds);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
-      if (e < tl.e1) kkt_gen(I, e, tl.t0, tl.t1, H, J, DX, D, K);
+      if (e < tl.e1) kkt_gen<false>(I, e, tl.t0, tl.t1, 0.0, Hm, Jm, DX, D, K);
     }
+  }
+}
+
+// Fused form: J, H and the line / generator rows of K in one pass over x.
+__global__ void __launch_bounds__(256) k_jhk_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                               int ntiles, int cap_seg, const double* __restrict__ X,
+                                               const double* __restrict__ LAM, double sigma, double* __restrict__ H,
+                                               double* __restrict__ J, const double* __restrict__ DX,
+                                               const double* __restrict__ D, double* __restrict__ K,
+                                               double* __restrict__ scr) {
+  extern __shared__ double lds[];
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    if (tl.kind == TK_BRANCH) {
+      kkt_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds);
+    } else {
+      const int e = tl.e0 + (int)threadIdx.x;
+      if (e < tl.e1) kkt_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K);
+    }
+  }
+}
+
+// Whole sweep, lines and generators: J, H, K rows, constraint rows, J^T v and
+// gradient entries of the line / generator variables in one pass over x.
+__global__ void __launch_bounds__(256) k_sweep_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                                 int ntiles, int cap_seg, const double* __restrict__ X,
+                                                 const double* __restrict__ LAM, double sigma,
+                                                 const double* __restrict__ V, double* __restrict__ H,
+                                                 double* __restrict__ J, const double* __restrict__ DX,
+                                                 const double* __restrict__ D, double* __restrict__ K,
+                                                 double* __restrict__ C, double* __restrict__ JTV,
+                                                 double* __restrict__ GR, double* __restrict__ scr) {
+  extern __shared__ double lds[];
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    if (tl.kind == TK_BRANCH) {
+      kkt_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, V, C, JTV, GR);
+    } else {
+      const int e = tl.e0 + (int)threadIdx.x;
+      if (e < tl.e1) kkt_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K, X, V, C, JTV, GR);
+    }
+  }
+}
+
+// Bus rows of K for one tile.  SWEEP: the same pass also produces the bus's
+// balance rows (and the reference row), J^T v on vm / va and their gradient
+// entries, from the same walk over the incident line ends (the flow values
+// of those ends and the J^T v hand-off records are gathered beside the
+// condensed records).  Summation orders equal those of the separate kernels.
+template <bool SWEEP>
+__device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const double* __restrict__ J,
+                         const double* __restrict__ DX, const double* __restrict__ D, double* __restrict__ K,
+                         const double* __restrict__ scr, double* __restrict__ lds, const double* __restrict__ X,
+                         const double* __restrict__ V, double* __restrict__ C, double* __restrict__ JTV,
+                         double* __restrict__ GR) {
+  double* svm = lds;
+  double* sva = lds + cap_vm;
+  const int64_t N = I.N, B = I.B, G = I.G;
+  const int64_t xFL = 2 * N + 2 * G;
+  const int tid = (int)threadIdx.x;
+  const int n = tl.e0 + tid;
+  const bool act = n < tl.e1;
+  const int b0 = I.krow[tl.e0], b1 = I.krow[tl.e1];
+  const int a0 = I.krow[N + tl.e0], a1 = I.krow[N + tl.e1];
+  int q0 = 0, q1 = 0, vmr = 0, var = 0, clo = 0, lva = 0, call = 0, g0 = 0, g1 = 0;
+  if (act) {
+    q0 = I.bus_ptr[n];
+    q1 = I.bus_ptr[n + 1];
+    vmr = I.krow[n] - b0;
+    var = I.krow[N + n] - a0;
+    clo = I.krow[n + 1] - I.krow[n] - 1;
+    lva = I.krow[N + n + 1] - I.krow[N + n];
+    call = lva - clo - 2;
+    if (SWEEP) {
+      g0 = I.bgen_ptr[n];
+      g1 = I.bgen_ptr[n + 1];
+    }
+  }
+  for (int t = tl.t0; t < tl.t1; ++t) {
+    double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
+    if (act) {
+      const int64_t xo = I.x_off + (int64_t)t * I.n_p;
+      const double* rs = scr + I.s_off + (int64_t)t * B * kScratchKkt;
+      const double* rj = scr + I.s_off + (int64_t)kScratchKkt * B * I.T + (int64_t)t * B * kScratchJt;
+      const double* xp = SWEEP ? X + xo : nullptr;
+      double svm_s = 0.0, svavm_s = 0.0, sva_s = 0.0;
+      double cvm = 0.0, cvavm = 0.0, cva = 0.0;
+      double bp = 0.0, bq = 0.0, jvm = 0.0, jva = 0.0;
+      if (SWEEP) {
+        for (int q = g0; q < g1; ++q) {
+          const int g = I.bgen[q];
+          bp += xp[2 * N + g];
+          bq += xp[2 * N + G + g];
+        }
+      }
+      int gi = 0, prev = -1;
+      constexpr int U = 4;
+      for (int aa = q0; aa < q1; aa += U) {
+        // issue the incidence loads and gathers of up to U ends together
+        int ad[U], nb[U];
+        double r[U][6], fp[U], fq[U], j0[U], j1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool ok = aa + u < q1;
+          ad[u] = ok ? I.bus_adj[aa + u] : 0;
+          nb[u] = ok ? I.bus_nb[aa + u] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool ok = nb[u] >= 0;
+          const int64_t l = ad[u] >> 1;
+          const int e = ad[u] & 1;
+          const double* rp = rs + l * kScratchKkt + 4 * e;
+#pragma unroll
+          for (int w = 0; w < 6; ++w) r[u][w] = ok ? rp[w] : 0.0;
+          if (SWEEP) {
+            const int64_t kp = e ? 2 : 0;
+            fp[u] = ok ? xp[xFL + kp * B + l] : 0.0;
+            fq[u] = ok ? xp[xFL + (kp + 1) * B + l] : 0.0;
+            j0[u] = ok ? rj[l * kScratchJt + (e ? 1 : 0)] : 0.0;
+            j1[u] = ok ? rj[l * kScratchJt + (e ? 3 : 2)] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (nb[u] < 0) break;
+          const int m = nb[u];
+          if (prev >= 0 && m != prev) {
+            if (prev < n) {
+              svm[vmr + gi] = cvm;
+              sva[var + gi] = cvavm;
+              sva[var + call + 1 + gi] = cva;
+            } else {
+              sva[var + gi + 1] = cvavm;
+            }
+            ++gi;
+            cvm = cvavm = cva = 0.0;
+          }
+          prev = m;
+          // own-end values at [0,4) of end i's window, [2,6) of end j's;
+          // the shared cross pair at [4,6) for end i, [0,2) for end j
+          const bool ej = ad[u] & 1;
+          svm_s += ej ? r[u][2] : r[u][0];
+          svavm_s += ej ? r[u][3] : r[u][1];
+          sva_s += ej ? r[u][4] : r[u][2];
+          cvavm += ej ? r[u][5] : r[u][3];
+          cvm += ej ? r[u][0] : r[u][4];
+          cva += ej ? r[u][1] : r[u][5];
+          if (SWEEP) {
+            bp -= fp[u];
+            bq -= fq[u];
+            jvm += j0[u];
+            jva += j1[u];
+          }
+        }
+      }
+      if (prev >= 0) {
+        if (prev < n) {
+          svm[vmr + gi] = cvm;
+          sva[var + gi] = cvavm;
+          sva[var + call + 1 + gi] = cva;
+        } else {
+          sva[var + gi + 1] = cvavm;
+        }
+      }
+      double dref = 0.0;
+      if (n == I.ref) {
+        const double jr = J[I.j_off + (int64_t)t * I.nnzj_p + 2LL * I.G + 4LL * I.B];
+        dref = D[I.c_off + (int64_t)t * I.m_p + 2 * N] * jr * jr;
+      }
+      svm[vmr + clo] = (DX ? DX[xo + n] : 0.0) + svm_s;
+      if (q1 > q0) sva[var + clo] = svavm_s;  // (va_n, vm_n) exists only with an incident line
+      sva[var + lva - 1] = (DX ? DX[xo + N + n] : 0.0) + sva_s + dref;
+      if (SWEEP) {
+        double* cp = C + I.c_off + (int64_t)t * I.m_p;
+        bp -= I.pd[(int64_t)t * N + n];
+        bq -= I.qd[(int64_t)t * N + n];
+        cp[n] = bp;
+        cp[N + n] = bq;
+        if (n == I.ref) {
+          cp[2 * N] = xp[N + n];
+          jva += V[I.c_off + (int64_t)t * I.m_p + 2 * N];
+        }
+        JTV[xo + n] = jvm;
+        JTV[xo + N + n] = jva;
+        GR[xo + n] = 0.0;
+        GR[xo + N + n] = 0.0;
+      }
+    }
+    __syncthreads();
+    for (int p = tid; p < b1 - b0; p += (int)blockDim.x) kb[b0 + p] = svm[p];
+    for (int p = tid; p < a1 - a0; p += (int)blockDim.x) kb[a0 + p] = sva[p];
+    __syncthreads();
   }
 }
 
@@ -721,102 +1090,25 @@ __global__ void __launch_bounds__(512) k_kkt_b(const InstDev* __restrict__ insts
                                                const double* __restrict__ DX, const double* __restrict__ D,
                                                double* __restrict__ K, const double* __restrict__ scr) {
   extern __shared__ double lds[];
-  double* svm = lds;
-  double* sva = lds + cap_vm;
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile tl = tiles[remap_tile(v, ntiles)];
-    const InstDev& I = insts[tl.inst];
-    const int64_t N = I.N;
-    const int tid = (int)threadIdx.x;
-    const int n = tl.e0 + tid;
-    const bool act = n < tl.e1;
-    const int b0 = I.krow[tl.e0], b1 = I.krow[tl.e1];
-    const int a0 = I.krow[N + tl.e0], a1 = I.krow[N + tl.e1];
-    int q0 = 0, q1 = 0, vmr = 0, var = 0, clo = 0, lva = 0, call = 0;
-    if (act) {
-      q0 = I.bus_ptr[n];
-      q1 = I.bus_ptr[n + 1];
-      vmr = I.krow[n] - b0;
-      var = I.krow[N + n] - a0;
-      clo = I.krow[n + 1] - I.krow[n] - 1;
-      lva = I.krow[N + n + 1] - I.krow[N + n];
-      call = lva - clo - 2;
-    }
-    for (int t = tl.t0; t < tl.t1; ++t) {
-      double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
-      if (act) {
-        const double* rs = scr + I.s_off + (int64_t)t * I.B * kScratchKkt;
-        double svm_s = 0.0, svavm_s = 0.0, sva_s = 0.0;
-        double cvm = 0.0, cvavm = 0.0, cva = 0.0;
-        int gi = 0, prev = -1;
-        constexpr int U = 4;
-        for (int a0 = q0; a0 < q1; a0 += U) {
-          // issue the incidence loads and record gathers of up to U ends together
-          int ad[U], nb[U];
-          double r[U][6];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const bool ok = a0 + u < q1;
-            ad[u] = ok ? I.bus_adj[a0 + u] : 0;
-            nb[u] = ok ? I.bus_nb[a0 + u] : -1;
-          }
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const double* rp = rs + (int64_t)(ad[u] >> 1) * kScratchKkt + 4 * (ad[u] & 1);
-#pragma unroll
-            for (int w = 0; w < 6; ++w) r[u][w] = nb[u] >= 0 ? rp[w] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            if (nb[u] < 0) break;
-            const int m = nb[u];
-            if (prev >= 0 && m != prev) {
-              if (prev < n) {
-                svm[vmr + gi] = cvm;
-                sva[var + gi] = cvavm;
-                sva[var + call + 1 + gi] = cva;
-              } else {
-                sva[var + gi + 1] = cvavm;
-              }
-              ++gi;
-              cvm = cvavm = cva = 0.0;
-            }
-            prev = m;
-            // own-end values at [0,4) of end i's window, [2,6) of end j's;
-            // the shared cross pair at [4,6) for end i, [0,2) for end j
-            const bool ej = ad[u] & 1;
-            svm_s += ej ? r[u][2] : r[u][0];
-            svavm_s += ej ? r[u][3] : r[u][1];
-            sva_s += ej ? r[u][4] : r[u][2];
-            cvavm += ej ? r[u][5] : r[u][3];
-            cvm += ej ? r[u][0] : r[u][4];
-            cva += ej ? r[u][1] : r[u][5];
-          }
-        }
-        if (prev >= 0) {
-          if (prev < n) {
-            svm[vmr + gi] = cvm;
-            sva[var + gi] = cvavm;
-            sva[var + call + 1 + gi] = cva;
-          } else {
-            sva[var + gi + 1] = cvavm;
-          }
-        }
-        const int64_t xo = I.x_off + (int64_t)t * I.n_p;
-        double dref = 0.0;
-        if (n == I.ref) {
-          const double jr = J[I.j_off + (int64_t)t * I.nnzj_p + 2LL * I.G + 4LL * I.B];
-          dref = D[I.c_off + (int64_t)t * I.m_p + 2 * N] * jr * jr;
-        }
-        svm[vmr + clo] = (DX ? DX[xo + n] : 0.0) + svm_s;
-        if (q1 > q0) sva[var + clo] = svavm_s;  // (va_n, vm_n) exists only with an incident line
-        sva[var + lva - 1] = (DX ? DX[xo + N + n] : 0.0) + sva_s + dref;
-      }
-      __syncthreads();
-      for (int p = tid; p < b1 - b0; p += (int)blockDim.x) kb[b0 + p] = svm[p];
-      for (int p = tid; p < a1 - a0; p += (int)blockDim.x) kb[a0 + p] = sva[p];
-      __syncthreads();
-    }
+    bus_tile<false>(insts[tl.inst], tl, cap_vm, J, DX, D, K, scr, lds, nullptr, nullptr, nullptr, nullptr, nullptr);
+  }
+}
+
+// Whole sweep, buses: K bus rows, balance and reference rows, J^T v and
+// gradient entries of vm / va.
+__global__ void __launch_bounds__(512) k_sweep_b(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                                 int ntiles, int cap_vm, const double* __restrict__ X,
+                                                 const double* __restrict__ V, const double* __restrict__ J,
+                                                 const double* __restrict__ DX, const double* __restrict__ D,
+                                                 double* __restrict__ K, double* __restrict__ C,
+                                                 double* __restrict__ JTV, double* __restrict__ GR,
+                                                 const double* __restrict__ scr) {
+  extern __shared__ double lds[];
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile tl = tiles[remap_tile(v, ntiles)];
+    bus_tile<true>(insts[tl.inst], tl, cap_vm, J, DX, D, K, scr, lds, X, V, C, JTV, GR);
   }
 }
 
@@ -1062,6 +1354,28 @@ hipError_t launch_kkt_a(const Launch& L, const double* h, const double* j, const
   if (L.ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_kkt_a, grid_of(L), dim3((unsigned)L.block), L.smem, L.stream, L.insts, L.tiles, L.ntiles,
                      L.cap0, h, j, dx, d, k, scratch);
+  return hipGetLastError();
+}
+hipError_t launch_jhk_a(const Launch& L, const double* x, const double* lam, double sigma, double* h, double* j,
+                        const double* dx, const double* d, double* k, double* scratch) {
+  if (L.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_jhk_a, grid_of(L), dim3((unsigned)L.block), L.smem, L.stream, L.insts, L.tiles, L.ntiles,
+                     L.cap0, x, lam, sigma, h, j, dx, d, k, scratch);
+  return hipGetLastError();
+}
+hipError_t launch_sweep_a(const Launch& L, const double* x, const double* lam, double sigma, const double* v,
+                          double* h, double* j, const double* dx, const double* d, double* k, double* c, double* jtv,
+                          double* g, double* scratch) {
+  if (L.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sweep_a, grid_of(L), dim3((unsigned)L.block), L.smem, L.stream, L.insts, L.tiles, L.ntiles,
+                     L.cap0, x, lam, sigma, v, h, j, dx, d, k, c, jtv, g, scratch);
+  return hipGetLastError();
+}
+hipError_t launch_sweep_b(const Launch& L, const double* x, const double* v, const double* j, const double* dx,
+                          const double* d, double* k, double* c, double* jtv, double* g, const double* scratch) {
+  if (L.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sweep_b, grid_of(L), dim3((unsigned)L.block), L.smem, L.stream, L.insts, L.tiles, L.ntiles,
+                     L.cap0, x, v, j, dx, d, k, c, jtv, g, scratch);
   return hipGetLastError();
 }
 hipError_t launch_kkt_b(const Launch& L, const double* j, const double* dx, const double* d, double* k,

@@ -159,3 +159,67 @@ def test_autotuned_shapes_keep_parity(torch_dev, tmp_path):
     _, G2 = _run_one(net, pt, torch_dev, model=M2)
     for key in ("f", "grad", "c", "jac", "hess", "jtv", "kkt"):
         assert np.array_equal(G[key], G2[key]), key
+
+
+@pytest.mark.parametrize("which", ["mid", "batched"])
+def test_fused_jhk_bitwise_equals_separate_calls(which, torch_dev):
+    torch, dev = torch_dev
+    capi = _capi()
+    if which == "mid":
+        nets = [synth.config_network("mid")]
+    else:
+        nets = [synth.make_network(120, 170, 24, 5, 101), synth.make_network(77, 108, 15, 11, 102)]
+    pts = [synth.make_point(n, 200 + k) for k, n in enumerate(nets)]
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    cat = lambda key: np.concatenate([getattr(p, key) for p in pts])
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    X, LAM, DX, D = t(cat("x")), t(cat("lam")), t(cat("diag_x")), t(cat("dcon"))
+    e = lambda k: torch.full((k,), float("nan"), dtype=torch.float64, device=dev)
+    j1, h1, k1 = e(M.nnz_jac), e(M.nnz_hess), e(M.nnz_kkt)
+    j2, h2, k2 = e(M.nnz_jac), e(M.nnz_hess), e(M.nnz_kkt)
+    print(f"fused vs separate: {which}", flush=True)
+    M.eval_jac(X, j1)
+    M.eval_hess(X, LAM, 0.37, h1)
+    M.assemble_condensed(h1, j1, DX, D, k1)
+    M.eval_jhk(X, LAM, 0.37, DX, D, j2, h2, k2)
+    torch.cuda.synchronize()
+    assert torch.equal(j1, j2)
+    assert torch.equal(h1, h2)
+    assert torch.equal(k1, k2)
+    # and against the oracle (first instance)
+    net, pt = nets[0], pts[0]
+    L = O.Layout(net)
+    jac = O.jacobian(net, pt.x)
+    hess = O.hessian(net, pt.x, pt.lam, 0.37)
+    _, _, kv, km = O.condensed(L.n, jac, hess, pt.diag_x, pt.dcon)
+    GC.assert_close(k2[:M.k_off[1]].cpu().numpy(), kv, km, GC.TOL_KKT, "fused K")
+
+
+@pytest.mark.parametrize("which", ["mid", "batched"])
+def test_fused_sweep_bitwise_equals_separate_calls(which, torch_dev):
+    torch, dev = torch_dev
+    capi = _capi()
+    if which == "mid":
+        nets = [synth.config_network("mid")]
+    else:
+        nets = [synth.make_network(150, 210, 30, 6, 111), synth.make_network(64, 90, 13, 13, 112),
+                pins.manual_network(4, [0, 0, 1, 1, 2], [1, 1, 0, 2, 3], [0.01] * 5, [0.1, 0.2, 0.15, 0.1, 0.3],
+                                    [0.02] * 5, [1, 1, 3], T=3, pd=np.full((3, 4), 0.2))]
+    pts = [synth.make_point(n, 300 + k) for k, n in enumerate(nets)]
+    M = capi.Model(nets, device=0)
+    cat = lambda key: np.concatenate([getattr(p, key) for p in pts])
+    print(f"fused sweep vs separate: {which}", flush=True)
+    v = np.random.default_rng(7).standard_normal(M.m)  # J^T v with v != lambda
+    E = GC.gpu_all(M, cat("x"), cat("lam"), 0.37, v, cat("diag_x"), cat("dcon"), torch, dev, graph=False)
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    X, LAM, V, DX, D = t(cat("x")), t(cat("lam")), t(v), t(cat("diag_x")), t(cat("dcon"))
+    e = lambda k: torch.full((k,), float("nan"), dtype=torch.float64, device=dev)
+    out = dict(f=e(M.ninst), grad=e(M.n), c=e(M.m), jvals=e(M.nnz_jac), hvals=e(M.nnz_hess), jtv=e(M.n),
+               kvals=e(M.nnz_kkt))
+    M.use_current_torch_stream()
+    M.sweep(M.sweep_args(x=X, lam=LAM, sigma=0.37, v=V, diag_x=DX, dcon=D, **out))
+    torch.cuda.synchronize()
+    for key, ek in (("f", "f"), ("grad", "grad"), ("c", "c"), ("jvals", "jac"), ("hvals", "hess"),
+                    ("jtv", "jtv"), ("kvals", "kkt")):
+        assert np.array_equal(out[key].cpu().numpy(), E[ek]), key
