@@ -210,6 +210,18 @@ int opf_sweep(opf_model *model, const opf_sweep_args *args);
  * argument set changes) and replayed with a single graph launch. */
 int opf_sweep_graph(opf_model *model, const opf_sweep_args *args);
 
+/* Per-kernel timing.  opf_set_timing(model, 1) clears the statistics and
+ * brackets every later kernel launch of the model with HIP events on the
+ * model's stream (launches recorded into a graph are not timed);
+ * opf_set_timing(model, 0) stops.  opf_kernel_stats returns, for kernel
+ * family index (0 .. until OPF_ERANGE), its name, the number of timed
+ * launches and their summed duration in milliseconds (it waits for the
+ * pending events).  For profiling the evaluation path; the events cost a
+ * few microseconds of host time per launch. */
+int opf_set_timing(opf_model *model, int enable);
+int opf_kernel_stats(opf_model *model, int32_t index, const char **name,
+                     int64_t *launches, double *total_ms);
+
 /* Chooses tile shapes (lines / buses / generators per tile, periods per
  * tile, persistent grid size) per kernel by timing candidates on the device.
  * cache_path (host string or NULL): JSON file read for a previous result

@@ -472,17 +472,23 @@ def load_adjoint(net, lam):
 # ----------------------------------------------------------------------------
 # condensed KKT matrix (Sec. III-B: M_cond = W + delta_w I + Sigma_x + A^T D A)
 # ----------------------------------------------------------------------------
-def condensed(n, jac, hess, diag_x, dcon, row_mask=None):
+def condensed(n, jac, hess, diag_x, dcon, row_mask=None, jac_mag=None, hess_mag=None):
     """K = lower(H + diag(diag_x) + J^T diag(dcon) J) by sort-and-reduce of
     every contribution (row, col, value).
 
     jac = (rows, cols, vals) with unique (row, col); hess = lower COO.
     Returns (rowptr int64 [n+1], colind int64, vals, mag) where mag is the
-    per-slot sum of |contribution|.  ``row_mask`` (bool [n]) restricts the
-    output to the selected rows (rowptr then still spans all n rows; the
-    values of the selected rows are exactly those of the full matrix)."""
+    per-slot sum of the contributions' magnitude scales: |d| m(J_a) m(J_b)
+    for a product, m(H) for a Hessian entry, |diag| -- with m(.) the
+    cancellation scale of a J / H entry when jac_mag / hess_mag are given
+    (the terms an entry is made of), else its absolute value.  ``row_mask``
+    (bool [n]) restricts the output to the selected rows (rowptr then still
+    spans all n rows; the values of the selected rows are exactly those of
+    the full matrix)."""
     jr, jc, jv = (np.asarray(a) for a in jac)
     hr, hc, hv = (np.asarray(a) for a in hess)
+    jm = np.abs(jv) if jac_mag is None else np.asarray(jac_mag, dtype=np.float64)
+    hm = np.abs(hv) if hess_mag is None else np.asarray(hess_mag, dtype=np.float64)
     dcon = np.asarray(dcon, dtype=np.float64)
     if diag_x is None:
         diag_x = np.zeros(n)
@@ -492,12 +498,12 @@ def condensed(n, jac, hess, diag_x, dcon, row_mask=None):
         keep_rows = np.zeros(int(jr.max()) + 1 if jr.size else 1, dtype=bool)
         keep_rows[jr[touch]] = True
         sel = keep_rows[jr]
-        jr, jc, jv = jr[sel], jc[sel], jv[sel]
+        jr, jc, jv, jm = jr[sel], jc[sel], jv[sel], jm[sel]
         hs = row_mask[hr]
-        hr, hc, hv = hr[hs], hc[hs], hv[hs]
+        hr, hc, hv, hm = hr[hs], hc[hs], hv[hs], hm[hs]
     # pairs of entries within each J row (entry with itself included)
     order = np.lexsort((jc, jr))
-    jr, jc, jv = jr[order], jc[order], jv[order]
+    jr, jc, jv, jm = jr[order], jc[order], jv[order], jm[order]
     if jr.size:
         key = jr * (n + 1) + jc
         if np.any(key[1:] == key[:-1]):
@@ -513,21 +519,24 @@ def condensed(n, jac, hess, diag_x, dcon, row_mask=None):
     pr = np.maximum(jc[e], jc[p])
     pc = np.minimum(jc[e], jc[p])
     pv = dcon[jr[e]] * jv[e] * jv[p]
+    pm = np.abs(dcon[jr[e]]) * jm[e] * jm[p]
     diag_idx = np.arange(n) if row_mask is None else np.nonzero(row_mask)[0]
+    dvals = np.asarray(diag_x, dtype=np.float64)[diag_idx]
     R = np.concatenate([pr, hr, diag_idx])
     C = np.concatenate([pc, hc, diag_idx])
-    Vv = np.concatenate([pv, hv, np.asarray(diag_x, dtype=np.float64)[diag_idx]])
+    Vv = np.concatenate([pv, hv, dvals])
+    Mv = np.concatenate([pm, hm, np.abs(dvals)])
     if row_mask is not None:
         s = row_mask[R]
-        R, C, Vv = R[s], C[s], Vv[s]
+        R, C, Vv, Mv = R[s], C[s], Vv[s], Mv[s]
     if np.any(C > R):
         raise ValueError("upper-triangular contribution")
     key = R.astype(np.int64) * n + C.astype(np.int64)
     o = np.argsort(key, kind="stable")
-    key, Vv = key[o], Vv[o]
+    key, Vv, Mv = key[o], Vv[o], Mv[o]
     uniq, first_idx = np.unique(key, return_index=True)
     vals = np.add.reduceat(Vv, first_idx) if key.size else np.zeros(0)
-    mag = np.add.reduceat(np.abs(Vv), first_idx) if key.size else np.zeros(0)
+    mag = np.add.reduceat(Mv, first_idx) if key.size else np.zeros(0)
     rows = uniq // n
     cols = uniq % n
     rowptr = np.zeros(n + 1, dtype=np.int64)

@@ -90,6 +90,9 @@ _SIGS = {
     "opf_sweep": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
     "opf_sweep_graph": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
     "opf_autotune": (C.c_int, [_vp, C.c_char_p]),
+    "opf_set_timing": (C.c_int, [_vp, C.c_int]),
+    "opf_kernel_stats": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double)]),
     "opf_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -278,6 +281,24 @@ class Model:
 
     def sweep_graph(self, args: opf_sweep_args):
         check(opf_sweep_graph(self.h, C.byref(args)), "opf_sweep_graph")
+
+    def set_timing(self, enable: bool):
+        check(opf_set_timing(self.h, 1 if enable else 0), "opf_set_timing")
+
+    def kernel_stats(self) -> dict:
+        """{kernel family: (timed launches, summed ms)} for families with launches."""
+        out = {}
+        i = 0
+        while True:
+            name, cnt, ms = C.c_char_p(), C.c_int64(), C.c_double()
+            rc = opf_kernel_stats(self.h, i, C.byref(name), C.byref(cnt), C.byref(ms))
+            if rc == OPF_ERANGE:
+                break
+            check(rc, "opf_kernel_stats")
+            if cnt.value:
+                out[name.value.decode()] = (cnt.value, ms.value)
+            i += 1
+        return out
 
     def autotune(self, cache_path: str | None = None):
         check(opf_autotune(self.h, cache_path.encode() if cache_path else None), "opf_autotune")

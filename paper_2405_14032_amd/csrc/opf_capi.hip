@@ -101,11 +101,78 @@ struct opf_model {
   hipGraphExec_t gexec = nullptr;
   opf_sweep_args gargs;
   bool gvalid = false;
+  // per-kernel timing (opf_set_timing / opf_kernel_stats)
+  struct Timed {
+    int id;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> events;  // free pool
+  std::vector<hipEvent_t> all_events;
+  double t_ms[OP_COUNT + 1] = {};
+  int64_t t_n[OP_COUNT + 1] = {};
 };
 
 namespace {
 
 bool host_only(const opf_model* M) { return M->device < 0; }
+
+// Timing id of the objective's final reduction (not a tile-list op).
+constexpr int kTimeObjFinal = OP_COUNT;
+
+hipEvent_t take_event(opf_model* M) {
+  if (!M->events.empty()) {
+    hipEvent_t e = M->events.back();
+    M->events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  M->all_events.push_back(e);
+  return e;
+}
+
+// Brackets one kernel launch with events on the model's stream when timing
+// is on (and the stream is not being recorded into a graph).
+struct TimerScope {
+  opf_model* M;
+  int id;
+  hipEvent_t a = nullptr;
+  TimerScope(opf_model* m, int i) : M(m), id(i) {
+    if (!M->timing) return;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(M->stream, &st) != hipSuccess || st != hipStreamCaptureStatusNone) return;
+    a = take_event(M);
+    if (a && hipEventRecord(a, M->stream) != hipSuccess) {
+      M->events.push_back(a);
+      a = nullptr;
+    }
+  }
+  ~TimerScope() {
+    if (!a) return;
+    hipEvent_t b = take_event(M);
+    if (b && hipEventRecord(b, M->stream) == hipSuccess) {
+      M->pending.push_back({id, a, b});
+    } else {
+      M->events.push_back(a);
+      if (b) M->events.push_back(b);
+    }
+  }
+};
+
+void flush_timing(opf_model* M) {
+  for (auto& r : M->pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      M->t_ms[r.id] += ms;
+      M->t_n[r.id] += 1;
+    }
+    M->events.push_back(r.a);
+    M->events.push_back(r.b);
+  }
+  M->pending.clear();
+}
 
 // Element classes of each op (in launch order inside one list).
 std::vector<int> kinds_of(int op) {
@@ -420,6 +487,7 @@ void release(opf_model* M) {
     (void)hipGetDevice(&cur);
     if (cur != M->device) (void)hipSetDevice(M->device);
     if (M->gexec) (void)hipGraphExecDestroy(M->gexec);
+    for (hipEvent_t e : M->all_events) (void)hipEventDestroy(e);
     for (auto& L : M->lists)
       if (L.d) (void)hipFree(L.d);
     if (M->arena) (void)hipFree(M->arena);
@@ -466,29 +534,32 @@ struct DeviceGuard {
 
 // ---------------------------------------------------------------- enqueue helpers
 int enq_obj(opf_model* M, const double* x, double* f) {
-  OPF_LAUNCHED(launch_obj_partial(launch_of(M, OP_OBJ), x, M->obj_partial), "objective kernel");
-  OPF_LAUNCHED(launch_obj_final(M->d_obj_begin, (int)M->inst.size(), M->obj_partial, f, M->stream),
-               "objective reduction kernel");
+  { TimerScope ts_(M, OP_OBJ); OPF_LAUNCHED(launch_obj_partial(launch_of(M, OP_OBJ), x, M->obj_partial), "objective kernel"); }
+  {
+    TimerScope ts_(M, kTimeObjFinal);
+    OPF_LAUNCHED(launch_obj_final(M->d_obj_begin, (int)M->inst.size(), M->obj_partial, f, M->stream),
+                 "objective reduction kernel");
+  }
   return OPF_OK;
 }
 
 int enq_jt(opf_model* M, const double* x, const double* v, double* out) {
-  OPF_LAUNCHED(launch_jt_a(launch_of(M, OP_JTA), x, v, out, M->scratch), "J^T v line kernel");
-  OPF_LAUNCHED(launch_jt_b(launch_of(M, OP_JTB), v, out, M->scratch), "J^T v bus kernel");
+  { TimerScope ts_(M, OP_JTA); OPF_LAUNCHED(launch_jt_a(launch_of(M, OP_JTA), x, v, out, M->scratch), "J^T v line kernel"); }
+  { TimerScope ts_(M, OP_JTB); OPF_LAUNCHED(launch_jt_b(launch_of(M, OP_JTB), v, out, M->scratch), "J^T v bus kernel"); }
   return OPF_OK;
 }
 
 int enq_kkt(opf_model* M, const double* h, const double* j, const double* dx, const double* d, double* k) {
-  OPF_LAUNCHED(launch_kkt_a(launch_of(M, OP_KKA), h, j, dx, d, k, M->scratch), "condensed line kernel");
-  OPF_LAUNCHED(launch_kkt_b(launch_of(M, OP_KKB), j, dx, d, k, M->scratch), "condensed bus kernel");
+  { TimerScope ts_(M, OP_KKA); OPF_LAUNCHED(launch_kkt_a(launch_of(M, OP_KKA), h, j, dx, d, k, M->scratch), "condensed line kernel"); }
+  { TimerScope ts_(M, OP_KKB); OPF_LAUNCHED(launch_kkt_b(launch_of(M, OP_KKB), j, dx, d, k, M->scratch), "condensed bus kernel"); }
   return OPF_OK;
 }
 
 int enq_jhk(opf_model* M, const double* x, const double* lam, double sigma, const double* dx, const double* d,
             double* j, double* h, double* k) {
-  OPF_LAUNCHED(launch_jhk_a(launch_of(M, OP_JHKA), x, lam, sigma, h, j, dx, d, k, M->scratch),
-               "fused J/H/condensed line kernel");
-  OPF_LAUNCHED(launch_kkt_b(launch_of(M, OP_KKB), j, dx, d, k, M->scratch), "condensed bus kernel");
+  { TimerScope ts_(M, OP_JHKA); OPF_LAUNCHED(launch_jhk_a(launch_of(M, OP_JHKA), x, lam, sigma, h, j, dx, d, k, M->scratch),
+               "fused J/H/condensed line kernel"); }
+  { TimerScope ts_(M, OP_KKB); OPF_LAUNCHED(launch_kkt_b(launch_of(M, OP_KKB), j, dx, d, k, M->scratch), "condensed bus kernel"); }
   return OPF_OK;
 }
 
@@ -508,12 +579,12 @@ int enq_sweep(opf_model* M, const opf_sweep_args* a) {
   // every per-element output requested: two fused passes (lines and
   // generators, then buses) plus the objective reduction
   if (a->grad && a->c && a->jvals && a->hvals && a->jtv && a->kvals) {
-    OPF_LAUNCHED(launch_sweep_a(launch_of(M, OP_SWA), a->x, a->lambda, a->sigma, a->v, a->hvals, a->jvals, a->diag_x,
+    { TimerScope ts_(M, OP_SWA); OPF_LAUNCHED(launch_sweep_a(launch_of(M, OP_SWA), a->x, a->lambda, a->sigma, a->v, a->hvals, a->jvals, a->diag_x,
                                 a->dcon, a->kvals, a->c, a->jtv, a->grad, M->scratch),
-                 "sweep line kernel");
-    OPF_LAUNCHED(launch_sweep_b(launch_of(M, OP_SWB), a->x, a->v, a->jvals, a->diag_x, a->dcon, a->kvals, a->c,
+                 "sweep line kernel"); }
+    { TimerScope ts_(M, OP_SWB); OPF_LAUNCHED(launch_sweep_b(launch_of(M, OP_SWB), a->x, a->v, a->jvals, a->diag_x, a->dcon, a->kvals, a->c,
                                 a->jtv, a->grad, M->scratch),
-                 "sweep bus kernel");
+                 "sweep bus kernel"); }
     if (a->f && (rc = enq_obj(M, a->x, a->f)) != OPF_OK) return rc;
     return OPF_OK;
   }
@@ -523,12 +594,12 @@ int enq_sweep(opf_model* M, const opf_sweep_args* a) {
     if ((rc = enq_jhk(M, a->x, a->lambda, a->sigma, a->diag_x, a->dcon, a->jvals, a->hvals, a->kvals)) != OPF_OK)
       return rc;
   } else {
-    if (a->jvals) OPF_LAUNCHED(launch_jac(launch_of(M, OP_JAC), a->x, a->jvals), "Jacobian kernel");
+    if (a->jvals) { TimerScope ts_(M, OP_JAC); OPF_LAUNCHED(launch_jac(launch_of(M, OP_JAC), a->x, a->jvals), "Jacobian kernel"); }
     if (a->hvals)
-      OPF_LAUNCHED(launch_hess(launch_of(M, OP_HESS), a->x, a->lambda, a->sigma, a->hvals), "Hessian kernel");
+      { TimerScope ts_(M, OP_HESS); OPF_LAUNCHED(launch_hess(launch_of(M, OP_HESS), a->x, a->lambda, a->sigma, a->hvals), "Hessian kernel"); }
   }
-  if (a->c) OPF_LAUNCHED(launch_cons(launch_of(M, OP_CONS), a->x, a->c), "constraint kernel");
-  if (a->grad) OPF_LAUNCHED(launch_grad(launch_of(M, OP_GRAD), a->x, a->grad), "gradient kernel");
+  if (a->c) { TimerScope ts_(M, OP_CONS); OPF_LAUNCHED(launch_cons(launch_of(M, OP_CONS), a->x, a->c), "constraint kernel"); }
+  if (a->grad) { TimerScope ts_(M, OP_GRAD); OPF_LAUNCHED(launch_grad(launch_of(M, OP_GRAD), a->x, a->grad), "gradient kernel"); }
   if (a->f && (rc = enq_obj(M, a->x, a->f)) != OPF_OK) return rc;
   if (a->jtv && (rc = enq_jt(M, a->x, a->v, a->jtv)) != OPF_OK) return rc;
   return OPF_OK;
@@ -680,31 +751,35 @@ int opf_set_stream(opf_model* M, void* s) {
   return OPF_OK;
 }
 
-int opf_bounds(const opf_model* M, double* lv, double* uv, double* lc, double* uc) {
+int opf_bounds(const opf_model* Mc, double* lv, double* uv, double* lc, double* uc) {
+  opf_model* M = const_cast<opf_model*>(Mc);
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(lv && uv && lc && uc, "a bounds array");
   DeviceGuard g(M->device);
-  OPF_LAUNCHED(launch_bounds(launch_of(M, OP_BOUNDS), lv, uv, lc, uc), "bounds kernel");
+  { TimerScope ts_(M, OP_BOUNDS); OPF_LAUNCHED(launch_bounds(launch_of(M, OP_BOUNDS), lv, uv, lc, uc), "bounds kernel"); }
   return OPF_OK;
 }
 
-int opf_jac_structure(const opf_model* M, int32_t* rows, int32_t* cols) {
+int opf_jac_structure(const opf_model* Mc, int32_t* rows, int32_t* cols) {
+  opf_model* M = const_cast<opf_model*>(Mc);
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(rows && cols, "rows / cols");
   DeviceGuard g(M->device);
-  OPF_LAUNCHED(launch_jac_struct(launch_of(M, OP_JSTR), rows, cols), "Jacobian structure kernel");
+  { TimerScope ts_(M, OP_JSTR); OPF_LAUNCHED(launch_jac_struct(launch_of(M, OP_JSTR), rows, cols), "Jacobian structure kernel"); }
   return OPF_OK;
 }
 
-int opf_hess_structure(const opf_model* M, int32_t* rows, int32_t* cols) {
+int opf_hess_structure(const opf_model* Mc, int32_t* rows, int32_t* cols) {
+  opf_model* M = const_cast<opf_model*>(Mc);
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(rows && cols, "rows / cols");
   DeviceGuard g(M->device);
-  OPF_LAUNCHED(launch_hess_struct(launch_of(M, OP_HSTR), rows, cols), "Hessian structure kernel");
+  { TimerScope ts_(M, OP_HSTR); OPF_LAUNCHED(launch_hess_struct(launch_of(M, OP_HSTR), rows, cols), "Hessian structure kernel"); }
   return OPF_OK;
 }
 
-int opf_kkt_structure(const opf_model* M, int64_t* rowptr, int32_t* colind) {
+int opf_kkt_structure(const opf_model* Mc, int64_t* rowptr, int32_t* colind) {
+  opf_model* M = const_cast<opf_model*>(Mc);
   if (!M) return fail(OPF_EINVAL, "model is NULL");
   OPF_REQUIRE(rowptr && colind, "rowptr / colind");
   try {
@@ -716,8 +791,8 @@ int opf_kkt_structure(const opf_model* M, int64_t* rowptr, int32_t* colind) {
     return fail(OPF_EINVAL, "unexpected host exception");
   }
   DeviceGuard g(M->device);
-  OPF_LAUNCHED(launch_kkt_struct(launch_of(M, OP_KSTR), (int)M->inst.size(), rowptr, colind),
-               "condensed structure kernel");
+  { TimerScope ts_(M, OP_KSTR); OPF_LAUNCHED(launch_kkt_struct(launch_of(M, OP_KSTR), (int)M->inst.size(), rowptr, colind),
+               "condensed structure kernel"); }
   return OPF_OK;
 }
 
@@ -732,7 +807,7 @@ int opf_eval_grad(opf_model* M, const double* x, double* gr) {
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(x && gr, "x / g");
   DeviceGuard g(M->device);
-  OPF_LAUNCHED(launch_grad(launch_of(M, OP_GRAD), x, gr), "gradient kernel");
+  { TimerScope ts_(M, OP_GRAD); OPF_LAUNCHED(launch_grad(launch_of(M, OP_GRAD), x, gr), "gradient kernel"); }
   return OPF_OK;
 }
 
@@ -740,7 +815,7 @@ int opf_eval_cons(opf_model* M, const double* x, double* c) {
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(x && c, "x / c");
   DeviceGuard g(M->device);
-  OPF_LAUNCHED(launch_cons(launch_of(M, OP_CONS), x, c), "constraint kernel");
+  { TimerScope ts_(M, OP_CONS); OPF_LAUNCHED(launch_cons(launch_of(M, OP_CONS), x, c), "constraint kernel"); }
   return OPF_OK;
 }
 
@@ -748,7 +823,7 @@ int opf_eval_jac(opf_model* M, const double* x, double* jv) {
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(x && jv, "x / jvals");
   DeviceGuard g(M->device);
-  OPF_LAUNCHED(launch_jac(launch_of(M, OP_JAC), x, jv), "Jacobian kernel");
+  { TimerScope ts_(M, OP_JAC); OPF_LAUNCHED(launch_jac(launch_of(M, OP_JAC), x, jv), "Jacobian kernel"); }
   return OPF_OK;
 }
 
@@ -756,7 +831,7 @@ int opf_eval_hess(opf_model* M, const double* x, const double* lam, double sigma
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(x && lam && hv, "x / lambda / hvals");
   DeviceGuard g(M->device);
-  OPF_LAUNCHED(launch_hess(launch_of(M, OP_HESS), x, lam, sigma, hv), "Hessian kernel");
+  { TimerScope ts_(M, OP_HESS); OPF_LAUNCHED(launch_hess(launch_of(M, OP_HESS), x, lam, sigma, hv), "Hessian kernel"); }
   return OPF_OK;
 }
 
@@ -784,7 +859,7 @@ int opf_load_adjoint(opf_model* M, const double* lam, double* gpd, double* gqd) 
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(lam && gpd && gqd, "lambda / gpd / gqd");
   DeviceGuard g(M->device);
-  OPF_LAUNCHED(launch_load_adjoint(launch_of(M, OP_LADJ), lam, gpd, gqd), "load adjoint kernel");
+  { TimerScope ts_(M, OP_LADJ); OPF_LAUNCHED(launch_load_adjoint(launch_of(M, OP_LADJ), lam, gpd, gqd), "load adjoint kernel"); }
   return OPF_OK;
 }
 
@@ -802,6 +877,29 @@ int opf_eval_jhk(opf_model* M, const double* x, const double* lam, double sigma,
   OPF_REQUIRE(x && lam && d && jv && hv && kv, "x / lambda / dcon / jvals / hvals / kvals");
   DeviceGuard g(M->device);
   return enq_jhk(M, x, lam, sigma, dx, d, jv, hv, kv);
+}
+
+int opf_set_timing(opf_model* M, int enable) {
+  OPF_CHECK_MODEL(M);
+  DeviceGuard g(M->device);
+  flush_timing(M);
+  for (int i = 0; i <= OP_COUNT; ++i) {
+    M->t_ms[i] = 0.0;
+    M->t_n[i] = 0;
+  }
+  M->timing = enable != 0;
+  return OPF_OK;
+}
+
+int opf_kernel_stats(opf_model* M, int32_t index, const char** name, int64_t* launches, double* total_ms) {
+  OPF_CHECK_MODEL(M);
+  if (index < 0 || index > OP_COUNT) return fail(OPF_ERANGE, "kernel index out of range");
+  DeviceGuard g(M->device);
+  flush_timing(M);
+  if (name) *name = index == kTimeObjFinal ? "obj_final" : kOpName[index];
+  if (launches) *launches = M->t_n[index];
+  if (total_ms) *total_ms = M->t_ms[index];
+  return OPF_OK;
 }
 
 int opf_sweep(opf_model* M, const opf_sweep_args* a) {

@@ -43,7 +43,8 @@ def oracle_all(net, pt, v=None, with_kkt=True):
     gp, gq = O.load_adjoint(net, pt.lam)
     out["load_adj"] = (gp.reshape(-1), gq.reshape(-1))
     if with_kkt:
-        rp, ci, kv, km = O.condensed(L.n, (jr, jc, jv), (hr, hc, hv), pt.diag_x, pt.dcon)
+        rp, ci, kv, km = O.condensed(L.n, (jr, jc, jv), (hr, hc, hv), pt.diag_x, pt.dcon, jac_mag=jm,
+                                     hess_mag=hm)
         out["kkt_idx"] = (rp, ci)
         out["kkt"] = (kv, km)
     return out

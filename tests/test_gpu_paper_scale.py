@@ -81,7 +81,8 @@ def test_paper_scale_parity():
     mask = np.zeros(L.n, dtype=bool)
     for tt in (0, 1, net.T // 2, net.T - 1):
         mask[tt * L.n_p:(tt + 1) * L.n_p] = True
-    orp, oci, okv, okm = O.condensed(L.n, (ojr, ojc, ojv), (ohr, ohc, ohv), pt.diag_x, pt.dcon, row_mask=mask)
+    orp, oci, okv, okm = O.condensed(L.n, (ojr, ojc, ojv), (ohr, ohc, ohv), pt.diag_x, pt.dcon, row_mask=mask,
+                                     jac_mag=ojm, hess_mag=ohm)
     sel = np.nonzero(mask)[0]
     a, b = rp[sel], rp[sel + 1]
     oa, ob = orp[sel], orp[sel + 1]

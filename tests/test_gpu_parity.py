@@ -82,10 +82,11 @@ def test_parity_sigma_and_null_diag(torch_dev):
     M.assemble_condensed(hv, jv, None, D, kv)
     torch.cuda.synchronize()
     L = O.Layout(net)
-    jac = O.jacobian(net, pt.x)
+    jr, jc, jval, jmag = O.jacobian(net, pt.x, with_mag=True)
     hess_r, hess_c, hess_v, hess_m = O.hessian(net, pt.x, pt.lam, pt.sigma, with_mag=True)
     GC.assert_close(hv.cpu().numpy(), hess_v, hess_m, GC.TOL, "H sigma=0.37")
-    rp, ci, kval, kmag = O.condensed(L.n, jac, (hess_r, hess_c, hess_v), None, pt.dcon)
+    rp, ci, kval, kmag = O.condensed(L.n, (jr, jc, jval), (hess_r, hess_c, hess_v), None, pt.dcon, jac_mag=jmag,
+                                     hess_mag=hess_m)
     GC.assert_close(kv.cpu().numpy(), kval, kmag, GC.TOL_KKT, "K without diag_x")
 
 
@@ -190,9 +191,10 @@ def test_fused_jhk_bitwise_equals_separate_calls(which, torch_dev):
     # and against the oracle (first instance)
     net, pt = nets[0], pts[0]
     L = O.Layout(net)
-    jac = O.jacobian(net, pt.x)
-    hess = O.hessian(net, pt.x, pt.lam, 0.37)
-    _, _, kv, km = O.condensed(L.n, jac, hess, pt.diag_x, pt.dcon)
+    jr, jc, jval, jmag = O.jacobian(net, pt.x, with_mag=True)
+    hr, hc, hval, hmag = O.hessian(net, pt.x, pt.lam, 0.37, with_mag=True)
+    _, _, kv, km = O.condensed(L.n, (jr, jc, jval), (hr, hc, hval), pt.diag_x, pt.dcon, jac_mag=jmag,
+                               hess_mag=hmag)
     GC.assert_close(k2[:M.k_off[1]].cpu().numpy(), kv, km, GC.TOL_KKT, "fused K")
 
 
