@@ -271,7 +271,7 @@ int lds_needs(const opf_model* M, int op, const std::vector<Tile>& tiles, const 
       cap2 = std::max<int>(cap2, I.krow[I.N + tl.e1] - I.krow[I.N + tl.e0]);
     }
   }
-  smem = line ? std::max((size_t)cap, (size_t)s.block * kScratchKkt) * sizeof(double)
+  smem = line ? (size_t)cap * sizeof(double)
                : ((size_t)cap + (size_t)cap2) * sizeof(double);
   if (smem > kMaxSmem) return fail(OPF_EINVAL, std::string("tile shape needs too much LDS for ") + kOpName[op]);
   return OPF_OK;
@@ -677,7 +677,7 @@ int opf_model_create(const opf_instance_desc* desc, int32_t ninst, int device, o
       return fail(rc, e);
     }
     size_t scr = 0;
-    for (const auto& I : M->inst) scr += 14ull * I.B * I.T;
+    for (const auto& I : M->inst) scr += (size_t)(kScratchPerLine * (int64_t)I.B * I.T + 7) / 8 * 8;
     if (hipMalloc(&M->scratch, std::max<size_t>(scr, 1) * sizeof(double)) != hipSuccess) {
       M->scratch = nullptr;
       release(M);

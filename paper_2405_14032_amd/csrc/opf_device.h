@@ -46,10 +46,30 @@ __device__ __forceinline__ int64_t kkt_period_offset_dev(int64_t nnzk_p, int32_t
   return (int64_t)t * nnzk_p + (t >= 1 ? (int64_t)(t - 1) * G : 0);
 }
 
-// Scratch doubles per line and period: 10 for the condensed assembly's
-// line -> bus hand-off, 4 for the J^T v line -> bus hand-off.
-constexpr int kScratchKkt = 10;
+// Per-instance scratch, in doubles, per line and period:
+//  * a line -> bus hand-off record per line end (kRecEnd doubles, one
+//    64-byte line): [0] the end's (vm,vm) diagonal sum, [1] its (va,vm)
+//    pair, [2] (va,va) diagonal, [3] (va_end, vm_other) cross pair, [4] p and
+//    [5] q of the flow leaving the bus through this end, [6] J^T v on vm,
+//    [7] J^T v on va of the end's bus; records are [t][line][end][8];
+//  * the line's (vm_i,vm_j) and (va_i,va_j) cross sums, [t][line][2], read
+//    by the higher-numbered end (it owns those slots);
+//  * the 4-value hand-off of the separate J^T v kernels, [t][line][4].
+constexpr int kRecEnd = 8;
+constexpr int kRecLine = 2 * kRecEnd;
+constexpr int kShared = 2;
 constexpr int kScratchJt = 4;
+constexpr int kScratchPerLine = kRecLine + kShared + kScratchJt;
+
+__device__ __forceinline__ double* rec_at(const InstDev& I, double* scr, int t) {
+  return scr + I.s_off + (int64_t)t * I.B * kRecLine;
+}
+__device__ __forceinline__ double* shared_at(const InstDev& I, double* scr, int t) {
+  return scr + I.s_off + (int64_t)kRecLine * I.B * I.T + (int64_t)t * I.B * kShared;
+}
+__device__ __forceinline__ double* jt_at(const InstDev& I, double* scr, int t) {
+  return scr + I.s_off + (int64_t)(kRecLine + kShared) * I.B * I.T + (int64_t)t * I.B * kScratchJt;
+}
 
 // Kernel launchers (opf_kernels.hip).  Each takes the device instance
 // array, a device tile list and a launch shape; returns the HIP error of the

@@ -446,7 +446,7 @@ __device__ void jt_branch(const InstDev& I, int l, int t0, int t1, const double*
     jt_line(vk, Jf, vp[b.cTHF + l], vp[b.cTHT + l], vp[b.cANG + l], fl, vbal, o4, rec);
 #pragma unroll
     for (int k = 0; k < 4; ++k) op[b.xFL + k * B + l] = o4[k];
-    double* r = scr + I.s_off + (int64_t)kScratchKkt * I.B * I.T + ((int64_t)t * B + l) * kScratchJt;
+    double* r = jt_at(I, scr, t) + (int64_t)l * kScratchJt;
 #pragma unroll
     for (int a = 0; a < 4; ++a) r[a] = rec[a];
   }
@@ -499,7 +499,7 @@ __global__ void __launch_bounds__(512) k_jt_b(const InstDev* __restrict__ insts,
     if (n >= tl.e1) continue;
     const int q0 = I.bus_ptr[n], q1 = I.bus_ptr[n + 1];
     for (int t = tl.t0; t < tl.t1; ++t) {
-      const double* rs = scr + I.s_off + (int64_t)kScratchKkt * I.B * I.T + (int64_t)t * I.B * kScratchJt;
+      const double* rs = jt_at(I, const_cast<double*>(scr), t);
       double svm = 0.0, sva = 0.0;
       for (int a = q0; a < q1; ++a) {
         const int ad = I.bus_adj[a];
@@ -649,10 +649,14 @@ __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, c
   }
 }
 
-// One line tile of the condensed assembly.  FUSED: J and H of the lines are
+// One line tile of the condensed assembly.  The four flow kinds are handled
+// one after the other (derivatives, K row through LDS, stream-out), so only
+// one kind's values are live at a time.  FUSED: J and H of the lines are
 // evaluated from x and lambda here, written out, and used directly (the
-// partner J entries are the structural -1 / +1 of the balance rows);
-// otherwise J and H are read from the given arrays.
+// partner J entries are the structural -1 / +1 of the balance rows), and
+// the optional sweep outputs (constraint rows, J^T v and gradient on the
+// flow variables, the bus hand-off of p, q and J^T v) are produced in the
+// same pass; otherwise J and H are read from the given arrays.
 template <bool FUSED>
 __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __restrict__ X,
                               const double* __restrict__ LAM, double* __restrict__ H, double* __restrict__ J,
@@ -665,105 +669,101 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
   const int tid = (int)threadIdx.x;
   const int l = tl.e0 + tid;
   const bool act = l < tl.e1;
-  const int nl = tl.e1 - tl.e0;
-  int sb[4], se[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    sb[k] = I.krow[b.xFL + k * B + tl.e0];
-    se[k] = I.krow[b.xFL + k * B + tl.e1];
-  }
-  int i = 0, j = 0, rs[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0};
+  int i = 0, j = 0;
   Coef cf;
   if (act) {
     i = I.f_bus[l];
     j = I.t_bus[l];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      rs[k] = I.krow[b.xFL + k * B + l] - sb[k];
-      re[k] = I.krow[b.xFL + k * B + l + 1] - sb[k];
-    }
     if (FUSED) load_coef(I, l, cf);
   }
   const bool ilo = i < j;
   for (int t = tl.t0; t < tl.t1; ++t) {
     double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
+    double* hp = H + I.h_off + (int64_t)t * I.nnzh_p;
+    const double* dp = D + I.c_off + (int64_t)t * I.m_p;
+    const int64_t xo = I.x_off + (int64_t)t * I.n_p;
     double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t) + (t >= 1 ? G : 0);
-    double Jf[4][5], df[4], Jb[4], Jt[4], Hth[4], dbal[4], dth[2], q[10];
-    if (act) {
-      double* hp = H + I.h_off + (int64_t)t * I.nnzh_p;
-      const double* dp = D + I.c_off + (int64_t)t * I.m_p;
+    double q[10], dbal[4], dth[2], Jt[4];
+    double vi = 0.0, vj = 0.0, vv = 0.0, sn = 0.0, cs = 0.0, ti = 0.0, tj = 0.0, fl[4], lf = 0.0, lt = 0.0;
+    double vk[4], svi = 0.0, svj = 0.0, sti = 0.0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) df[k] = dp[b.cFLOW + k * B + l];
+    for (int a = 0; a < 10; ++a) q[a] = 0.0;
+    if (act) {
       dbal[0] = dp[i];
       dbal[1] = dp[N + i];
       dbal[2] = dp[j];
       dbal[3] = dp[N + j];
       dth[0] = dp[b.cTHF + l];
       dth[1] = dp[b.cTHT + l];
-      const double dang = dp[b.cANG + l];
-      double Ja0, Ja1;
-      double vi = 0.0, vj = 0.0, vv = 0.0, sn = 0.0, cs = 0.0, ti = 0.0, tj = 0.0, fl[4];
-      const double* lp = nullptr;
       if constexpr (FUSED) {
-        const double* xp = X + I.x_off + (int64_t)t * I.n_p;
-        lp = LAM + I.c_off + (int64_t)t * I.m_p;
+        const double* xp = X + xo;
+        const double* lp = LAM + I.c_off + (int64_t)t * I.m_p;
         vi = xp[i];
         vj = xp[j];
         ti = xp[N + i];
         tj = xp[N + j];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) fl[k] = xp[b.xFL + k * B + l];
+        for (int k = 0; k < 4; ++k) {
+          fl[k] = xp[b.xFL + k * B + l];
+          Jt[k] = 2.0 * fl[k];
+        }
         sincos(ti - tj, &sn, &cs);
         vv = vi * vj;
-        const double lf = 2.0 * lp[b.cTHF + l], lt = 2.0 * lp[b.cTHT + l];
+        lf = 2.0 * lp[b.cTHF + l];
+        lt = 2.0 * lp[b.cTHT + l];
+        if (JTV) {
+          const double* vp = V + I.c_off + (int64_t)t * I.m_p;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          Jb[k] = -1.0;
-          Jt[k] = 2.0 * fl[k];
-          Hth[k] = k < 2 ? lf : lt;
-          jp[b.jBAL + k * B + l] = Jb[k];
-          jp[b.jTH + k * B + l] = Jt[k];
-          hp[b.hTH + k * B + l] = Hth[k];
+          for (int k = 0; k < 4; ++k) vk[k] = vp[b.cFLOW + k * B + l];
         }
-        Ja0 = 1.0;
-        Ja1 = -1.0;
-        jp[b.jANG + l] = Ja0;
-        jp[b.jANG + B + l] = Ja1;
       } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-#pragma unroll
-          for (int a = 0; a < 5; ++a) Jf[k][a] = jp[b.jFLOW + (int64_t)(k * 5 + a) * B + l];
-          Jb[k] = jp[b.jBAL + k * B + l];
-          Jt[k] = jp[b.jTH + k * B + l];
-          Hth[k] = hp[b.hTH + k * B + l];
-        }
-        Ja0 = jp[b.jANG + l];
-        Ja1 = jp[b.jANG + B + l];
+        for (int k = 0; k < 4; ++k) Jt[k] = jp[b.jTH + k * B + l];
       }
-      // bus-variable contributions: sum_k d_k J_k,a J_k,b + angle + H
+    }
 #pragma unroll
-      for (int a = 0; a < 10; ++a) q[a] = 0.0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        double hf[9];
+    for (int k = 0; k < 4; ++k) {
+      const int sb = I.krow[b.xFL + k * B + tl.e0], se = I.krow[b.xFL + k * B + tl.e1];
+      if (act) {
+        const int rs = I.krow[b.xFL + k * B + l] - sb, re = I.krow[b.xFL + k * B + l + 1] - sb;
+        double Jk[5], hf[9], Jbk, Hthk;
+        const double dfk = dp[b.cFLOW + k * B + l];
         if constexpr (FUSED) {
-          flow_kind(cf, k, vi, vj, vv, sn, cs, -lp[b.cFLOW + k * B + l], Jf[k], hf);
+          const double* lp = LAM + I.c_off + (int64_t)t * I.m_p;
+          flow_kind(cf, k, vi, vj, vv, sn, cs, -lp[b.cFLOW + k * B + l], Jk, hf);
           double* jq = jp + b.jFLOW + (int64_t)(k * 5) * B + l;
 #pragma unroll
-          for (int a = 0; a < 5; ++a) jq[a * B] = Jf[k][a];
+          for (int a = 0; a < 5; ++a) jq[a * B] = Jk[a];
           double* hq = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
 #pragma unroll
           for (int a = 0; a < 9; ++a) hq[a * B] = hf[a];
+          Jbk = -1.0;
+          Hthk = k < 2 ? lf : lt;
+          jp[b.jBAL + k * B + l] = Jbk;
+          jp[b.jTH + k * B + l] = Jt[k];
+          hp[b.hTH + k * B + l] = Hthk;
+          if (C) C[I.c_off + (int64_t)t * I.m_p + b.cFLOW + k * B + l] =
+              fl[k] - flow_value(cf, k, vi, vj, vv, flow_w(cf, k, sn, cs));
+          if (JTV) {
+            svi += vk[k] * Jk[1];
+            svj += vk[k] * Jk[2];
+            sti += vk[k] * Jk[3];
+          }
         } else {
+          const double* jq = jp + b.jFLOW + (int64_t)(k * 5) * B + l;
+#pragma unroll
+          for (int a = 0; a < 5; ++a) Jk[a] = jq[a * B];
           const double* hq = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
 #pragma unroll
           for (int a = 0; a < 9; ++a) hf[a] = hq[a * B];
+          Jbk = jp[b.jBAL + k * B + l];
+          Hthk = hp[b.hTH + k * B + l];
         }
-        const double a1 = Jf[k][1], a2 = Jf[k][2], a3 = Jf[k][3], a4 = Jf[k][4];
-        const double d1 = df[k] * a1, d2 = df[k] * a2, d3 = df[k] * a3, d4 = df[k] * a4;
-        // local H order: from end (0,0)(1,0)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3);
-        // to end (1,0)(1,1)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3)
+        // bus-variable contributions: d_k J_k,a J_k,b + H (local H order:
+        // from end (0,0)(1,0)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3); to end
+        // (1,0)(1,1)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3))
+        const double a1 = Jk[1], a2 = Jk[2], a3 = Jk[3], a4 = Jk[4];
+        const double d1 = dfk * a1, d2 = dfk * a2, d3 = dfk * a3, d4 = dfk * a4;
         if (k < 2) {
           q[0] += d1 * a1 + hf[0];
           q[6] += d2 * a2;
@@ -780,63 +780,23 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
         q[7] += d4 * a2 + hf[6];
         q[5] += d4 * a3 + hf[7];
         q[8] += d4 * a4 + hf[8];
-      }
-      q[2] += dang * Ja0 * Ja0;
-      q[8] += dang * Ja1 * Ja1;
-      q[5] += dang * Ja1 * Ja0;
-      if constexpr (FUSED) {
-        // the rest of the sweep on this line: its constraint rows, J^T v on
-        // its flow variables (bus sums through a hand-off record), gradient
-        const int64_t xo = I.x_off + (int64_t)t * I.n_p;
-        if (C) {
-          double* cp = C + I.c_off + (int64_t)t * I.m_p;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            cp[b.cFLOW + k * B + l] = fl[k] - flow_value(cf, k, vi, vj, vv, flow_w(cf, k, sn, cs));
-          cp[b.cTHF + l] = fl[0] * fl[0] + fl[1] * fl[1];
-          cp[b.cTHT + l] = fl[2] * fl[2] + fl[3] * fl[3];
-          cp[b.cANG + l] = ti - tj;
-        }
-        if (JTV) {
-          const double* vp = V + I.c_off + (int64_t)t * I.m_p;
-          double vk[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) vk[k] = vp[b.cFLOW + k * B + l];
-          const double vbal[4] = {vp[i], vp[N + i], vp[j], vp[N + j]};
-          double o4[4], rj[4];
-          jt_line(vk, Jf, vp[b.cTHF + l], vp[b.cTHT + l], vp[b.cANG + l], fl, vbal, o4, rj);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) JTV[xo + b.xFL + k * B + l] = o4[k];
-          double* r = scr + I.s_off + (int64_t)kScratchKkt * I.B * I.T + ((int64_t)t * B + l) * kScratchJt;
-#pragma unroll
-          for (int a = 0; a < 4; ++a) r[a] = rj[a];
-        }
-        if (GR) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) GR[xo + b.xFL + k * B + l] = 0.0;
-        }
-      }
-    }
-    // flow-variable rows, one kind at a time through LDS
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (act) {
-        const double pk = df[k] * Jf[k][0];
-        double* row = seg + rs[k];
+        // this kind's K row into the LDS copy of the block's row segment
+        const double pk = dfk * Jk[0];
+        double* row = seg + rs;
         if (ilo) {
-          row[0] = pk * Jf[k][1];
-          row[1] = pk * Jf[k][2];
-          row[2] = pk * Jf[k][3];
-          row[3] = pk * Jf[k][4];
+          row[0] = pk * Jk[1];
+          row[1] = pk * Jk[2];
+          row[2] = pk * Jk[3];
+          row[3] = pk * Jk[4];
         } else {
-          row[0] = pk * Jf[k][2];
-          row[1] = pk * Jf[k][1];
-          row[2] = pk * Jf[k][4];
-          row[3] = pk * Jf[k][3];
+          row[0] = pk * Jk[2];
+          row[1] = pk * Jk[1];
+          row[2] = pk * Jk[4];
+          row[3] = pk * Jk[3];
         }
-        const double pb = dbal[k] * Jb[k];
-        for (int p = rs[k] + 4; p < re[k] - 1; ++p) {
-          const int src = I.ksrc[sb[k] + p];
+        const double pb = dbal[k] * Jbk;
+        for (int p = rs + 4; p < re - 1; ++p) {
+          const int src = I.ksrc[sb + p];
           double v;
           if ((k & 1) && src < 0) {
             v = dth[k >> 1] * Jt[k ^ 1] * Jt[k];  // thermal partner
@@ -847,26 +807,72 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
           }
           seg[p] = v;
         }
-        const double dxv = DX ? DX[I.x_off + (int64_t)t * I.n_p + b.xFL + k * B + l] : 0.0;
-        seg[re[k] - 1] = dxv + pk * Jf[k][0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jb[k] + Hth[k];
+        const double dxv = DX ? DX[xo + b.xFL + k * B + l] : 0.0;
+        seg[re - 1] = dxv + pk * Jk[0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jbk + Hthk;
       }
       __syncthreads();
-      stream_segment<!FUSED>(seg, I.ksrc + sb[k], jp, kb + sb[k], se[k] - sb[k]);
+      stream_segment<!FUSED>(seg, I.ksrc + sb, jp, kb + sb, se - sb);
       __syncthreads();
     }
-    // hand-off records through the (now free) segment buffer
     if (act) {
+      const double dang = dp[b.cANG + l];
+      double Ja0, Ja1;
+      if constexpr (FUSED) {
+        Ja0 = 1.0;
+        Ja1 = -1.0;
+        jp[b.jANG + l] = Ja0;
+        jp[b.jANG + B + l] = Ja1;
+      } else {
+        Ja0 = jp[b.jANG + l];
+        Ja1 = jp[b.jANG + B + l];
+      }
+      q[2] += dang * Ja0 * Ja0;
+      q[8] += dang * Ja1 * Ja1;
+      q[5] += dang * Ja1 * Ja0;
+      double pfl[4] = {0.0, 0.0, 0.0, 0.0}, jtr[4] = {0.0, 0.0, 0.0, 0.0};
+      if constexpr (FUSED) {
+        if (C) {
+          double* cp = C + I.c_off + (int64_t)t * I.m_p;
+          cp[b.cTHF + l] = fl[0] * fl[0] + fl[1] * fl[1];
+          cp[b.cTHT + l] = fl[2] * fl[2] + fl[3] * fl[3];
+          cp[b.cANG + l] = ti - tj;
+        }
 #pragma unroll
-      for (int a = 0; a < kScratchKkt; ++a) seg[tid * kScratchKkt + a] = q[a];
+        for (int k = 0; k < 4; ++k) pfl[k] = fl[k];
+        if (JTV) {
+          const double* vp = V + I.c_off + (int64_t)t * I.m_p;
+          const double vtf = vp[b.cTHF + l], vtt = vp[b.cTHT + l], vang = vp[b.cANG + l];
+          const double vbal[4] = {vp[i], vp[N + i], vp[j], vp[N + j]};
+          JTV[xo + b.xFL + l] = vk[0] + vtf * (2.0 * fl[0]) - vbal[0];
+          JTV[xo + b.xFL + B + l] = vk[1] + vtf * (2.0 * fl[1]) - vbal[1];
+          JTV[xo + b.xFL + 2 * B + l] = vk[2] + vtt * (2.0 * fl[2]) - vbal[2];
+          JTV[xo + b.xFL + 3 * B + l] = vk[3] + vtt * (2.0 * fl[3]) - vbal[3];
+          jtr[0] = svi;
+          jtr[1] = sti + vang;
+          jtr[2] = svj;
+          jtr[3] = -sti - vang;
+        }
+        if (GR) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) GR[xo + b.xFL + k * B + l] = 0.0;
+        }
+      }
+      // hand-off: one 64-byte record per line end, the shared cross pair
+      double2* ri = reinterpret_cast<double2*>(rec_at(I, scr, t) + (int64_t)l * kRecLine);
+      ri[0] = make_double2(q[0], q[1]);
+      ri[1] = make_double2(q[2], q[3]);
+      ri[2] = make_double2(pfl[0], pfl[1]);
+      ri[3] = make_double2(jtr[0], jtr[1]);
+      ri[4] = make_double2(q[6], q[7]);
+      ri[5] = make_double2(q[8], q[9]);
+      ri[6] = make_double2(pfl[2], pfl[3]);
+      ri[7] = make_double2(jtr[2], jtr[3]);
+      reinterpret_cast<double2*>(shared_at(I, scr, t))[l] = make_double2(q[4], q[5]);
     }
-    __syncthreads();
-    double* dst = scr + I.s_off + ((int64_t)t * B + tl.e0) * kScratchKkt;
-    for (int p = tid; p < nl * kScratchKkt; p += (int)blockDim.x) dst[p] = seg[p];
-    __syncthreads();
   }
 }
 
-// Dynamic LDS: seg[max(cap_seg, blockDim * 10)] doubles.
+// Dynamic LDS: seg[cap_seg] doubles (the longest K row segment of a tile).
 __global__ void __launch_bounds__(256) k_kkt_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
                                                int ntiles, int cap_seg, const double* __restrict__ H,
                                                const double* __restrict__ J, const double* __restrict__ DX,
@@ -970,8 +976,9 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
     double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
     if (act) {
       const int64_t xo = I.x_off + (int64_t)t * I.n_p;
-      const double* rs = scr + I.s_off + (int64_t)t * B * kScratchKkt;
-      const double* rj = scr + I.s_off + (int64_t)kScratchKkt * B * I.T + (int64_t)t * B * kScratchJt;
+      double* scr_m = const_cast<double*>(scr);
+      const double* rs = rec_at(I, scr_m, t);
+      const double2* sh = reinterpret_cast<const double2*>(shared_at(I, scr_m, t));
       const double* xp = SWEEP ? X + xo : nullptr;
       double svm_s = 0.0, svavm_s = 0.0, sva_s = 0.0;
       double cvm = 0.0, cvavm = 0.0, cva = 0.0;
@@ -986,9 +993,9 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
       int gi = 0, prev = -1;
       constexpr int U = 4;
       for (int aa = q0; aa < q1; aa += U) {
-        // issue the incidence loads and gathers of up to U ends together
+        // issue the incidence loads and record gathers of up to U ends together
         int ad[U], nb[U];
-        double r[U][6], fp[U], fq[U], j0[U], j1[U];
+        double2 r[U][4], x2[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const bool ok = aa + u < q1;
@@ -999,17 +1006,11 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
         for (int u = 0; u < U; ++u) {
           const bool ok = nb[u] >= 0;
           const int64_t l = ad[u] >> 1;
-          const int e = ad[u] & 1;
-          const double* rp = rs + l * kScratchKkt + 4 * e;
+          const double2* rp = reinterpret_cast<const double2*>(rs + l * kRecLine + (ad[u] & 1) * kRecEnd);
+          const int w1 = SWEEP ? 4 : 2;
 #pragma unroll
-          for (int w = 0; w < 6; ++w) r[u][w] = ok ? rp[w] : 0.0;
-          if (SWEEP) {
-            const int64_t kp = e ? 2 : 0;
-            fp[u] = ok ? xp[xFL + kp * B + l] : 0.0;
-            fq[u] = ok ? xp[xFL + (kp + 1) * B + l] : 0.0;
-            j0[u] = ok ? rj[l * kScratchJt + (e ? 1 : 0)] : 0.0;
-            j1[u] = ok ? rj[l * kScratchJt + (e ? 3 : 2)] : 0.0;
-          }
+          for (int w = 0; w < 4; ++w) r[u][w] = (ok && w < w1) ? rp[w] : make_double2(0.0, 0.0);
+          x2[u] = (ok && nb[u] < n) ? sh[l] : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1027,20 +1028,17 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
             cvm = cvavm = cva = 0.0;
           }
           prev = m;
-          // own-end values at [0,4) of end i's window, [2,6) of end j's;
-          // the shared cross pair at [4,6) for end i, [0,2) for end j
-          const bool ej = ad[u] & 1;
-          svm_s += ej ? r[u][2] : r[u][0];
-          svavm_s += ej ? r[u][3] : r[u][1];
-          sva_s += ej ? r[u][4] : r[u][2];
-          cvavm += ej ? r[u][5] : r[u][3];
-          cvm += ej ? r[u][0] : r[u][4];
-          cva += ej ? r[u][1] : r[u][5];
+          svm_s += r[u][0].x;
+          svavm_s += r[u][0].y;
+          sva_s += r[u][1].x;
+          cvavm += r[u][1].y;
+          cvm += x2[u].x;
+          cva += x2[u].y;
           if (SWEEP) {
-            bp -= fp[u];
-            bq -= fq[u];
-            jvm += j0[u];
-            jva += j1[u];
+            bp -= r[u][2].x;
+            bq -= r[u][2].y;
+            jvm += r[u][3].x;
+            jva += r[u][3].y;
           }
         }
       }

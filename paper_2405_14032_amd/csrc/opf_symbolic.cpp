@@ -310,7 +310,9 @@ int assign_offsets(std::vector<InstHost>& insts, std::string& err) {
     ho += I.nnzh;
     ko += I.nnzk;
     lo += (int64_t)I.T * I.N;
-    so += 14LL * I.B * I.T;  // 10 (condensed hand-off) + 4 (J^T v hand-off) per line-period
+    // hand-off scratch: 22 doubles per line-period (two 8-value end records,
+    // the shared cross pair, the separate J^T v record), rounded up to 64 B
+    so += (22LL * I.B * I.T + 7) / 8 * 8;
   }
   if (xo > kI32Max || co > kI32Max) {
     err = "total variables / rows exceed int32 indices";
