@@ -551,3 +551,136 @@ def hessian_dense(n, hess):
     H = np.zeros((n, n))
     np.add.at(H, (hr, hc), hv)
     return H + np.tril(H, -1).T
+
+
+# ----------------------------------------------------------------------------
+# lifted-KKT condensation: right-hand side and step recovery (Sec. III-B)
+# ----------------------------------------------------------------------------
+def jprod(net, x, v, with_mag=False):
+    """J v by a COO sparse product over this module's own Jacobian (the
+    A dx term of the step recovery)."""
+    import scipy.sparse as sp
+    L = Layout(net)
+    rows, cols, vals, mags = jacobian(net, x, with_mag=True)
+    J = sp.coo_matrix((vals, (rows, cols)), shape=(L.m, L.n))
+    out = J @ np.asarray(v, dtype=np.float64)
+    if with_mag:
+        Jm = sp.coo_matrix((mags, (rows, cols)), shape=(L.m, L.n))
+        return out, Jm @ np.abs(v)
+    return out
+
+
+def _bound_terms(val, lo, hi, zlo, zhi, mu):
+    """Barrier terms of the box lo <= val <= hi, entry by entry.
+
+    Returns (sigma, p_lo, p_hi, gap_lo, gap_hi, has_lo, has_hi):
+    sigma = Z_lo (val - lo)^-1 + Z_hi (hi - val)^-1 (Sigma_x / Sigma_s of
+    Sec. III-B), p_lo = Z_lo (val - lo) - mu and p_hi = Z_hi (hi - val) - mu
+    (the complementarity residuals; reading: the paper prints two of the four
+    with the wrong variable, each is read as the residual of its own bound).
+    An infinite bound has no multiplier and contributes nothing (the limit
+    of every term as the bound goes to infinity with its multiplier at 0)."""
+    has_lo, has_hi = np.isfinite(lo), np.isfinite(hi)
+    gap_lo = np.where(has_lo, val - np.where(has_lo, lo, 0.0), 1.0)
+    gap_hi = np.where(has_hi, np.where(has_hi, hi, 0.0) - val, 1.0)
+    zlo = np.where(has_lo, zlo, 0.0)
+    zhi = np.where(has_hi, zhi, 0.0)
+    sigma = zlo / gap_lo + zhi / gap_hi
+    p_lo = np.where(has_lo, zlo * gap_lo - mu, 0.0)
+    p_hi = np.where(has_hi, zhi * gap_hi - mu, 0.0)
+    return sigma, p_lo, p_hi, gap_lo, gap_hi, has_lo, has_hi
+
+
+def _row_terms(st, c):
+    """Row-space quantities of Sec. III-B: Sigma_s, q_s, q_y = p_y, C, D and
+    the slack-bound residuals.  p_s = -z_s_lo + z_s_hi + y, p_y = g(x) - s,
+    q_s = p_s + (S - S_lo)^-1 p_lo - (S_hi - S)^-1 p_hi,
+    C = (delta_c Sigma_s + (1 + delta_c delta_w) I)^-1,
+    D = (Sigma_s + delta_w I) C."""
+    sig_s, p_lo, p_hi, g_lo, g_hi, h_lo, h_hi = _bound_terms(st.s, st.sl, st.su, st.vl, st.vu, st.mu)
+    vl = np.where(h_lo, st.vl, 0.0)
+    vu = np.where(h_hi, st.vu, 0.0)
+    p_s = -vl + vu + st.y
+    p_y = np.asarray(c) - st.s
+    q_s = p_s + np.where(h_lo, p_lo / g_lo, 0.0) - np.where(h_hi, p_hi / g_hi, 0.0)
+    C = 1.0 / (st.delta_c * sig_s + (1.0 + st.delta_c * st.delta_w))
+    D = (sig_s + st.delta_w) * C
+    return dict(sig_s=sig_s, p_lo=p_lo, p_hi=p_hi, g_lo=g_lo, g_hi=g_hi, h_lo=h_lo, h_hi=h_hi, vl=vl, vu=vu,
+                p_s=p_s, p_y=p_y, q_s=q_s, C=C, D=D)
+
+
+def _row_terms_mag(st, c, R):
+    """Cancellation scales of q_s and p_y (every term by its absolute value)."""
+    ps_m = np.abs(R["vl"]) + np.abs(R["vu"]) + np.abs(st.y)
+    plo_m = np.where(R["h_lo"], np.abs(R["vl"] * R["g_lo"]) + st.mu, 0.0)
+    phi_m = np.where(R["h_hi"], np.abs(R["vu"] * R["g_hi"]) + st.mu, 0.0)
+    qs_m = ps_m + plo_m / R["g_lo"] + phi_m / R["g_hi"]
+    py_m = np.abs(np.asarray(c)) + np.abs(st.s)
+    return qs_m, py_m, plo_m, phi_m
+
+
+def condensed_rhs(net, st, grad, c, with_mag=False):
+    """The condensed system's diagonal weights and right-hand side (Sec.
+    III-B): diag_x = delta_w + Sigma_x, dcon = D and
+    rhs = q_x + A^T (C q_s + D q_y), with p_x = grad f - A^T y - z_lo + z_hi
+    and q_x = p_x + (X - X_lo)^-1 p_lo - (X_hi - X)^-1 p_hi.
+    grad = grad f(x) and c = g(x) at st.x.  With ``with_mag`` also returns the
+    cancellation scale of each rhs entry."""
+    sig_x, pz_lo, pz_hi, gx_lo, gx_hi, hx_lo, hx_hi = _bound_terms(st.x, st.xl, st.xu, st.zl, st.zu, st.mu)
+    zl = np.where(hx_lo, st.zl, 0.0)
+    zu = np.where(hx_hi, st.zu, 0.0)
+    R = _row_terms(st, c)
+    jty, jty_m = jtprod(net, st.x, st.y, with_mag=True)
+    p_x = np.asarray(grad) - jty - zl + zu
+    q_x = p_x + np.where(hx_lo, pz_lo / gx_lo, 0.0) - np.where(hx_hi, pz_hi / gx_hi, 0.0)
+    w = R["C"] * R["q_s"] + R["D"] * R["p_y"]
+    jtw, jtw_m = jtprod(net, st.x, w, with_mag=True)
+    rhs = q_x + jtw
+    diag_x = st.delta_w + sig_x
+    if not with_mag:
+        return diag_x, R["D"], rhs
+    qs_m, py_m, _, _ = _row_terms_mag(st, c, R)
+    w_m = R["C"] * qs_m + R["D"] * py_m
+    _, jtw_m = jtprod(net, st.x, w_m, with_mag=True)
+    pzl_m = np.where(hx_lo, np.abs(zl * gx_lo) + st.mu, 0.0)
+    pzu_m = np.where(hx_hi, np.abs(zu * gx_hi) + st.mu, 0.0)
+    qx_m = np.abs(grad) + jty_m + np.abs(zl) + np.abs(zu) + pzl_m / gx_lo + pzu_m / gx_hi
+    return diag_x, R["D"], rhs, qx_m + jtw_m
+
+
+def recover_step(net, st, c, dx, with_mag=False):
+    """Slack, multiplier and bound-multiplier steps from the condensed
+    solution dx (Sec. III-B):
+      ds  = C (A dx + delta_c q_s - q_y)   (reading: the printed formula
+            carries A dx with the opposite sign, which contradicts the
+            condensed system it comes from; eliminating the third block row
+            of the full system gives this sign),
+      dy  = (Sigma_s + delta_w I) ds - q_s,
+      dz_lo = (X - X_lo)^-1 (-Z_lo dx + p_lo),  dz_hi = (X_hi - X)^-1 (Z_hi dx + p_hi),
+      and the same for the slack bounds with ds.
+    Returns (ds, dy, dzl, dzu, dvl, dvu)[, and their cancellation scales]."""
+    _, pz_lo, pz_hi, gx_lo, gx_hi, hx_lo, hx_hi = _bound_terms(st.x, st.xl, st.xu, st.zl, st.zu, st.mu)
+    zl = np.where(hx_lo, st.zl, 0.0)
+    zu = np.where(hx_hi, st.zu, 0.0)
+    R = _row_terms(st, c)
+    adx, adx_m = jprod(net, st.x, dx, with_mag=True)
+    dx = np.asarray(dx)
+    ds = R["C"] * (adx + st.delta_c * R["q_s"] - R["p_y"])
+    dy = (R["sig_s"] + st.delta_w) * ds - R["q_s"]
+    dzl = np.where(hx_lo, (-zl * dx + pz_lo) / gx_lo, 0.0)
+    dzu = np.where(hx_hi, (zu * dx + pz_hi) / gx_hi, 0.0)
+    dvl = np.where(R["h_lo"], (-R["vl"] * ds + R["p_lo"]) / R["g_lo"], 0.0)
+    dvu = np.where(R["h_hi"], (R["vu"] * ds + R["p_hi"]) / R["g_hi"], 0.0)
+    out = (ds, dy, dzl, dzu, dvl, dvu)
+    if not with_mag:
+        return out
+    qs_m, py_m, plo_m, phi_m = _row_terms_mag(st, c, R)
+    ds_m = R["C"] * (adx_m + st.delta_c * qs_m + py_m)
+    dy_m = (R["sig_s"] + st.delta_w) * ds_m + qs_m
+    pzl_m = np.where(hx_lo, np.abs(zl * gx_lo) + st.mu, 0.0)
+    pzu_m = np.where(hx_hi, np.abs(zu * gx_hi) + st.mu, 0.0)
+    dzl_m = (np.abs(zl * dx) + pzl_m) / gx_lo
+    dzu_m = (np.abs(zu * dx) + pzu_m) / gx_hi
+    dvl_m = (np.abs(R["vl"]) * ds_m + plo_m) / R["g_lo"]
+    dvu_m = (np.abs(R["vu"]) * ds_m + phi_m) / R["g_hi"]
+    return out, (ds_m, dy_m, dzl_m, dzu_m, dvl_m, dvu_m)

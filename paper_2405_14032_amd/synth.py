@@ -207,3 +207,60 @@ def make_point(net: Network, seed: int, stress: bool = False) -> Point:
     diag_x = 10.0 ** rng.uniform(-4.0, 4.0, net.n)
     dcon = 10.0 ** rng.uniform(-4.0, 4.0, net.m)
     return Point(np.ascontiguousarray(x), lam, 1.0, diag_x, dcon)
+
+
+@dataclass
+class IpmState:
+    """An iterate of the lifted interior-point method: primal x, slacks s of
+    the relaxed rows c(x) - s = 0, multipliers y of those rows, bound
+    multipliers (zl, zu of x, vl, vu of s), the bounds themselves (+-inf =
+    absent), the barrier parameter and the two regularisations."""
+
+    x: np.ndarray
+    s: np.ndarray
+    y: np.ndarray
+    zl: np.ndarray
+    zu: np.ndarray
+    vl: np.ndarray
+    vu: np.ndarray
+    xl: np.ndarray
+    xu: np.ndarray
+    sl: np.ndarray
+    su: np.ndarray
+    mu: float
+    delta_w: float
+    delta_c: float
+
+
+def _interior(rng, lo, hi):
+    """One value strictly inside each [lo, hi] (either side may be infinite)."""
+    fl, fu = np.isfinite(lo), np.isfinite(hi)
+    u = rng.uniform(0.05, 0.95, lo.shape)
+    e = np.exp(rng.uniform(-3.0, 1.0, lo.shape))
+    z = rng.standard_normal(lo.shape)
+    out = np.where(fl & fu, np.where(fl & fu, lo, 0.0) + u * np.where(fl & fu, hi - lo, 0.0), z)
+    out = np.where(fl & ~fu, np.where(fl, lo, 0.0) + e, out)
+    out = np.where(~fl & fu, np.where(fu, hi, 0.0) - e, out)
+    return out
+
+
+def make_ipm_state(xl, xu, cl, cu, seed: int, eps: float = 1e-4) -> IpmState:
+    """Draw an interior iterate for the given variable and row bounds.
+
+    Slack bounds are the row bounds with equality rows widened to +-eps (the
+    relaxation width is the solver's choice); x and s lie strictly inside
+    their bounds (free entries ~ N(0, 1)); each multiplier of a finite bound
+    is log-uniform on [1e-3, 1e1], 0 where the bound is absent; y ~ N(0, 1);
+    mu = 0.1, delta_w = 1e-4, delta_c = 1e-6."""
+    rng = np.random.default_rng(20_000 + seed)
+    xl, xu = np.asarray(xl, dtype=np.float64), np.asarray(xu, dtype=np.float64)
+    cl, cu = np.asarray(cl, dtype=np.float64), np.asarray(cu, dtype=np.float64)
+    eq = cl == cu
+    sl = np.where(eq, cl - eps, cl)
+    su = np.where(eq, cu + eps, cu)
+    x = _interior(rng, xl, xu)
+    s = _interior(rng, sl, su)
+    mult = lambda b: np.where(np.isfinite(b), 10.0 ** rng.uniform(-3.0, 1.0, b.shape), 0.0)
+    zl, zu, vl, vu = mult(xl), mult(xu), mult(sl), mult(su)
+    y = rng.standard_normal(cl.shape)
+    return IpmState(x, s, y, zl, zu, vl, vu, xl, xu, sl, su, 0.1, 1e-4, 1e-6)

@@ -405,3 +405,92 @@ def nnz_kkt_closed_form(net):
     k = deg + np.bincount(net.gen_bus, minlength=net.N)
     per = 3 * net.N + 2 * net.G + 26 * net.B + int(np.sum(k * (k - 1)))
     return net.T * per + net.G * (net.T - 1)
+
+
+# ---------------------------------------------------------------- lifted KKT
+def ipm_case(N=6, B=8, G=2, T=3, seed=5):
+    net = synth.make_network(N, B, G, T, seed)
+    st = synth.make_ipm_state(*O.bounds(net), seed=seed)
+    return net, st
+
+
+def full_kkt_solution(net, st):
+    """Dense solve of the full lifted KKT system of Sec. III-B (seven block
+    rows: stationarity in x and s, the relaxed rows, four complementarity
+    blocks), assembled block by block from its printed layout, with one
+    multiplier per finite bound.  Returns (dx, ds, dy, dzl, dzu, dvl, dvu)
+    with the bound steps scattered to full length (0 where absent)."""
+    L = O.Layout(net)
+    n, m = L.n, L.m
+    x, s, y, mu, dw, dc = st.x, st.s, st.y, st.mu, st.delta_w, st.delta_c
+    A = dense_jac(net, x)
+    W = O.hessian_dense(n, O.hessian(net, x, -y, 1.0))  # W = Hess f - sum y_i Hess g_i
+    c = O.constraints(net, x)
+    grad = O.gradient(net, x)
+    hl, hu, gl, gu = (np.isfinite(b) for b in (st.xl, st.xu, st.sl, st.su))
+    Pl, Pu, Ql, Qu = np.eye(n)[hl], np.eye(n)[hu], np.eye(m)[gl], np.eye(m)[gu]
+    sizes = [n, m, m, int(hl.sum()), int(hu.sum()), int(gl.sum()), int(gu.sum())]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    M = np.zeros((off[-1], off[-1]))
+
+    def put(i, j, blk):
+        M[off[i]:off[i + 1], off[j]:off[j + 1]] += blk
+
+    zl, zu, vl, vu = st.zl[hl], st.zu[hu], st.vl[gl], st.vu[gu]
+    put(0, 0, W + dw * np.eye(n))
+    put(0, 2, A.T)
+    put(0, 3, -Pl.T)
+    put(0, 4, Pu.T)
+    put(1, 1, dw * np.eye(m))
+    put(1, 2, -np.eye(m))
+    put(1, 5, -Ql.T)
+    put(1, 6, Qu.T)
+    put(2, 0, A)
+    put(2, 1, -np.eye(m))
+    put(2, 2, -dc * np.eye(m))
+    put(3, 0, zl[:, None] * Pl)
+    put(3, 3, np.diag(x[hl] - st.xl[hl]))
+    put(4, 0, -zu[:, None] * Pu)
+    put(4, 4, np.diag(st.xu[hu] - x[hu]))
+    put(5, 1, vl[:, None] * Ql)
+    put(5, 5, np.diag(s[gl] - st.sl[gl]))
+    put(6, 1, -vu[:, None] * Qu)
+    put(6, 6, np.diag(st.su[gu] - s[gu]))
+    rhs = np.concatenate([
+        grad - A.T @ y - Pl.T @ zl + Pu.T @ zu,
+        -Ql.T @ vl + Qu.T @ vu + y,
+        c - s,
+        zl * (x[hl] - st.xl[hl]) - mu,
+        zu * (st.xu[hu] - x[hu]) - mu,
+        vl * (s[gl] - st.sl[gl]) - mu,
+        vu * (st.su[gu] - s[gu]) - mu,
+    ])
+    sol = np.linalg.solve(M, rhs)
+    blk = [sol[off[i]:off[i + 1]] for i in range(7)]
+    out = blk[:3]
+    for b, mask, size in ((blk[3], hl, n), (blk[4], hu, n), (blk[5], gl, m), (blk[6], gu, m)):
+        full = np.zeros(size)
+        full[mask] = b
+        out.append(full)
+    return out
+
+
+def check_lifted_kkt(net, st):
+    """Condense (oracle K with diag_x, D and the condensed right-hand side),
+    solve the condensed system densely, recover the other steps, and compare
+    every block with the full system's dense solution; returns the largest
+    block error relative to that block's max norm."""
+    L = O.Layout(net)
+    c = O.constraints(net, st.x)
+    grad = O.gradient(net, st.x)
+    diag_x, dcon, rhs = O.condensed_rhs(net, st, grad, c)
+    jac = O.jacobian(net, st.x)
+    hess = O.hessian(net, st.x, -st.y, 1.0)
+    rowptr, colind, vals, _ = O.condensed(L.n, jac, hess, diag_x, dcon)
+    K = np.zeros((L.n, L.n))
+    K[np.repeat(np.arange(L.n), np.diff(rowptr)), colind] = vals
+    K = K + np.tril(K, -1).T
+    dx = np.linalg.solve(K, rhs)
+    mine = [dx] + list(O.recover_step(net, st, c, dx))
+    ref = full_kkt_solution(net, st)
+    return max(float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b))))) for a, b in zip(mine, ref))

@@ -161,6 +161,43 @@ def test_bounds_layout():
     assert np.all(pt.x >= lv) and np.all(pt.x <= uv)
 
 
+def test_jprod_directional_derivative():
+    # J v against the central difference of c along v
+    net, pt = pins.tiny_case()
+    rng = np.random.default_rng(12)
+    v = rng.standard_normal(pt.x.size)
+    h = 1e-6
+    fd = (O.constraints(net, pt.x + h * v) - O.constraints(net, pt.x - h * v)) / (2 * h)
+    jv = O.jprod(net, pt.x, v)
+    assert np.max(np.abs(fd - jv) / (1 + np.abs(fd))) <= 1e-7
+
+
+@pytest.mark.parametrize("shape", [(6, 8, 2, 3, 5), (14, 20, 5, 4, 1)])
+def test_lifted_kkt_condense_and_recover_equals_full_system(shape):
+    # Sec. III-B: condensing, solving and recovering reproduces the dense
+    # solution of the full seven-block system
+    net, st = pins.ipm_case(*shape)
+    assert pins.check_lifted_kkt(net, st) <= 1e-8
+
+
+def test_lifted_kkt_degenerate_no_bounds():
+    # no finite bound and delta_c = 0: C = I, D = delta_w I, the recovered
+    # slack step is A dx - (c - s) and the multiplier step delta_w ds - y
+    net, st = pins.ipm_case()
+    inf = np.inf
+    st.xl[:], st.xu[:], st.sl[:], st.su[:] = -inf, inf, -inf, inf
+    st.delta_c = 0.0
+    c = O.constraints(net, st.x)
+    diag_x, dcon, rhs = O.condensed_rhs(net, st, O.gradient(net, st.x), c)
+    assert np.all(diag_x == st.delta_w) and np.all(dcon == st.delta_w)
+    dx = np.random.default_rng(2).standard_normal(st.x.size)
+    ds, dy, dzl, dzu, dvl, dvu = O.recover_step(net, st, c, dx)
+    J = pins.dense_jac(net, st.x)
+    assert np.allclose(ds, J @ dx - (c - st.s), rtol=1e-13, atol=1e-13)
+    assert np.allclose(dy, st.delta_w * ds - st.y, rtol=1e-13, atol=1e-13)
+    assert not (dzl.any() or dzu.any() or dvl.any() or dvu.any())
+
+
 # ------------------------------------------------------------------ planted
 # Mistakes planted in the oracle (on the CPU) must be caught by the pins.
 def _mutate(monkeypatch, name, fn):
@@ -241,3 +278,43 @@ def test_planted_transposed_condensation(monkeypatch):
     _mutate(monkeypatch, "condensed", bad)
     net, pt = pins.tiny_case()
     assert pins.check_condensed_dense(net, pt) > 1e-3
+
+
+def test_planted_printed_recovery_sign(monkeypatch):
+    # the slack recovery with A dx taken at the printed sign disagrees with
+    # the full system
+    orig = O.jprod
+
+    def bad(net, x, v, with_mag=False):
+        r = orig(net, x, v, with_mag)
+        return (-r[0], r[1]) if with_mag else -r
+
+    _mutate(monkeypatch, "jprod", bad)
+    net, st = pins.ipm_case()
+    assert pins.check_lifted_kkt(net, st) > 1e-3
+
+
+def test_planted_bound_residual_sign(monkeypatch):
+    orig = O._bound_terms
+
+    def bad(val, lo, hi, zlo, zhi, mu):
+        sig, plo, phi, glo, ghi, hlo, hhi = orig(val, lo, hi, zlo, zhi, mu)
+        return sig, -plo, phi, glo, ghi, hlo, hhi
+
+    _mutate(monkeypatch, "_bound_terms", bad)
+    net, st = pins.ipm_case()
+    assert pins.check_lifted_kkt(net, st) > 1e-3
+
+
+def test_planted_missing_slack_weight(monkeypatch):
+    # D without the C factor
+    orig = O._row_terms
+
+    def bad(st, c):
+        R = orig(st, c)
+        R["D"] = R["sig_s"] + st.delta_w
+        return R
+
+    _mutate(monkeypatch, "_row_terms", bad)
+    net, st = pins.ipm_case()
+    assert pins.check_lifted_kkt(net, st) > 1e-3
