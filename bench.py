@@ -48,6 +48,13 @@ def call_bytes(net, model):
         # fused J + H + K: x (vm, va, flows), 6 multipliers per line-period,
         # c2, row weights, diagonal in; J, H, K out
         "jhk": 8 * (2 * N * T + 4 * B * T + 6 * B * T + G + m + n + nj + nh + nk),
+        # lifted-KKT calls: x (vm, va, flows) and v in, J v out
+        "jprod": 8 * (2 * N * T + 4 * B * T + n + m),
+        # x, its bounds and multipliers, grad; s, y, slack bounds and
+        # multipliers, c; diag_x, dcon, rhs out
+        "condensed_rhs": 8 * (8 * n + 8 * m),
+        # the same state and dx in; ds, dy, dvl, dvu, dzl, dzu out
+        "recover_step": 8 * (8 * n + 11 * m),
     }
 
 
@@ -171,6 +178,22 @@ def bench_plain(torch, dev, args):
         "condensed": lambda: M.assemble_condensed(out["hvals"], out["jvals"], DX, D, out["kvals"]),
         "jhk": lambda: M.eval_jhk(X, LAM, pt.sigma, DX, D, out["jvals"], out["hvals"], out["kvals"]),
     }
+    # lifted-KKT calls around K (Sec. III-B) on one interior iterate inside
+    # the model's bounds
+    bnd = [torch.empty(k, dtype=torch.float64, device=dev) for k in (M.n, M.n, M.m, M.m)]
+    M.bounds(*bnd)
+    sh = synth.make_ipm_state(*(b.cpu().numpy() for b in bnd), seed=3)
+    del bnd
+    tt = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    keep = {f: tt(getattr(sh, f)) for f in ("x", "s", "y", "zl", "zu", "vl", "vu", "xl", "xu", "sl", "su")}
+    st = M.ipm_state(**keep, mu=sh.mu, delta_w=sh.delta_w, delta_c=sh.delta_c)
+    del sh
+    e = lambda k: torch.empty(k, dtype=torch.float64, device=dev)
+    rhs, jvo, dxo, dco = e(M.n), e(M.m), e(M.n), e(M.m)
+    rec = [e(M.m), e(M.m), e(M.n), e(M.n), e(M.m), e(M.m)]
+    calls["jprod"] = lambda: M.jprod(keep["x"], X, jvo)
+    calls["condensed_rhs"] = lambda: M.condensed_rhs(st, out["grad"], out["c"], dxo, dco, rhs)
+    calls["recover_step"] = lambda: M.recover_step(st, out["c"], rhs, *rec)
     per = {}
     for name, fn in calls.items():
         t = event_time(torch, fn, args.call_reps)

@@ -192,6 +192,60 @@ int opf_assemble_condensed(opf_model *model, const double *hvals,
                            const double *jvals, const double *diag_x,
                            const double *dcon, double *kvals);
 
+/* ---- lifted-KKT condensation around the condensed matrix (Sec. III-B) ----
+ *
+ * One iterate of the lifted interior-point method: the rows are relaxed to
+ * c(x) - s = 0 with sl <= s <= su (equality rows get a small band chosen by
+ * the solver), and the variables keep xl <= x <= xu.  All arrays are device
+ * pointers over the concatenated instances; a bound of +-inf is absent (its
+ * multiplier entry is ignored and every term of that bound vanishes).  The
+ * caller owns every array; none is retained. */
+typedef struct {
+  const double *x;         /* [n] primal point (strictly inside finite bounds) */
+  const double *s;         /* [m] slacks (strictly inside finite bounds) */
+  const double *y;         /* [m] multipliers of c(x) - s = 0 (the paper's y) */
+  const double *zl, *zu;   /* [n] multipliers of x >= xl and x <= xu (>= 0) */
+  const double *vl, *vu;   /* [m] multipliers of s >= sl and s <= su (>= 0) */
+  const double *xl, *xu;   /* [n] variable bounds */
+  const double *sl, *su;   /* [m] slack bounds */
+  double mu;               /* barrier parameter (>= 0) */
+  double delta_w, delta_c; /* primal and dual regularisation (>= 0) */
+} opf_ipm_state;
+
+/* Forward product J(x) v: the A dx term of the step recovery.  [m] */
+int opf_jprod(opf_model *model, const double *x, const double *v, double *jv);
+
+/* The condensed system's weights and right-hand side (Sec. III-B):
+ *   diag_x = delta_w + Sigma_x,  Sigma_x = Zl (X - Xl)^-1 + Zu (Xu - X)^-1,
+ *   dcon   = D = (Sigma_s + delta_w) C,
+ *            C = (delta_c Sigma_s + (1 + delta_c delta_w))^-1,
+ *   rhs    = q_x + J^T (C q_s + D q_y),
+ * with p_x = grad - J^T y - zl + zu, p_s = -vl + vu + y, q_y = c - s,
+ * q_x = p_x + (X - Xl)^-1 p_zl - (Xu - X)^-1 p_zu and the same for q_s, and
+ * the complementarity residuals p_zl = zl (x - xl) - mu,
+ * p_zu = zu (xu - x) - mu (likewise for s).  grad = grad f(x) [n] and
+ * c = c(x) [m] as produced by opf_eval_grad / opf_eval_cons at st->x.
+ * Outputs: diag_x [n], dcon [m], rhs [n]; they feed opf_assemble_condensed
+ * and the solve of K dx = rhs.  Outputs must not alias inputs.  Uses the
+ * model's work vector: calls on one model must not overlap. */
+int opf_condensed_rhs(opf_model *model, const opf_ipm_state *st,
+                      const double *grad, const double *c, double *diag_x,
+                      double *dcon, double *rhs);
+
+/* Recovery of the other step components from the condensed solution dx
+ * (Sec. III-B):
+ *   ds  = C (J dx + delta_c q_s - q_y),  dy = (Sigma_s + delta_w) ds - q_s,
+ *   dzl = (X - Xl)^-1 (-zl dx + p_zl),   dzu = (Xu - X)^-1 (zu dx + p_zu),
+ *   dvl = (S - Sl)^-1 (-vl ds + p_vl),   dvu = (Su - S)^-1 (vu ds + p_vu),
+ * (the slack step takes +J dx: eliminating the relaxed rows of the full
+ * system gives that sign; the paper's printed formula has the other one);
+ * entries of absent bounds are 0.  c = c(x) [m]; outputs ds, dy, dvl, dvu
+ * [m] and dzl, dzu [n], none aliasing an input.  Uses the model's work
+ * vector. */
+int opf_recover_step(opf_model *model, const opf_ipm_state *st,
+                     const double *c, const double *dx, double *ds, double *dy,
+                     double *dzl, double *dzu, double *dvl, double *dvu);
+
 /* Jacobian, Hessian and condensed matrix in one pass over x: the values of
  * opf_eval_jac, opf_eval_hess and opf_assemble_condensed (bitwise identical
  * to those three calls), with K built from the J / H values while they are

@@ -65,6 +65,13 @@ class opf_sweep_args(C.Structure):
                 ("kvals", C.c_void_p)]
 
 
+class opf_ipm_state(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("s", C.c_void_p), ("y", C.c_void_p),
+                ("zl", C.c_void_p), ("zu", C.c_void_p), ("vl", C.c_void_p), ("vu", C.c_void_p),
+                ("xl", C.c_void_p), ("xu", C.c_void_p), ("sl", C.c_void_p), ("su", C.c_void_p),
+                ("mu", C.c_double), ("delta_w", C.c_double), ("delta_c", C.c_double)]
+
+
 _vp = C.c_void_p
 _SIGS = {
     "opf_validate": (C.c_int, [C.POINTER(opf_instance_desc), C.c_int32]),
@@ -89,6 +96,9 @@ _SIGS = {
     "opf_eval_jhk": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _vp, _vp, _vp, _vp]),
     "opf_sweep": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
     "opf_sweep_graph": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
+    "opf_jprod": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "opf_condensed_rhs": (C.c_int, [_vp, C.POINTER(opf_ipm_state), _vp, _vp, _vp, _vp, _vp]),
+    "opf_recover_step": (C.c_int, [_vp, C.POINTER(opf_ipm_state), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "opf_autotune": (C.c_int, [_vp, C.c_char_p]),
     "opf_set_timing": (C.c_int, [_vp, C.c_int]),
     "opf_kernel_stats": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
@@ -266,6 +276,28 @@ class Model:
     def eval_jhk(self, x, lam, sigma, diag_x, dcon, jv, hv, kv):
         check(opf_eval_jhk(self.h, _ptr(x), _ptr(lam), float(sigma), _ptr(diag_x), _ptr(dcon), _ptr(jv),
                            _ptr(hv), _ptr(kv)), "opf_eval_jhk")
+
+    def jprod(self, x, v, out):
+        check(opf_jprod(self.h, _ptr(x), _ptr(v), _ptr(out)), "opf_jprod")
+
+    @staticmethod
+    def ipm_state(x, s, y, zl, zu, vl, vu, xl, xu, sl, su, mu, delta_w, delta_c) -> opf_ipm_state:
+        """The C state struct over device tensors (the tensors must outlive
+        the calls that use it)."""
+        st = opf_ipm_state()
+        st.x, st.s, st.y = _ptr(x), _ptr(s), _ptr(y)
+        st.zl, st.zu, st.vl, st.vu = _ptr(zl), _ptr(zu), _ptr(vl), _ptr(vu)
+        st.xl, st.xu, st.sl, st.su = _ptr(xl), _ptr(xu), _ptr(sl), _ptr(su)
+        st.mu, st.delta_w, st.delta_c = float(mu), float(delta_w), float(delta_c)
+        return st
+
+    def condensed_rhs(self, st, grad, c, diag_x, dcon, rhs):
+        check(opf_condensed_rhs(self.h, C.byref(st), _ptr(grad), _ptr(c), _ptr(diag_x), _ptr(dcon), _ptr(rhs)),
+              "opf_condensed_rhs")
+
+    def recover_step(self, st, c, dx, ds, dy, dzl, dzu, dvl, dvu):
+        check(opf_recover_step(self.h, C.byref(st), _ptr(c), _ptr(dx), _ptr(ds), _ptr(dy), _ptr(dzl), _ptr(dzu),
+                               _ptr(dvl), _ptr(dvu)), "opf_recover_step")
 
     @staticmethod
     def sweep_args(x=None, lam=None, sigma=1.0, v=None, diag_x=None, dcon=None, f=None, grad=None, c=None,

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -54,12 +55,18 @@ enum Op {
   OP_JHKA,
   OP_SWA,
   OP_SWB,
+  OP_JV,
+  OP_RHSR,  // flat element-wise kernels (no tile list; timing ids only)
+  OP_RHSV,
+  OP_RECR,
+  OP_RECV,
   OP_COUNT
 };
 
 const char* kOpName[OP_COUNT] = {"jac", "hess", "cons", "grad", "obj", "jt_a", "jt_b",
                                  "kkt_a", "kkt_b", "jac_struct", "hess_struct", "kkt_struct",
-                                 "bounds", "load_adjoint", "jhk_a", "sweep_a", "sweep_b"};
+                                 "bounds", "load_adjoint", "jhk_a", "sweep_a", "sweep_b", "jv",
+                                 "rhs_rows", "rhs_vars", "rec_rows", "rec_vars"};
 
 struct Shape {
   int block = 256;  // elements per tile = threads per block
@@ -93,6 +100,7 @@ struct opf_model {
   InstDev* d_inst = nullptr;
   std::vector<InstDev> h_dev;  // host mirror of d_inst
   double* scratch = nullptr;
+  double* wbuf = nullptr;  // [m]: row vector of the condensation calls
   double* obj_partial = nullptr;
   int obj_partial_cap = 0;
   int32_t* d_obj_begin = nullptr;
@@ -187,6 +195,7 @@ std::vector<int> kinds_of(int op) {
     case OP_HSTR:
       return {TK_BRANCH, TK_GEN};
     case OP_CONS:
+    case OP_JV:
       return {TK_BRANCH, TK_BUS, TK_GEN};
     case OP_GRAD:
       return {TK_VAR};
@@ -271,8 +280,10 @@ int lds_needs(const opf_model* M, int op, const std::vector<Tile>& tiles, const 
       cap2 = std::max<int>(cap2, I.krow[I.N + tl.e1] - I.krow[I.N + tl.e0]);
     }
   }
-  smem = line ? (size_t)cap * sizeof(double)
-               : ((size_t)cap + (size_t)cap2) * sizeof(double);
+  // the fused line kernels also keep each lane's eight admittances in LDS
+  const size_t adm = (op == OP_JHKA || op == OP_SWA) ? 8 * (size_t)s.block : 0;
+  smem = line ? ((size_t)cap + adm) * sizeof(double)
+              : ((size_t)cap + (size_t)cap2) * sizeof(double);
   if (smem > kMaxSmem) return fail(OPF_EINVAL, std::string("tile shape needs too much LDS for ") + kOpName[op]);
   return OPF_OK;
 }
@@ -492,6 +503,7 @@ void release(opf_model* M) {
       if (L.d) (void)hipFree(L.d);
     if (M->arena) (void)hipFree(M->arena);
     if (M->scratch) (void)hipFree(M->scratch);
+    if (M->wbuf) (void)hipFree(M->wbuf);
     if (M->obj_partial) (void)hipFree(M->obj_partial);
     if (M->d_obj_begin) (void)hipFree(M->d_obj_begin);
     if (M->cap_stream) (void)hipStreamDestroy(M->cap_stream);
@@ -683,6 +695,11 @@ int opf_model_create(const opf_instance_desc* desc, int32_t ninst, int device, o
       release(M);
       return fail(OPF_ENOMEM, "scratch allocation failed");
     }
+    if (hipMalloc(&M->wbuf, std::max<size_t>((size_t)M->m, 1) * sizeof(double)) != hipSuccess) {
+      M->wbuf = nullptr;
+      release(M);
+      return fail(OPF_ENOMEM, "work vector allocation failed");
+    }
     if (hipMalloc(&M->d_obj_begin, (ninst + 1) * sizeof(int32_t)) != hipSuccess) {
       M->d_obj_begin = nullptr;
       release(M);
@@ -860,6 +877,58 @@ int opf_load_adjoint(opf_model* M, const double* lam, double* gpd, double* gqd) 
   OPF_REQUIRE(lam && gpd && gqd, "lambda / gpd / gqd");
   DeviceGuard g(M->device);
   { TimerScope ts_(M, OP_LADJ); OPF_LAUNCHED(launch_load_adjoint(launch_of(M, OP_LADJ), lam, gpd, gqd), "load adjoint kernel"); }
+  return OPF_OK;
+}
+
+int opf_jprod(opf_model* M, const double* x, const double* v, double* jv) {
+  OPF_CHECK_MODEL(M);
+  OPF_REQUIRE(x && v && jv, "x / v / jv");
+  DeviceGuard g(M->device);
+  { TimerScope ts_(M, OP_JV); OPF_LAUNCHED(launch_jv(launch_of(M, OP_JV), x, v, jv), "J v kernel"); }
+  return OPF_OK;
+}
+
+namespace {
+int ipm_dev(const opf_ipm_state* st, IpmDev& d) {
+  if (!st) return fail(OPF_EINVAL, "state is NULL");
+  if (!(st->x && st->s && st->y && st->zl && st->zu && st->vl && st->vu && st->xl && st->xu && st->sl && st->su))
+    return fail(OPF_EINVAL, "state: an array is NULL");
+  if (!(std::isfinite(st->mu) && std::isfinite(st->delta_w) && std::isfinite(st->delta_c) && st->mu >= 0.0 &&
+        st->delta_w >= 0.0 && st->delta_c >= 0.0))
+    return fail(OPF_EINVAL, "state: mu, delta_w and delta_c must be finite and >= 0");
+  d = IpmDev{st->x, st->s, st->y, st->zl, st->zu, st->vl, st->vu, st->xl, st->xu, st->sl, st->su,
+             st->mu, st->delta_w, st->delta_c};
+  return OPF_OK;
+}
+}  // namespace
+
+int opf_condensed_rhs(opf_model* M, const opf_ipm_state* st, const double* grad, const double* c, double* diag_x,
+                      double* dcon, double* rhs) {
+  if (!M) return fail(OPF_EINVAL, "model is NULL");
+  IpmDev d;
+  int rc = ipm_dev(st, d);
+  if (rc != OPF_OK) return rc;
+  OPF_REQUIRE(grad && c && diag_x && dcon && rhs, "grad / c / diag_x / dcon / rhs");
+  OPF_CHECK_MODEL(M);
+  DeviceGuard g(M->device);
+  { TimerScope ts_(M, OP_RHSR); OPF_LAUNCHED(launch_rhs_rows(Flat{M->m, M->stream}, d, c, dcon, M->wbuf), "condensed rhs row kernel"); }
+  if ((rc = enq_jt(M, st->x, M->wbuf, rhs)) != OPF_OK) return rc;
+  { TimerScope ts_(M, OP_RHSV); OPF_LAUNCHED(launch_rhs_vars(Flat{M->n, M->stream}, d, grad, diag_x, rhs), "condensed rhs variable kernel"); }
+  return OPF_OK;
+}
+
+int opf_recover_step(opf_model* M, const opf_ipm_state* st, const double* c, const double* dx, double* ds,
+                     double* dy, double* dzl, double* dzu, double* dvl, double* dvu) {
+  if (!M) return fail(OPF_EINVAL, "model is NULL");
+  IpmDev d;
+  int rc = ipm_dev(st, d);
+  if (rc != OPF_OK) return rc;
+  OPF_REQUIRE(c && dx && ds && dy && dzl && dzu && dvl && dvu, "c / dx / ds / dy / dzl / dzu / dvl / dvu");
+  OPF_CHECK_MODEL(M);
+  DeviceGuard g(M->device);
+  { TimerScope ts_(M, OP_JV); OPF_LAUNCHED(launch_jv(launch_of(M, OP_JV), st->x, dx, M->wbuf), "J v kernel"); }
+  { TimerScope ts_(M, OP_RECR); OPF_LAUNCHED(launch_rec_rows(Flat{M->m, M->stream}, d, c, M->wbuf, ds, dy, dvl, dvu), "step recovery row kernel"); }
+  { TimerScope ts_(M, OP_RECV); OPF_LAUNCHED(launch_rec_vars(Flat{M->n, M->stream}, d, dx, dzl, dzu), "step recovery variable kernel"); }
   return OPF_OK;
 }
 
@@ -1094,6 +1163,8 @@ extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
                               M->scratch);
       case OP_SWB:
         return launch_sweep_b(launch_of(M, op), x, lam, jv, dx, d, kv, out_m, out_n, dx_out, M->scratch);
+      case OP_JV:
+        return launch_jv(launch_of(M, op), x, dx, out_m);
     }
     return hipSuccess;
   };
@@ -1101,7 +1172,7 @@ extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
   (void)run(OP_JAC);
   (void)run(OP_HESS);
   const int tuned[] = {OP_JAC, OP_HESS, OP_CONS, OP_GRAD, OP_OBJ, OP_JTA, OP_JTB, OP_KKA, OP_KKB, OP_JHKA,
-                       OP_SWA, OP_SWB};
+                       OP_SWA, OP_SWB, OP_JV};
   const int blocks[] = {64, 128, 256, 512};
   const int ppts[] = {1, 2, 4, 8};
   rc = OPF_OK;

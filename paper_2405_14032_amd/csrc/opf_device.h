@@ -46,6 +46,66 @@ __device__ __forceinline__ int64_t kkt_period_offset_dev(int64_t nnzk_p, int32_t
   return (int64_t)t * nnzk_p + (t >= 1 ? (int64_t)(t - 1) * G : 0);
 }
 
+// Access to a per-period block through its (wave-uniform) base pointer and
+// a 32-bit element offset.  Every per-period block is far below 4 GiB, so
+// the byte offset fits 32 bits; written this way the address is a scalar
+// base plus one 32-bit vector offset instead of a 64-bit vector address.
+template <class T>
+__device__ __forceinline__ T ldo(const T* base, uint32_t e) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + e * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void sto(T* base, uint32_t e, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + e * (uint32_t)sizeof(T)) = v;
+}
+
+// Buffer-resource access: a wave-uniform 128-bit descriptor (base address,
+// unlimited extent) in scalar registers plus a 32-bit per-lane byte offset,
+// the addressing form of the vector memory unit that needs no 64-bit
+// per-lane address.  Used by the kernels that touch many arrays per element
+// (each array block gets its own descriptor; offsets stay below 4 GiB
+// because every such block is a per-period or per-instance slice).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ rsrc_t rsrc(const void* base) {
+  // word 3 of the descriptor for raw (untyped) access on gfx9-family parts
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
+}
+__device__ __forceinline__ double bld(rsrc_t r, uint32_t e) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8u, 0, 0));
+}
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t e, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, e * 8u, 0, 0);
+}
+__device__ __forceinline__ int32_t bldi(rsrc_t r, uint32_t e) {
+  return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, e * 4u, 0, 0);
+}
+// Split addressing: a per-lane byte offset (vo, shared by many accesses)
+// plus a wave-uniform byte offset (so, in the instruction's scalar-offset
+// operand), so a lane keeps a handful of offsets instead of one per stream.
+__device__ __forceinline__ double bldv(rsrc_t r, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+__device__ __forceinline__ void bstv(rsrc_t r, uint32_t vo, uint32_t so, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, vo, so, 0);
+}
+__device__ __forceinline__ int32_t bldiv(rsrc_t r, uint32_t vo, uint32_t so) {
+  return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+}
+__device__ __forceinline__ void bst2v(rsrc_t r, uint32_t vo, uint32_t so, double2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, vo, so, 0);
+}
+__device__ __forceinline__ double2 bld2v(rsrc_t r, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+}
+__device__ __forceinline__ double2 bld2(rsrc_t r, uint32_t e) {  // e: index of the double2
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, e * 16u, 0, 0));
+}
+__device__ __forceinline__ void bst2(rsrc_t r, uint32_t e, double2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, e * 16u, 0, 0);
+}
+
 // Per-instance scratch, in doubles, per line and period:
 //  * a line -> bus hand-off record per line end (kRecEnd doubles, one
 //    64-byte line): [0] the end's (vm,vm) diagonal sum, [1] its (va,vm)
@@ -105,6 +165,25 @@ hipError_t launch_sweep_b(const Launch& L, const double* x, const double* v, con
                           const double* d, double* k, double* c, double* jtv, double* g, const double* scratch);
 hipError_t launch_kkt_b(const Launch& L, const double* j, const double* dx, const double* d, double* k,
                         const double* scratch);
+// One iterate of the lifted interior-point method (device pointers over the
+// concatenated instances; +-inf bounds are absent).
+struct IpmDev {
+  const double *x, *s, *y, *zl, *zu, *vl, *vu, *xl, *xu, *sl, *su;
+  double mu, dw, dc;
+};
+
+// Flat element-wise launch over [0, count).
+struct Flat {
+  int64_t count;
+  hipStream_t stream;
+};
+
+hipError_t launch_jv(const Launch& L, const double* x, const double* v, double* jv);
+hipError_t launch_rhs_rows(const Flat& F, const IpmDev& st, const double* c, double* dcon, double* w);
+hipError_t launch_rhs_vars(const Flat& F, const IpmDev& st, const double* grad, double* diag_x, double* rhs);
+hipError_t launch_rec_rows(const Flat& F, const IpmDev& st, const double* c, const double* adx, double* ds,
+                           double* dy, double* dvl, double* dvu);
+hipError_t launch_rec_vars(const Flat& F, const IpmDev& st, const double* dx, double* dzl, double* dzu);
 hipError_t launch_jac_struct(const Launch& L, int32_t* rows, int32_t* cols);
 hipError_t launch_hess_struct(const Launch& L, int32_t* rows, int32_t* cols);
 hipError_t launch_kkt_struct(const Launch& L, int ninst, int64_t* rowptr, int32_t* colind);

@@ -62,6 +62,29 @@ __device__ __forceinline__ void load_coef(const InstDev& I, int l, Coef& c) {
   c.be[3] = -gtf;
 }
 
+// Kind k's coefficients from an LDS copy of the line's eight admittances
+// (SoA, stride bd): the same values load_coef gives for that kind, without
+// keeping all twelve in registers across a loop over periods.
+__device__ __forceinline__ void coef_kind_lds(const double* sadm, int bd, int tid, int k, Coef& c) {
+  if (k == 0) {
+    c.S[0] = sadm[tid];
+    c.al[0] = sadm[2 * bd + tid];
+    c.be[0] = sadm[3 * bd + tid];
+  } else if (k == 1) {
+    c.S[1] = -sadm[bd + tid];
+    c.al[1] = -sadm[3 * bd + tid];
+    c.be[1] = sadm[2 * bd + tid];
+  } else if (k == 2) {
+    c.S[2] = sadm[6 * bd + tid];
+    c.al[2] = sadm[4 * bd + tid];
+    c.be[2] = -sadm[5 * bd + tid];
+  } else {
+    c.S[3] = -sadm[7 * bd + tid];
+    c.al[3] = -sadm[5 * bd + tid];
+    c.be[3] = -sadm[4 * bd + tid];
+  }
+}
+
 // Per-period block bases (local offsets inside one period).
 struct Bases {
   int64_t N, B, G;
@@ -348,6 +371,190 @@ __global__ void __launch_bounds__(512) k_cons(const InstDev* __restrict__ insts,
   }
 }
 
+// ---------------------------------------------------------------- J v
+// Forward product J(x) v, row by row in the canonical row order; the tiles
+// are those of the constraint kernel (lines: flow, thermal and angle rows;
+// buses: balance and reference rows; generators: ramp rows).
+__device__ void jv_branch(const InstDev& I, int l, int t0, int t1, const double* __restrict__ x,
+                          const double* __restrict__ v, double* __restrict__ out) {
+  const Bases b(I);
+  Coef cf;
+  load_coef(I, l, cf);
+  const int64_t B = b.B;
+  const int i = I.f_bus[l], j = I.t_bus[l];
+  for (int t = t0; t < t1; ++t) {
+    const int64_t xo = I.x_off + (int64_t)t * I.n_p;
+    const double* xp = x + xo;
+    const double* vp = v + xo;
+    double* op = out + I.c_off + (int64_t)t * I.m_p;
+    const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
+    const double wvi = vp[i], wvj = vp[j], wti = vp[b.N + i], wtj = vp[b.N + j];
+    double fl[4], wf[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      fl[k] = xp[b.xFL + k * B + l];
+      wf[k] = vp[b.xFL + k * B + l];
+    }
+    double sn, cs;
+    sincos(ti - tj, &sn, &cs);
+    const double vv = vi * vj;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double Jk[5], h[9];
+      flow_kind(cf, k, vi, vj, vv, sn, cs, 0.0, Jk, h);
+      op[b.cFLOW + k * B + l] = Jk[0] * wf[k] + Jk[1] * wvi + Jk[2] * wvj + Jk[3] * wti + Jk[4] * wtj;
+    }
+    op[b.cTHF + l] = (2.0 * fl[0]) * wf[0] + (2.0 * fl[1]) * wf[1];
+    op[b.cTHT + l] = (2.0 * fl[2]) * wf[2] + (2.0 * fl[3]) * wf[3];
+    op[b.cANG + l] = wti - wtj;
+  }
+}
+
+__device__ void jv_bus(const InstDev& I, int n, int t0, int t1, const double* __restrict__ v,
+                       double* __restrict__ out) {
+  const Bases b(I);
+  const int64_t B = b.B;
+  const int q0 = I.bus_ptr[n], q1 = I.bus_ptr[n + 1];
+  const int g0 = I.bgen_ptr[n], g1 = I.bgen_ptr[n + 1];
+  for (int t = t0; t < t1; ++t) {
+    const double* vp = v + I.x_off + (int64_t)t * I.n_p;
+    double* op = out + I.c_off + (int64_t)t * I.m_p;
+    double bp = 0.0, bq = 0.0;
+    for (int q = g0; q < g1; ++q) {
+      const int g = I.bgen[q];
+      bp += vp[2 * b.N + g];
+      bq += vp[2 * b.N + b.G + g];
+    }
+    for (int q = q0; q < q1; ++q) {
+      const int a = I.bus_adj[q];
+      const int64_t l = a >> 1;
+      const int64_t kp = (a & 1) ? 2 : 0;
+      bp -= vp[b.xFL + kp * B + l];
+      bq -= vp[b.xFL + (kp + 1) * B + l];
+    }
+    op[n] = bp;
+    op[b.N + n] = bq;
+    if (n == I.ref) op[b.cREF] = vp[b.N + n];
+  }
+}
+
+__global__ void __launch_bounds__(512) k_jv(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
+                                            int ntiles, const double* __restrict__ x, const double* __restrict__ v,
+                                            double* __restrict__ out) {
+  for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+    const Tile tl = tiles[remap_tile(w, ntiles)];
+    const InstDev& I = insts[tl.inst];
+    const int e = tl.e0 + (int)threadIdx.x;
+    if (e >= tl.e1) continue;
+    if (tl.kind == TK_BRANCH) {
+      jv_branch(I, e, tl.t0, tl.t1, x, v, out);
+    } else if (tl.kind == TK_BUS) {
+      jv_bus(I, e, tl.t0, tl.t1, v, out);
+    } else {
+      const int64_t pg = 2LL * I.N + e;
+      for (int t = tl.t0 < 1 ? 1 : tl.t0; t < tl.t1; ++t) {
+        const double* vp = v + I.x_off + (int64_t)t * I.n_p;
+        out[I.c_off + (int64_t)I.T * I.m_p + (int64_t)(t - 1) * I.G + e] = vp[pg] - vp[pg - I.n_p];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------- lifted-KKT condensation
+// Barrier terms of one box lo <= val <= hi (Sec. III-B): sigma = z_lo / gap_lo
+// + z_hi / gap_hi, the complementarity residuals z_lo gap_lo - mu and
+// z_hi gap_hi - mu, and the gaps.  An infinite bound is absent: its
+// multiplier is taken as 0, its gap as 1 and its residual as 0.
+struct BoxTerms {
+  double sig, plo, phi, glo, ghi, zlo, zhi;
+  bool hlo, hhi;
+};
+
+__device__ __forceinline__ BoxTerms box_terms(double val, double lo, double hi, double zlo, double zhi,
+                                              double mu) {
+  BoxTerms b;
+  b.hlo = __builtin_isfinite(lo);
+  b.hhi = __builtin_isfinite(hi);
+  b.glo = b.hlo ? val - lo : 1.0;
+  b.ghi = b.hhi ? hi - val : 1.0;
+  b.zlo = b.hlo ? zlo : 0.0;
+  b.zhi = b.hhi ? zhi : 0.0;
+  b.sig = b.zlo / b.glo + b.zhi / b.ghi;
+  b.plo = b.hlo ? b.zlo * b.glo - mu : 0.0;
+  b.phi = b.hhi ? b.zhi * b.ghi - mu : 0.0;
+  return b;
+}
+
+// Row-space terms: q_s = p_s + p_lo / gap_lo - p_hi / gap_hi with
+// p_s = -z_lo + z_hi + y, q_y = c - s, C = 1 / (dc sigma + 1 + dc dw).
+struct RowTerms {
+  BoxTerms b;
+  double qs, qy, C;
+};
+
+__device__ __forceinline__ RowTerms row_terms(const IpmDev& st, int64_t r, double cr) {
+  RowTerms R;
+  const double sr = st.s[r], yr = st.y[r];
+  R.b = box_terms(sr, st.sl[r], st.su[r], st.vl[r], st.vu[r], st.mu);
+  const double ps = -R.b.zlo + R.b.zhi + yr;
+  R.qy = cr - sr;
+  R.qs = ps + R.b.plo / R.b.glo - R.b.phi / R.b.ghi;
+  R.C = 1.0 / (st.dc * R.b.sig + (1.0 + st.dc * st.dw));
+  return R;
+}
+
+// Rows: D and the vector w = C q_s + D q_y - y whose transposed product
+// with J gives A^T (C q_s + D q_y) - A^T y.
+__global__ void __launch_bounds__(256) k_rhs_rows(int64_t m, IpmDev st, const double* __restrict__ c,
+                                                  double* __restrict__ dcon, double* __restrict__ w) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    const RowTerms R = row_terms(st, r, c[r]);
+    const double D = (R.b.sig + st.dw) * R.C;
+    dcon[r] = D;
+    w[r] = R.C * R.qs + D * R.qy - st.y[r];
+  }
+}
+
+// Variables: diag_x = dw + Sigma_x and rhs = q_x + (J^T w) with
+// q_x (without its -A^T y term, carried by w) = grad - z_lo + z_hi
+// + p_lo / gap_lo - p_hi / gap_hi; rhs holds J^T w on entry.
+__global__ void __launch_bounds__(256) k_rhs_vars(int64_t n, IpmDev st, const double* __restrict__ grad,
+                                                  double* __restrict__ diag_x, double* __restrict__ rhs) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const BoxTerms b = box_terms(st.x[i], st.xl[i], st.xu[i], st.zl[i], st.zu[i], st.mu);
+    diag_x[i] = st.dw + b.sig;
+    const double qx = grad[i] - b.zlo + b.zhi + b.plo / b.glo - b.phi / b.ghi;
+    rhs[i] = qx + rhs[i];
+  }
+}
+
+// Recovery, rows: ds = C (A dx + dc q_s - q_y), dy = (Sigma_s + dw) ds - q_s,
+// and the slack-bound multiplier steps.
+__global__ void __launch_bounds__(256) k_rec_rows(int64_t m, IpmDev st, const double* __restrict__ c,
+                                                  const double* __restrict__ adx, double* __restrict__ ds,
+                                                  double* __restrict__ dy, double* __restrict__ dvl,
+                                                  double* __restrict__ dvu) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    const RowTerms R = row_terms(st, r, c[r]);
+    const double d = R.C * (adx[r] + st.dc * R.qs - R.qy);
+    ds[r] = d;
+    dy[r] = (R.b.sig + st.dw) * d - R.qs;
+    dvl[r] = R.b.hlo ? (-R.b.zlo * d + R.b.plo) / R.b.glo : 0.0;
+    dvu[r] = R.b.hhi ? (R.b.zhi * d + R.b.phi) / R.b.ghi : 0.0;
+  }
+}
+
+// Recovery, variables: the bound-multiplier steps of x.
+__global__ void __launch_bounds__(256) k_rec_vars(int64_t n, IpmDev st, const double* __restrict__ dx,
+                                                  double* __restrict__ dzl, double* __restrict__ dzu) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const BoxTerms b = box_terms(st.x[i], st.xl[i], st.xu[i], st.zl[i], st.zu[i], st.mu);
+    const double d = dx[i];
+    dzl[i] = b.hlo ? (-b.zlo * d + b.plo) / b.glo : 0.0;
+    dzu[i] = b.hhi ? (b.zhi * d + b.phi) / b.ghi : 0.0;
+  }
+}
+
 // ---------------------------------------------------------------- gradient
 __global__ void __launch_bounds__(512) k_grad(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
                                               int ntiles, const double* __restrict__ x, double* __restrict__ gv) {
@@ -622,8 +829,7 @@ __device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, double sigma, d
 // entry; four slots per lane are handled per step so their template loads
 // and J gathers are in flight together.
 template <bool GATHER>
-__device__ __forceinline__ void stream_segment(const double* __restrict__ seg, const int32_t* __restrict__ src,
-                                               const double* __restrict__ jp, double* __restrict__ dst,
+__device__ __forceinline__ void stream_segment(const double* __restrict__ seg, rsrc_t src, rsrc_t jp, rsrc_t dst,
                                                int len) {
   constexpr int U = 4;
   const int bd = (int)blockDim.x;
@@ -633,18 +839,18 @@ __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, c
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = p0 + u * bd;
-      sr[u] = (GATHER && p < len) ? src[p] : -2;
+      sr[u] = (GATHER && p < len) ? bldi(src, (uint32_t)p) : -2;
       v[u] = p < len ? seg[p] : 0.0;
     }
     if (GATHER) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (sr[u] >= 0) v[u] *= jp[sr[u]];
+        if (sr[u] >= 0) v[u] *= bld(jp, (uint32_t)sr[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = p0 + u * bd;
-      if (p < len) dst[p] = v[u];
+      if (p < len) bst(dst, (uint32_t)p, v[u]);
     }
   }
 }
@@ -661,103 +867,117 @@ template <bool FUSED>
 __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __restrict__ X,
                               const double* __restrict__ LAM, double* __restrict__ H, double* __restrict__ J,
                               const double* __restrict__ DX, const double* __restrict__ D, double* __restrict__ K,
-                              double* __restrict__ scr, double* __restrict__ seg,
+                              double* __restrict__ scr, double* __restrict__ seg, double* sadm,
                               const double* __restrict__ V = nullptr, double* __restrict__ C = nullptr,
                               double* __restrict__ JTV = nullptr, double* __restrict__ GR = nullptr) {
   const Bases b(I);
-  const int64_t B = b.B, N = b.N, G = b.G;
+  // element offsets inside one period block, as byte offsets (every period
+  // block is far below 4 GiB)
+  const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, G = (uint32_t)b.G;
+  const uint32_t xFL8 = (uint32_t)b.xFL * 8u, jFLOW8 = (uint32_t)b.jFLOW * 8u, jBAL8 = (uint32_t)b.jBAL * 8u,
+                 jTH8 = (uint32_t)b.jTH * 8u, jANG8 = (uint32_t)b.jANG * 8u, hFLOW8 = (uint32_t)b.hFLOW * 8u,
+                 hTH8 = (uint32_t)b.hTH * 8u, cFLOW8 = (uint32_t)b.cFLOW * 8u, cTHF8 = (uint32_t)b.cTHF * 8u,
+                 cTHT8 = (uint32_t)b.cTHT * 8u, cANG8 = (uint32_t)b.cANG * 8u;
   const int tid = (int)threadIdx.x;
-  const int l = tl.e0 + tid;
-  const bool act = l < tl.e1;
-  int i = 0, j = 0;
-  Coef cf;
-  if (act) {
-    i = I.f_bus[l];
-    j = I.t_bus[l];
-    if (FUSED) load_coef(I, l, cf);
+  const uint32_t l = (uint32_t)(tl.e0 + tid);
+  const bool act = (int)l < tl.e1;
+  const int nl = tl.e1 - tl.e0;
+  // lane offsets: every per-line stream is (uniform stream offset) + vL
+  const uint32_t vL = l * 8u, vL4 = l * 4u, vR = l * (uint32_t)(kRecLine * 8);
+  const rsrc_t rKrow = rsrc(I.krow), rKsrc = rsrc(I.ksrc);
+  const uint32_t FL4 = (uint32_t)b.xFL * 4u, Bq = (uint32_t)b.B * 4u;
+  int sb[4], se[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    sb[k] = __builtin_amdgcn_readfirstlane(bldi(rKrow, (uint32_t)b.xFL + (uint32_t)k * (uint32_t)b.B + tl.e0));
+    se[k] = __builtin_amdgcn_readfirstlane(bldi(rKrow, (uint32_t)b.xFL + (uint32_t)k * (uint32_t)b.B + tl.e1));
   }
-  const bool ilo = i < j;
+  uint32_t vI = 0, vJ = 0;
+  bool ilo = true;
+  const int bd = (int)blockDim.x;
+  if (act) {
+    const int i = bldi(rsrc(I.f_bus), l), j = bldi(rsrc(I.t_bus), l);
+    ilo = i < j;
+    vI = (uint32_t)i * 8u;
+    vJ = (uint32_t)j * 8u;
+    if (FUSED) {
+      const rsrc_t rA = rsrc(I.adm);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) sadm[a * bd + tid] = bldv(rA, vL, (uint32_t)a * B8);
+    }
+  }
+  (void)nl;
   for (int t = tl.t0; t < tl.t1; ++t) {
-    double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
-    double* hp = H + I.h_off + (int64_t)t * I.nnzh_p;
-    const double* dp = D + I.c_off + (int64_t)t * I.m_p;
     const int64_t xo = I.x_off + (int64_t)t * I.n_p;
-    double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t) + (t >= 1 ? G : 0);
-    double q[10], dbal[4], dth[2], Jt[4];
+    const int64_t co = I.c_off + (int64_t)t * I.m_p;
+    const rsrc_t rJ = rsrc(J + I.j_off + (int64_t)t * I.nnzj_p);
+    const rsrc_t rH = rsrc(H + I.h_off + (int64_t)t * I.nnzh_p);
+    const rsrc_t rD = rsrc(D + co);
+    double* kbase = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t) + (t >= 1 ? G : 0);
+    double q[10], dth[2], Jt[4];
     double vi = 0.0, vj = 0.0, vv = 0.0, sn = 0.0, cs = 0.0, ti = 0.0, tj = 0.0, fl[4], lf = 0.0, lt = 0.0;
-    double vk[4], svi = 0.0, svj = 0.0, sti = 0.0;
+    double svi = 0.0, svj = 0.0, sti = 0.0;
 #pragma unroll
     for (int a = 0; a < 10; ++a) q[a] = 0.0;
     if (act) {
-      dbal[0] = dp[i];
-      dbal[1] = dp[N + i];
-      dbal[2] = dp[j];
-      dbal[3] = dp[N + j];
-      dth[0] = dp[b.cTHF + l];
-      dth[1] = dp[b.cTHT + l];
+      dth[0] = bldv(rD, vL, cTHF8);
+      dth[1] = bldv(rD, vL, cTHT8);
       if constexpr (FUSED) {
-        const double* xp = X + xo;
-        const double* lp = LAM + I.c_off + (int64_t)t * I.m_p;
-        vi = xp[i];
-        vj = xp[j];
-        ti = xp[N + i];
-        tj = xp[N + j];
+        const rsrc_t rX = rsrc(X + xo), rL = rsrc(LAM + co);
+        vi = bldv(rX, vI, 0);
+        vj = bldv(rX, vJ, 0);
+        ti = bldv(rX, vI, N8);
+        tj = bldv(rX, vJ, N8);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          fl[k] = xp[b.xFL + k * B + l];
+          fl[k] = bldv(rX, vL, xFL8 + (uint32_t)k * B8);
           Jt[k] = 2.0 * fl[k];
         }
         sincos(ti - tj, &sn, &cs);
         vv = vi * vj;
-        lf = 2.0 * lp[b.cTHF + l];
-        lt = 2.0 * lp[b.cTHT + l];
-        if (JTV) {
-          const double* vp = V + I.c_off + (int64_t)t * I.m_p;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) vk[k] = vp[b.cFLOW + k * B + l];
-        }
+        lf = 2.0 * bldv(rL, vL, cTHF8);
+        lt = 2.0 * bldv(rL, vL, cTHT8);
       } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) Jt[k] = jp[b.jTH + k * B + l];
+        for (int k = 0; k < 4; ++k) Jt[k] = bldv(rJ, vL, jTH8 + (uint32_t)k * B8);
       }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int sb = I.krow[b.xFL + k * B + tl.e0], se = I.krow[b.xFL + k * B + tl.e1];
+      const uint32_t kB8 = (uint32_t)k * B8;
       if (act) {
-        const int rs = I.krow[b.xFL + k * B + l] - sb, re = I.krow[b.xFL + k * B + l + 1] - sb;
+        const int rs = bldiv(rKrow, vL4, FL4 + (uint32_t)k * Bq) - sb[k];
+        const int re = bldiv(rKrow, vL4, FL4 + (uint32_t)k * Bq + 4u) - sb[k];
         double Jk[5], hf[9], Jbk, Hthk;
-        const double dfk = dp[b.cFLOW + k * B + l];
+        const double dfk = bldv(rD, vL, cFLOW8 + kB8);
         if constexpr (FUSED) {
-          const double* lp = LAM + I.c_off + (int64_t)t * I.m_p;
-          flow_kind(cf, k, vi, vj, vv, sn, cs, -lp[b.cFLOW + k * B + l], Jk, hf);
-          double* jq = jp + b.jFLOW + (int64_t)(k * 5) * B + l;
+          const rsrc_t rL = rsrc(LAM + co);
+          Coef cf;
+          coef_kind_lds(sadm, bd, tid, k, cf);
+          flow_kind(cf, k, vi, vj, vv, sn, cs, -bldv(rL, vL, cFLOW8 + kB8), Jk, hf);
 #pragma unroll
-          for (int a = 0; a < 5; ++a) jq[a * B] = Jk[a];
-          double* hq = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
+          for (int a = 0; a < 5; ++a) bstv(rJ, vL, jFLOW8 + (uint32_t)(k * 5 + a) * B8, Jk[a]);
 #pragma unroll
-          for (int a = 0; a < 9; ++a) hq[a * B] = hf[a];
+          for (int a = 0; a < 9; ++a) bstv(rH, vL, hFLOW8 + (uint32_t)(k * 9 + a) * B8, hf[a]);
           Jbk = -1.0;
           Hthk = k < 2 ? lf : lt;
-          jp[b.jBAL + k * B + l] = Jbk;
-          jp[b.jTH + k * B + l] = Jt[k];
-          hp[b.hTH + k * B + l] = Hthk;
-          if (C) C[I.c_off + (int64_t)t * I.m_p + b.cFLOW + k * B + l] =
-              fl[k] - flow_value(cf, k, vi, vj, vv, flow_w(cf, k, sn, cs));
+          bstv(rJ, vL, jBAL8 + kB8, Jbk);
+          bstv(rJ, vL, jTH8 + kB8, Jt[k]);
+          bstv(rH, vL, hTH8 + kB8, Hthk);
+          if (C) bstv(rsrc(C + co), vL, cFLOW8 + kB8, fl[k] - flow_value(cf, k, vi, vj, vv, flow_w(cf, k, sn, cs)));
           if (JTV) {
-            svi += vk[k] * Jk[1];
-            svj += vk[k] * Jk[2];
-            sti += vk[k] * Jk[3];
+            const double vkk = bldv(rsrc(V + co), vL, cFLOW8 + kB8);
+            svi += vkk * Jk[1];
+            svj += vkk * Jk[2];
+            sti += vkk * Jk[3];
           }
         } else {
-          const double* jq = jp + b.jFLOW + (int64_t)(k * 5) * B + l;
 #pragma unroll
-          for (int a = 0; a < 5; ++a) Jk[a] = jq[a * B];
-          const double* hq = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
+          for (int a = 0; a < 5; ++a) Jk[a] = bldv(rJ, vL, jFLOW8 + (uint32_t)(k * 5 + a) * B8);
 #pragma unroll
-          for (int a = 0; a < 9; ++a) hf[a] = hq[a * B];
-          Jbk = jp[b.jBAL + k * B + l];
-          Hthk = hp[b.hTH + k * B + l];
+          for (int a = 0; a < 9; ++a) hf[a] = bldv(rH, vL, hFLOW8 + (uint32_t)(k * 9 + a) * B8);
+          Jbk = bldv(rJ, vL, jBAL8 + kB8);
+          Hthk = bldv(rH, vL, hTH8 + kB8);
         }
         // bus-variable contributions: d_k J_k,a J_k,b + H (local H order:
         // from end (0,0)(1,0)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3); to end
@@ -794,37 +1014,37 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
           row[2] = pk * Jk[4];
           row[3] = pk * Jk[3];
         }
-        const double pb = dbal[k] * Jbk;
+        const double pb = bldv(rD, k < 2 ? vI : vJ, (k & 1) ? N8 : 0u) * Jbk;
         for (int p = rs + 4; p < re - 1; ++p) {
-          const int src = I.ksrc[sb + p];
+          const int src = bldi(rKsrc, (uint32_t)(sb[k] + p));
           double v;
           if ((k & 1) && src < 0) {
             v = dth[k >> 1] * Jt[k ^ 1] * Jt[k];  // thermal partner
           } else if (FUSED) {
-            v = pb * (src < 2 * G ? 1.0 : -1.0);  // balance partner: generator +1, line end -1
+            v = pb * (src < (int)(2 * G) ? 1.0 : -1.0);  // balance partner: generator +1, line end -1
           } else {
             v = pb;  // factor; the stream-out multiplies by the partner's J entry
           }
           seg[p] = v;
         }
-        const double dxv = DX ? DX[xo + b.xFL + k * B + l] : 0.0;
+        const double dxv = DX ? bldv(rsrc(DX + xo), vL, xFL8 + kB8) : 0.0;
         seg[re - 1] = dxv + pk * Jk[0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jbk + Hthk;
       }
       __syncthreads();
-      stream_segment<!FUSED>(seg, I.ksrc + sb, jp, kb + sb, se - sb);
+      stream_segment<!FUSED>(seg, rsrc(I.ksrc + sb[k]), rJ, rsrc(kbase + sb[k]), se[k] - sb[k]);
       __syncthreads();
     }
     if (act) {
-      const double dang = dp[b.cANG + l];
+      const double dang = bldv(rD, vL, cANG8);
       double Ja0, Ja1;
       if constexpr (FUSED) {
         Ja0 = 1.0;
         Ja1 = -1.0;
-        jp[b.jANG + l] = Ja0;
-        jp[b.jANG + B + l] = Ja1;
+        bstv(rJ, vL, jANG8, Ja0);
+        bstv(rJ, vL, jANG8 + B8, Ja1);
       } else {
-        Ja0 = jp[b.jANG + l];
-        Ja1 = jp[b.jANG + B + l];
+        Ja0 = bldv(rJ, vL, jANG8);
+        Ja1 = bldv(rJ, vL, jANG8 + B8);
       }
       q[2] += dang * Ja0 * Ja0;
       q[8] += dang * Ja1 * Ja1;
@@ -832,42 +1052,46 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
       double pfl[4] = {0.0, 0.0, 0.0, 0.0}, jtr[4] = {0.0, 0.0, 0.0, 0.0};
       if constexpr (FUSED) {
         if (C) {
-          double* cp = C + I.c_off + (int64_t)t * I.m_p;
-          cp[b.cTHF + l] = fl[0] * fl[0] + fl[1] * fl[1];
-          cp[b.cTHT + l] = fl[2] * fl[2] + fl[3] * fl[3];
-          cp[b.cANG + l] = ti - tj;
+          const rsrc_t rC = rsrc(C + co);
+          bstv(rC, vL, cTHF8, fl[0] * fl[0] + fl[1] * fl[1]);
+          bstv(rC, vL, cTHT8, fl[2] * fl[2] + fl[3] * fl[3]);
+          bstv(rC, vL, cANG8, ti - tj);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) pfl[k] = fl[k];
         if (JTV) {
-          const double* vp = V + I.c_off + (int64_t)t * I.m_p;
-          const double vtf = vp[b.cTHF + l], vtt = vp[b.cTHT + l], vang = vp[b.cANG + l];
-          const double vbal[4] = {vp[i], vp[N + i], vp[j], vp[N + j]};
-          JTV[xo + b.xFL + l] = vk[0] + vtf * (2.0 * fl[0]) - vbal[0];
-          JTV[xo + b.xFL + B + l] = vk[1] + vtf * (2.0 * fl[1]) - vbal[1];
-          JTV[xo + b.xFL + 2 * B + l] = vk[2] + vtt * (2.0 * fl[2]) - vbal[2];
-          JTV[xo + b.xFL + 3 * B + l] = vk[3] + vtt * (2.0 * fl[3]) - vbal[3];
+          const rsrc_t rV = rsrc(V + co), rO = rsrc(JTV + xo);
+          const double vtf = bldv(rV, vL, cTHF8), vtt = bldv(rV, vL, cTHT8), vang = bldv(rV, vL, cANG8);
+          double vk[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) vk[k] = bldv(rV, vL, cFLOW8 + (uint32_t)k * B8);
+          const double vbal[4] = {bldv(rV, vI, 0), bldv(rV, vI, N8), bldv(rV, vJ, 0), bldv(rV, vJ, N8)};
+          bstv(rO, vL, xFL8, vk[0] + vtf * (2.0 * fl[0]) - vbal[0]);
+          bstv(rO, vL, xFL8 + B8, vk[1] + vtf * (2.0 * fl[1]) - vbal[1]);
+          bstv(rO, vL, xFL8 + 2 * B8, vk[2] + vtt * (2.0 * fl[2]) - vbal[2]);
+          bstv(rO, vL, xFL8 + 3 * B8, vk[3] + vtt * (2.0 * fl[3]) - vbal[3]);
           jtr[0] = svi;
           jtr[1] = sti + vang;
           jtr[2] = svj;
           jtr[3] = -sti - vang;
         }
         if (GR) {
+          const rsrc_t rG = rsrc(GR + xo);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) GR[xo + b.xFL + k * B + l] = 0.0;
+          for (int k = 0; k < 4; ++k) bstv(rG, vL, xFL8 + (uint32_t)k * B8, 0.0);
         }
       }
       // hand-off: one 64-byte record per line end, the shared cross pair
-      double2* ri = reinterpret_cast<double2*>(rec_at(I, scr, t) + (int64_t)l * kRecLine);
-      ri[0] = make_double2(q[0], q[1]);
-      ri[1] = make_double2(q[2], q[3]);
-      ri[2] = make_double2(pfl[0], pfl[1]);
-      ri[3] = make_double2(jtr[0], jtr[1]);
-      ri[4] = make_double2(q[6], q[7]);
-      ri[5] = make_double2(q[8], q[9]);
-      ri[6] = make_double2(pfl[2], pfl[3]);
-      ri[7] = make_double2(jtr[2], jtr[3]);
-      reinterpret_cast<double2*>(shared_at(I, scr, t))[l] = make_double2(q[4], q[5]);
+      const rsrc_t rR = rsrc(rec_at(I, scr, t));
+      bst2v(rR, vR, 0, make_double2(q[0], q[1]));
+      bst2v(rR, vR, 16, make_double2(q[2], q[3]));
+      bst2v(rR, vR, 32, make_double2(pfl[0], pfl[1]));
+      bst2v(rR, vR, 48, make_double2(jtr[0], jtr[1]));
+      bst2v(rR, vR, 64, make_double2(q[6], q[7]));
+      bst2v(rR, vR, 80, make_double2(q[8], q[9]));
+      bst2v(rR, vR, 96, make_double2(pfl[2], pfl[3]));
+      bst2v(rR, vR, 112, make_double2(jtr[2], jtr[3]));
+      bst2v(rsrc(shared_at(I, scr, t)), vL * 2u, 0, make_double2(q[4], q[5]));
     }
   }
 }
@@ -887,7 +1111,7 @@ __global__ void __launch_bounds__(256) k_kkt_a(const InstDev* __restrict__ insts
     const Tile tl = tiles[remap_tile(v, ntiles)];
     const InstDev& I = insts[tl.inst];
     if (tl.kind == TK_BRANCH) {
-      kkt_line_tile<false>(I, tl, nullptr, nullptr, Hm, Jm, DX, D, K, scr, lds);
+      kkt_line_tile<false>(I, tl, nullptr, nullptr, Hm, Jm, DX, D, K, scr, lds, nullptr);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
       if (e < tl.e1) kkt_gen<false>(I, e, tl.t0, tl.t1, 0.0, Hm, Jm, DX, D, K);
@@ -896,6 +1120,7 @@ __global__ void __launch_bounds__(256) k_kkt_a(const InstDev* __restrict__ insts
 }
 
 // Fused form: J, H and the line / generator rows of K in one pass over x.
+// Dynamic LDS: seg[cap_seg] doubles, then the lanes' admittances [8][blockDim].
 __global__ void __launch_bounds__(256) k_jhk_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
                                                int ntiles, int cap_seg, const double* __restrict__ X,
                                                const double* __restrict__ LAM, double sigma, double* __restrict__ H,
@@ -907,7 +1132,7 @@ __global__ void __launch_bounds__(256) k_jhk_a(const InstDev* __restrict__ insts
     const Tile tl = tiles[remap_tile(v, ntiles)];
     const InstDev& I = insts[tl.inst];
     if (tl.kind == TK_BRANCH) {
-      kkt_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds);
+      kkt_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, lds + cap_seg);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
       if (e < tl.e1) kkt_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K);
@@ -917,6 +1142,7 @@ __global__ void __launch_bounds__(256) k_jhk_a(const InstDev* __restrict__ insts
 
 // Whole sweep, lines and generators: J, H, K rows, constraint rows, J^T v and
 // gradient entries of the line / generator variables in one pass over x.
+// Dynamic LDS as in k_jhk_a.
 __global__ void __launch_bounds__(256) k_sweep_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
                                                  int ntiles, int cap_seg, const double* __restrict__ X,
                                                  const double* __restrict__ LAM, double sigma,
@@ -930,7 +1156,7 @@ __global__ void __launch_bounds__(256) k_sweep_a(const InstDev* __restrict__ ins
     const Tile tl = tiles[remap_tile(v, ntiles)];
     const InstDev& I = insts[tl.inst];
     if (tl.kind == TK_BRANCH) {
-      kkt_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, V, C, JTV, GR);
+      kkt_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, lds + cap_seg, V, C, JTV, GR);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
       if (e < tl.e1) kkt_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K, X, V, C, JTV, GR);
@@ -951,43 +1177,55 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
                          double* __restrict__ GR) {
   double* svm = lds;
   double* sva = lds + cap_vm;
-  const int64_t N = I.N, B = I.B, G = I.G;
-  const int64_t xFL = 2 * N + 2 * G;
+  const int64_t N = I.N;
+  const uint32_t N4 = (uint32_t)N * 4u, N8 = (uint32_t)N * 8u, G = (uint32_t)I.G;
   const int tid = (int)threadIdx.x;
   const int n = tl.e0 + tid;
   const bool act = n < tl.e1;
-  const int b0 = I.krow[tl.e0], b1 = I.krow[tl.e1];
-  const int a0 = I.krow[N + tl.e0], a1 = I.krow[N + tl.e1];
+  // lane offsets (bytes): int32 tables and doubles indexed by the bus
+  const uint32_t vN4 = (uint32_t)n * 4u, vN8 = (uint32_t)n * 8u;
+  const rsrc_t rKrow = rsrc(I.krow);
+  const int b0 = __builtin_amdgcn_readfirstlane(bldi(rKrow, (uint32_t)tl.e0));
+  const int b1 = __builtin_amdgcn_readfirstlane(bldi(rKrow, (uint32_t)tl.e1));
+  const int a0 = __builtin_amdgcn_readfirstlane(bldi(rKrow, (uint32_t)(N + tl.e0)));
+  const int a1 = __builtin_amdgcn_readfirstlane(bldi(rKrow, (uint32_t)(N + tl.e1)));
   int q0 = 0, q1 = 0, vmr = 0, var = 0, clo = 0, lva = 0, call = 0, g0 = 0, g1 = 0;
   if (act) {
-    q0 = I.bus_ptr[n];
-    q1 = I.bus_ptr[n + 1];
-    vmr = I.krow[n] - b0;
-    var = I.krow[N + n] - a0;
-    clo = I.krow[n + 1] - I.krow[n] - 1;
-    lva = I.krow[N + n + 1] - I.krow[N + n];
+    const rsrc_t rBp = rsrc(I.bus_ptr);
+    q0 = bldiv(rBp, vN4, 0);
+    q1 = bldiv(rBp, vN4, 4);
+    const int k0 = bldiv(rKrow, vN4, 0), k1 = bldiv(rKrow, vN4, 4);
+    const int k2 = bldiv(rKrow, vN4, N4), k3 = bldiv(rKrow, vN4, N4 + 4);
+    vmr = k0 - b0;
+    var = k2 - a0;
+    clo = k1 - k0 - 1;
+    lva = k3 - k2;
     call = lva - clo - 2;
     if (SWEEP) {
-      g0 = I.bgen_ptr[n];
-      g1 = I.bgen_ptr[n + 1];
+      const rsrc_t rGp = rsrc(I.bgen_ptr);
+      g0 = bldiv(rGp, vN4, 0);
+      g1 = bldiv(rGp, vN4, 4);
     }
   }
+  const rsrc_t rAdj = rsrc(I.bus_adj), rNb = rsrc(I.bus_nb);
   for (int t = tl.t0; t < tl.t1; ++t) {
     double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
     if (act) {
       const int64_t xo = I.x_off + (int64_t)t * I.n_p;
+      const int64_t co = I.c_off + (int64_t)t * I.m_p;
       double* scr_m = const_cast<double*>(scr);
-      const double* rs = rec_at(I, scr_m, t);
-      const double2* sh = reinterpret_cast<const double2*>(shared_at(I, scr_m, t));
-      const double* xp = SWEEP ? X + xo : nullptr;
+      // record of line end (l, e) at byte (2 l + e) * 64 = adjacency entry * 64
+      static_assert(kRecEnd * sizeof(double) == 64 && kRecLine == 2 * kRecEnd, "hand-off record layout");
+      const rsrc_t rR = rsrc(rec_at(I, scr_m, t)), rS = rsrc(shared_at(I, scr_m, t));
       double svm_s = 0.0, svavm_s = 0.0, sva_s = 0.0;
       double cvm = 0.0, cvavm = 0.0, cva = 0.0;
       double bp = 0.0, bq = 0.0, jvm = 0.0, jva = 0.0;
       if (SWEEP) {
+        const rsrc_t rX = rsrc(X + xo), rBg = rsrc(I.bgen);
         for (int q = g0; q < g1; ++q) {
-          const int g = I.bgen[q];
-          bp += xp[2 * N + g];
-          bq += xp[2 * N + G + g];
+          const uint32_t g8 = (uint32_t)bldi(rBg, (uint32_t)q) * 8u;
+          bp += bldv(rX, g8, 2 * N8);
+          bq += bldv(rX, g8, 2 * N8 + G * 8u);
         }
       }
       int gi = 0, prev = -1;
@@ -999,18 +1237,18 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const bool ok = aa + u < q1;
-          ad[u] = ok ? I.bus_adj[aa + u] : 0;
-          nb[u] = ok ? I.bus_nb[aa + u] : -1;
+          ad[u] = ok ? bldi(rAdj, (uint32_t)(aa + u)) : 0;
+          nb[u] = ok ? bldi(rNb, (uint32_t)(aa + u)) : -1;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const bool ok = nb[u] >= 0;
-          const int64_t l = ad[u] >> 1;
-          const double2* rp = reinterpret_cast<const double2*>(rs + l * kRecLine + (ad[u] & 1) * kRecEnd);
+          const uint32_t ro = (uint32_t)ad[u] * 64u;
           const int w1 = SWEEP ? 4 : 2;
 #pragma unroll
-          for (int w = 0; w < 4; ++w) r[u][w] = (ok && w < w1) ? rp[w] : make_double2(0.0, 0.0);
-          x2[u] = (ok && nb[u] < n) ? sh[l] : make_double2(0.0, 0.0);
+          for (int w = 0; w < 4; ++w)
+            r[u][w] = (ok && w < w1) ? bld2v(rR, ro, (uint32_t)w * 16u) : make_double2(0.0, 0.0);
+          x2[u] = (ok && nb[u] < n) ? bld2v(rS, (uint32_t)(ad[u] >> 1) * 16u, 0) : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1051,33 +1289,42 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
           sva[var + gi + 1] = cvavm;
         }
       }
+      const rsrc_t rD = rsrc(D + co);
       double dref = 0.0;
       if (n == I.ref) {
         const double jr = J[I.j_off + (int64_t)t * I.nnzj_p + 2LL * I.G + 4LL * I.B];
-        dref = D[I.c_off + (int64_t)t * I.m_p + 2 * N] * jr * jr;
+        dref = bld(rD, (uint32_t)(2 * N)) * jr * jr;
       }
-      svm[vmr + clo] = (DX ? DX[xo + n] : 0.0) + svm_s;
+      double dxm = 0.0, dxa = 0.0;
+      if (DX) {
+        const rsrc_t rDX = rsrc(DX + xo);
+        dxm = bldv(rDX, vN8, 0);
+        dxa = bldv(rDX, vN8, N8);
+      }
+      svm[vmr + clo] = dxm + svm_s;
       if (q1 > q0) sva[var + clo] = svavm_s;  // (va_n, vm_n) exists only with an incident line
-      sva[var + lva - 1] = (DX ? DX[xo + N + n] : 0.0) + sva_s + dref;
+      sva[var + lva - 1] = dxa + sva_s + dref;
       if (SWEEP) {
-        double* cp = C + I.c_off + (int64_t)t * I.m_p;
-        bp -= I.pd[(int64_t)t * N + n];
-        bq -= I.qd[(int64_t)t * N + n];
-        cp[n] = bp;
-        cp[N + n] = bq;
+        const rsrc_t rC = rsrc(C + co), rP = rsrc(I.pd + (int64_t)t * N), rQ = rsrc(I.qd + (int64_t)t * N);
+        bp -= bldv(rP, vN8, 0);
+        bq -= bldv(rQ, vN8, 0);
+        bstv(rC, vN8, 0, bp);
+        bstv(rC, vN8, N8, bq);
         if (n == I.ref) {
-          cp[2 * N] = xp[N + n];
-          jva += V[I.c_off + (int64_t)t * I.m_p + 2 * N];
+          bst(rC, (uint32_t)(2 * N), X[xo + N + n]);
+          jva += V[co + 2 * N];
         }
-        JTV[xo + n] = jvm;
-        JTV[xo + N + n] = jva;
-        GR[xo + n] = 0.0;
-        GR[xo + N + n] = 0.0;
+        const rsrc_t rO = rsrc(JTV + xo), rG = rsrc(GR + xo);
+        bstv(rO, vN8, 0, jvm);
+        bstv(rO, vN8, N8, jva);
+        bstv(rG, vN8, 0, 0.0);
+        bstv(rG, vN8, N8, 0.0);
       }
     }
     __syncthreads();
-    for (int p = tid; p < b1 - b0; p += (int)blockDim.x) kb[b0 + p] = svm[p];
-    for (int p = tid; p < a1 - a0; p += (int)blockDim.x) kb[a0 + p] = sva[p];
+    const rsrc_t rKm = rsrc(kb + b0), rKa = rsrc(kb + a0);
+    for (int p = tid; p < b1 - b0; p += (int)blockDim.x) bst(rKm, (uint32_t)p, svm[p]);
+    for (int p = tid; p < a1 - a0; p += (int)blockDim.x) bst(rKa, (uint32_t)p, sva[p]);
     __syncthreads();
   }
 }
@@ -1333,6 +1580,41 @@ hipError_t launch_hess(const Launch& L, const double* x, const double* lam, doub
   OPF_LAUNCH(k_hess, L, x, lam, sigma, hv);
 }
 hipError_t launch_cons(const Launch& L, const double* x, double* c) { OPF_LAUNCH(k_cons, L, x, c); }
+hipError_t launch_jv(const Launch& L, const double* x, const double* v, double* jv) {
+  OPF_LAUNCH(k_jv, L, x, v, jv);
+}
+
+namespace {
+// Grid of a flat launch: 256 lanes per block, at most 8 blocks per CU's
+// worth (2048) of blocks, each striding over the range.
+dim3 flat_grid(int64_t count) {
+  const int64_t blocks = (count + 255) / 256;
+  return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(blocks, 1), 2048));
+}
+}  // namespace
+
+hipError_t launch_rhs_rows(const Flat& F, const IpmDev& st, const double* c, double* dcon, double* w) {
+  if (F.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rhs_rows, flat_grid(F.count), dim3(256), 0, F.stream, F.count, st, c, dcon, w);
+  return hipGetLastError();
+}
+hipError_t launch_rhs_vars(const Flat& F, const IpmDev& st, const double* grad, double* diag_x, double* rhs) {
+  if (F.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rhs_vars, flat_grid(F.count), dim3(256), 0, F.stream, F.count, st, grad, diag_x, rhs);
+  return hipGetLastError();
+}
+hipError_t launch_rec_rows(const Flat& F, const IpmDev& st, const double* c, const double* adx, double* ds,
+                           double* dy, double* dvl, double* dvu) {
+  if (F.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rec_rows, flat_grid(F.count), dim3(256), 0, F.stream, F.count, st, c, adx, ds, dy, dvl,
+                     dvu);
+  return hipGetLastError();
+}
+hipError_t launch_rec_vars(const Flat& F, const IpmDev& st, const double* dx, double* dzl, double* dzu) {
+  if (F.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rec_vars, flat_grid(F.count), dim3(256), 0, F.stream, F.count, st, dx, dzl, dzu);
+  return hipGetLastError();
+}
 hipError_t launch_grad(const Launch& L, const double* x, double* g) { OPF_LAUNCH(k_grad, L, x, g); }
 hipError_t launch_obj_partial(const Launch& L, const double* x, double* partial) {
   OPF_LAUNCH(k_obj_partial, L, x, partial);

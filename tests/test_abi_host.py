@@ -165,3 +165,39 @@ def test_host_kkt_pattern_isolated_bus():
     orp, oci = _oracle_pattern(net)
     assert np.array_equal(rp, orp)
     assert np.array_equal(ci.astype(np.int64), oci)
+
+
+def _fake_state(**over):
+    # non-NULL placeholder addresses: validation happens before any device work
+    st = capi.opf_ipm_state()
+    for name in ("x", "s", "y", "zl", "zu", "vl", "vu", "xl", "xu", "sl", "su"):
+        setattr(st, name, 0x1000)
+    st.mu, st.delta_w, st.delta_c = 0.1, 1e-4, 1e-6
+    for k, v in over.items():
+        setattr(st, k, v)
+    return st
+
+
+@pytest.mark.parametrize("over", [dict(y=None), dict(su=None), dict(mu=-1.0), dict(delta_w=float("nan")),
+                                  dict(delta_c=-1e-9)])
+def test_condensation_calls_validate_state(over):
+    M = capi.Model([synth.config_network("tiny")], device=-1)
+    st = _fake_state(**over)
+    p = 0x1000
+    assert capi.opf_condensed_rhs(M.h, C.byref(st), p, p, p, p, p) == capi.OPF_EINVAL
+    assert len(capi.opf_last_error()) > 0
+    assert capi.opf_recover_step(M.h, C.byref(st), p, p, p, p, p, p, p, p) == capi.OPF_EINVAL
+    assert capi.opf_condensed_rhs(M.h, None, p, p, p, p, p) == capi.OPF_EINVAL
+
+
+def test_condensation_calls_need_outputs_and_a_device():
+    M = capi.Model([synth.config_network("tiny")], device=-1)
+    st = _fake_state()
+    p = 0x1000
+    assert capi.opf_condensed_rhs(M.h, C.byref(st), p, p, None, p, p) == capi.OPF_EINVAL
+    assert capi.opf_recover_step(M.h, C.byref(st), p, p, p, p, p, None, p, p) == capi.OPF_EINVAL
+    assert capi.opf_condensed_rhs(None, C.byref(st), p, p, p, p, p) == capi.OPF_EINVAL
+    # valid arguments on a host-only model: no device to run on
+    assert capi.opf_condensed_rhs(M.h, C.byref(st), p, p, p, p, p) == capi.OPF_ENODEV
+    assert capi.opf_recover_step(M.h, C.byref(st), p, p, p, p, p, p, p, p) == capi.OPF_ENODEV
+    assert capi.opf_jprod(M.h, p, p, p) == capi.OPF_ENODEV

@@ -1,0 +1,139 @@
+"""Lifted-KKT condensation calls on the GPU (Sec. III-B): J v, the condensed
+right-hand side with its weights, and the step recovery, against the oracle
+on the same seeded iterates; plus the whole chain (GPU weights, GPU
+condensed matrix, a dense solve on the host, GPU recovery) against the
+dense solution of the full seven-block system."""
+import numpy as np
+import pytest
+
+from oracle import opf_oracle as O
+from paper_2405_14032_amd import synth
+
+import gpu_common as GC
+import pins
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+CASES = {
+    "tiny": lambda: [synth.config_network("tiny")],
+    "ragged": lambda: [synth.make_network(301, 517, 63, 7, 41)],
+    "one_bus": lambda: [pins.manual_network(1, [], [], [], [], [], [0], T=3, pd=np.full((3, 1), 0.4))],
+    "parallel": lambda: [pins.manual_network(4, [0, 0, 1, 1, 2], [1, 1, 0, 2, 3], [0.01] * 5,
+                                             [0.1, 0.2, 0.15, 0.1, 0.3], [0.02] * 5, [1, 1, 3], T=3,
+                                             pd=np.full((3, 4), 0.2))],
+    "batched": lambda: [synth.make_network(31, 45, 7, 3, 71), synth.make_network(14, 20, 5, 5, 72),
+                        synth.make_network(57, 80, 11, 2, 73)],
+    "mid": lambda: [synth.config_network("mid")],
+}
+
+
+def _states(nets, seed0):
+    return [synth.make_ipm_state(*O.bounds(net), seed=seed0 + k) for k, net in enumerate(nets)]
+
+
+def _cat(states, field):
+    return np.concatenate([getattr(s, field) for s in states])
+
+
+def _device_state(M, states, torch, dev):
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    keep = {f: t(_cat(states, f)) for f in ("x", "s", "y", "zl", "zu", "vl", "vu", "xl", "xu", "sl", "su")}
+    st0 = states[0]
+    st = M.ipm_state(**keep, mu=st0.mu, delta_w=st0.delta_w, delta_c=st0.delta_c)
+    return st, keep
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_condensation_parity(name, dev):
+    import torch
+    from paper_2405_14032_amd import capi
+    nets = CASES[name]()
+    states = _states(nets, 300)
+    print(f"condensation case {name}: {[(n.N, n.B, n.G, n.T) for n in nets]}", flush=True)
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    st, keep = _device_state(M, states, torch, dev)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    grads = [O.gradient(net, s.x) for net, s in zip(nets, states)]
+    cons = [O.constraints(net, s.x) for net, s in zip(nets, states)]
+    rng = np.random.default_rng(77)
+    dxs = [rng.standard_normal(s.x.size) for s in states]
+    vs = [rng.standard_normal(s.x.size) for s in states]
+    GR, CC, DX, VV = t(np.concatenate(grads)), t(np.concatenate(cons)), t(np.concatenate(dxs)), t(np.concatenate(vs))
+    nan = lambda k: torch.full((k,), float("nan"), dtype=torch.float64, device=dev)
+    diag_x, dcon, rhs = nan(M.n), nan(M.m), nan(M.n)
+    M.condensed_rhs(st, GR, CC, diag_x, dcon, rhs)
+    outs = [nan(M.m), nan(M.m), nan(M.n), nan(M.n), nan(M.m), nan(M.m)]
+    M.recover_step(st, CC, DX, *outs)
+    jv = nan(M.m)
+    M.jprod(keep["x"], VV, jv)
+    torch.cuda.synchronize()
+    h = lambda a: a.cpu().numpy()
+    diag_x, dcon, rhs, jv = h(diag_x), h(dcon), h(rhs), h(jv)
+    outs = [h(o) for o in outs]
+    xo = co = 0
+    for k, (net, s) in enumerate(zip(nets, states)):
+        L = O.Layout(net)
+        xs, cs = slice(xo, xo + L.n), slice(co, co + L.m)
+        rdx, rd, rr, rrm = O.condensed_rhs(net, s, grads[k], cons[k], with_mag=True)
+        # Sigma_x, D: sums and products of positive terms, no cancellation
+        GC.assert_close(diag_x[xs], rdx, np.abs(rdx), GC.TOL, f"{name}[{k}] diag_x")
+        GC.assert_close(dcon[cs], rd, np.abs(rd), GC.TOL, f"{name}[{k}] dcon")
+        GC.assert_close(rhs[xs], rr, rrm, GC.TOL, f"{name}[{k}] rhs")
+        ref, mags = O.recover_step(net, s, cons[k], dxs[k], with_mag=True)
+        for what, g, r, mg, sl in zip(("ds", "dy", "dzl", "dzu", "dvl", "dvu"), outs, ref, mags,
+                                      (cs, cs, xs, xs, cs, cs)):
+            GC.assert_close(g[sl], r, mg, GC.TOL, f"{name}[{k}] {what}")
+        rj, rjm = O.jprod(net, s.x, vs[k], with_mag=True)
+        GC.assert_close(jv[cs], rj, rjm, GC.TOL, f"{name}[{k}] J v")
+        xo += L.n
+        co += L.m
+    M.close()
+
+
+@pytest.mark.parametrize("shape", [(6, 8, 2, 3, 5), (14, 20, 5, 4, 1)])
+def test_gpu_chain_solves_full_system(shape, dev):
+    """GPU weights and right-hand side, GPU J / H / K, a dense host solve of
+    K dx = rhs, GPU recovery: equal to the dense solution of the full
+    system."""
+    import torch
+    from paper_2405_14032_amd import capi
+    net, s = pins.ipm_case(*shape)
+    M = capi.Model([net], device=0)
+    M.use_current_torch_stream()
+    st, keep = _device_state(M, [s], torch, dev)
+    e = lambda k: torch.empty(k, dtype=torch.float64, device=dev)
+    grad, c = e(M.n), e(M.m)
+    M.eval_grad(keep["x"], grad)
+    M.eval_cons(keep["x"], c)
+    diag_x, dcon, rhs = e(M.n), e(M.m), e(M.n)
+    M.condensed_rhs(st, grad, c, diag_x, dcon, rhs)
+    jv, hv, kv = e(M.nnz_jac), e(M.nnz_hess), e(M.nnz_kkt)
+    M.eval_jhk(keep["x"], -keep["y"], 1.0, diag_x, dcon, jv, hv, kv)  # W = Hess f - sum y_i Hess c_i
+    rp = torch.empty(M.n + 1, dtype=torch.int64, device=dev)
+    ci = torch.empty(M.nnz_kkt, dtype=torch.int32, device=dev)
+    M.kkt_structure(rp, ci)
+    torch.cuda.synchronize()
+    rp_h, ci_h, kv_h = rp.cpu().numpy(), ci.cpu().numpy(), kv.cpu().numpy()
+    K = np.zeros((M.n, M.n))
+    K[np.repeat(np.arange(M.n), np.diff(rp_h)), ci_h] = kv_h
+    K = K + np.tril(K, -1).T
+    dx = np.linalg.solve(K, rhs.cpu().numpy())
+    DX = torch.tensor(dx, dtype=torch.float64, device=dev)
+    outs = [e(M.m), e(M.m), e(M.n), e(M.n), e(M.m), e(M.m)]
+    M.recover_step(st, c, DX, *outs)
+    torch.cuda.synchronize()
+    mine = [dx] + [o.cpu().numpy() for o in outs]
+    ref = pins.full_kkt_solution(net, s)
+    for what, a, b in zip(("dx", "ds", "dy", "dzl", "dzu", "dvl", "dvu"), mine, ref):
+        err = float(np.max(np.abs(a - b))) / max(1.0, float(np.max(np.abs(b))))
+        assert err <= 1e-8, (what, err)
+    M.close()
