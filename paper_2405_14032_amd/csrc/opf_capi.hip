@@ -355,7 +355,7 @@ struct Arena {
 int upload_model(opf_model* M) {
   Arena a;
   struct Place {
-    size_t f_bus, t_bus, gen_bus, adm, c2, c1, c0, pd, qd, bus_ptr, bus_adj, bus_nb, bgen_ptr, bgen, krow, kcol, ksrc;
+    size_t f_bus, t_bus, gen_bus, adm, c2, c1, c0, pd, qd, bus_ptr, bus_adj, bus_nb, bgen_ptr, bgen, krow, kcol, ksrc, kinfo;
     size_t vmin, vmax, pmin, pmax, qmin, qmax, ramp, rate, angmin, angmax;
   };
   std::vector<Place> pl(M->inst.size());
@@ -381,6 +381,7 @@ int upload_model(opf_model* M) {
     p.krow = a.take(b4(I.krow.size()));
     p.kcol = a.take(b4(I.kcol.size()));
     p.ksrc = a.take(b4(I.ksrc.size()));
+    p.kinfo = a.take(b4(I.kinfo.size()));
     p.vmin = a.take(b8(I.vmin.size()));
     p.vmax = a.take(b8(I.vmax.size()));
     p.pmin = a.take(b8(I.pmin.size()));
@@ -423,6 +424,7 @@ int upload_model(opf_model* M) {
     PUT(krow);
     PUT(kcol);
     PUT(ksrc);
+    PUT(kinfo);
     PUT(vmin);
     PUT(vmax);
     PUT(pmin);
@@ -472,6 +474,7 @@ int upload_model(opf_model* M) {
     PTR(krow, const int32_t*);
     PTR(kcol, const int32_t*);
     PTR(ksrc, const int32_t*);
+    PTR(kinfo, const int32_t*);
     PTR(vmin, const double*);
     PTR(vmax, const double*);
     PTR(pmin, const double*);

@@ -19,7 +19,7 @@ struct InstDev {
   const double *c2, *c1, *c0;
   double *pd, *qd;  // [T][N]
   const int32_t *bus_ptr, *bus_adj, *bus_nb, *bgen_ptr, *bgen;
-  const int32_t *krow, *kcol, *ksrc;
+  const int32_t *krow, *kcol, *ksrc, *kinfo;
   const double *vmin, *vmax, *pmin, *pmax, *qmin, *qmax, *ramp, *rate, *angmin, *angmax;
 };
 
@@ -89,6 +89,14 @@ __device__ __forceinline__ double bldv(rsrc_t r, uint32_t vo, uint32_t so) {
 }
 __device__ __forceinline__ void bstv(rsrc_t r, uint32_t vo, uint32_t so, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, vo, so, 0);
+}
+// Non-temporal variants (cache policy nt): output streams that no later
+// step of the same kernel reads back.
+__device__ __forceinline__ void bstvn(rsrc_t r, uint32_t vo, uint32_t so, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, vo, so, 2);
+}
+__device__ __forceinline__ void bstn(rsrc_t r, uint32_t e, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, e * 8u, 0, 2);
 }
 __device__ __forceinline__ int32_t bldiv(rsrc_t r, uint32_t vo, uint32_t so) {
   return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);

@@ -42,6 +42,11 @@ struct InstHost {
   // n_p local rows, local column, and per slot the J local index of the
   // partner entry (kSrcNone / kSrcThermal otherwise)
   std::vector<int32_t> krow, kcol, ksrc;
+  // per flow row (k * B + l): the kinds of its partner slots (the slots
+  // between the four bus-variable slots and the diagonal), packed as
+  // (number of leading generator partners) | (thermal slot offset << 16),
+  // offset 0xFFFF when the row has no thermal partner
+  std::vector<int32_t> kinfo;
 };
 
 // Validates the descriptors.  Returns OPF_OK or an error code with a message.

@@ -828,7 +828,7 @@ __device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, double sigma, d
 // balance partner) holds the factor d_bal * J_bal and is multiplied by that
 // entry; four slots per lane are handled per step so their template loads
 // and J gathers are in flight together.
-template <bool GATHER>
+template <bool GATHER, bool NT = false>
 __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, rsrc_t src, rsrc_t jp, rsrc_t dst,
                                                int len) {
   constexpr int U = 4;
@@ -850,7 +850,10 @@ __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, r
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = p0 + u * bd;
-      if (p < len) bst(dst, (uint32_t)p, v[u]);
+      if (p < len) {
+        if (NT) bstn(dst, (uint32_t)p, v[u]);
+        else bst(dst, (uint32_t)p, v[u]);
+      }
     }
   }
 }
@@ -1096,6 +1099,234 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
   }
 }
 
+// One line tile of the fused evaluation: J and H of the lines from x and
+// lambda, written out and used directly for the flow rows of K (the partner
+// J entries are the structural +1 / -1 of the balance rows); with SWEEP also
+// the constraint rows, J^T v and gradient on the flow variables and the bus
+// hand-off of p, q and J^T v.  Every load of a line-period is issued before
+// its first store: vector-memory completions are counted in order, so a
+// load issued after stores cannot be consumed before those stores are done.
+// The partner kinds of each K flow row come from the template's per-row
+// summary (leading generator partners, thermal slot), not from per-slot
+// source indices.
+template <bool SWEEP>
+__device__ void fused_line_tile(const InstDev& I, const Tile& tl, const double* __restrict__ X,
+                                const double* __restrict__ LAM, double* __restrict__ H, double* __restrict__ J,
+                                const double* __restrict__ DX, const double* __restrict__ D, double* __restrict__ K,
+                                double* __restrict__ scr, double* __restrict__ seg, double* sadm,
+                                const double* __restrict__ V, double* __restrict__ C, double* __restrict__ JTV,
+                                double* __restrict__ GR) {
+  const Bases b(I);
+  // element offsets inside one period block, as byte offsets (every period
+  // block is far below 4 GiB)
+  const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, G = (uint32_t)b.G;
+  const uint32_t xFL8 = (uint32_t)b.xFL * 8u, jFLOW8 = (uint32_t)b.jFLOW * 8u, jBAL8 = (uint32_t)b.jBAL * 8u,
+                 jTH8 = (uint32_t)b.jTH * 8u, jANG8 = (uint32_t)b.jANG * 8u, hFLOW8 = (uint32_t)b.hFLOW * 8u,
+                 hTH8 = (uint32_t)b.hTH * 8u, cFLOW8 = (uint32_t)b.cFLOW * 8u, cTHF8 = (uint32_t)b.cTHF * 8u,
+                 cTHT8 = (uint32_t)b.cTHT * 8u, cANG8 = (uint32_t)b.cANG * 8u;
+  const int tid = (int)threadIdx.x;
+  const int bd = (int)blockDim.x;
+  const uint32_t l = (uint32_t)(tl.e0 + tid);
+  const bool act = (int)l < tl.e1;
+  // lane offsets: every per-line stream is (uniform stream offset) + vL
+  const uint32_t vL = l * 8u, vL4 = l * 4u, vR = l * (uint32_t)(kRecLine * 8);
+  const rsrc_t rKrow = rsrc(I.krow);
+  const uint32_t FL4 = (uint32_t)b.xFL * 4u, Bq = (uint32_t)b.B * 4u;
+  int sb[4], se[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    sb[k] = __builtin_amdgcn_readfirstlane(bldi(rKrow, (uint32_t)b.xFL + (uint32_t)k * (uint32_t)b.B + tl.e0));
+    se[k] = __builtin_amdgcn_readfirstlane(bldi(rKrow, (uint32_t)b.xFL + (uint32_t)k * (uint32_t)b.B + tl.e1));
+  }
+  // per-line constants of the tile: bus offsets, K row bounds and partner
+  // summaries of the four flow rows, the admittances (into LDS)
+  uint32_t vI = 0, vJ = 0;
+  bool ilo = true;
+  int rs[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0}, kinf[4] = {0, 0, 0, 0};
+  if (act) {
+    const int i = bldi(rsrc(I.f_bus), l), j = bldi(rsrc(I.t_bus), l);
+    ilo = i < j;
+    vI = (uint32_t)i * 8u;
+    vJ = (uint32_t)j * 8u;
+    const rsrc_t rA = rsrc(I.adm), rKi = rsrc(I.kinfo);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) sadm[a * bd + tid] = bldv(rA, vL, (uint32_t)a * B8);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      rs[k] = bldiv(rKrow, vL4, FL4 + (uint32_t)k * Bq) - sb[k];
+      re[k] = bldiv(rKrow, vL4, FL4 + (uint32_t)k * Bq + 4u) - sb[k];
+      kinf[k] = bldiv(rKi, vL4, (uint32_t)k * Bq);
+    }
+  }
+  for (int t = tl.t0; t < tl.t1; ++t) {
+    const int64_t xo = I.x_off + (int64_t)t * I.n_p;
+    const int64_t co = I.c_off + (int64_t)t * I.m_p;
+    const rsrc_t rJ = rsrc(J + I.j_off + (int64_t)t * I.nnzj_p);
+    const rsrc_t rH = rsrc(H + I.h_off + (int64_t)t * I.nnzh_p);
+    const rsrc_t rD = rsrc(D + co), rX = rsrc(X + xo), rL = rsrc(LAM + co);
+    double* kbase = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t) + (t >= 1 ? G : 0);
+    // ---- every load of this line-period
+    double vi = 0.0, vj = 0.0, ti = 0.0, tj = 0.0, fl[4] = {0.0, 0.0, 0.0, 0.0}, lf = 0.0, lt = 0.0;
+    double dth[2] = {0.0, 0.0}, dang = 0.0, dfk[4], lamk[4], dbk[4], dxk[4], vk[4];
+    double vtf = 0.0, vtt = 0.0, vang = 0.0, vbal[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dfk[k] = lamk[k] = dbk[k] = dxk[k] = vk[k] = vbal[k] = 0.0;
+    if (act) {
+      vi = bldv(rX, vI, 0);
+      vj = bldv(rX, vJ, 0);
+      ti = bldv(rX, vI, N8);
+      tj = bldv(rX, vJ, N8);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) fl[k] = bldv(rX, vL, xFL8 + (uint32_t)k * B8);
+      lf = 2.0 * bldv(rL, vL, cTHF8);
+      lt = 2.0 * bldv(rL, vL, cTHT8);
+      dth[0] = bldv(rD, vL, cTHF8);
+      dth[1] = bldv(rD, vL, cTHT8);
+      dang = bldv(rD, vL, cANG8);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        dfk[k] = bldv(rD, vL, cFLOW8 + (uint32_t)k * B8);
+        lamk[k] = bldv(rL, vL, cFLOW8 + (uint32_t)k * B8);
+        dbk[k] = bldv(rD, k < 2 ? vI : vJ, (k & 1) ? N8 : 0u);
+      }
+      if (DX) {
+        const rsrc_t rDX = rsrc(DX + xo);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dxk[k] = bldv(rDX, vL, xFL8 + (uint32_t)k * B8);
+      }
+      if constexpr (SWEEP) {
+        const rsrc_t rV = rsrc(V + co);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) vk[k] = bldv(rV, vL, cFLOW8 + (uint32_t)k * B8);
+        vtf = bldv(rV, vL, cTHF8);
+        vtt = bldv(rV, vL, cTHT8);
+        vang = bldv(rV, vL, cANG8);
+        vbal[0] = bldv(rV, vI, 0);
+        vbal[1] = bldv(rV, vI, N8);
+        vbal[2] = bldv(rV, vJ, 0);
+        vbal[3] = bldv(rV, vJ, N8);
+      }
+    }
+    double sn = 0.0, cs = 0.0;
+    sincos(ti - tj, &sn, &cs);
+    const double vv = vi * vj;
+    double q[10], Jt[4];
+#pragma unroll
+    for (int a = 0; a < 10; ++a) q[a] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Jt[k] = 2.0 * fl[k];
+    double svi = 0.0, svj = 0.0, sti = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t kB8 = (uint32_t)k * B8;
+      if (act) {
+        double Jk[5], hf[9];
+        Coef cf;
+        coef_kind_lds(sadm, bd, tid, k, cf);
+        flow_kind(cf, k, vi, vj, vv, sn, cs, -lamk[k], Jk, hf);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) bstvn(rJ, vL, jFLOW8 + (uint32_t)(k * 5 + a) * B8, Jk[a]);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) bstvn(rH, vL, hFLOW8 + (uint32_t)(k * 9 + a) * B8, hf[a]);
+        const double Jbk = -1.0;
+        const double Hthk = k < 2 ? lf : lt;
+        bstvn(rJ, vL, jBAL8 + kB8, Jbk);
+        bstvn(rJ, vL, jTH8 + kB8, Jt[k]);
+        bstvn(rH, vL, hTH8 + kB8, Hthk);
+        if constexpr (SWEEP) {
+          bstvn(rsrc(C + co), vL, cFLOW8 + kB8, fl[k] - flow_value(cf, k, vi, vj, vv, flow_w(cf, k, sn, cs)));
+          svi += vk[k] * Jk[1];
+          svj += vk[k] * Jk[2];
+          sti += vk[k] * Jk[3];
+        }
+        // bus-variable contributions: d_k J_k,a J_k,b + H (local H order:
+        // from end (0,0)(1,0)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3); to end
+        // (1,0)(1,1)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3))
+        const double a1 = Jk[1], a2 = Jk[2], a3 = Jk[3], a4 = Jk[4];
+        const double dk = dfk[k];
+        const double d1 = dk * a1, d2 = dk * a2, d3 = dk * a3, d4 = dk * a4;
+        if (k < 2) {
+          q[0] += d1 * a1 + hf[0];
+          q[6] += d2 * a2;
+          q[4] += d2 * a1 + hf[1];
+        } else {
+          q[0] += d1 * a1;
+          q[6] += d2 * a2 + hf[1];
+          q[4] += d2 * a1 + hf[0];
+        }
+        q[1] += d3 * a1 + hf[2];
+        q[3] += d3 * a2 + hf[3];
+        q[2] += d3 * a3 + hf[4];
+        q[9] += d4 * a1 + hf[5];
+        q[7] += d4 * a2 + hf[6];
+        q[5] += d4 * a3 + hf[7];
+        q[8] += d4 * a4 + hf[8];
+        // this kind's K row into the LDS copy of the block's row segment
+        const double pk = dk * Jk[0];
+        double* row = seg + rs[k];
+        if (ilo) {
+          row[0] = pk * Jk[1];
+          row[1] = pk * Jk[2];
+          row[2] = pk * Jk[3];
+          row[3] = pk * Jk[4];
+        } else {
+          row[0] = pk * Jk[2];
+          row[1] = pk * Jk[1];
+          row[2] = pk * Jk[4];
+          row[3] = pk * Jk[3];
+        }
+        // partners: generators (+1) first, then line ends (-1), with the
+        // thermal partner (odd kinds) at its summarised slot
+        const double pb = dbk[k] * Jbk;
+        const int ngen = kinf[k] & 0xFFFF, th = (int)((uint32_t)kinf[k] >> 16);
+        const double thv = dth[k >> 1] * Jt[k ^ 1] * Jt[k];
+        const double gv = pb * 1.0, lv = pb * -1.0;
+        for (int p = 0; p < re[k] - rs[k] - 5; ++p) seg[rs[k] + 4 + p] = p == th ? thv : (p < ngen ? gv : lv);
+        seg[re[k] - 1] = dxk[k] + pk * Jk[0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jbk + Hthk;
+      }
+      __syncthreads();
+      stream_segment<false, true>(seg, rKrow, rKrow, rsrc(kbase + sb[k]), se[k] - sb[k]);
+      __syncthreads();
+    }
+    if (act) {
+      const double Ja0 = 1.0, Ja1 = -1.0;
+      bstvn(rJ, vL, jANG8, Ja0);
+      bstvn(rJ, vL, jANG8 + B8, Ja1);
+      q[2] += dang * Ja0 * Ja0;
+      q[8] += dang * Ja1 * Ja1;
+      q[5] += dang * Ja1 * Ja0;
+      double jtr[4] = {0.0, 0.0, 0.0, 0.0};
+      if constexpr (SWEEP) {
+        const rsrc_t rC = rsrc(C + co), rO = rsrc(JTV + xo), rG = rsrc(GR + xo);
+        bstvn(rC, vL, cTHF8, fl[0] * fl[0] + fl[1] * fl[1]);
+        bstvn(rC, vL, cTHT8, fl[2] * fl[2] + fl[3] * fl[3]);
+        bstvn(rC, vL, cANG8, ti - tj);
+        bstvn(rO, vL, xFL8, vk[0] + vtf * (2.0 * fl[0]) - vbal[0]);
+        bstvn(rO, vL, xFL8 + B8, vk[1] + vtf * (2.0 * fl[1]) - vbal[1]);
+        bstvn(rO, vL, xFL8 + 2 * B8, vk[2] + vtt * (2.0 * fl[2]) - vbal[2]);
+        bstvn(rO, vL, xFL8 + 3 * B8, vk[3] + vtt * (2.0 * fl[3]) - vbal[3]);
+        jtr[0] = svi;
+        jtr[1] = sti + vang;
+        jtr[2] = svj;
+        jtr[3] = -sti - vang;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bstvn(rG, vL, xFL8 + (uint32_t)k * B8, 0.0);
+      }
+      // hand-off: one 64-byte record per line end, the shared cross pair
+      const rsrc_t rR = rsrc(rec_at(I, scr, t));
+      bst2v(rR, vR, 0, make_double2(q[0], q[1]));
+      bst2v(rR, vR, 16, make_double2(q[2], q[3]));
+      bst2v(rR, vR, 32, make_double2(fl[0], fl[1]));
+      bst2v(rR, vR, 48, make_double2(jtr[0], jtr[1]));
+      bst2v(rR, vR, 64, make_double2(q[6], q[7]));
+      bst2v(rR, vR, 80, make_double2(q[8], q[9]));
+      bst2v(rR, vR, 96, make_double2(fl[2], fl[3]));
+      bst2v(rR, vR, 112, make_double2(jtr[2], jtr[3]));
+      bst2v(rsrc(shared_at(I, scr, t)), vL * 2u, 0, make_double2(q[4], q[5]));
+    }
+  }
+}
+
 // Dynamic LDS: seg[cap_seg] doubles (the longest K row segment of a tile).
 __global__ void __launch_bounds__(256) k_kkt_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
                                                int ntiles, int cap_seg, const double* __restrict__ H,
@@ -1132,7 +1363,7 @@ __global__ void __launch_bounds__(256) k_jhk_a(const InstDev* __restrict__ insts
     const Tile tl = tiles[remap_tile(v, ntiles)];
     const InstDev& I = insts[tl.inst];
     if (tl.kind == TK_BRANCH) {
-      kkt_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, lds + cap_seg);
+      fused_line_tile<false>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, lds + cap_seg, nullptr, nullptr, nullptr, nullptr);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
       if (e < tl.e1) kkt_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K);
@@ -1156,7 +1387,7 @@ __global__ void __launch_bounds__(256) k_sweep_a(const InstDev* __restrict__ ins
     const Tile tl = tiles[remap_tile(v, ntiles)];
     const InstDev& I = insts[tl.inst];
     if (tl.kind == TK_BRANCH) {
-      kkt_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, lds + cap_seg, V, C, JTV, GR);
+      fused_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, lds + cap_seg, V, C, JTV, GR);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
       if (e < tl.e1) kkt_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K, X, V, C, JTV, GR);
@@ -1308,23 +1539,23 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
         const rsrc_t rC = rsrc(C + co), rP = rsrc(I.pd + (int64_t)t * N), rQ = rsrc(I.qd + (int64_t)t * N);
         bp -= bldv(rP, vN8, 0);
         bq -= bldv(rQ, vN8, 0);
-        bstv(rC, vN8, 0, bp);
-        bstv(rC, vN8, N8, bq);
+        bstvn(rC, vN8, 0, bp);
+        bstvn(rC, vN8, N8, bq);
         if (n == I.ref) {
           bst(rC, (uint32_t)(2 * N), X[xo + N + n]);
           jva += V[co + 2 * N];
         }
         const rsrc_t rO = rsrc(JTV + xo), rG = rsrc(GR + xo);
-        bstv(rO, vN8, 0, jvm);
-        bstv(rO, vN8, N8, jva);
-        bstv(rG, vN8, 0, 0.0);
-        bstv(rG, vN8, N8, 0.0);
+        bstvn(rO, vN8, 0, jvm);
+        bstvn(rO, vN8, N8, jva);
+        bstvn(rG, vN8, 0, 0.0);
+        bstvn(rG, vN8, N8, 0.0);
       }
     }
     __syncthreads();
     const rsrc_t rKm = rsrc(kb + b0), rKa = rsrc(kb + a0);
-    for (int p = tid; p < b1 - b0; p += (int)blockDim.x) bst(rKm, (uint32_t)p, svm[p]);
-    for (int p = tid; p < a1 - a0; p += (int)blockDim.x) bst(rKa, (uint32_t)p, sva[p]);
+    for (int p = tid; p < b1 - b0; p += (int)blockDim.x) bstn(rKm, (uint32_t)p, svm[p]);
+    for (int p = tid; p < a1 - a0; p += (int)blockDim.x) bstn(rKa, (uint32_t)p, sva[p]);
     __syncthreads();
   }
 }

@@ -254,6 +254,8 @@ int build_instance(const opf_instance_desc& d, InstHost& I, std::string& err) {
   }
   // flow rows: the four bus variables of the line, the lower members of
   // the balance row the flow enters, the thermal partner, the diagonal
+  I.kinfo.assign(4 * (size_t)B, 0);
+  bool small = true;
   for (int k = 0; k < 4; ++k) {
     const bool is_p = (k % 2) == 0;
     for (int32_t l = 0; l < B; ++l) {
@@ -279,7 +281,21 @@ int build_instance(const opf_instance_desc& d, InstHost& I, std::string& err) {
       if (k == 3) row.push_back({FL + 2LL * B + l, kSrcThermal});
       row.push_back({own, kSrcNone});
       ok &= flush(own);
+      // partner slot kinds of the row just emitted (columns ascending:
+      // generator partners come before every flow-variable partner)
+      const int32_t p0 = I.krow[own] + 4, p1 = I.krow[own + 1] - 1;
+      int32_t ngen = 0, th = 0xFFFF;
+      for (int32_t q = p0; q < p1; ++q) {
+        if (I.ksrc[q] == kSrcThermal) th = q - p0;
+        else if (I.ksrc[q] >= 0 && I.ksrc[q] < 2 * G) ++ngen;
+      }
+      small &= (p1 - p0) < 0xFFFF;
+      I.kinfo[(size_t)k * B + l] = (int32_t)((uint32_t)ngen | ((uint32_t)th << 16));
     }
+  }
+  if (!small) {
+    err = "a bus has too many incident lines and generators for the condensed-matrix template";
+    return OPF_ERANGE;
   }
   if (!ok) {
     err = "internal: duplicate column in the condensed-matrix template";
