@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -98,7 +99,38 @@ def event_time(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(periods: int = 24):
+PROFILE = os.path.join(ROOT, "profiles", "sweep_paper_scale.txt")
+KERNEL_SOURCES = ("paper_2405_14032_amd/csrc/opf_kernels.hip", "paper_2405_14032_amd/csrc/opf_device.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3
+    summary (calibrated FETCH_SIZE + WRITE_SIZE), or None when the summary
+    is missing or was taken on other kernel sources."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel sources sha256\[:16\][^:]*:\s*([0-9a-f]+)", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    for line in text.splitlines():
+        f = line.split()
+        if f and f[0] == kernel and len(f) == 9:
+            return float(f[8]) * 1e6
+    return None
+
+
+def cpu_baseline(periods: int = 96):
     """The oracle as it stands, on the paper-scale grid over a shorter
     horizon (a bounded sample), one full sweep; nnz/s like the GPU value."""
     from oracle import opf_oracle as O
@@ -217,7 +249,8 @@ def bench_plain(torch, dev, args):
     res["roofline"] = {"bound": "hbm", "kernel": "k_sweep_a (lines and generators of the fused sweep)",
                        "achieved": round(kb["sweep_a"] / kt / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(kb["sweep_a"] / kt / 1e6 / HBM_PEAK_GBS, 4),
-                       "algorithmic_bytes": kb["sweep_a"], "avg_ms": kt, "traffic": None}
+                       "algorithmic_bytes": kb["sweep_a"], "avg_ms": kt, "traffic": profiled_traffic("k_sweep_a"),
+                       "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
     kt_b = kernels["sweep_b"]["avg_ms"]
     res["roofline_bus"] = {"kernel": "k_sweep_b", "achieved": round(kb["sweep_b"] / kt_b / 1e6, 1),
                            "algorithmic_bytes": kb["sweep_b"], "avg_ms": kt_b}

@@ -46,19 +46,6 @@ __device__ __forceinline__ int64_t kkt_period_offset_dev(int64_t nnzk_p, int32_t
   return (int64_t)t * nnzk_p + (t >= 1 ? (int64_t)(t - 1) * G : 0);
 }
 
-// Access to a per-period block through its (wave-uniform) base pointer and
-// a 32-bit element offset.  Every per-period block is far below 4 GiB, so
-// the byte offset fits 32 bits; written this way the address is a scalar
-// base plus one 32-bit vector offset instead of a 64-bit vector address.
-template <class T>
-__device__ __forceinline__ T ldo(const T* base, uint32_t e) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + e * (uint32_t)sizeof(T));
-}
-template <class T>
-__device__ __forceinline__ void sto(T* base, uint32_t e, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + e * (uint32_t)sizeof(T)) = v;
-}
-
 // Buffer-resource access: a wave-uniform 128-bit descriptor (base address,
 // unlimited extent) in scalar registers plus a 32-bit per-lane byte offset,
 // the addressing form of the vector memory unit that needs no 64-bit
@@ -106,12 +93,6 @@ __device__ __forceinline__ void bst2v(rsrc_t r, uint32_t vo, uint32_t so, double
 }
 __device__ __forceinline__ double2 bld2v(rsrc_t r, uint32_t vo, uint32_t so) {
   return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
-}
-__device__ __forceinline__ double2 bld2(rsrc_t r, uint32_t e) {  // e: index of the double2
-  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, e * 16u, 0, 0));
-}
-__device__ __forceinline__ void bst2(rsrc_t r, uint32_t e, double2 v) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, e * 16u, 0, 0);
 }
 
 // Per-instance scratch, in doubles, per line and period:

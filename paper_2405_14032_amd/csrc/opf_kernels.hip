@@ -755,42 +755,22 @@ __global__ void __launch_bounds__(512) k_jt_b(const InstDev* __restrict__ insts,
 // diagonal; qg: balance partners, diagonal).  FUSED: the generator's J and H
 // entries are produced here (structural constants and 2 sigma c2) and
 // written, and K uses those values; otherwise K reads them from J and H.
-template <bool FUSED>
-__device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, double sigma, double* __restrict__ H,
-                        double* __restrict__ J, const double* __restrict__ DX, const double* __restrict__ D,
-                        double* __restrict__ K, const double* __restrict__ X = nullptr,
-                        const double* __restrict__ V = nullptr, double* __restrict__ C = nullptr,
-                        double* __restrict__ JTV = nullptr, double* __restrict__ GR = nullptr) {
+// One generator of the condensed assembly over its tile's periods: the pg
+// and qg rows of K from the given J / H values.
+__device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, const double* __restrict__ H,
+                        const double* __restrict__ J, const double* __restrict__ DX, const double* __restrict__ D,
+                        double* __restrict__ K) {
   const int64_t N = I.N, G = I.G;
   const int n = I.gen_bus[g];
   const int64_t rp = 2 * N + g, rq = 2 * N + G + g;
   const int ps = I.krow[rp], pe = I.krow[rp + 1], qs = I.krow[rq], qe = I.krow[rq + 1];
-  double* jr = J + I.j_off + (int64_t)I.T * I.nnzj_p;   // ramp block of J
-  const double* dr = D + I.c_off + (int64_t)I.T * I.m_p;  // ramp rows of D
-  const double hobj = 2.0 * sigma * I.c2[g];
+  const double* jr = J + I.j_off + (int64_t)I.T * I.nnzj_p;  // ramp block of J
+  const double* dr = D + I.c_off + (int64_t)I.T * I.m_p;     // ramp rows of D
   for (int t = t0; t < t1; ++t) {
-    double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
+    const double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
     const double* dp = D + I.c_off + (int64_t)t * I.m_p;
     double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
-    double Jgp, Jgq, Hg;
-    if constexpr (FUSED) {
-      Jgp = 1.0;
-      Jgq = 1.0;
-      Hg = hobj;
-      jp[g] = Jgp;
-      jp[G + g] = Jgq;
-      if (g == 0) jp[2 * G + 4LL * I.B] = 1.0;  // reference-angle row
-      H[I.h_off + (int64_t)t * I.nnzh_p + g] = Hg;
-      if (t >= 1) {
-        double* jt = jr + (int64_t)(t - 1) * 2 * G;
-        jt[g] = 1.0;
-        jt[G + g] = -1.0;
-      }
-    } else {
-      Jgp = jp[g];
-      Jgq = jp[G + g];
-      Hg = H[I.h_off + (int64_t)t * I.nnzh_p + g];
-    }
+    const double Jgp = jp[g], Jgq = jp[G + g], Hg = H[I.h_off + (int64_t)t * I.nnzh_p + g];
     const double pbp = dp[n] * Jgp, pbq = dp[N + n] * Jgq;
     const int64_t xo = I.x_off + (int64_t)t * I.n_p;
     double diag = (DX ? DX[xo + rp] : 0.0) + pbp * Jgp + Hg;
@@ -798,27 +778,99 @@ __device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, double sigma, d
     if (t >= 1) {
       const double* jt = jr + (int64_t)(t - 1) * 2 * G;
       const double d = dr[(int64_t)(t - 1) * G + g];
-      const double j0 = FUSED ? 1.0 : jt[g], j1 = FUSED ? -1.0 : jt[G + g];
+      const double j0 = jt[g], j1 = jt[G + g];
       kb[ps + g] = d * j0 * j1;
       diag += d * j0 * j0;
     }
     if (t + 1 < I.T) {
-      const double j1 = FUSED ? -1.0 : jr[(int64_t)t * 2 * G + G + g];
+      const double j1 = jr[(int64_t)t * 2 * G + G + g];
       diag += dr[(int64_t)t * G + g] * j1 * j1;
     }
-    // balance partners of a generator row are generators (J = +1)
-    for (int p = ps; p < pe - 1; ++p) kb[p + sp] = pbp * (FUSED ? 1.0 : jp[I.ksrc[p]]);
+    // balance partners of a generator row are generators
+    for (int p = ps; p < pe - 1; ++p) kb[p + sp] = pbp * jp[I.ksrc[p]];
     kb[pe - 1 + sp] = diag;
-    for (int p = qs; p < qe - 1; ++p) kb[p + sq] = pbq * (FUSED ? 1.0 : jp[I.ksrc[p]]);
+    for (int p = qs; p < qe - 1; ++p) kb[p + sq] = pbq * jp[I.ksrc[p]];
     kb[qe - 1 + sq] = (DX ? DX[xo + rq] : 0.0) + pbq * Jgq;
-    if constexpr (FUSED) {
-      // the rest of the sweep on this generator: ramp row, J^T v, gradient
-      if (C && t >= 1) C[I.c_off + (int64_t)I.T * I.m_p + (int64_t)(t - 1) * G + g] = X[xo + rp] - X[xo + rp - I.n_p];
-      if (JTV) jt_gen_period(I, g, n, t, V, JTV);
-      if (GR) {
-        GR[xo + rp] = 2.0 * I.c2[g] * X[xo + rp] + I.c1[g];
-        GR[xo + rq] = 0.0;
-      }
+  }
+}
+
+// One generator of the fused evaluation over its tile's periods: J, H and
+// the generator rows of K (balance partners are generators, J = +1), and
+// with SWEEP the ramp row, J^T v and gradient entries of pg / qg.  Loads of
+// a period come before its stores (in-order completion counting), and the
+// output streams use non-temporal stores; values are the same expressions
+// as kkt_gen's.
+template <bool SWEEP>
+__device__ void fused_gen(const InstDev& I, int g, int t0, int t1, double sigma, double* __restrict__ H,
+                          double* __restrict__ J, const double* __restrict__ DX, const double* __restrict__ D,
+                          double* __restrict__ K, const double* __restrict__ X, const double* __restrict__ V,
+                          double* __restrict__ C, double* __restrict__ JTV, double* __restrict__ GR) {
+  const int64_t N = I.N, G = I.G;
+  const int n = I.gen_bus[g];
+  const int64_t rp = 2 * N + g, rq = 2 * N + G + g;
+  const int ps = I.krow[rp], pe = I.krow[rp + 1], qs = I.krow[rq], qe = I.krow[rq + 1];
+  double* jr = J + I.j_off + (int64_t)I.T * I.nnzj_p;   // ramp block of J
+  const double* dr = D + I.c_off + (int64_t)I.T * I.m_p;  // ramp rows of D
+  const double hobj = 2.0 * sigma * I.c2[g];
+  const double c2g = SWEEP ? I.c2[g] : 0.0, c1g = SWEEP ? I.c1[g] : 0.0;
+  const double* vr = SWEEP ? V + I.c_off + (int64_t)I.T * I.m_p : nullptr;
+  for (int t = t0; t < t1; ++t) {
+    double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
+    const double* dp = D + I.c_off + (int64_t)t * I.m_p;
+    double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
+    const int64_t xo = I.x_off + (int64_t)t * I.n_p;
+    const int64_t co = I.c_off + (int64_t)t * I.m_p;
+    const bool up = t >= 1, dn = t + 1 < I.T;
+    // ---- loads
+    const double dpn = dp[n], dqn = dp[N + n];
+    const double dxp = DX ? DX[xo + rp] : 0.0, dxq = DX ? DX[xo + rq] : 0.0;
+    const double drm = up ? dr[(int64_t)(t - 1) * G + g] : 0.0, drp = dn ? dr[(int64_t)t * G + g] : 0.0;
+    double xg = 0.0, xgm = 0.0, vpn = 0.0, vqn = 0.0, vrm = 0.0, vrp = 0.0;
+    if constexpr (SWEEP) {
+      xg = X[xo + rp];
+      xgm = up ? X[xo + rp - I.n_p] : 0.0;
+      vpn = V[co + n];
+      vqn = V[co + N + n];
+      vrm = up ? vr[(int64_t)(t - 1) * G + g] : 0.0;
+      vrp = dn ? vr[(int64_t)t * G + g] : 0.0;
+    }
+    // ---- stores
+    const double Jgp = 1.0, Jgq = 1.0, Hg = hobj;
+    __builtin_nontemporal_store(Jgp, jp + g);
+    __builtin_nontemporal_store(Jgq, jp + G + g);
+    if (g == 0) __builtin_nontemporal_store(1.0, jp + 2 * G + 4LL * I.B);  // reference-angle row
+    __builtin_nontemporal_store(Hg, H + I.h_off + (int64_t)t * I.nnzh_p + g);
+    if (up) {
+      double* jt = jr + (int64_t)(t - 1) * 2 * G;
+      __builtin_nontemporal_store(1.0, jt + g);
+      __builtin_nontemporal_store(-1.0, jt + G + g);
+    }
+    const double pbp = dpn * Jgp, pbq = dqn * Jgq;
+    double diag = dxp + pbp * Jgp + Hg;
+    const int sp = up ? g + 1 : 0, sq = up ? (int)G : 0;
+    if (up) {
+      const double j0 = 1.0, j1 = -1.0;
+      __builtin_nontemporal_store(drm * j0 * j1, kb + ps + g);
+      diag += drm * j0 * j0;
+    }
+    if (dn) {
+      const double j1 = -1.0;
+      diag += drp * j1 * j1;
+    }
+    // balance partners of a generator row are generators (J = +1)
+    for (int p = ps; p < pe - 1; ++p) __builtin_nontemporal_store(pbp * 1.0, kb + p + sp);
+    __builtin_nontemporal_store(diag, kb + pe - 1 + sp);
+    for (int p = qs; p < qe - 1; ++p) __builtin_nontemporal_store(pbq * 1.0, kb + p + sq);
+    __builtin_nontemporal_store(dxq + pbq * Jgq, kb + qe - 1 + sq);
+    if constexpr (SWEEP) {
+      if (up) __builtin_nontemporal_store(xg - xgm, C + I.c_off + (int64_t)I.T * I.m_p + (int64_t)(t - 1) * G + g);
+      double a = vpn;
+      if (up) a += vrm;
+      if (dn) a -= vrp;
+      __builtin_nontemporal_store(a, JTV + xo + 2 * N + g);
+      __builtin_nontemporal_store(vqn, JTV + xo + 2 * N + G + g);
+      __builtin_nontemporal_store(2.0 * c2g * xg + c1g, GR + xo + rp);
+      __builtin_nontemporal_store(0.0, GR + xo + rq);
     }
   }
 }
@@ -831,7 +883,9 @@ __device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, double sigma, d
 template <bool GATHER, bool NT = false>
 __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, rsrc_t src, rsrc_t jp, rsrc_t dst,
                                                int len) {
-  constexpr int U = 4;
+  // GATHER: the template loads and J gathers of up to U slots per lane are
+  // all issued before the first store (in-order completion counting)
+  constexpr int U = GATHER ? 12 : 4;
   const int bd = (int)blockDim.x;
   for (int p0 = (int)threadIdx.x; p0 < len; p0 += U * bd) {
     int sr[U];
@@ -858,34 +912,25 @@ __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, r
   }
 }
 
-// One line tile of the condensed assembly.  The four flow kinds are handled
-// one after the other (derivatives, K row through LDS, stream-out), so only
-// one kind's values are live at a time.  FUSED: J and H of the lines are
-// evaluated from x and lambda here, written out, and used directly (the
-// partner J entries are the structural -1 / +1 of the balance rows), and
-// the optional sweep outputs (constraint rows, J^T v and gradient on the
-// flow variables, the bus hand-off of p, q and J^T v) are produced in the
-// same pass; otherwise J and H are read from the given arrays.
-template <bool FUSED>
-__device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __restrict__ X,
-                              const double* __restrict__ LAM, double* __restrict__ H, double* __restrict__ J,
-                              const double* __restrict__ DX, const double* __restrict__ D, double* __restrict__ K,
-                              double* __restrict__ scr, double* __restrict__ seg, double* sadm,
-                              const double* __restrict__ V = nullptr, double* __restrict__ C = nullptr,
-                              double* __restrict__ JTV = nullptr, double* __restrict__ GR = nullptr) {
+// One line tile of the condensed assembly from given J and H values.  All
+// J / H / weight loads of a line-period are issued before its first store
+// (completions are counted in order); the four flow kinds then build their
+// K rows one after the other in an LDS copy of the block's row segment,
+// which is streamed out with consecutive lanes on consecutive slots, the
+// balance-partner slots multiplied by the partner's J entry on the way.
+__device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __restrict__ H,
+                              const double* __restrict__ J, const double* __restrict__ DX,
+                              const double* __restrict__ D, double* __restrict__ K, double* __restrict__ scr,
+                              double* __restrict__ seg) {
   const Bases b(I);
-  // element offsets inside one period block, as byte offsets (every period
-  // block is far below 4 GiB)
-  const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, G = (uint32_t)b.G;
+  const uint32_t B8 = (uint32_t)b.B * 8u, G = (uint32_t)b.G;
   const uint32_t xFL8 = (uint32_t)b.xFL * 8u, jFLOW8 = (uint32_t)b.jFLOW * 8u, jBAL8 = (uint32_t)b.jBAL * 8u,
                  jTH8 = (uint32_t)b.jTH * 8u, jANG8 = (uint32_t)b.jANG * 8u, hFLOW8 = (uint32_t)b.hFLOW * 8u,
                  hTH8 = (uint32_t)b.hTH * 8u, cFLOW8 = (uint32_t)b.cFLOW * 8u, cTHF8 = (uint32_t)b.cTHF * 8u,
-                 cTHT8 = (uint32_t)b.cTHT * 8u, cANG8 = (uint32_t)b.cANG * 8u;
+                 cTHT8 = (uint32_t)b.cTHT * 8u, cANG8 = (uint32_t)b.cANG * 8u, N8 = (uint32_t)b.N * 8u;
   const int tid = (int)threadIdx.x;
   const uint32_t l = (uint32_t)(tl.e0 + tid);
   const bool act = (int)l < tl.e1;
-  const int nl = tl.e1 - tl.e0;
-  // lane offsets: every per-line stream is (uniform stream offset) + vL
   const uint32_t vL = l * 8u, vL4 = l * 4u, vR = l * (uint32_t)(kRecLine * 8);
   const rsrc_t rKrow = rsrc(I.krow), rKsrc = rsrc(I.ksrc);
   const uint32_t FL4 = (uint32_t)b.xFL * 4u, Bq = (uint32_t)b.B * 4u;
@@ -897,19 +942,19 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
   }
   uint32_t vI = 0, vJ = 0;
   bool ilo = true;
-  const int bd = (int)blockDim.x;
+  int rs[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0}, th[4] = {0xFFFF, 0xFFFF, 0xFFFF, 0xFFFF};
   if (act) {
     const int i = bldi(rsrc(I.f_bus), l), j = bldi(rsrc(I.t_bus), l);
     ilo = i < j;
     vI = (uint32_t)i * 8u;
     vJ = (uint32_t)j * 8u;
-    if (FUSED) {
-      const rsrc_t rA = rsrc(I.adm);
 #pragma unroll
-      for (int a = 0; a < 8; ++a) sadm[a * bd + tid] = bldv(rA, vL, (uint32_t)a * B8);
+    for (int k = 0; k < 4; ++k) {
+      rs[k] = bldiv(rKrow, vL4, FL4 + (uint32_t)k * Bq) - sb[k];
+      re[k] = bldiv(rKrow, vL4, FL4 + (uint32_t)k * Bq + 4u) - sb[k];
+      th[k] = (int)((uint32_t)bldiv(rsrc(I.kinfo), vL4, (uint32_t)k * Bq) >> 16);
     }
   }
-  (void)nl;
   for (int t = tl.t0; t < tl.t1; ++t) {
     const int64_t xo = I.x_off + (int64_t)t * I.n_p;
     const int64_t co = I.c_off + (int64_t)t * I.m_p;
@@ -917,76 +962,53 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
     const rsrc_t rH = rsrc(H + I.h_off + (int64_t)t * I.nnzh_p);
     const rsrc_t rD = rsrc(D + co);
     double* kbase = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t) + (t >= 1 ? G : 0);
-    double q[10], dth[2], Jt[4];
-    double vi = 0.0, vj = 0.0, vv = 0.0, sn = 0.0, cs = 0.0, ti = 0.0, tj = 0.0, fl[4], lf = 0.0, lt = 0.0;
-    double svi = 0.0, svj = 0.0, sti = 0.0;
-#pragma unroll
-    for (int a = 0; a < 10; ++a) q[a] = 0.0;
-    if (act) {
-      dth[0] = bldv(rD, vL, cTHF8);
-      dth[1] = bldv(rD, vL, cTHT8);
-      if constexpr (FUSED) {
-        const rsrc_t rX = rsrc(X + xo), rL = rsrc(LAM + co);
-        vi = bldv(rX, vI, 0);
-        vj = bldv(rX, vJ, 0);
-        ti = bldv(rX, vI, N8);
-        tj = bldv(rX, vJ, N8);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          fl[k] = bldv(rX, vL, xFL8 + (uint32_t)k * B8);
-          Jt[k] = 2.0 * fl[k];
-        }
-        sincos(ti - tj, &sn, &cs);
-        vv = vi * vj;
-        lf = 2.0 * bldv(rL, vL, cTHF8);
-        lt = 2.0 * bldv(rL, vL, cTHT8);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Jt[k] = bldv(rJ, vL, jTH8 + (uint32_t)k * B8);
-      }
-    }
+    // ---- every load of this line-period
+    double Jf[4][5], Hf[4][9], Jb[4], Jt[4], Hth[4], dfk[4], dbk[4], dxk[4], dth[2] = {0.0, 0.0};
+    double Ja0 = 0.0, Ja1 = 0.0, dang = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const uint32_t kB8 = (uint32_t)k * B8;
+      Jb[k] = Jt[k] = Hth[k] = dfk[k] = dbk[k] = dxk[k] = 0.0;
+#pragma unroll
+      for (int a = 0; a < 5; ++a) Jf[k][a] = 0.0;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) Hf[k][a] = 0.0;
+    }
+    if (act) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t kB8 = (uint32_t)k * B8;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) Jf[k][a] = bldv(rJ, vL, jFLOW8 + (uint32_t)(k * 5 + a) * B8);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) Hf[k][a] = bldv(rH, vL, hFLOW8 + (uint32_t)(k * 9 + a) * B8);
+        Jb[k] = bldv(rJ, vL, jBAL8 + kB8);
+        Jt[k] = bldv(rJ, vL, jTH8 + kB8);
+        Hth[k] = bldv(rH, vL, hTH8 + kB8);
+        dfk[k] = bldv(rD, vL, cFLOW8 + kB8);
+        dbk[k] = bldv(rD, k < 2 ? vI : vJ, (k & 1) ? N8 : 0u);
+      }
+      if (DX) {
+        const rsrc_t rDX = rsrc(DX + xo);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dxk[k] = bldv(rDX, vL, xFL8 + (uint32_t)k * B8);
+      }
+      dth[0] = bldv(rD, vL, cTHF8);
+      dth[1] = bldv(rD, vL, cTHT8);
+      dang = bldv(rD, vL, cANG8);
+      Ja0 = bldv(rJ, vL, jANG8);
+      Ja1 = bldv(rJ, vL, jANG8 + B8);
+    }
+    double q[10];
+#pragma unroll
+    for (int a = 0; a < 10; ++a) q[a] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
       if (act) {
-        const int rs = bldiv(rKrow, vL4, FL4 + (uint32_t)k * Bq) - sb[k];
-        const int re = bldiv(rKrow, vL4, FL4 + (uint32_t)k * Bq + 4u) - sb[k];
-        double Jk[5], hf[9], Jbk, Hthk;
-        const double dfk = bldv(rD, vL, cFLOW8 + kB8);
-        if constexpr (FUSED) {
-          const rsrc_t rL = rsrc(LAM + co);
-          Coef cf;
-          coef_kind_lds(sadm, bd, tid, k, cf);
-          flow_kind(cf, k, vi, vj, vv, sn, cs, -bldv(rL, vL, cFLOW8 + kB8), Jk, hf);
-#pragma unroll
-          for (int a = 0; a < 5; ++a) bstv(rJ, vL, jFLOW8 + (uint32_t)(k * 5 + a) * B8, Jk[a]);
-#pragma unroll
-          for (int a = 0; a < 9; ++a) bstv(rH, vL, hFLOW8 + (uint32_t)(k * 9 + a) * B8, hf[a]);
-          Jbk = -1.0;
-          Hthk = k < 2 ? lf : lt;
-          bstv(rJ, vL, jBAL8 + kB8, Jbk);
-          bstv(rJ, vL, jTH8 + kB8, Jt[k]);
-          bstv(rH, vL, hTH8 + kB8, Hthk);
-          if (C) bstv(rsrc(C + co), vL, cFLOW8 + kB8, fl[k] - flow_value(cf, k, vi, vj, vv, flow_w(cf, k, sn, cs)));
-          if (JTV) {
-            const double vkk = bldv(rsrc(V + co), vL, cFLOW8 + kB8);
-            svi += vkk * Jk[1];
-            svj += vkk * Jk[2];
-            sti += vkk * Jk[3];
-          }
-        } else {
-#pragma unroll
-          for (int a = 0; a < 5; ++a) Jk[a] = bldv(rJ, vL, jFLOW8 + (uint32_t)(k * 5 + a) * B8);
-#pragma unroll
-          for (int a = 0; a < 9; ++a) hf[a] = bldv(rH, vL, hFLOW8 + (uint32_t)(k * 9 + a) * B8);
-          Jbk = bldv(rJ, vL, jBAL8 + kB8);
-          Hthk = bldv(rH, vL, hTH8 + kB8);
-        }
-        // bus-variable contributions: d_k J_k,a J_k,b + H (local H order:
-        // from end (0,0)(1,0)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3); to end
-        // (1,0)(1,1)(2,0)(2,1)(2,2)(3,0)(3,1)(3,2)(3,3))
+        const double* Jk = Jf[k];
+        const double* hf = Hf[k];
         const double a1 = Jk[1], a2 = Jk[2], a3 = Jk[3], a4 = Jk[4];
-        const double d1 = dfk * a1, d2 = dfk * a2, d3 = dfk * a3, d4 = dfk * a4;
+        const double dk = dfk[k];
+        const double d1 = dk * a1, d2 = dk * a2, d3 = dk * a3, d4 = dk * a4;
         if (k < 2) {
           q[0] += d1 * a1 + hf[0];
           q[6] += d2 * a2;
@@ -1003,9 +1025,8 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
         q[7] += d4 * a2 + hf[6];
         q[5] += d4 * a3 + hf[7];
         q[8] += d4 * a4 + hf[8];
-        // this kind's K row into the LDS copy of the block's row segment
-        const double pk = dfk * Jk[0];
-        double* row = seg + rs;
+        const double pk = dk * Jk[0];
+        double* row = seg + rs[k];
         if (ilo) {
           row[0] = pk * Jk[1];
           row[1] = pk * Jk[2];
@@ -1017,86 +1038,30 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
           row[2] = pk * Jk[4];
           row[3] = pk * Jk[3];
         }
-        const double pb = bldv(rD, k < 2 ? vI : vJ, (k & 1) ? N8 : 0u) * Jbk;
-        for (int p = rs + 4; p < re - 1; ++p) {
-          const int src = bldi(rKsrc, (uint32_t)(sb[k] + p));
-          double v;
-          if ((k & 1) && src < 0) {
-            v = dth[k >> 1] * Jt[k ^ 1] * Jt[k];  // thermal partner
-          } else if (FUSED) {
-            v = pb * (src < (int)(2 * G) ? 1.0 : -1.0);  // balance partner: generator +1, line end -1
-          } else {
-            v = pb;  // factor; the stream-out multiplies by the partner's J entry
-          }
-          seg[p] = v;
-        }
-        const double dxv = DX ? bldv(rsrc(DX + xo), vL, xFL8 + kB8) : 0.0;
-        seg[re - 1] = dxv + pk * Jk[0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jbk + Hthk;
+        // partners: the factor d_bal J_bal (the stream-out multiplies by the
+        // partner's J entry), or the thermal pair of odd kinds
+        const double pb = dbk[k] * Jb[k];
+        const double thv = dth[k >> 1] * Jt[k ^ 1] * Jt[k];
+        for (int p = 0; p < re[k] - rs[k] - 5; ++p) seg[rs[k] + 4 + p] = p == th[k] ? thv : pb;
+        seg[re[k] - 1] = dxk[k] + pk * Jk[0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jb[k] + Hth[k];
       }
       __syncthreads();
-      stream_segment<!FUSED>(seg, rsrc(I.ksrc + sb[k]), rJ, rsrc(kbase + sb[k]), se[k] - sb[k]);
+      stream_segment<true, true>(seg, rsrc(I.ksrc + sb[k]), rJ, rsrc(kbase + sb[k]), se[k] - sb[k]);
       __syncthreads();
     }
     if (act) {
-      const double dang = bldv(rD, vL, cANG8);
-      double Ja0, Ja1;
-      if constexpr (FUSED) {
-        Ja0 = 1.0;
-        Ja1 = -1.0;
-        bstv(rJ, vL, jANG8, Ja0);
-        bstv(rJ, vL, jANG8 + B8, Ja1);
-      } else {
-        Ja0 = bldv(rJ, vL, jANG8);
-        Ja1 = bldv(rJ, vL, jANG8 + B8);
-      }
       q[2] += dang * Ja0 * Ja0;
       q[8] += dang * Ja1 * Ja1;
       q[5] += dang * Ja1 * Ja0;
-      double pfl[4] = {0.0, 0.0, 0.0, 0.0}, jtr[4] = {0.0, 0.0, 0.0, 0.0};
-      if constexpr (FUSED) {
-        if (C) {
-          const rsrc_t rC = rsrc(C + co);
-          bstv(rC, vL, cTHF8, fl[0] * fl[0] + fl[1] * fl[1]);
-          bstv(rC, vL, cTHT8, fl[2] * fl[2] + fl[3] * fl[3]);
-          bstv(rC, vL, cANG8, ti - tj);
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) pfl[k] = fl[k];
-        if (JTV) {
-          const rsrc_t rV = rsrc(V + co), rO = rsrc(JTV + xo);
-          const double vtf = bldv(rV, vL, cTHF8), vtt = bldv(rV, vL, cTHT8), vang = bldv(rV, vL, cANG8);
-          double vk[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) vk[k] = bldv(rV, vL, cFLOW8 + (uint32_t)k * B8);
-          const double vbal[4] = {bldv(rV, vI, 0), bldv(rV, vI, N8), bldv(rV, vJ, 0), bldv(rV, vJ, N8)};
-          bstv(rO, vL, xFL8, vk[0] + vtf * (2.0 * fl[0]) - vbal[0]);
-          bstv(rO, vL, xFL8 + B8, vk[1] + vtf * (2.0 * fl[1]) - vbal[1]);
-          bstv(rO, vL, xFL8 + 2 * B8, vk[2] + vtt * (2.0 * fl[2]) - vbal[2]);
-          bstv(rO, vL, xFL8 + 3 * B8, vk[3] + vtt * (2.0 * fl[3]) - vbal[3]);
-          jtr[0] = svi;
-          jtr[1] = sti + vang;
-          jtr[2] = svj;
-          jtr[3] = -sti - vang;
-        }
-        if (GR) {
-          const rsrc_t rG = rsrc(GR + xo);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) bstv(rG, vL, xFL8 + (uint32_t)k * B8, 0.0);
-        }
-      }
-      // hand-off: one 64-byte record per line end, the shared cross pair
       const rsrc_t rR = rsrc(rec_at(I, scr, t));
       bst2v(rR, vR, 0, make_double2(q[0], q[1]));
       bst2v(rR, vR, 16, make_double2(q[2], q[3]));
-      bst2v(rR, vR, 32, make_double2(pfl[0], pfl[1]));
-      bst2v(rR, vR, 48, make_double2(jtr[0], jtr[1]));
       bst2v(rR, vR, 64, make_double2(q[6], q[7]));
       bst2v(rR, vR, 80, make_double2(q[8], q[9]));
-      bst2v(rR, vR, 96, make_double2(pfl[2], pfl[3]));
-      bst2v(rR, vR, 112, make_double2(jtr[2], jtr[3]));
       bst2v(rsrc(shared_at(I, scr, t)), vL * 2u, 0, make_double2(q[4], q[5]));
     }
   }
+  (void)rKsrc;
 }
 
 // One line tile of the fused evaluation: J and H of the lines from x and
@@ -1334,18 +1299,14 @@ __global__ void __launch_bounds__(256) k_kkt_a(const InstDev* __restrict__ insts
                                                const double* __restrict__ D, double* __restrict__ K,
                                                double* __restrict__ scr) {
   extern __shared__ double lds[];
-  // read-only J / H in this form (the templates take writable pointers for
-  // the fused form, which writes them)
-  double* Hm = const_cast<double*>(H);
-  double* Jm = const_cast<double*>(J);
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile tl = tiles[remap_tile(v, ntiles)];
     const InstDev& I = insts[tl.inst];
     if (tl.kind == TK_BRANCH) {
-      kkt_line_tile<false>(I, tl, nullptr, nullptr, Hm, Jm, DX, D, K, scr, lds, nullptr);
+      kkt_line_tile(I, tl, H, J, DX, D, K, scr, lds);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
-      if (e < tl.e1) kkt_gen<false>(I, e, tl.t0, tl.t1, 0.0, Hm, Jm, DX, D, K);
+      if (e < tl.e1) kkt_gen(I, e, tl.t0, tl.t1, H, J, DX, D, K);
     }
   }
 }
@@ -1366,7 +1327,7 @@ __global__ void __launch_bounds__(256) k_jhk_a(const InstDev* __restrict__ insts
       fused_line_tile<false>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, lds + cap_seg, nullptr, nullptr, nullptr, nullptr);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
-      if (e < tl.e1) kkt_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K);
+      if (e < tl.e1) fused_gen<false>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K, nullptr, nullptr, nullptr, nullptr, nullptr);
     }
   }
 }
@@ -1390,7 +1351,7 @@ __global__ void __launch_bounds__(256) k_sweep_a(const InstDev* __restrict__ ins
       fused_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, lds + cap_seg, V, C, JTV, GR);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
-      if (e < tl.e1) kkt_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K, X, V, C, JTV, GR);
+      if (e < tl.e1) fused_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K, X, V, C, JTV, GR);
     }
   }
 }
