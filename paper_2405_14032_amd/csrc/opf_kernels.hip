@@ -180,20 +180,35 @@ __device__ __forceinline__ void jt_line(const double vk[4], const double Jf[4][5
 }
 
 // ---------------------------------------------------------------- Jacobian
+// Loads of the next period are issued before the stores of the current one
+// (completions are counted in order); outputs use non-temporal stores.
 __device__ void jac_branch(const InstDev& I, int l, int t0, int t1, const double* __restrict__ x,
                            double* __restrict__ jv) {
   const Bases b(I);
   Coef cf;
   load_coef(I, l, cf);
-  const int64_t B = b.B;
-  const int i = I.f_bus[l], j = I.t_bus[l];
+  const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, vL = (uint32_t)l * 8u;
+  const uint32_t xFL8 = (uint32_t)b.xFL * 8u, jFLOW8 = (uint32_t)b.jFLOW * 8u, jBAL8 = (uint32_t)b.jBAL * 8u,
+                 jTH8 = (uint32_t)b.jTH * 8u, jANG8 = (uint32_t)b.jANG * 8u;
+  const uint32_t vI = (uint32_t)I.f_bus[l] * 8u, vJ = (uint32_t)I.t_bus[l] * 8u;
+  double in[8];  // vi, vj, ti, tj, flows
+  auto load = [&](int t, double* v) {
+    const rsrc_t rX = rsrc(x + I.x_off + (int64_t)t * I.n_p);
+    v[0] = bldv(rX, vI, 0);
+    v[1] = bldv(rX, vJ, 0);
+    v[2] = bldv(rX, vI, N8);
+    v[3] = bldv(rX, vJ, N8);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[4 + k] = bldv(rX, vL, xFL8 + (uint32_t)k * B8);
+  };
+  load(t0, in);
   for (int t = t0; t < t1; ++t) {
-    const double* xp = x + I.x_off + (int64_t)t * I.n_p;
-    double* jp = jv + I.j_off + (int64_t)t * I.nnzj_p;
-    const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
+    const double vi = in[0], vj = in[1], ti = in[2], tj = in[3];
     double fl[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) fl[k] = xp[b.xFL + k * B + l];
+    for (int k = 0; k < 4; ++k) fl[k] = in[4 + k];
+    if (t + 1 < t1) load(t + 1, in);
+    const rsrc_t rJ = rsrc(jv + I.j_off + (int64_t)t * I.nnzj_p);
     double s, c;
     sincos(ti - tj, &s, &c);
     const double vv = vi * vj;
@@ -201,17 +216,16 @@ __device__ void jac_branch(const InstDev& I, int l, int t0, int t1, const double
     for (int k = 0; k < 4; ++k) {
       double Jk[5], h[9];
       flow_kind(cf, k, vi, vj, vv, s, c, 0.0, Jk, h);
-      double* q = jp + b.jFLOW + (int64_t)(k * 5) * B + l;
 #pragma unroll
-      for (int a = 0; a < 5; ++a) q[a * B] = Jk[a];
+      for (int a = 0; a < 5; ++a) bstvn(rJ, vL, jFLOW8 + (uint32_t)(k * 5 + a) * B8, Jk[a]);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      jp[b.jBAL + k * B + l] = -1.0;
-      jp[b.jTH + k * B + l] = 2.0 * fl[k];
+      bstvn(rJ, vL, jBAL8 + (uint32_t)k * B8, -1.0);
+      bstvn(rJ, vL, jTH8 + (uint32_t)k * B8, 2.0 * fl[k]);
     }
-    jp[b.jANG + l] = 1.0;
-    jp[b.jANG + B + l] = -1.0;
+    bstvn(rJ, vL, jANG8, 1.0);
+    bstvn(rJ, vL, jANG8 + B8, -1.0);
   }
 }
 
@@ -250,29 +264,45 @@ __device__ void hess_branch(const InstDev& I, int l, int t0, int t1, const doubl
   const Bases b(I);
   Coef cf;
   load_coef(I, l, cf);
-  const int64_t B = b.B;
-  const int i = I.f_bus[l], j = I.t_bus[l];
+  const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, vL = (uint32_t)l * 8u;
+  const uint32_t hFLOW8 = (uint32_t)b.hFLOW * 8u, hTH8 = (uint32_t)b.hTH * 8u, cFLOW8 = (uint32_t)b.cFLOW * 8u,
+                 cTHF8 = (uint32_t)b.cTHF * 8u, cTHT8 = (uint32_t)b.cTHT * 8u;
+  const uint32_t vI = (uint32_t)I.f_bus[l] * 8u, vJ = (uint32_t)I.t_bus[l] * 8u;
+  double in[10];  // vi, vj, ti, tj, lambda of the 4 flow rows, the 2 thermal rows
+  auto load = [&](int t, double* v) {
+    const rsrc_t rX = rsrc(x + I.x_off + (int64_t)t * I.n_p), rL = rsrc(lam + I.c_off + (int64_t)t * I.m_p);
+    v[0] = bldv(rX, vI, 0);
+    v[1] = bldv(rX, vJ, 0);
+    v[2] = bldv(rX, vI, N8);
+    v[3] = bldv(rX, vJ, N8);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[4 + k] = bldv(rL, vL, cFLOW8 + (uint32_t)k * B8);
+    v[8] = bldv(rL, vL, cTHF8);
+    v[9] = bldv(rL, vL, cTHT8);
+  };
+  load(t0, in);
   for (int t = t0; t < t1; ++t) {
-    const double* xp = x + I.x_off + (int64_t)t * I.n_p;
-    const double* lp = lam + I.c_off + (int64_t)t * I.m_p;
-    double* hp = hv + I.h_off + (int64_t)t * I.nnzh_p;
-    const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
+    const double vi = in[0], vj = in[1], ti = in[2], tj = in[3];
+    double lk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lk[k] = in[4 + k];
+    const double lf = 2.0 * in[8], lt = 2.0 * in[9];
+    if (t + 1 < t1) load(t + 1, in);
+    const rsrc_t rH = rsrc(hv + I.h_off + (int64_t)t * I.nnzh_p);
     double s, c;
     sincos(ti - tj, &s, &c);
     const double vv = vi * vj;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       double Jk[5], h[9];
-      flow_kind(cf, k, vi, vj, vv, s, c, -lp[b.cFLOW + k * B + l], Jk, h);
-      double* q = hp + b.hFLOW + (int64_t)(k * 9) * B + l;
+      flow_kind(cf, k, vi, vj, vv, s, c, -lk[k], Jk, h);
 #pragma unroll
-      for (int a = 0; a < 9; ++a) q[a * B] = h[a];
+      for (int a = 0; a < 9; ++a) bstvn(rH, vL, hFLOW8 + (uint32_t)(k * 9 + a) * B8, h[a]);
     }
-    const double lf = 2.0 * lp[b.cTHF + l], lt = 2.0 * lp[b.cTHT + l];
-    hp[b.hTH + l] = lf;
-    hp[b.hTH + B + l] = lf;
-    hp[b.hTH + 2 * B + l] = lt;
-    hp[b.hTH + 3 * B + l] = lt;
+    bstvn(rH, vL, hTH8, lf);
+    bstvn(rH, vL, hTH8 + B8, lf);
+    bstvn(rH, vL, hTH8 + 2 * B8, lt);
+    bstvn(rH, vL, hTH8 + 3 * B8, lt);
   }
 }
 
@@ -300,53 +330,84 @@ __device__ void cons_branch(const InstDev& I, int l, int t0, int t1, const doubl
   const Bases b(I);
   Coef cf;
   load_coef(I, l, cf);
-  const int64_t B = b.B;
-  const int i = I.f_bus[l], j = I.t_bus[l];
+  const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, vL = (uint32_t)l * 8u;
+  const uint32_t xFL8 = (uint32_t)b.xFL * 8u, cFLOW8 = (uint32_t)b.cFLOW * 8u, cTHF8 = (uint32_t)b.cTHF * 8u,
+                 cTHT8 = (uint32_t)b.cTHT * 8u, cANG8 = (uint32_t)b.cANG * 8u;
+  const uint32_t vI = (uint32_t)I.f_bus[l] * 8u, vJ = (uint32_t)I.t_bus[l] * 8u;
+  double in[8];
+  auto load = [&](int t, double* w) {
+    const rsrc_t rX = rsrc(x + I.x_off + (int64_t)t * I.n_p);
+    w[0] = bldv(rX, vI, 0);
+    w[1] = bldv(rX, vJ, 0);
+    w[2] = bldv(rX, vI, N8);
+    w[3] = bldv(rX, vJ, N8);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[4 + k] = bldv(rX, vL, xFL8 + (uint32_t)k * B8);
+  };
+  load(t0, in);
   for (int t = t0; t < t1; ++t) {
-    const double* xp = x + I.x_off + (int64_t)t * I.n_p;
-    double* cp = cv + I.c_off + (int64_t)t * I.m_p;
-    const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
+    const double vi = in[0], vj = in[1], ti = in[2], tj = in[3];
     double fl[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) fl[k] = xp[b.xFL + k * B + l];
+    for (int k = 0; k < 4; ++k) fl[k] = in[4 + k];
+    if (t + 1 < t1) load(t + 1, in);
+    const rsrc_t rC = rsrc(cv + I.c_off + (int64_t)t * I.m_p);
     double s, c;
     sincos(ti - tj, &s, &c);
     const double vv = vi * vj;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) cp[b.cFLOW + k * B + l] = fl[k] - flow_value(cf, k, vi, vj, vv, flow_w(cf, k, s, c));
-    cp[b.cTHF + l] = fl[0] * fl[0] + fl[1] * fl[1];
-    cp[b.cTHT + l] = fl[2] * fl[2] + fl[3] * fl[3];
-    cp[b.cANG + l] = ti - tj;
+    for (int k = 0; k < 4; ++k)
+      bstvn(rC, vL, cFLOW8 + (uint32_t)k * B8, fl[k] - flow_value(cf, k, vi, vj, vv, flow_w(cf, k, s, c)));
+    bstvn(rC, vL, cTHF8, fl[0] * fl[0] + fl[1] * fl[1]);
+    bstvn(rC, vL, cTHT8, fl[2] * fl[2] + fl[3] * fl[3]);
+    bstvn(rC, vL, cANG8, ti - tj);
   }
 }
 
 __device__ void cons_bus(const InstDev& I, int n, int t0, int t1, const double* __restrict__ x,
                          double* __restrict__ cv) {
   const Bases b(I);
-  const int64_t B = b.B;
+  const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, G8 = (uint32_t)b.G * 8u;
+  const uint32_t xFL8 = (uint32_t)b.xFL * 8u, vN = (uint32_t)n * 8u;
   const int q0 = I.bus_ptr[n], q1 = I.bus_ptr[n + 1];
   const int g0 = I.bgen_ptr[n], g1 = I.bgen_ptr[n + 1];
+  const rsrc_t rAdj = rsrc(I.bus_adj), rBg = rsrc(I.bgen);
   for (int t = t0; t < t1; ++t) {
-    const double* xp = x + I.x_off + (int64_t)t * I.n_p;
-    double* cp = cv + I.c_off + (int64_t)t * I.m_p;
+    const rsrc_t rX = rsrc(x + I.x_off + (int64_t)t * I.n_p);
     double bp = 0.0, bq = 0.0;
     for (int q = g0; q < g1; ++q) {
-      const int g = I.bgen[q];
-      bp += xp[2 * b.N + g];
-      bq += xp[2 * b.N + b.G + g];
+      const uint32_t g8 = (uint32_t)bldi(rBg, (uint32_t)q) * 8u;
+      bp += bldv(rX, g8, 2 * N8);
+      bq += bldv(rX, g8, 2 * N8 + G8);
     }
-    for (int q = q0; q < q1; ++q) {
-      const int a = I.bus_adj[q];
-      const int64_t l = a >> 1;
-      const int64_t kp = (a & 1) ? 2 : 0;
-      bp -= xp[b.xFL + kp * B + l];
-      bq -= xp[b.xFL + (kp + 1) * B + l];
+    // incident line ends, four in flight per lane; the flow leaving the bus
+    // is (pf, qf) at a from end and (pt, qt) at a to end
+    constexpr int U = 4;
+    for (int aa = q0; aa < q1; aa += U) {
+      int ad[U];
+      double fp[U], fq[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) ad[u] = aa + u < q1 ? bldi(rAdj, (uint32_t)(aa + u)) : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t o = ad[u] < 0 ? 0u : (uint32_t)(ad[u] >> 1) * 8u + ((ad[u] & 1) ? 2u * B8 : 0u);
+        fp[u] = ad[u] < 0 ? 0.0 : bldv(rX, o, xFL8);
+        fq[u] = ad[u] < 0 ? 0.0 : bldv(rX, o, xFL8 + B8);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ad[u] < 0) break;
+        bp -= fp[u];
+        bq -= fq[u];
+      }
     }
     bp -= I.pd[(int64_t)t * b.N + n];
     bq -= I.qd[(int64_t)t * b.N + n];
-    cp[n] = bp;
-    cp[b.N + n] = bq;
-    if (n == I.ref) cp[b.cREF] = xp[b.N + n];
+    const rsrc_t rC = rsrc(cv + I.c_off + (int64_t)t * I.m_p);
+    const double vref = n == I.ref ? bldv(rX, vN, N8) : 0.0;
+    bstvn(rC, vN, 0, bp);
+    bstvn(rC, vN, N8, bq);
+    if (n == I.ref) bstn(rC, (uint32_t)b.cREF, vref);
   }
 }
 
@@ -380,21 +441,39 @@ __device__ void jv_branch(const InstDev& I, int l, int t0, int t1, const double*
   const Bases b(I);
   Coef cf;
   load_coef(I, l, cf);
-  const int64_t B = b.B;
-  const int i = I.f_bus[l], j = I.t_bus[l];
+  const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, vL = (uint32_t)l * 8u;
+  const uint32_t xFL8 = (uint32_t)b.xFL * 8u, cFLOW8 = (uint32_t)b.cFLOW * 8u, cTHF8 = (uint32_t)b.cTHF * 8u,
+                 cTHT8 = (uint32_t)b.cTHT * 8u, cANG8 = (uint32_t)b.cANG * 8u;
+  const uint32_t vI = (uint32_t)I.f_bus[l] * 8u, vJ = (uint32_t)I.t_bus[l] * 8u;
+  double in[16];  // x: vi, vj, ti, tj, flows; v: the same eight entries
+  auto load = [&](int t, double* w) {
+    const rsrc_t rX = rsrc(x + I.x_off + (int64_t)t * I.n_p), rV = rsrc(v + I.x_off + (int64_t)t * I.n_p);
+    w[0] = bldv(rX, vI, 0);
+    w[1] = bldv(rX, vJ, 0);
+    w[2] = bldv(rX, vI, N8);
+    w[3] = bldv(rX, vJ, N8);
+    w[8] = bldv(rV, vI, 0);
+    w[9] = bldv(rV, vJ, 0);
+    w[10] = bldv(rV, vI, N8);
+    w[11] = bldv(rV, vJ, N8);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      w[4 + k] = bldv(rX, vL, xFL8 + (uint32_t)k * B8);
+      w[12 + k] = bldv(rV, vL, xFL8 + (uint32_t)k * B8);
+    }
+  };
+  load(t0, in);
   for (int t = t0; t < t1; ++t) {
-    const int64_t xo = I.x_off + (int64_t)t * I.n_p;
-    const double* xp = x + xo;
-    const double* vp = v + xo;
-    double* op = out + I.c_off + (int64_t)t * I.m_p;
-    const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
-    const double wvi = vp[i], wvj = vp[j], wti = vp[b.N + i], wtj = vp[b.N + j];
+    const double vi = in[0], vj = in[1], ti = in[2], tj = in[3];
+    const double wvi = in[8], wvj = in[9], wti = in[10], wtj = in[11];
     double fl[4], wf[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      fl[k] = xp[b.xFL + k * B + l];
-      wf[k] = vp[b.xFL + k * B + l];
+      fl[k] = in[4 + k];
+      wf[k] = in[12 + k];
     }
+    if (t + 1 < t1) load(t + 1, in);
+    const rsrc_t rO = rsrc(out + I.c_off + (int64_t)t * I.m_p);
     double sn, cs;
     sincos(ti - tj, &sn, &cs);
     const double vv = vi * vj;
@@ -402,39 +481,54 @@ __device__ void jv_branch(const InstDev& I, int l, int t0, int t1, const double*
     for (int k = 0; k < 4; ++k) {
       double Jk[5], h[9];
       flow_kind(cf, k, vi, vj, vv, sn, cs, 0.0, Jk, h);
-      op[b.cFLOW + k * B + l] = Jk[0] * wf[k] + Jk[1] * wvi + Jk[2] * wvj + Jk[3] * wti + Jk[4] * wtj;
+      bstvn(rO, vL, cFLOW8 + (uint32_t)k * B8, Jk[0] * wf[k] + Jk[1] * wvi + Jk[2] * wvj + Jk[3] * wti + Jk[4] * wtj);
     }
-    op[b.cTHF + l] = (2.0 * fl[0]) * wf[0] + (2.0 * fl[1]) * wf[1];
-    op[b.cTHT + l] = (2.0 * fl[2]) * wf[2] + (2.0 * fl[3]) * wf[3];
-    op[b.cANG + l] = wti - wtj;
+    bstvn(rO, vL, cTHF8, (2.0 * fl[0]) * wf[0] + (2.0 * fl[1]) * wf[1]);
+    bstvn(rO, vL, cTHT8, (2.0 * fl[2]) * wf[2] + (2.0 * fl[3]) * wf[3]);
+    bstvn(rO, vL, cANG8, wti - wtj);
   }
 }
 
 __device__ void jv_bus(const InstDev& I, int n, int t0, int t1, const double* __restrict__ v,
                        double* __restrict__ out) {
   const Bases b(I);
-  const int64_t B = b.B;
+  const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, G8 = (uint32_t)b.G * 8u;
+  const uint32_t xFL8 = (uint32_t)b.xFL * 8u, vN = (uint32_t)n * 8u;
   const int q0 = I.bus_ptr[n], q1 = I.bus_ptr[n + 1];
   const int g0 = I.bgen_ptr[n], g1 = I.bgen_ptr[n + 1];
+  const rsrc_t rAdj = rsrc(I.bus_adj), rBg = rsrc(I.bgen);
   for (int t = t0; t < t1; ++t) {
-    const double* vp = v + I.x_off + (int64_t)t * I.n_p;
-    double* op = out + I.c_off + (int64_t)t * I.m_p;
+    const rsrc_t rV = rsrc(v + I.x_off + (int64_t)t * I.n_p);
     double bp = 0.0, bq = 0.0;
     for (int q = g0; q < g1; ++q) {
-      const int g = I.bgen[q];
-      bp += vp[2 * b.N + g];
-      bq += vp[2 * b.N + b.G + g];
+      const uint32_t g8 = (uint32_t)bldi(rBg, (uint32_t)q) * 8u;
+      bp += bldv(rV, g8, 2 * N8);
+      bq += bldv(rV, g8, 2 * N8 + G8);
     }
-    for (int q = q0; q < q1; ++q) {
-      const int a = I.bus_adj[q];
-      const int64_t l = a >> 1;
-      const int64_t kp = (a & 1) ? 2 : 0;
-      bp -= vp[b.xFL + kp * B + l];
-      bq -= vp[b.xFL + (kp + 1) * B + l];
+    constexpr int U = 4;
+    for (int aa = q0; aa < q1; aa += U) {
+      int ad[U];
+      double fp[U], fq[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) ad[u] = aa + u < q1 ? bldi(rAdj, (uint32_t)(aa + u)) : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t o = ad[u] < 0 ? 0u : (uint32_t)(ad[u] >> 1) * 8u + ((ad[u] & 1) ? 2u * B8 : 0u);
+        fp[u] = ad[u] < 0 ? 0.0 : bldv(rV, o, xFL8);
+        fq[u] = ad[u] < 0 ? 0.0 : bldv(rV, o, xFL8 + B8);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ad[u] < 0) break;
+        bp -= fp[u];
+        bq -= fq[u];
+      }
     }
-    op[n] = bp;
-    op[b.N + n] = bq;
-    if (n == I.ref) op[b.cREF] = vp[b.N + n];
+    const rsrc_t rO = rsrc(out + I.c_off + (int64_t)t * I.m_p);
+    const double vref = n == I.ref ? bldv(rV, vN, N8) : 0.0;
+    bstvn(rO, vN, 0, bp);
+    bstvn(rO, vN, N8, bq);
+    if (n == I.ref) bstn(rO, (uint32_t)b.cREF, vref);
   }
 }
 
@@ -630,32 +724,57 @@ __device__ void jt_branch(const InstDev& I, int l, int t0, int t1, const double*
   const Bases b(I);
   Coef cf;
   load_coef(I, l, cf);
-  const int64_t B = b.B;
-  const int i = I.f_bus[l], j = I.t_bus[l];
-  for (int t = t0; t < t1; ++t) {
-    const double* xp = x + I.x_off + (int64_t)t * I.n_p;
-    const double* vp = vv_ + I.c_off + (int64_t)t * I.m_p;
-    double* op = out + I.x_off + (int64_t)t * I.n_p;
-    const double vi = xp[i], vj = xp[j], ti = xp[b.N + i], tj = xp[b.N + j];
-    double fl[4], vk[4], Jf[4][5], h[9];
+  const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, vL = (uint32_t)l * 8u;
+  const uint32_t xFL8 = (uint32_t)b.xFL * 8u, cFLOW8 = (uint32_t)b.cFLOW * 8u, cTHF8 = (uint32_t)b.cTHF * 8u,
+                 cTHT8 = (uint32_t)b.cTHT * 8u, cANG8 = (uint32_t)b.cANG * 8u;
+  const uint32_t vI = (uint32_t)I.f_bus[l] * 8u, vJ = (uint32_t)I.t_bus[l] * 8u;
+  // x: vi, vj, ti, tj, flows; v: flow rows, thermal rows, angle row, balance rows at both ends
+  double in[19];
+  auto load = [&](int t, double* w) {
+    const rsrc_t rX = rsrc(x + I.x_off + (int64_t)t * I.n_p), rV = rsrc(vv_ + I.c_off + (int64_t)t * I.m_p);
+    w[0] = bldv(rX, vI, 0);
+    w[1] = bldv(rX, vJ, 0);
+    w[2] = bldv(rX, vI, N8);
+    w[3] = bldv(rX, vJ, N8);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      fl[k] = xp[b.xFL + k * B + l];
-      vk[k] = vp[b.cFLOW + k * B + l];
+      w[4 + k] = bldv(rX, vL, xFL8 + (uint32_t)k * B8);
+      w[8 + k] = bldv(rV, vL, cFLOW8 + (uint32_t)k * B8);
     }
-    const double vbal[4] = {vp[i], vp[b.N + i], vp[j], vp[b.N + j]};
+    w[12] = bldv(rV, vL, cTHF8);
+    w[13] = bldv(rV, vL, cTHT8);
+    w[14] = bldv(rV, vL, cANG8);
+    w[15] = bldv(rV, vI, 0);
+    w[16] = bldv(rV, vI, N8);
+    w[17] = bldv(rV, vJ, 0);
+    w[18] = bldv(rV, vJ, N8);
+  };
+  load(t0, in);
+  for (int t = t0; t < t1; ++t) {
+    const double vi = in[0], vj = in[1], ti = in[2], tj = in[3];
+    double fl[4], vk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      fl[k] = in[4 + k];
+      vk[k] = in[8 + k];
+    }
+    const double vtf = in[12], vtt = in[13], vang = in[14];
+    const double vbal[4] = {in[15], in[16], in[17], in[18]};
+    if (t + 1 < t1) load(t + 1, in);
+    double Jf[4][5], h[9];
     double s, c;
     sincos(ti - tj, &s, &c);
     const double vv = vi * vj;
 #pragma unroll
     for (int k = 0; k < 4; ++k) flow_kind(cf, k, vi, vj, vv, s, c, 0.0, Jf[k], h);
     double o4[4], rec[4];
-    jt_line(vk, Jf, vp[b.cTHF + l], vp[b.cTHT + l], vp[b.cANG + l], fl, vbal, o4, rec);
+    jt_line(vk, Jf, vtf, vtt, vang, fl, vbal, o4, rec);
+    const rsrc_t rO = rsrc(out + I.x_off + (int64_t)t * I.n_p);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) op[b.xFL + k * B + l] = o4[k];
-    double* r = jt_at(I, scr, t) + (int64_t)l * kScratchJt;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) r[a] = rec[a];
+    for (int k = 0; k < 4; ++k) bstvn(rO, vL, xFL8 + (uint32_t)k * B8, o4[k]);
+    const rsrc_t rR = rsrc(jt_at(I, scr, t));
+    bst2v(rR, vL * (uint32_t)kScratchJt, 0, make_double2(rec[0], rec[1]));
+    bst2v(rR, vL * (uint32_t)kScratchJt, 16, make_double2(rec[2], rec[3]));
   }
 }
 
@@ -705,24 +824,35 @@ __global__ void __launch_bounds__(512) k_jt_b(const InstDev* __restrict__ insts,
     const int n = tl.e0 + (int)threadIdx.x;
     if (n >= tl.e1) continue;
     const int q0 = I.bus_ptr[n], q1 = I.bus_ptr[n + 1];
+    const rsrc_t rAdj = rsrc(I.bus_adj);
+    const uint32_t vN = (uint32_t)n * 8u, N8 = (uint32_t)I.N * 8u;
     for (int t = tl.t0; t < tl.t1; ++t) {
-      const double* rs = jt_at(I, const_cast<double*>(scr), t);
+      // the line's 4-value record: J^T v on vm_i, vm_j, va_i, va_j
+      const rsrc_t rR = rsrc(jt_at(I, const_cast<double*>(scr), t));
       double svm = 0.0, sva = 0.0;
-      for (int a = q0; a < q1; ++a) {
-        const int ad = I.bus_adj[a];
-        const double* r = rs + (int64_t)(ad >> 1) * kScratchJt;
-        if (ad & 1) {
-          svm += r[1];
-          sva += r[3];
-        } else {
-          svm += r[0];
-          sva += r[2];
+      constexpr int U = 4;
+      for (int aa = q0; aa < q1; aa += U) {
+        int ad[U];
+        double rm[U], ra[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ad[u] = aa + u < q1 ? bldi(rAdj, (uint32_t)(aa + u)) : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t o = ad[u] < 0 ? 0u : (uint32_t)(ad[u] >> 1) * (uint32_t)(kScratchJt * 8) + ((ad[u] & 1) ? 8u : 0u);
+          rm[u] = ad[u] < 0 ? 0.0 : bldv(rR, o, 0);
+          ra[u] = ad[u] < 0 ? 0.0 : bldv(rR, o, 16);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (ad[u] < 0) break;
+          svm += rm[u];
+          sva += ra[u];
         }
       }
       if (n == I.ref) sva += v[I.c_off + (int64_t)t * I.m_p + 2LL * I.N];
-      double* op = out + I.x_off + (int64_t)t * I.n_p;
-      op[n] = svm;
-      op[I.N + n] = sva;
+      const rsrc_t rO = rsrc(out + I.x_off + (int64_t)t * I.n_p);
+      bstvn(rO, vN, 0, svm);
+      bstvn(rO, vN, N8, sva);
     }
   }
 }
