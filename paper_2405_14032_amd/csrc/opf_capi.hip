@@ -280,7 +280,10 @@ int lds_needs(const opf_model* M, int op, const std::vector<Tile>& tiles, const 
       cap2 = std::max<int>(cap2, I.krow[I.N + tl.e1] - I.krow[I.N + tl.e0]);
     }
   }
-  // the fused line kernels also keep each lane's eight admittances in LDS
+  // the line kernels stage their hand-off records in the segment region
+  // (a padded 17-double stride per lane), and the fused ones also keep each
+  // lane's eight admittances in LDS
+  if (line) cap = std::max<int>(cap, 17 * s.block);
   const size_t adm = (op == OP_JHKA || op == OP_SWA) ? 8 * (size_t)s.block : 0;
   smem = line ? ((size_t)cap + adm) * sizeof(double)
               : ((size_t)cap + (size_t)cap2) * sizeof(double);

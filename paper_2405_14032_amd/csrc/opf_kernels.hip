@@ -1042,6 +1042,24 @@ __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, r
   }
 }
 
+// Hand-off records of a line tile through LDS: lane l leaves its line's 16
+// values (two 64-byte end records) at a padded stride, then the block's
+// records, contiguous in memory for lines e0 .. e1, are streamed out with
+// consecutive lanes on consecutive 16-byte chunks (whole cache lines per
+// wave instead of one partial line per lane).  Ends with a barrier, so the
+// LDS region is free again.
+constexpr int kRecLds = kRecLine + 1;  // padded LDS stride (doubles) of one line's records
+
+__device__ __forceinline__ void stream_records(double* __restrict__ seg, int nl, rsrc_t dst) {
+  __syncthreads();
+  const int bd = (int)blockDim.x;
+  for (int p = (int)threadIdx.x; p < nl * (kRecLine / 2); p += bd) {
+    const int ln = p / (kRecLine / 2), c = (p % (kRecLine / 2)) * 2;
+    bst2v(dst, (uint32_t)p * 16u, 0, make_double2(seg[ln * kRecLds + c], seg[ln * kRecLds + c + 1]));
+  }
+  __syncthreads();
+}
+
 // One line tile of the condensed assembly from given J and H values.  All
 // J / H / weight loads of a line-period are issued before its first store
 // (completions are counted in order); the four flow kinds then build their
@@ -1061,7 +1079,7 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
   const int tid = (int)threadIdx.x;
   const uint32_t l = (uint32_t)(tl.e0 + tid);
   const bool act = (int)l < tl.e1;
-  const uint32_t vL = l * 8u, vL4 = l * 4u, vR = l * (uint32_t)(kRecLine * 8);
+  const uint32_t vL = l * 8u, vL4 = l * 4u;
   const rsrc_t rKrow = rsrc(I.krow), rKsrc = rsrc(I.ksrc);
   const uint32_t FL4 = (uint32_t)b.xFL * 4u, Bq = (uint32_t)b.B * 4u;
   int sb[4], se[4];
@@ -1183,13 +1201,14 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
       q[2] += dang * Ja0 * Ja0;
       q[8] += dang * Ja1 * Ja1;
       q[5] += dang * Ja1 * Ja0;
-      const rsrc_t rR = rsrc(rec_at(I, scr, t));
-      bst2v(rR, vR, 0, make_double2(q[0], q[1]));
-      bst2v(rR, vR, 16, make_double2(q[2], q[3]));
-      bst2v(rR, vR, 64, make_double2(q[6], q[7]));
-      bst2v(rR, vR, 80, make_double2(q[8], q[9]));
+      // records: the K sums of both ends (p, q and J^T v slots unused here)
+      const double rec[kRecLine] = {q[0], q[1], q[2], q[3], 0.0, 0.0, 0.0, 0.0,
+                                    q[6], q[7], q[8], q[9], 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < kRecLine; ++a) seg[tid * kRecLds + a] = rec[a];
       bst2v(rsrc(shared_at(I, scr, t)), vL * 2u, 0, make_double2(q[4], q[5]));
     }
+    stream_records(seg, tl.e1 - tl.e0, rsrc(rec_at(I, scr, t) + (int64_t)tl.e0 * kRecLine));
   }
   (void)rKsrc;
 }
@@ -1224,7 +1243,7 @@ __device__ void fused_line_tile(const InstDev& I, const Tile& tl, const double* 
   const uint32_t l = (uint32_t)(tl.e0 + tid);
   const bool act = (int)l < tl.e1;
   // lane offsets: every per-line stream is (uniform stream offset) + vL
-  const uint32_t vL = l * 8u, vL4 = l * 4u, vR = l * (uint32_t)(kRecLine * 8);
+  const uint32_t vL = l * 8u, vL4 = l * 4u;
   const rsrc_t rKrow = rsrc(I.krow);
   const uint32_t FL4 = (uint32_t)b.xFL * 4u, Bq = (uint32_t)b.B * 4u;
   int sb[4], se[4];
@@ -1407,18 +1426,15 @@ __device__ void fused_line_tile(const InstDev& I, const Tile& tl, const double* 
 #pragma unroll
         for (int k = 0; k < 4; ++k) bstvn(rG, vL, xFL8 + (uint32_t)k * B8, 0.0);
       }
-      // hand-off: one 64-byte record per line end, the shared cross pair
-      const rsrc_t rR = rsrc(rec_at(I, scr, t));
-      bst2v(rR, vR, 0, make_double2(q[0], q[1]));
-      bst2v(rR, vR, 16, make_double2(q[2], q[3]));
-      bst2v(rR, vR, 32, make_double2(fl[0], fl[1]));
-      bst2v(rR, vR, 48, make_double2(jtr[0], jtr[1]));
-      bst2v(rR, vR, 64, make_double2(q[6], q[7]));
-      bst2v(rR, vR, 80, make_double2(q[8], q[9]));
-      bst2v(rR, vR, 96, make_double2(fl[2], fl[3]));
-      bst2v(rR, vR, 112, make_double2(jtr[2], jtr[3]));
+      // hand-off: one 64-byte record per line end (through LDS), the shared
+      // cross pair
+      const double rec[kRecLine] = {q[0], q[1], q[2], q[3], fl[0], fl[1], jtr[0], jtr[1],
+                                    q[6], q[7], q[8], q[9], fl[2], fl[3], jtr[2], jtr[3]};
+#pragma unroll
+      for (int a = 0; a < kRecLine; ++a) seg[tid * kRecLds + a] = rec[a];
       bst2v(rsrc(shared_at(I, scr, t)), vL * 2u, 0, make_double2(q[4], q[5]));
     }
+    stream_records(seg, tl.e1 - tl.e0, rsrc(rec_at(I, scr, t) + (int64_t)tl.e0 * kRecLine));
   }
 }
 

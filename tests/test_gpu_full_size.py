@@ -1,0 +1,192 @@
+"""Parity at the full sizes of the batched and adjoint forms and of the
+lifted-KKT calls, in the launch configuration the benchmark times (tuned
+shapes from the committed cache, the sweep replayed from its HIP graph).
+
+* Batched: 64 uneven instances (sum n = 12.7M) in one graph replay; every
+  element of every instance bitwise equal to that instance's own plain
+  sweep, and three sampled instances (smallest, largest, one in between)
+  element by element against the oracle, K included.
+* Adjoint: 16 mid instances through the autograd function; two sampled
+  instances against the oracle, and the whole batch against central
+  differences of the GPU forward.
+* Condensation calls at paper scale: diag_x, D, the right-hand side, J v
+  and the recovered steps against the oracle everywhere (those calls are
+  vector-valued and the oracle computes them in seconds at this size)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import opf_oracle as O
+from paper_2405_14032_amd import synth
+
+import gpu_common as GC
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TUNE_CACHE = os.path.join(ROOT, "paper_2405_14032_amd", "tune", "mi355x.json")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def _t(torch, dev, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def _outputs(torch, dev, M):
+    e = lambda k: torch.full((k,), float("nan"), dtype=torch.float64, device=dev)
+    return dict(f=e(M.ninst), grad=e(M.n), c=e(M.m), jvals=e(M.nnz_jac), hvals=e(M.nnz_hess), jtv=e(M.n),
+                kvals=e(M.nnz_kkt))
+
+
+@pytest.mark.timeout(900)
+def test_batched_64_uneven_instances(dev):
+    import torch
+    from paper_2405_14032_amd import capi
+    nets = synth.batched_networks(64)
+    pts = [synth.make_point(n, synth.BATCH_SEED0 + k) for k, n in enumerate(nets)]
+    print(f"batched: 64 instances, sum n = {sum(n.n for n in nets)}", flush=True)
+    MB = capi.Model(nets, device=0)
+    MB.use_current_torch_stream()
+    MB.autotune(TUNE_CACHE)
+    cat = lambda key: np.concatenate([getattr(p, key) for p in pts])
+    X, LAM, DX, D = (_t(torch, dev, cat(k)) for k in ("x", "lam", "diag_x", "dcon"))
+    ob = _outputs(torch, dev, MB)
+    sb = MB.sweep_args(x=X, lam=LAM, sigma=1.0, v=LAM, diag_x=DX, dcon=D, **ob)
+    for _ in range(3):  # replays: every one must give the same result
+        MB.sweep_graph(sb)
+    torch.cuda.synchronize()
+    # every instance bitwise equal to its own plain sweep
+    for k, (net, pt) in enumerate(zip(nets, pts)):
+        Mk = capi.Model([net], device=0)
+        Mk.use_current_torch_stream()
+        xs = [_t(torch, dev, a) for a in (pt.x, pt.lam, pt.diag_x, pt.dcon)]
+        ok = _outputs(torch, dev, Mk)
+        Mk.sweep(Mk.sweep_args(x=xs[0], lam=xs[1], sigma=1.0, v=xs[1], diag_x=xs[2], dcon=xs[3], **ok))
+        torch.cuda.synchronize()
+        for key, offs in (("grad", MB.x_off), ("c", MB.c_off), ("jvals", MB.j_off), ("hvals", MB.h_off),
+                          ("jtv", MB.x_off), ("kvals", MB.k_off)):
+            assert torch.equal(ob[key][offs[k]:offs[k + 1]], ok[key]), (k, key)
+        Mk.close()
+    # sampled instances against the oracle
+    sizes = [n.n for n in nets]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), int(np.argsort(sizes)[len(sizes) // 2])})
+    jr = torch.empty(MB.nnz_jac, dtype=torch.int32, device=dev)
+    jc = torch.empty_like(jr)
+    hr = torch.empty(MB.nnz_hess, dtype=torch.int32, device=dev)
+    hc = torch.empty_like(hr)
+    rp = torch.empty(MB.n + 1, dtype=torch.int64, device=dev)
+    ci = torch.empty(MB.nnz_kkt, dtype=torch.int32, device=dev)
+    MB.jac_structure(jr, jc)
+    MB.hess_structure(hr, hc)
+    MB.kkt_structure(rp, ci)
+    torch.cuda.synchronize()
+    G = {k: v.cpu().numpy() for k, v in ob.items()}
+    jr, jc, hr, hc = (a.cpu().numpy().astype(np.int64) for a in (jr, jc, hr, hc))
+    rp, ci = rp.cpu().numpy(), ci.cpu().numpy().astype(np.int64)
+    for k in picks:
+        net, pt = nets[k], pts[k]
+        print(f"oracle for instance {k}: N={net.N} B={net.B} G={net.G} T={net.T}", flush=True)
+        xo, co, jo, ho, ko = MB.x_off[k], MB.c_off[k], MB.j_off[k], MB.h_off[k], MB.k_off[k]
+        R = GC.oracle_all(net, pt)
+        L = O.Layout(net)
+        dd = O.dims(net.N, net.B, net.G, net.T)
+        nj, nh = dd["nnz_jac"], dd["nnz_hess"]
+        sl = lambda a, o, n: a[o:o + n]
+        GC.assert_close(G["f"][k:k + 1], np.array([R["f"][0]]), np.array([R["f"][1]]), GC.TOL, f"[{k}] f")
+        GC.assert_close(sl(G["grad"], xo, L.n), *R["grad"], GC.TOL, f"[{k}] grad")
+        GC.assert_close(sl(G["c"], co, L.m), *R["c"], GC.TOL, f"[{k}] c")
+        GC.assert_close(sl(G["jvals"], jo, nj), *R["jac"], GC.TOL, f"[{k}] J")
+        GC.assert_close(sl(G["hvals"], ho, nh), *R["hess"], GC.TOL, f"[{k}] H")
+        GC.assert_close(sl(G["jtv"], xo, L.n), *R["jtv"], GC.TOL, f"[{k}] J^T v")
+        assert np.array_equal(sl(jr, jo, nj) - co, R["jac_idx"][0])
+        assert np.array_equal(sl(jc, jo, nj) - xo, R["jac_idx"][1])
+        assert np.array_equal(sl(hr, ho, nh) - xo, R["hess_idx"][0])
+        assert np.array_equal(sl(hc, ho, nh) - xo, R["hess_idx"][1])
+        orp, oci = R["kkt_idx"]
+        nk = int(orp[-1])
+        assert np.array_equal(rp[xo:xo + L.n + 1] - ko, orp)
+        assert np.array_equal(sl(ci, ko, nk) - xo, oci)
+        GC.assert_close(sl(G["kvals"], ko, nk), *R["kkt"], GC.TOL_KKT, f"[{k}] K")
+    MB.close()
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_16_mid_instances(dev):
+    import torch
+    from paper_2405_14032_amd import autograd, capi
+    nets = synth.adjoint_networks(16)
+    pts = [synth.make_point(n, synth.ADJOINT_SEED0 + k) for k, n in enumerate(nets)]
+    M = capi.Model(nets, device=0)
+    M.autotune(TUNE_CACHE)
+    x = _t(torch, dev, np.concatenate([p.x for p in pts])).requires_grad_(True)
+    pd = _t(torch, dev, np.concatenate([n.pd.reshape(-1) for n in nets])).requires_grad_(True)
+    qd = _t(torch, dev, np.concatenate([n.qd.reshape(-1) for n in nets])).requires_grad_(True)
+    lam = _t(torch, dev, np.concatenate([p.lam for p in pts]))
+    c = autograd.opf_cons(x, pd, qd, M)
+    gx, gpd, gqd = torch.autograd.grad(c, (x, pd, qd), grad_outputs=lam)
+    torch.cuda.synchronize()
+    C, GX, GP, GQ, LM = (a.detach().cpu().numpy() for a in (c, gx, gpd, gqd, lam))
+    for k in (0, 11):
+        net, pt = nets[k], pts[k]
+        L = O.Layout(net)
+        xs, cs = slice(M.x_off[k], M.x_off[k] + L.n), slice(M.c_off[k], M.c_off[k] + L.m)
+        ls = slice(k * net.T * net.N, (k + 1) * net.T * net.N)
+        GC.assert_close(C[cs], *O.constraints(net, pt.x, with_mag=True), GC.TOL, f"adjoint[{k}] c")
+        GC.assert_close(GX[xs], *O.jtprod(net, pt.x, LM[cs], with_mag=True), GC.TOL, f"adjoint[{k}] J^T lam")
+        op, oq = O.load_adjoint(net, LM[cs])
+        assert np.array_equal(GP[ls], op.reshape(-1)) and np.array_equal(GQ[ls], oq.reshape(-1))
+    # the whole batch against central differences of the GPU forward (h = 1e-6)
+    rng = np.random.default_rng(23)
+    dx = _t(torch, dev, rng.standard_normal(M.n))
+    dp = _t(torch, dev, rng.standard_normal(pd.numel()))
+    dq = _t(torch, dev, rng.standard_normal(qd.numel()))
+    adj = float((gx * dx).sum() + (gpd * dp).sum() + (gqd * dq).sum())
+    h = 1e-6
+    with torch.no_grad():
+        cp = autograd.opf_cons(x + h * dx, pd + h * dp, qd + h * dq, M)
+        cm = autograd.opf_cons(x - h * dx, pd - h * dp, qd - h * dq, M)
+        fd = float((lam * (cp - cm)).sum()) / (2 * h)
+    torch.cuda.synchronize()
+    assert abs(adj - fd) <= 1e-8 * max(1.0, abs(adj)), (adj, fd)
+    M.close()
+
+
+@pytest.mark.timeout(900)
+def test_condensation_calls_paper_scale(dev):
+    import torch
+    from paper_2405_14032_amd import capi
+    net = synth.config_network("paper")
+    st = synth.make_ipm_state(*O.bounds(net), seed=3)
+    M = capi.Model([net], device=0)
+    M.use_current_torch_stream()
+    M.autotune(TUNE_CACHE)
+    keep = {f: _t(torch, dev, getattr(st, f)) for f in ("x", "s", "y", "zl", "zu", "vl", "vu", "xl", "xu", "sl", "su")}
+    cst = M.ipm_state(**keep, mu=st.mu, delta_w=st.delta_w, delta_c=st.delta_c)
+    grad, c = O.gradient(net, st.x), O.constraints(net, st.x)
+    dxv = np.random.default_rng(5).standard_normal(M.n)
+    GR, CC, DXV = _t(torch, dev, grad), _t(torch, dev, c), _t(torch, dev, dxv)
+    e = lambda k: torch.empty(k, dtype=torch.float64, device=dev)
+    diag_x, dcon, rhs, jv = e(M.n), e(M.m), e(M.n), e(M.m)
+    M.condensed_rhs(cst, GR, CC, diag_x, dcon, rhs)
+    outs = [e(M.m), e(M.m), e(M.n), e(M.n), e(M.m), e(M.m)]
+    M.recover_step(cst, CC, DXV, *outs)
+    M.jprod(keep["x"], DXV, jv)
+    torch.cuda.synchronize()
+    h = lambda a: a.cpu().numpy()
+    M.close()
+    print("gpu done; oracle", flush=True)
+    rdx, rd, rr, rrm = O.condensed_rhs(net, st, grad, c, with_mag=True)
+    GC.assert_close(h(diag_x), rdx, np.abs(rdx), GC.TOL, "paper diag_x")
+    GC.assert_close(h(dcon), rd, np.abs(rd), GC.TOL, "paper dcon")
+    GC.assert_close(h(rhs), rr, rrm, GC.TOL, "paper rhs")
+    GC.assert_close(h(jv), *O.jprod(net, st.x, dxv, with_mag=True), GC.TOL, "paper J v")
+    ref, mags = O.recover_step(net, st, c, dxv, with_mag=True)
+    for what, g, r, mg in zip(("ds", "dy", "dzl", "dzu", "dvl", "dvu"), outs, ref, mags):
+        GC.assert_close(h(g), r, mg, GC.TOL, "paper " + what)
