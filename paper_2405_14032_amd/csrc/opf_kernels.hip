@@ -1011,20 +1011,26 @@ __device__ void fused_gen(const InstDev& I, int g, int t0, int t1, double sigma,
 // entry; four slots per lane are handled per step so their template loads
 // and J gathers are in flight together.
 template <bool GATHER, bool NT = false>
-__device__ __forceinline__ void stream_segment(const double* __restrict__ seg, rsrc_t src, rsrc_t jp, rsrc_t dst,
+__device__ __forceinline__ void stream_segment(const double* __restrict__ seg, rsrc_t src, rsrc_t jp, double* dst,
                                                int len) {
   // GATHER: the template loads and J gathers of up to U slots per lane are
-  // all issued before the first store (in-order completion counting)
+  // all issued before the first store (in-order completion counting).
+  // Lane i writes slot i - d, d = the destination's offset inside its 64-byte
+  // line, so every wave's stores cover whole lines except at the ends of the
+  // segment (partial-line writes cost far more than their bytes).
   constexpr int U = GATHER ? 12 : 4;
+  const int d = (int)(((uintptr_t)dst >> 3) & 7);
+  const rsrc_t rd = rsrc(dst - d);
   const int bd = (int)blockDim.x;
-  for (int p0 = (int)threadIdx.x; p0 < len; p0 += U * bd) {
+  for (int p0 = (int)threadIdx.x; p0 < len + d; p0 += U * bd) {
     int sr[U];
     double v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int p = p0 + u * bd;
-      sr[u] = (GATHER && p < len) ? bldi(src, (uint32_t)p) : -2;
-      v[u] = p < len ? seg[p] : 0.0;
+      const int p = p0 + u * bd - d;
+      const bool ok = p >= 0 && p < len;
+      sr[u] = (GATHER && ok) ? bldi(src, (uint32_t)p) : -2;
+      v[u] = ok ? seg[p] : 0.0;
     }
     if (GATHER) {
 #pragma unroll
@@ -1033,10 +1039,10 @@ __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, r
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int p = p0 + u * bd;
-      if (p < len) {
-        if (NT) bstn(dst, (uint32_t)p, v[u]);
-        else bst(dst, (uint32_t)p, v[u]);
+      const int p = p0 + u * bd - d;
+      if (p >= 0 && p < len) {
+        if (NT) bstn(rd, (uint32_t)(p + d), v[u]);
+        else bst(rd, (uint32_t)(p + d), v[u]);
       }
     }
   }
@@ -1194,7 +1200,7 @@ __device__ void kkt_line_tile(const InstDev& I, const Tile& tl, const double* __
         seg[re[k] - 1] = dxk[k] + pk * Jk[0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jb[k] + Hth[k];
       }
       __syncthreads();
-      stream_segment<true, true>(seg, rsrc(I.ksrc + sb[k]), rJ, rsrc(kbase + sb[k]), se[k] - sb[k]);
+      stream_segment<true, true>(seg, rsrc(I.ksrc + sb[k]), rJ, kbase + sb[k], se[k] - sb[k]);
       __syncthreads();
     }
     if (act) {
@@ -1399,7 +1405,7 @@ __device__ void fused_line_tile(const InstDev& I, const Tile& tl, const double* 
         seg[re[k] - 1] = dxk[k] + pk * Jk[0] + dth[k >> 1] * Jt[k] * Jt[k] + pb * Jbk + Hthk;
       }
       __syncthreads();
-      stream_segment<false, true>(seg, rKrow, rKrow, rsrc(kbase + sb[k]), se[k] - sb[k]);
+      stream_segment<false, true>(seg, rKrow, rKrow, kbase + sb[k], se[k] - sb[k]);
       __syncthreads();
     }
     if (act) {
@@ -1660,9 +1666,8 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
       }
     }
     __syncthreads();
-    const rsrc_t rKm = rsrc(kb + b0), rKa = rsrc(kb + a0);
-    for (int p = tid; p < b1 - b0; p += (int)blockDim.x) bstn(rKm, (uint32_t)p, svm[p]);
-    for (int p = tid; p < a1 - a0; p += (int)blockDim.x) bstn(rKa, (uint32_t)p, sva[p]);
+    stream_segment<false, true>(svm, rKrow, rKrow, kb + b0, b1 - b0);
+    stream_segment<false, true>(sva, rKrow, rKrow, kb + a0, a1 - a0);
     __syncthreads();
   }
 }
