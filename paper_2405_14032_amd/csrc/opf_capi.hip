@@ -265,6 +265,11 @@ int lds_needs(const opf_model* M, int op, const std::vector<Tile>& tiles, const 
               size_t& smem) {
   cap = 0;
   smem = 0;
+  if (op == OP_JAC) {  // staged line tiles: 15 streams of blockDim doubles
+    smem = 15 * (size_t)s.block * sizeof(double);
+    if (smem > kMaxSmem) return fail(OPF_EINVAL, "tile shape needs too much LDS for jac");
+    return OPF_OK;
+  }
   const bool line = op == OP_KKA || op == OP_JHKA || op == OP_SWA;
   if (!line && op != OP_KKB && op != OP_SWB) return OPF_OK;
   if (line && s.block > 256) return fail(OPF_EINVAL, "condensed line kernel: block > 256");

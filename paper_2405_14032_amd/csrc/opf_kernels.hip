@@ -179,53 +179,82 @@ __device__ __forceinline__ void jt_line(const double vk[4], const double Jf[4][5
   rec[3] = -sti - vang;
 }
 
+// Copies src[0 .. n) (LDS) to dst[0 .. n) in global memory, lane i writing
+// element i - d with d = dst's offset inside its 64-byte line, so that each
+// wave writes whole lines except at the two ends of the range.
+__device__ __forceinline__ void aligned_out(const double* __restrict__ src, int n, double* dst) {
+  const int d = (int)(((uintptr_t)dst >> 3) & 7);
+  const rsrc_t rd = rsrc(dst - d);
+  for (int i = (int)threadIdx.x; i < n + d; i += (int)blockDim.x) {
+    const int p = i - d;
+    if (p >= 0) bstn(rd, (uint32_t)i, src[p]);
+  }
+}
+
 // ---------------------------------------------------------------- Jacobian
-// Loads of the next period are issued before the stores of the current one
-// (completions are counted in order); outputs use non-temporal stores.
-__device__ void jac_branch(const InstDev& I, int l, int t0, int t1, const double* __restrict__ x,
-                           double* __restrict__ jv) {
+// One line tile of the Jacobian, block-cooperative: each lane evaluates its
+// line's 30 entries, which leave through LDS in two rounds of 15 streams so
+// that every stream is written with whole 64-byte lines (the per-period J
+// block starts at an arbitrary 8-byte offset).  Dynamic LDS: [15][blockDim].
+__device__ void jac_line_tile(const InstDev& I, const Tile& tl, const double* __restrict__ x,
+                              double* __restrict__ jv, double* __restrict__ stg) {
   const Bases b(I);
+  const int tid = (int)threadIdx.x, bd = (int)blockDim.x;
+  const int l = tl.e0 + tid;
+  const bool act = l < tl.e1;
+  const int nl = tl.e1 - tl.e0;
   Coef cf;
-  load_coef(I, l, cf);
+  uint32_t vI = 0, vJ = 0;
   const uint32_t B8 = (uint32_t)b.B * 8u, N8 = (uint32_t)b.N * 8u, vL = (uint32_t)l * 8u;
-  const uint32_t xFL8 = (uint32_t)b.xFL * 8u, jFLOW8 = (uint32_t)b.jFLOW * 8u, jBAL8 = (uint32_t)b.jBAL * 8u,
-                 jTH8 = (uint32_t)b.jTH * 8u, jANG8 = (uint32_t)b.jANG * 8u;
-  const uint32_t vI = (uint32_t)I.f_bus[l] * 8u, vJ = (uint32_t)I.t_bus[l] * 8u;
-  double in[8];  // vi, vj, ti, tj, flows
-  auto load = [&](int t, double* v) {
-    const rsrc_t rX = rsrc(x + I.x_off + (int64_t)t * I.n_p);
-    v[0] = bldv(rX, vI, 0);
-    v[1] = bldv(rX, vJ, 0);
-    v[2] = bldv(rX, vI, N8);
-    v[3] = bldv(rX, vJ, N8);
+  const uint32_t xFL8 = (uint32_t)b.xFL * 8u;
+  if (act) {
+    load_coef(I, l, cf);
+    vI = (uint32_t)I.f_bus[l] * 8u;
+    vJ = (uint32_t)I.t_bus[l] * 8u;
+  }
+  for (int t = tl.t0; t < tl.t1; ++t) {
+    double val[30];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v[4 + k] = bldv(rX, vL, xFL8 + (uint32_t)k * B8);
-  };
-  load(t0, in);
-  for (int t = t0; t < t1; ++t) {
-    const double vi = in[0], vj = in[1], ti = in[2], tj = in[3];
-    double fl[4];
+    for (int a = 0; a < 30; ++a) val[a] = 0.0;
+    if (act) {
+      const rsrc_t rX = rsrc(x + I.x_off + (int64_t)t * I.n_p);
+      const double vi = bldv(rX, vI, 0), vj = bldv(rX, vJ, 0), ti = bldv(rX, vI, N8), tj = bldv(rX, vJ, N8);
+      double fl[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) fl[k] = in[4 + k];
-    if (t + 1 < t1) load(t + 1, in);
-    const rsrc_t rJ = rsrc(jv + I.j_off + (int64_t)t * I.nnzj_p);
-    double s, c;
-    sincos(ti - tj, &s, &c);
-    const double vv = vi * vj;
+      for (int k = 0; k < 4; ++k) fl[k] = bldv(rX, vL, xFL8 + (uint32_t)k * B8);
+      double sn, cs;
+      sincos(ti - tj, &sn, &cs);
+      const double vv = vi * vj;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      double Jk[5], h[9];
-      flow_kind(cf, k, vi, vj, vv, s, c, 0.0, Jk, h);
+      for (int k = 0; k < 4; ++k) {
+        double Jk[5], h[9];
+        flow_kind(cf, k, vi, vj, vv, sn, cs, 0.0, Jk, h);
 #pragma unroll
-      for (int a = 0; a < 5; ++a) bstvn(rJ, vL, jFLOW8 + (uint32_t)(k * 5 + a) * B8, Jk[a]);
+        for (int a = 0; a < 5; ++a) val[k * 5 + a] = Jk[a];
+        val[20 + k] = -1.0;
+        val[24 + k] = 2.0 * fl[k];
+      }
+      val[28] = 1.0;
+      val[29] = -1.0;
     }
+    double* jp = jv + I.j_off + (int64_t)t * I.nnzj_p;
+    // stream s of the 30: flows (k * 5 + a), balance (20 + k), thermal (24 + k), angle (28, 29)
+    auto stream_base = [&](int st) -> int64_t {
+      if (st < 20) return b.jFLOW + (int64_t)st * b.B;
+      if (st < 24) return b.jBAL + (int64_t)(st - 20) * b.B;
+      if (st < 28) return b.jTH + (int64_t)(st - 24) * b.B;
+      return b.jANG + (int64_t)(st - 28) * b.B;
+    };
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      bstvn(rJ, vL, jBAL8 + (uint32_t)k * B8, -1.0);
-      bstvn(rJ, vL, jTH8 + (uint32_t)k * B8, 2.0 * fl[k]);
+    for (int r = 0; r < 2; ++r) {
+      if (act) {
+#pragma unroll
+        for (int a = 0; a < 15; ++a) stg[a * bd + tid] = val[r * 15 + a];
+      }
+      __syncthreads();
+      for (int a = 0; a < 15; ++a) aligned_out(stg + a * bd, nl, jp + stream_base(r * 15 + a) + tl.e0);
+      __syncthreads();
     }
-    bstvn(rJ, vL, jANG8, 1.0);
-    bstvn(rJ, vL, jANG8 + B8, -1.0);
   }
 }
 
@@ -244,17 +273,19 @@ __device__ void jac_gen(const InstDev& I, int g, int t0, int t1, double* __restr
   }
 }
 
+// Dynamic LDS: [15][blockDim] doubles (the staged line tiles).
 __global__ void __launch_bounds__(512) k_jac(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
                                              int ntiles, const double* __restrict__ x, double* __restrict__ jv) {
+  extern __shared__ double lds[];
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile tl = tiles[remap_tile(v, ntiles)];
     const InstDev& I = insts[tl.inst];
+    if (tl.kind == TK_BRANCH) {
+      jac_line_tile(I, tl, x, jv, lds);
+      continue;
+    }
     const int e = tl.e0 + (int)threadIdx.x;
-    if (e >= tl.e1) continue;
-    if (tl.kind == TK_BRANCH)
-      jac_branch(I, e, tl.t0, tl.t1, x, jv);
-    else
-      jac_gen(I, e, tl.t0, tl.t1, jv);
+    if (e < tl.e1) jac_gen(I, e, tl.t0, tl.t1, jv);
   }
 }
 
@@ -1918,7 +1949,12 @@ dim3 grid_of(const Launch& L) { return dim3((unsigned)(L.grid > 0 ? L.grid : L.n
     return hipGetLastError();                                                                   \
   } while (0)
 
-hipError_t launch_jac(const Launch& L, const double* x, double* jv) { OPF_LAUNCH(k_jac, L, x, jv); }
+hipError_t launch_jac(const Launch& L, const double* x, double* jv) {
+  if (L.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_jac, grid_of(L), dim3((unsigned)L.block), L.smem, L.stream, L.insts, L.tiles, L.ntiles, x,
+                     jv);
+  return hipGetLastError();
+}
 hipError_t launch_hess(const Launch& L, const double* x, const double* lam, double sigma, double* hv) {
   OPF_LAUNCH(k_hess, L, x, lam, sigma, hv);
 }
