@@ -39,6 +39,29 @@ def manual_network(N, f_bus, t_bus, r, x, b, gen_bus, T=1, pd=None):
         pd=pd, qd=0.3 * pd)
 
 
+def hub_network():
+    """A star: bus 7 joined to every other bus (one line reversed), two lines
+    doubled (one of them anti-parallel), a few lines among the leaves, five
+    generators on the hub, off-nominal taps and phase shifts: high-degree
+    incidence loops, long K rows, several generators sharing balance rows."""
+    N, hub = 40, 7
+    f, t = [], []
+    for k in range(N):
+        if k != hub:
+            f.append(hub if k != 25 else k)
+            t.append(k if k != 25 else hub)
+    f += [hub, 20, 3, 11, 30]
+    t += [3, hub, 4, 12, 31]
+    B = len(f)
+    rng = np.random.default_rng(61)
+    net = manual_network(N, f, t, list(rng.uniform(0.005, 0.03, B)), list(rng.uniform(0.05, 0.3, B)),
+                              list(rng.uniform(0.0, 0.08, B)), [hub, hub, 3, hub, 30, hub, hub], T=3,
+                              pd=rng.uniform(0.0, 0.3, (3, N)))
+    net.tap[:] = rng.uniform(0.95, 1.05, B)
+    net.shift[:] = rng.uniform(-0.1, 0.1, B)
+    return net
+
+
 def dense_jac(net, x):
     L = O.Layout(net)
     r, c, v = O.jacobian(net, x)

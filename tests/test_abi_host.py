@@ -201,3 +201,13 @@ def test_condensation_calls_need_outputs_and_a_device():
     assert capi.opf_condensed_rhs(M.h, C.byref(st), p, p, p, p, p) == capi.OPF_ENODEV
     assert capi.opf_recover_step(M.h, C.byref(st), p, p, p, p, p, p, p, p) == capi.OPF_ENODEV
     assert capi.opf_jprod(M.h, p, p, p) == capi.OPF_ENODEV
+
+
+def test_host_kkt_pattern_hub():
+    # a 41-line star with doubled, anti-parallel and leaf lines and five
+    # generators on the hub
+    net = pins.hub_network()
+    M = capi.Model([net], device=-1)
+    rp, ci = M.kkt_structure_host()
+    orp, oci = _oracle_pattern(net, 62)
+    assert np.array_equal(rp, orp) and np.array_equal(ci.astype(np.int64), oci)

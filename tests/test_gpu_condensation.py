@@ -32,6 +32,7 @@ CASES = {
     "batched": lambda: [synth.make_network(31, 45, 7, 3, 71), synth.make_network(14, 20, 5, 5, 72),
                         synth.make_network(57, 80, 11, 2, 73)],
     "mid": lambda: [synth.config_network("mid")],
+    "hub": lambda: [pins.hub_network()],
 }
 
 

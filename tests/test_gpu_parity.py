@@ -47,6 +47,15 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_parity_hub(graph, torch_dev):
+    net = pins.hub_network()
+    pt = synth.make_point(net, 62, stress=True)
+    M, G = _run_one(net, pt, torch_dev, graph=graph)
+    R = GC.oracle_all(net, pt)
+    GC.compare(G, R, f"hub graph={graph}")
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_parity_small(name, torch_dev):
     net, seed, stress = CASES[name]()
