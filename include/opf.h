@@ -129,7 +129,12 @@ int opf_validate(const opf_instance_desc *desc, int32_t ninst);
  * and expanded over the data) and scratch are uploaded to that HIP device.
  * device < 0: host-only model, only dims / offsets / opf_kkt_structure
  * (into HOST arrays) are available; evaluation calls return OPF_ENODEV.
- * *out receives the model (NULL on failure). */
+ * *out receives the model (NULL on failure).  Errors: those of
+ * opf_validate; OPF_ENOMEM / OPF_EHIP on device allocation or upload
+ * failure; OPF_EINVAL if the condensed matrix's rows for one tile of lines
+ * or buses cannot be staged in on-chip memory at any launch shape (a bus
+ * joined to thousands of lines), or a bus's K rows would exceed 65534
+ * partner slots (OPF_ERANGE). */
 int opf_model_create(const opf_instance_desc *desc, int32_t ninst, int device,
                      opf_model **out);
 void opf_model_destroy(opf_model *model); /* NULL is a no-op */

@@ -286,9 +286,9 @@ int lds_needs(const opf_model* M, int op, const std::vector<Tile>& tiles, const 
     }
   }
   // the line kernels stage their hand-off records in the segment region
-  // (a padded 17-double stride per lane), and the fused ones also keep each
-  // lane's eight admittances in LDS
-  if (line) cap = std::max<int>(cap, 17 * s.block);
+  // (a padded stride per lane), and the fused ones also keep each lane's
+  // eight admittances in LDS
+  if (line) cap = std::max<int>(cap, kRecLds * s.block);
   const size_t adm = (op == OP_JHKA || op == OP_SWA) ? 8 * (size_t)s.block : 0;
   smem = line ? ((size_t)cap + adm) * sizeof(double)
               : ((size_t)cap + (size_t)cap2) * sizeof(double);
@@ -334,6 +334,18 @@ int set_shape(opf_model* M, int op, const Shape& s) {
   }
   M->gvalid = false;
   return OPF_OK;
+}
+
+// The default shape of an op, or narrower tiles when a tile's K rows do
+// not fit the LDS budget (buses of high degree).
+int set_default_shape(opf_model* M, int op) {
+  Shape s;
+  int rc = set_shape(M, op, s);
+  for (int blk = s.block / 2; rc == OPF_EINVAL && blk >= 64; blk /= 2) {
+    s.block = blk;
+    rc = set_shape(M, op, s);
+  }
+  return rc;
 }
 
 Launch launch_of(const opf_model* M, int op) {
@@ -722,8 +734,7 @@ int opf_model_create(const opf_instance_desc* desc, int32_t ninst, int device, o
       return fail(OPF_EHIP, "stream creation failed");
     }
     for (int op = 0; op < OP_COUNT; ++op) {
-      Shape s;
-      if ((rc = set_shape(M, op, s)) != OPF_OK) {
+      if ((rc = set_default_shape(M, op)) != OPF_OK) {
         std::string e = g_err;
         release(M);
         return fail(rc, e);
@@ -1114,7 +1125,7 @@ extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
     for (int op = 0; op < OP_COUNT && ok; ++op) ok = set_shape(M, op, cached[op]) == OPF_OK;
     if (ok) return OPF_OK;
     for (int op = 0; op < OP_COUNT; ++op)  // stale entry: back to defaults, then tune
-      if ((rc = set_shape(M, op, Shape())) != OPF_OK) return rc;
+      if ((rc = set_default_shape(M, op)) != OPF_OK) return rc;
   }
   // scratch inputs / outputs for timing (contents only need to be finite)
   const size_t n = M->n, m = M->m;

@@ -109,6 +109,9 @@ constexpr int kRecLine = 2 * kRecEnd;
 constexpr int kShared = 2;
 constexpr int kScratchJt = 4;
 constexpr int kScratchPerLine = kRecLine + kShared + kScratchJt;
+// LDS stride (doubles) of one line's two records when a line tile stages
+// them (padded by one to spread the lanes over the LDS banks).
+constexpr int kRecLds = kRecLine + 1;
 
 __device__ __forceinline__ double* rec_at(const InstDev& I, double* scr, int t) {
   return scr + I.s_off + (int64_t)t * I.B * kRecLine;

@@ -112,12 +112,7 @@ struct Bases {
   }
 };
 
-// First and second derivatives of flow kind k of one line at one period.
-// Jk: the flow row's J entries (own, vm_i, vm_j, va_i, va_j); h: the nine
-// lower-triangle Hessian entries of -ck * Hess(phi_k) in the local order of
-// the kind (ck = the row's multiplier).  Every kernel that produces J or H
-// values goes through this function, so separate and fused evaluations
-// give bitwise identical values.
+// w_k = alpha_k cos(delta) + beta_k sin(delta).
 __device__ __forceinline__ double flow_w(const Coef& cf, int k, double s, double c) {
   return cf.al[k] * c + cf.be[k] * s;
 }
@@ -128,6 +123,12 @@ __device__ __forceinline__ double flow_value(const Coef& cf, int k, double vi, d
   return cf.S[k] * vo * vo + vv * w;
 }
 
+// First and second derivatives of flow kind k of one line at one period.
+// Jk: the flow row's J entries (own, vm_i, vm_j, va_i, va_j); h: the nine
+// lower-triangle Hessian entries of -ck * Hess(phi_k) in the local order of
+// the kind (ck = the row's multiplier).  Every kernel that produces J or H
+// values goes through this function, so separate and fused evaluations
+// give bitwise identical values.
 __device__ __forceinline__ void flow_kind(const Coef& cf, int k, double vi, double vj, double vv, double s,
                                           double c, double ck, double Jk[5], double h[9]) {
   const double w = flow_w(cf, k, s, c);
@@ -895,27 +896,17 @@ __global__ void __launch_bounds__(512) k_jt_b(const InstDev* __restrict__ insts,
 // one kind at a time.  Those rows are contiguous in K (rows are in x order),
 // so the block first builds the kind's row segment in LDS (owner lane per
 // row: the four bus-variable pairs of its flow row, the thermal partner,
-// the diagonal, and for every balance-row partner the factor d_bal * J_bal)
-// and then streams the segment to HBM with consecutive lanes on consecutive
-// slots; in that pass a lane whose slot is a balance partner multiplies by
-// the partner's J entry (one independent gather per lane).  Each line also
-// reduces its own contributions to the bus-variable slots it touches into a
-// 10-value hand-off record, staged in LDS and stored contiguously.
+// the diagonal, and for every balance-row partner d_bal * J_bal times the
+// partner's J entry) and then streams the segment to HBM with consecutive
+// lanes on consecutive slots.  Each line also sums its contributions to the
+// bus-variable slots it touches into one 64-byte record per line end (the
+// layout is described with rec_at) plus the shared cross pair.
 // Generators own the pg / qg rows (balance partners, the ramp pair of
 // t >= 1, diagonal).
 // Bus phase: a bus owns its vm and va rows; one pass over its incident line
 // ends (sorted by neighbour) sums the records, merging parallel lines, into
 // an LDS copy of the block's row segments, streamed out the same way.
 //
-// Hand-off record of a line and period, laid out so that each end reads six
-// consecutive values (end i: [0, 6), end j: [4, 10)):
-//   [0] (vm_i,vm_i)  [1] (va_i,vm_i)  [2] (va_i,va_i)  [3] (va_i,vm_j)
-//   [4] (vm_j,vm_i)  [5] (va_j,va_i)
-//   [6] (vm_j,vm_j)  [7] (va_j,vm_j)  [8] (va_j,va_j)  [9] (va_j,vm_i)
-// Generator rows of K (pg: balance partners, the ramp pair of t >= 1, the
-// diagonal; qg: balance partners, diagonal).  FUSED: the generator's J and H
-// entries are produced here (structural constants and 2 sigma c2) and
-// written, and K uses those values; otherwise K reads them from J and H.
 // One generator of the condensed assembly over its tile's periods: the pg
 // and qg rows of K from the given J / H values.
 __device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, const double* __restrict__ H,
@@ -1039,8 +1030,7 @@ __device__ void fused_gen(const InstDev& I, int g, int t0, int t1, double sigma,
 // Streams a K row segment from LDS to HBM with consecutive lanes on
 // consecutive slots.  GATHER: a slot whose template source is a J entry (a
 // balance partner) holds the factor d_bal * J_bal and is multiplied by that
-// entry; four slots per lane are handled per step so their template loads
-// and J gathers are in flight together.
+// entry.
 template <bool GATHER, bool NT = false>
 __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, rsrc_t src, rsrc_t jp, double* dst,
                                                int len) {
@@ -1085,8 +1075,6 @@ __device__ __forceinline__ void stream_segment(const double* __restrict__ seg, r
 // consecutive lanes on consecutive 16-byte chunks (whole cache lines per
 // wave instead of one partial line per lane).  Ends with a barrier, so the
 // LDS region is free again.
-constexpr int kRecLds = kRecLine + 1;  // padded LDS stride (doubles) of one line's records
-
 __device__ __forceinline__ void stream_records(double* __restrict__ seg, int nl, rsrc_t dst) {
   __syncthreads();
   const int bd = (int)blockDim.x;
@@ -1475,7 +1463,8 @@ __device__ void fused_line_tile(const InstDev& I, const Tile& tl, const double* 
   }
 }
 
-// Dynamic LDS: seg[cap_seg] doubles (the longest K row segment of a tile).
+// Dynamic LDS: seg[cap_seg] doubles (the longest K row segment of a tile,
+// at least the padded records of a block).
 __global__ void __launch_bounds__(256) k_kkt_a(const InstDev* __restrict__ insts, const Tile* __restrict__ tiles,
                                                int ntiles, int cap_seg, const double* __restrict__ H,
                                                const double* __restrict__ J, const double* __restrict__ DX,

@@ -39,12 +39,12 @@ def manual_network(N, f_bus, t_bus, r, x, b, gen_bus, T=1, pd=None):
         pd=pd, qd=0.3 * pd)
 
 
-def hub_network():
+def hub_network(N=40):
     """A star: bus 7 joined to every other bus (one line reversed), two lines
     doubled (one of them anti-parallel), a few lines among the leaves, five
     generators on the hub, off-nominal taps and phase shifts: high-degree
     incidence loops, long K rows, several generators sharing balance rows."""
-    N, hub = 40, 7
+    hub = 7
     f, t = [], []
     for k in range(N):
         if k != hub:
