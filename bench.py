@@ -171,7 +171,10 @@ def bench_plain(torch, dev, args):
     net = synth.config_network("paper")
     pt = synth.make_point(net, 3)
     log(f"paper-scale instance: N={net.N} B={net.B} G={net.G} T={net.T}")
-    M = capi.Model([net], device=0)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter()
+    M = capi.Model([net], device=0)  # host symbolic analysis + upload (once per model)
+    create_s = time.perf_counter() - t_create
     M.use_current_torch_stream()
     M.autotune(args.tune_cache)
     X, LAM, DX, D = make_inputs(torch, dev, net, pt)
@@ -211,7 +214,14 @@ def bench_plain(torch, dev, args):
     n_p = 2 * net.N + 2 * net.G + 4 * net.B
     starts = torch.arange(net.T, device=dev) * n_p
     kbus = int((rp[starts + 2 * net.N] - rp[starts]).sum())
-    del ci
+    # symbolic outputs (J / H COO indices, K CSR) generated on the device
+    jr, jc = (torch.empty(M.nnz_jac, dtype=torch.int32, device=dev) for _ in range(2))
+    hr, hc = (torch.empty(M.nnz_hess, dtype=torch.int32, device=dev) for _ in range(2))
+    symbolic = {"model_create_s": round(create_s, 3),
+                "jac_structure_ms": round(event_time(torch, lambda: M.jac_structure(jr, jc), 3), 4),
+                "hess_structure_ms": round(event_time(torch, lambda: M.hess_structure(hr, hc), 3), 4),
+                "kkt_structure_ms": round(event_time(torch, lambda: M.kkt_structure(rp, ci), 3), 4)}
+    del jr, jc, hr, hc, ci
     kb = sweep_kernel_bytes(net, M, kbus)
     # per-call times, events on the model's (current) stream
     calls = {
@@ -267,6 +277,7 @@ def bench_plain(torch, dev, args):
         "calls": per,
         "separate_jhk_ms": round(per["jac"]["ms"] + per["hess"]["ms"] + per["condensed"]["ms"], 4),
         "kernels": kernels,
+        "symbolic": symbolic,
     }
     kt = kernels["sweep_a"]["avg_ms"]
     res["roofline"] = {"bound": "hbm", "kernel": "k_sweep_a (lines and generators of the fused sweep)",
@@ -436,7 +447,7 @@ def main():
             "config": res["config"], "hbm_gbs": res["hbm_gbs"], "sweep_bytes": res["sweep_bytes"],
             "graph_sweep_ms": res["graph_sweep_ms"], "eager_sweep_ms": res["eager_sweep_ms"],
             "jhk": res["jhk"], "separate_jhk_ms": res["separate_jhk_ms"],
-            "calls": res["calls"], "kernels": res["kernels"], "roofline": res["roofline"],
+            "calls": res["calls"], "kernels": res["kernels"], "symbolic": res["symbolic"], "roofline": res["roofline"],
             "roofline_bus": res["roofline_bus"]}
     if not args.only_plain:
         line["batched"] = bench_batched(torch, dev, args)
