@@ -684,3 +684,41 @@ def recover_step(net, st, c, dx, with_mag=False):
     dvl_m = (np.abs(R["vl"]) * ds_m + plo_m) / R["g_lo"]
     dvu_m = (np.abs(R["vu"]) * ds_m + phi_m) / R["g_hi"]
     return out, (ds_m, dy_m, dzl_m, dzu_m, dvl_m, dvu_m)
+
+
+# ----------------------------------------------------------------------------
+# the condensed system (Sec. III-B): K dx = rhs
+# ----------------------------------------------------------------------------
+def kkt_full(n, rowptr, colind, vals):
+    """The full symmetric K (scipy CSR) from its lower-triangle CSR: the
+    strictly lower entries mirrored above the diagonal, the diagonal once."""
+    import scipy.sparse as sp
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colind = np.asarray(colind, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
+    Lo = sp.csr_matrix((vals, (rows, colind)), shape=(n, n))
+    strict = sp.tril(Lo, -1)
+    return (Lo + strict.T).tocsr()
+
+
+def kkt_solve(n, rowptr, colind, vals, b):
+    """dx with K dx = b for K given by its lower CSR (the condensed system of
+    Sec. III-B), by a general sparse LU of the full symmetric matrix (a
+    library primitive: the solution of a nonsingular system is unique, so any
+    exact method defines it)."""
+    import scipy.sparse.linalg as sla
+    K = kkt_full(n, rowptr, colind, vals).tocsc()
+    return sla.spsolve(K, np.asarray(b, dtype=np.float64))
+
+
+def kkt_is_positive_definite(n, rowptr, colind, vals):
+    """Whether K is positive definite, by a dense Cholesky attempt (small
+    cases only): the property static pivoting relies on (Sec. III-B, K is
+    positive definite after inertia correction)."""
+    K = kkt_full(n, rowptr, colind, vals).toarray()
+    try:
+        np.linalg.cholesky(K)
+        return True
+    except np.linalg.LinAlgError:
+        return False

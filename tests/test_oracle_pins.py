@@ -318,3 +318,71 @@ def test_planted_missing_slack_weight(monkeypatch):
     _mutate(monkeypatch, "_row_terms", bad)
     net, st = pins.ipm_case()
     assert pins.check_lifted_kkt(net, st) > 1e-3
+
+
+# ---------------------------------------------------------------- K dx = rhs
+def _lower_csr(A):
+    """Lower-triangle CSR of a dense symmetric matrix, written out plainly."""
+    n = A.shape[0]
+    rp, ci, vv = [0], [], []
+    for i in range(n):
+        for j in range(i + 1):
+            if A[i, j] != 0.0:
+                ci.append(j)
+                vv.append(A[i, j])
+        rp.append(len(ci))
+    return np.array(rp), np.array(ci), np.array(vv)
+
+
+def test_kkt_solve_hand_case():
+    # 3 x 3 symmetric positive definite system written out by hand, x = (1, 2, 3)
+    rp = np.array([0, 1, 3, 5])
+    ci = np.array([0, 0, 1, 1, 2])
+    vv = np.array([4.0, 1.0, 3.0, 1.0, 2.0])
+    full = np.array([[4.0, 1.0, 0.0], [1.0, 3.0, 1.0], [0.0, 1.0, 2.0]])
+    assert np.array_equal(O.kkt_full(3, rp, ci, vv).toarray(), full)
+    b = np.array([6.0, 10.0, 8.0])
+    assert np.allclose(O.kkt_solve(3, rp, ci, vv, b), [1.0, 2.0, 3.0], rtol=0, atol=1e-14)
+    assert O.kkt_is_positive_definite(3, rp, ci, vv)
+    assert not O.kkt_is_positive_definite(3, rp, ci, np.array([4.0, 1.0, -3.0, 1.0, 2.0]))
+
+
+def _grid_kkt(seed=5):
+    net = synth.config_network("tiny")
+    pt = synth.make_point(net, seed)
+    L = O.Layout(net)
+    jac = O.jacobian(net, pt.x)
+    hess = O.hessian(net, pt.x, 1e-3 * pt.lam)
+    rng = np.random.default_rng(seed)
+    dx = rng.uniform(1.0, 10.0, L.n)
+    d = rng.uniform(0.5, 2.0, L.m)
+    rp, ci, kv, _ = O.condensed(L.n, jac, hess, dx, d)
+    # the same matrix built densely from the J and H entries
+    Jd = np.zeros((L.m, L.n))
+    np.add.at(Jd, (jac[0], jac[1]), jac[2])
+    Kd = O.hessian_dense(L.n, hess) + np.diag(dx) + Jd.T @ np.diag(d) @ Jd
+    return L.n, rp, ci, kv, Kd, rng
+
+
+def test_kkt_solve_grid_against_dense_system():
+    n, rp, ci, kv, Kd, rng = _grid_kkt()
+    b = rng.standard_normal(n)
+    x = O.kkt_solve(n, rp, ci, kv, b)
+    res = np.max(np.abs(Kd @ x - b)) / (np.max(np.abs(Kd)) * np.max(np.abs(x)) + np.max(np.abs(b)))
+    assert res <= 1e-14, res
+    assert O.kkt_is_positive_definite(n, rp, ci, kv)
+
+
+def test_planted_doubled_diagonal(monkeypatch):
+    # mirroring the whole lower triangle (diagonal included) is a plausible
+    # slip; the dense check catches it
+    import scipy.sparse as sp
+
+    def wrong(n, rowptr, colind, vals):
+        rows = np.repeat(np.arange(n), np.diff(rowptr))
+        Lo = sp.csr_matrix((vals, (rows, colind)), shape=(n, n))
+        return (Lo + Lo.T).tocsr()
+
+    monkeypatch.setattr(O, "kkt_full", wrong)
+    with pytest.raises(AssertionError):
+        test_kkt_solve_grid_against_dense_system()
