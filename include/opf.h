@@ -287,6 +287,77 @@ int opf_kernel_stats(opf_model *model, int32_t index, const char **name,
  * for this model shape and written after tuning. */
 int opf_autotune(opf_model *model, const char *cache_path);
 
+/* ---- static-pivot sparse Cholesky of the condensed matrix (Sec. III-B) ----
+ *
+ * After inertia correction the condensed matrix K is positive definite, so
+ * it is factored as K = L L^T without numerical pivoting; a pivot that is not
+ * above the caller's threshold is replaced (static pivoting) and counted, so
+ * the caller can tell that K was not positive definite and correct the
+ * inertia.  Structure used (Sec. II, eq. (1k)): periods couple only through
+ * the ramp rows, i.e. through the pg variables, and every period block has
+ * the same pattern.  One ordering of a period's variables serves all
+ * periods: the other variables first (approximate minimum degree), the pg
+ * variables last; the interior fronts of all periods are factored together,
+ * then the pg fronts form a chain over the periods (block elimination in
+ * time).  Instances of a batched model are factored one after another. */
+typedef struct opf_chol opf_chol;
+
+typedef struct {
+  int64_t factor_entries; /* stored factor doubles, all instances and periods */
+  int64_t arena_entries;  /* update-matrix workspace doubles                  */
+  double flops;           /* factorization flops (multiply-add = 2)           */
+  double flops_interior;  /* of which in the per-period interior fronts       */
+  int32_t nodes;          /* interior fronts per period, summed over instances */
+  int32_t levels;         /* largest interior tree height                      */
+  int32_t chunk;          /* periods whose interior fronts are factored together
+                             (smallest over instances)                         */
+  int32_t large_nodes;    /* fronts factored by the blocked kernels            */
+} opf_chol_info;
+
+/* Symbolic analysis of the model's K pattern (opf_kkt_structure): ordering,
+ * assembly tree, front sizes, assembly maps; on a device model it also
+ * allocates the factor and its workspace on the model's device.  Works on a
+ * host-only model (analysis only).  *out receives the factor object (NULL on
+ * failure); it refers to the model, which must outlive it.  Errors:
+ * OPF_EINVAL (NULL arguments, a front too large for the kernels),
+ * OPF_ENOMEM (host or device allocation), OPF_EHIP.  The update-matrix
+ * workspace holds the fronts of as many periods as fit in 8 GiB (the
+ * environment variable OPF_CHOL_ARENA_BYTES, read here, overrides the
+ * budget); those periods are factored together. */
+int opf_chol_analyze(opf_model *model, opf_chol **out);
+void opf_chol_destroy(opf_chol *chol); /* NULL is a no-op */
+int opf_chol_get_info(const opf_chol *chol, opf_chol_info *info);
+
+/* The analysis of instance inst, into HOST arrays (for checking it):
+ * opf_chol_tree_size gives the number of interior fronts per period and the
+ * total count of their update rows; opf_chol_tree fills perm [n_p] (position
+ * in the elimination order -> position in the period block of x), first,
+ * npiv, parent [nodes] (front s eliminates positions first[s] ..
+ * first[s] + npiv[s] - 1; parent -1 = the period's pg front), rowptr
+ * [nodes + 1] and rows [rows] (update rows of each front, in elimination
+ * positions, ascending).  Positions n_p - G .. n_p - 1 are the pg
+ * variables in their natural order. */
+int opf_chol_tree_size(const opf_chol *chol, int32_t inst, int32_t *nodes,
+                       int64_t *rows);
+int opf_chol_tree(const opf_chol *chol, int32_t inst, int32_t *perm,
+                  int32_t *first, int32_t *npiv, int32_t *parent,
+                  int64_t *rowptr, int32_t *rows);
+
+/* Numeric factorization of K from its values kvals [nnz_kkt] (device, the
+ * order of opf_kkt_structure).  A pivot d (the diagonal entry after the
+ * updates of the columns before it) with !(d > pivot_tol) is replaced by
+ * pivot_repl (> 0) and counted into *npert (device int32, overwritten).
+ * Enqueued on the model's stream; the factor stays in the opf_chol object.
+ * Errors: OPF_EINVAL (NULL, pivot_repl not > 0), OPF_ENODEV (host-only
+ * model), OPF_EHIP. */
+int opf_chol_factor(opf_chol *chol, const double *kvals, double pivot_tol,
+                    double pivot_repl, int32_t *npert);
+
+/* Solves L L^T x = b with the last factorization: b, x device [n] (may be
+ * the same array).  Enqueued on the model's stream; uses the factor
+ * object's work vectors, so solves on one object must not overlap. */
+int opf_chol_solve(opf_chol *chol, const double *b, double *x);
+
 /* Last error message of the calling thread ("" if none). */
 const char *opf_last_error(void);
 

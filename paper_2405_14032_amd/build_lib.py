@@ -6,7 +6,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/opf_capi.hip", "csrc/opf_kernels.hip", "csrc/opf_symbolic.cpp"]
+SOURCES = ["csrc/opf_capi.hip", "csrc/opf_kernels.hip", "csrc/opf_symbolic.cpp", "csrc/opf_chol.hip",
+           "csrc/opf_chol_symbolic.cpp"]
 LIB = os.path.join(HERE, "libopf.so")
 
 

@@ -65,6 +65,12 @@ class opf_sweep_args(C.Structure):
                 ("kvals", C.c_void_p)]
 
 
+class opf_chol_info(C.Structure):
+    _fields_ = [("factor_entries", C.c_int64), ("arena_entries", C.c_int64), ("flops", C.c_double),
+                ("flops_interior", C.c_double), ("nodes", C.c_int32), ("levels", C.c_int32),
+                ("chunk", C.c_int32), ("large_nodes", C.c_int32)]
+
+
 class opf_ipm_state(C.Structure):
     _fields_ = [("x", C.c_void_p), ("s", C.c_void_p), ("y", C.c_void_p),
                 ("zl", C.c_void_p), ("zu", C.c_void_p), ("vl", C.c_void_p), ("vu", C.c_void_p),
@@ -100,6 +106,13 @@ _SIGS = {
     "opf_condensed_rhs": (C.c_int, [_vp, C.POINTER(opf_ipm_state), _vp, _vp, _vp, _vp, _vp]),
     "opf_recover_step": (C.c_int, [_vp, C.POINTER(opf_ipm_state), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "opf_autotune": (C.c_int, [_vp, C.c_char_p]),
+    "opf_chol_analyze": (C.c_int, [_vp, C.POINTER(_vp)]),
+    "opf_chol_destroy": (None, [_vp]),
+    "opf_chol_get_info": (C.c_int, [_vp, C.POINTER(opf_chol_info)]),
+    "opf_chol_tree_size": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "opf_chol_tree": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "opf_chol_factor": (C.c_int, [_vp, _vp, C.c_double, C.c_double, _vp]),
+    "opf_chol_solve": (C.c_int, [_vp, _vp, _vp]),
     "opf_set_timing": (C.c_int, [_vp, C.c_int]),
     "opf_kernel_stats": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]),
@@ -334,3 +347,54 @@ class Model:
 
     def autotune(self, cache_path: str | None = None):
         check(opf_autotune(self.h, cache_path.encode() if cache_path else None), "opf_autotune")
+
+
+class Chol:
+    """Owns an opf_chol handle: the static-pivot sparse Cholesky of the
+    model's condensed matrix (analysis at construction; factor / solve on
+    device arrays)."""
+
+    def __init__(self, model: Model):
+        h = _vp()
+        check(opf_chol_analyze(model.h, C.byref(h)), "opf_chol_analyze")
+        self.h = h
+        self.model = model
+
+    def close(self):
+        if getattr(self, "h", None):
+            opf_chol_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = opf_chol_info()
+        check(opf_chol_get_info(self.h, C.byref(i)), "opf_chol_get_info")
+        return {k: getattr(i, k) for k, _ in opf_chol_info._fields_}
+
+    def tree(self, inst: int = 0) -> dict:
+        """The analysis of one instance as numpy arrays (host)."""
+        nn, nr = C.c_int32(), C.c_int64()
+        check(opf_chol_tree_size(self.h, inst, C.byref(nn), C.byref(nr)), "opf_chol_tree_size")
+        net = self.model.nets[inst]
+        n_p = 2 * net.N + 2 * net.G + 4 * net.B
+        perm = np.zeros(n_p, dtype=np.int32)
+        first = np.zeros(nn.value, dtype=np.int32)
+        npiv = np.zeros(nn.value, dtype=np.int32)
+        parent = np.zeros(nn.value, dtype=np.int32)
+        rowptr = np.zeros(nn.value + 1, dtype=np.int64)
+        rows = np.zeros(max(1, nr.value), dtype=np.int32)
+        check(opf_chol_tree(self.h, inst, perm.ctypes.data, first.ctypes.data, npiv.ctypes.data,
+                            parent.ctypes.data, rowptr.ctypes.data, rows.ctypes.data), "opf_chol_tree")
+        return dict(perm=perm, first=first, npiv=npiv, parent=parent, rowptr=rowptr, rows=rows[:nr.value])
+
+    def factor(self, kvals, pivot_tol: float, pivot_repl: float, npert):
+        check(opf_chol_factor(self.h, _ptr(kvals), float(pivot_tol), float(pivot_repl), _ptr(npert)),
+              "opf_chol_factor")
+
+    def solve(self, b, x):
+        check(opf_chol_solve(self.h, _ptr(b), _ptr(x)), "opf_chol_solve")

@@ -17,6 +17,7 @@
 
 #include "../../include/opf.h"
 #include "opf_device.h"
+#include "opf_api_internal.h"
 #include "opf_host.h"
 
 using namespace opf;
@@ -641,6 +642,16 @@ int enq_sweep(opf_model* M, const opf_sweep_args* a) {
 }
 
 }  // namespace
+
+// Accessors for the other ABI translation units (opf_api_internal.h).
+namespace opf {
+int api_fail(int code, const std::string& msg) { return fail(code, msg); }
+int model_device(const opf_model* M) { return M->device; }
+hipStream_t model_stream(const opf_model* M) { return M->stream; }
+const std::vector<InstHost>& model_insts(const opf_model* M) { return M->inst; }
+int64_t model_n(const opf_model* M) { return M->n; }
+int64_t model_nnzk(const opf_model* M) { return M->nnzk; }
+}  // namespace opf
 
 // ============================================================== C ABI
 extern "C" {

@@ -1,0 +1,1022 @@
+// Static-pivot sparse Cholesky of the condensed matrix (Sec. III-B): device
+// kernels and the opf_chol_* entry points.
+//
+// Numeric scheme (multifrontal, the plan from opf_chol_symbolic.cpp):
+//   * the factor of every interior front s of every period lives in one
+//     column-major (p+u) x p block (p pivots, u update rows); its update
+//     matrix (u x u, lower part) lives in a workspace arena until the
+//     parent has collected it;
+//   * K's entries are written straight into the factor blocks; each front
+//     then pulls its children's update matrices (extend-add, no atomics: a
+//     work item owns a set of the parent's columns), is factored in place
+//     (small fronts in LDS by one wavefront, large ones by blocked panel +
+//     trailing-update kernels), batched over the periods of a chunk;
+//   * the pg front of period t (G pivots, update rows pg_{t+1}) collects the
+//     period's tree roots and the previous pg front's update: a chain over t.
+// Solves run the same tree forward (update vectors pulled by the parent)
+// and backward (gathers of the ancestors' solution), batched over periods.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/opf.h"
+#include "opf_api_internal.h"
+#include "opf_chol_host.h"
+
+namespace opf {
+namespace {
+
+constexpr int kSmall = 64;   // largest front factored in LDS by one wavefront
+constexpr int kNB = 32;      // panel width of the blocked fronts
+constexpr int kTile = 64;    // trailing-update tile
+constexpr int kMaxPiv = 8192;  // pivots of one front held in LDS by the solves
+
+// Device view of one instance's plan.
+struct CDev {
+  const int32_t *node_f, *node_p, *node_u, *rel, *kids, *rows;
+  const int64_t *node_loff, *node_uoff, *node_woff, *row_ptr, *kid_ptr;
+  int64_t lsize, usize, wsize;
+  int32_t n_p, n_int, G;
+};
+
+// One front as the blocked kernels see it: factor block (ld x p, first p
+// columns of the front) and update block (ldU x u), per-period strides.
+struct FrontArg {
+  double* L;
+  int64_t Lstride;
+  int32_t ld, p, u;
+  double* U;
+  int64_t Ustride;
+  int32_t ldU;
+};
+
+__device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_fill(double* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// K's template slots of periods t0 .. t0+nt-1 into the factor blocks (or the
+// pg front's pivot block).  Every destination receives one entry.
+__global__ void k_scatter(const double* __restrict__ kv, int64_t k_off, int64_t nnzk_p, int32_t G, int32_t t0,
+                          int32_t nslots, const int64_t* __restrict__ dst, const int32_t* __restrict__ kpos0,
+                          const int32_t* __restrict__ kpos1, double* __restrict__ Lf, int64_t lsize,
+                          double* __restrict__ Cf, int64_t csize) {
+  const int t = t0 + (int)blockIdx.y;
+  const int64_t kp = k_off + (int64_t)t * nnzk_p + (t >= 1 ? (int64_t)(t - 1) * G : 0);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nslots; q += gridDim.x * blockDim.x) {
+    const double v = kv[kp + (t == 0 ? kpos0[q] : kpos1[q])];
+    const int64_t d = dst[q];
+    if (d >= 0) Lf[(int64_t)t * lsize + d] = v;
+    else Cf[(int64_t)t * csize + (-1 - d)] = v;
+  }
+}
+
+// The ramp pairs (pg_t,g , pg_{t-1},g), t in [t0, t1), t >= 1: entries of
+// the L21 block of pg front t-1 (row G + g, column g).
+__global__ void k_scatter_ramp(const double* __restrict__ kv, int64_t k_off, int64_t nnzk_p, int32_t G, int32_t t0,
+                               const int32_t* __restrict__ ramp_pos, double* __restrict__ Cf, int64_t csize) {
+  const int t = t0 + (int)blockIdx.y;
+  const int64_t kp = k_off + (int64_t)t * nnzk_p + (int64_t)(t - 1) * G;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x)
+    Cf[(int64_t)(t - 1) * csize + (int64_t)g * 2 * G + G + g] = kv[kp + ramp_pos[g]];
+}
+
+// Extend-add for the fronts of one level: work item (s, c0) owns columns
+// [c0, c0 + cb) of front s; it clears their update part, then adds each
+// child's update matrix entries that land there, child by child.
+__global__ void __launch_bounds__(256) k_extend(CDev D, const int32_t* __restrict__ items, int64_t item0,
+                                                int32_t cb, int32_t t0, double* __restrict__ Lf,
+                                                double* __restrict__ Ar) {
+  const int tt = (int)blockIdx.y;
+  const int s = items[2 * (item0 + blockIdx.x)], c0 = items[2 * (item0 + blockIdx.x) + 1];
+  const int p = D.node_p[s], u = D.node_u[s], ld = p + u;
+  const int c1 = min(c0 + cb, ld);
+  double* L = Lf + (int64_t)(t0 + tt) * D.lsize + D.node_loff[s];
+  double* U = Ar + (int64_t)tt * D.usize + D.node_uoff[s];
+  for (int j = max(c0, p); j < c1; ++j)
+    for (int i = j + (int)threadIdx.x; i < ld; i += (int)blockDim.x) U[(int64_t)(j - p) * u + (i - p)] = 0.0;
+  __syncthreads();
+  for (int64_t q = D.kid_ptr[s]; q < D.kid_ptr[s + 1]; ++q) {
+    const int c = D.kids[q];
+    const int uc = D.node_u[c];
+    const int32_t* rel = D.rel + D.row_ptr[c];
+    const double* Uc = Ar + (int64_t)tt * D.usize + D.node_uoff[c];
+    const int b0 = lower_bound_i32(rel, uc, c0), b1 = lower_bound_i32(rel, uc, c1);
+    for (int b = b0; b < b1; ++b) {
+      const int j = rel[b];
+      for (int a = b + (int)threadIdx.x; a < uc; a += (int)blockDim.x) {
+        const int i = rel[a];
+        const double v = Uc[(int64_t)b * uc + a];
+        if (j < p) L[(int64_t)j * ld + i] += v;
+        else U[(int64_t)(j - p) * u + (i - p)] += v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The period's tree roots into its pg front (ld 2G, pivot block only).
+__global__ void __launch_bounds__(256) k_extend_root(CDev D, const int32_t* __restrict__ roots, int32_t nroots,
+                                                     int32_t cb, int32_t t0, double* __restrict__ Cf, int64_t csize,
+                                                     const double* __restrict__ Ar) {
+  const int tt = (int)blockIdx.y;
+  const int c0 = (int)blockIdx.x * cb, c1 = min(c0 + cb, D.G);
+  double* L = Cf + (int64_t)(t0 + tt) * csize;
+  const int64_t ld = 2 * (int64_t)D.G;
+  for (int k = 0; k < nroots; ++k) {
+    const int c = roots[k];
+    const int uc = D.node_u[c];
+    const int32_t* rel = D.rel + D.row_ptr[c];
+    const double* Uc = Ar + (int64_t)tt * D.usize + D.node_uoff[c];
+    const int b0 = lower_bound_i32(rel, uc, c0), b1 = lower_bound_i32(rel, uc, c1);
+    for (int b = b0; b < b1; ++b) {
+      const int j = rel[b];
+      for (int a = b + (int)threadIdx.x; a < uc; a += (int)blockDim.x)
+        L[(int64_t)j * ld + rel[a]] += Uc[(int64_t)b * uc + a];
+    }
+    __syncthreads();
+  }
+}
+
+// Static pivot rule: d <= tol (or NaN) is replaced by repl and counted.
+__device__ __forceinline__ double pivot_sqrt(double d, double tol, double repl, int32_t* npert, bool count) {
+  if (!(d > tol)) {
+    d = repl;
+    if (count) atomicAdd(npert, 1);
+  }
+  return sqrt(d);
+}
+
+// Small fronts (p + u <= 64): one wavefront per (front, period), the whole
+// lower front in LDS, right-looking elimination of the p pivots.
+__global__ void __launch_bounds__(64) k_factor_small(CDev D, const int32_t* __restrict__ list, int64_t l0,
+                                                     int32_t t0, double* __restrict__ Lf, double* __restrict__ Ar,
+                                                     double tol, double repl, int32_t* __restrict__ npert) {
+  __shared__ double F[kSmall * (kSmall + 1)];
+  constexpr int S = kSmall + 1;
+  const int tt = (int)blockIdx.y;
+  const int s = list[l0 + blockIdx.x];
+  const int p = D.node_p[s], u = D.node_u[s], f = p + u;
+  const int i = (int)threadIdx.x;
+  double* L = Lf + (int64_t)(t0 + tt) * D.lsize + D.node_loff[s];
+  double* U = Ar + (int64_t)tt * D.usize + D.node_uoff[s];
+  for (int j = 0; j < f; ++j)
+    if (i >= j && i < f) F[j * S + i] = j < p ? L[(int64_t)j * f + i] : U[(int64_t)(j - p) * u + (i - p)];
+  __syncthreads();
+  for (int k = 0; k < p; ++k) {
+    if (i == k) F[k * S + k] = pivot_sqrt(F[k * S + k], tol, repl, npert, true);
+    __syncthreads();
+    if (i > k && i < f) F[k * S + i] /= F[k * S + k];
+    __syncthreads();
+    if (i > k && i < f) {
+      const double aik = F[k * S + i];
+      for (int j = k + 1; j <= i; ++j) F[j * S + i] -= aik * F[k * S + j];
+    }
+    __syncthreads();
+  }
+  for (int j = 0; j < f; ++j)
+    if (i >= j && i < f) {
+      if (j < p) L[(int64_t)j * f + i] = F[j * S + i];
+      else U[(int64_t)(j - p) * u + (i - p)] = F[j * S + i];
+    }
+}
+
+// Blocked front, one panel [k0, k0+kb), step 1: the kb x kb diagonal block
+// factored in place in LDS by one block per period (pivots counted here).
+__global__ void __launch_bounds__(64) k_diag(FrontArg A, int32_t k0, int32_t kb, double tol, double repl,
+                                             int32_t* __restrict__ npert) {
+  __shared__ double Dg[kNB * (kNB + 1)];
+  constexpr int S = kNB + 1;
+  double* L = A.L + (int64_t)blockIdx.x * A.Lstride;
+  const int64_t ld = A.ld;
+  const int tid = (int)threadIdx.x;
+  for (int e = tid; e < kb * kb; e += (int)blockDim.x) {
+    const int j = e / kb, i = e % kb;
+    if (i >= j) Dg[j * S + i] = L[(int64_t)(k0 + j) * ld + k0 + i];
+  }
+  __syncthreads();
+  for (int k = 0; k < kb; ++k) {
+    if (tid == k) Dg[k * S + k] = pivot_sqrt(Dg[k * S + k], tol, repl, npert, true);
+    __syncthreads();
+    if (tid > k && tid < kb) Dg[k * S + tid] /= Dg[k * S + k];
+    __syncthreads();
+    if (tid > k && tid < kb) {
+      const double aik = Dg[k * S + tid];
+      for (int j = k + 1; j <= tid; ++j) Dg[j * S + tid] -= aik * Dg[k * S + j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kb * kb; e += (int)blockDim.x) {
+    const int j = e / kb, i = e % kb;
+    if (i >= j) L[(int64_t)(k0 + j) * ld + k0 + i] = Dg[j * S + i];
+  }
+}
+
+// Step 2: the rows below the panel, L21 = A21 L11^-T, 256 rows per block
+// against the factored diagonal block (read-only here).
+__global__ void __launch_bounds__(256) k_panel(FrontArg A, int32_t k0, int32_t kb) {
+  __shared__ double Dg[kNB * (kNB + 1)];
+  constexpr int S = kNB + 1;
+  double* L = A.L + (int64_t)blockIdx.y * A.Lstride;
+  const int64_t ld = A.ld;
+  const int rows = A.p + A.u;
+  const int tid = (int)threadIdx.x;
+  for (int e = tid; e < kb * kb; e += (int)blockDim.x) {
+    const int j = e / kb, i = e % kb;
+    if (i >= j) Dg[j * S + i] = L[(int64_t)(k0 + j) * ld + k0 + i];
+  }
+  __syncthreads();
+  const int r = k0 + kb + (int)blockIdx.x * (int)blockDim.x + tid;
+  if (r >= rows) return;
+  double x[kNB];
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) x[j] = j < kb ? L[(int64_t)(k0 + j) * ld + r] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) {
+    if (j < kb) {
+      double sacc = x[j];
+#pragma unroll
+      for (int l = 0; l < j; ++l) sacc -= x[l] * Dg[l * S + j];
+      x[j] = sacc / Dg[j * S + j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kNB; ++j)
+    if (j < kb) L[(int64_t)(k0 + j) * ld + r] = x[j];
+}
+
+// Trailing update after a panel: C -= P P^T on the lower part of rows and
+// columns [r0, p+u), 64 x 64 tiles, 4 x 4 outputs per thread.  Columns < p
+// live in the factor block, the others in the update block.
+__global__ void __launch_bounds__(256) k_update(FrontArg A, int32_t k0, int32_t kb) {
+  __shared__ double Pi[kNB][kTile + 1], Pj[kNB][kTile + 1];
+  const int64_t x = blockIdx.x;
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > x) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
+  const int64_t tj = x - ti * (ti + 1) / 2;
+  double* L = A.L + (int64_t)blockIdx.y * A.Lstride;
+  double* U = A.U + (int64_t)blockIdx.y * A.Ustride;
+  const int64_t ld = A.ld;
+  const int rows = A.p + A.u, r0 = k0 + kb;
+  const int i0 = r0 + (int)ti * kTile, j0 = r0 + (int)tj * kTile;
+  const int tid = (int)threadIdx.x;
+  for (int e = tid; e < kNB * kTile; e += (int)blockDim.x) {
+    const int l = e / kTile, rr = e % kTile;
+    Pi[l][rr] = (l < kb && i0 + rr < rows) ? L[(int64_t)(k0 + l) * ld + i0 + rr] : 0.0;
+    Pj[l][rr] = (l < kb && j0 + rr < rows) ? L[(int64_t)(k0 + l) * ld + j0 + rr] : 0.0;
+  }
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[4][4] = {};
+  for (int l = 0; l < kb; ++l) {
+    double a[4], b[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a[q] = Pi[l][tx + 16 * q];
+      b[q] = Pj[l][ty + 16 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[q][c] += a[q] * b[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int j = j0 + ty + 16 * c;
+    if (j >= rows) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + tx + 16 * q;
+      if (i >= rows || i < j) continue;
+      if (j < A.p) L[(int64_t)j * ld + i] -= acc[q][c];
+      else U[(int64_t)(j - A.p) * A.ldU + (i - A.p)] -= acc[q][c];
+    }
+  }
+}
+
+// G x G lower update block of pg front t-1 into the pivot block of front t.
+__global__ void k_add_chain(const double* __restrict__ Us, int32_t G, double* __restrict__ C) {
+  const int64_t n = (int64_t)G * G;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / G, i = e % G;
+    if (i >= j) C[j * 2 * G + i] += Us[e];
+  }
+}
+
+// ------------------------------------------------------------------ solves
+__global__ void k_gather(const double* __restrict__ b, int32_t n_p, int32_t T, const int32_t* __restrict__ perm,
+                         double* __restrict__ Y) {
+  const int64_t n = (int64_t)n_p * T;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = e / n_p, k = e % n_p;
+    Y[e] = b[t * n_p + perm[k]];
+  }
+}
+
+__global__ void k_scatter_out(const double* __restrict__ Y, int32_t n_p, int32_t T,
+                              const int32_t* __restrict__ perm, double* __restrict__ x) {
+  const int64_t n = (int64_t)n_p * T;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = e / n_p, k = e % n_p;
+    x[t * n_p + perm[k]] = Y[e];
+  }
+}
+
+// Forward, small fronts: v = b(pivots) - children's pivot-row updates,
+// children's other rows summed into this front's update vector, then
+// L11 z = v and w += L21 z.  W holds, per front, what its subtree
+// subtracts from the right-hand side at the front's update rows.
+__global__ void __launch_bounds__(64) k_fwd_small(CDev D, const int32_t* __restrict__ list, int64_t l0,
+                                                  const double* __restrict__ Lf, double* __restrict__ Y,
+                                                  double* __restrict__ W) {
+  __shared__ double v[kSmall];
+  const int t = (int)blockIdx.y;
+  const int s = list[l0 + blockIdx.x];
+  const int p = D.node_p[s], u = D.node_u[s], f = p + u, fs = D.node_f[s];
+  const int i = (int)threadIdx.x;
+  const double* L = Lf + (int64_t)t * D.lsize + D.node_loff[s];
+  double* Yt = Y + (int64_t)t * D.n_p;
+  double* Wt = W + (int64_t)t * D.wsize;
+  if (i < f) v[i] = i < p ? Yt[fs + i] : 0.0;
+  __syncthreads();
+  for (int64_t q = D.kid_ptr[s]; q < D.kid_ptr[s + 1]; ++q) {
+    const int c = D.kids[q];
+    const int uc = D.node_u[c];
+    const int32_t* rel = D.rel + D.row_ptr[c];
+    const double* Wc = Wt + D.node_woff[c];
+    for (int a = i; a < uc; a += (int)blockDim.x) {
+      const int r = rel[a];
+      if (r < p) v[r] -= Wc[a];
+      else v[r] += Wc[a];
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < p; ++k) {
+    if (i == k) v[k] /= L[(int64_t)k * f + k];
+    __syncthreads();
+    if (i > k && i < f) {
+      const double z = v[k] * L[(int64_t)k * f + i];
+      if (i < p) v[i] -= z;
+      else v[i] += z;
+    }
+    __syncthreads();
+  }
+  if (i < p) Yt[fs + i] = v[i];
+  else if (i < f) Wt[D.node_woff[s] + i - p] = v[i];
+}
+
+// Forward, large front, step 1: pull the children's update vectors (pivot
+// rows subtracted from Y in place, other rows summed into this front's W).
+__global__ void __launch_bounds__(256) k_fwd_pull(CDev D, int32_t s, double* __restrict__ Y,
+                                                  double* __restrict__ W) {
+  const int t = (int)blockIdx.x;
+  const int p = D.node_p[s], u = D.node_u[s], fs = D.node_f[s];
+  double* Yt = Y + (int64_t)t * D.n_p;
+  double* Wt = W + (int64_t)t * D.wsize;
+  double* Ws = Wt + D.node_woff[s];
+  for (int a = (int)threadIdx.x; a < u; a += (int)blockDim.x) Ws[a] = 0.0;
+  __syncthreads();
+  for (int64_t q = D.kid_ptr[s]; q < D.kid_ptr[s + 1]; ++q) {
+    const int c = D.kids[q];
+    const int uc = D.node_u[c];
+    const int32_t* rel = D.rel + D.row_ptr[c];
+    const double* Wc = Wt + D.node_woff[c];
+    for (int a = (int)threadIdx.x; a < uc; a += (int)blockDim.x) {
+      const int r = rel[a];
+      if (r < p) Yt[fs + r] -= Wc[a];
+      else Ws[r - p] += Wc[a];
+    }
+    __syncthreads();
+  }
+}
+
+// The period's tree roots' update vectors into its pg right-hand side.
+__global__ void __launch_bounds__(256) k_fwd_root_pull(CDev D, const int32_t* __restrict__ roots, int32_t nroots,
+                                                       double* __restrict__ Y, const double* __restrict__ W) {
+  const int t = (int)blockIdx.x;
+  double* Yp = Y + (int64_t)t * D.n_p + D.n_int;
+  const double* Wt = W + (int64_t)t * D.wsize;
+  for (int k = 0; k < nroots; ++k) {
+    const int c = roots[k];
+    const int uc = D.node_u[c];
+    const int32_t* rel = D.rel + D.row_ptr[c];
+    const double* Wc = Wt + D.node_woff[c];
+    for (int a = (int)threadIdx.x; a < uc; a += (int)blockDim.x) Yp[rel[a]] -= Wc[a];
+    __syncthreads();
+  }
+}
+
+// Forward triangle L11 z = y - win on one front per block (y: p entries at
+// stride ystride per block), blocked by 64 columns; dynamic LDS p doubles.
+__global__ void __launch_bounds__(256) k_fwd_tri(const double* __restrict__ Lb, int64_t Lstride, int32_t ld,
+                                                 int32_t p, double* __restrict__ yb, int64_t ystride,
+                                                 const double* __restrict__ win) {
+  extern __shared__ double v[];
+  const double* L = Lb + (int64_t)blockIdx.x * Lstride;
+  double* y = yb + (int64_t)blockIdx.x * ystride;
+  const int tid = (int)threadIdx.x;
+  for (int i = tid; i < p; i += (int)blockDim.x) v[i] = y[i] - (win ? win[i] : 0.0);
+  __syncthreads();
+  for (int k0 = 0; k0 < p; k0 += 64) {
+    const int k1 = min(k0 + 64, p);
+    for (int k = k0; k < k1; ++k) {
+      if (tid == 0) v[k] /= L[(int64_t)k * ld + k];
+      __syncthreads();
+      for (int i = k + 1 + tid; i < k1; i += (int)blockDim.x) v[i] -= L[(int64_t)k * ld + i] * v[k];
+      __syncthreads();
+    }
+    for (int i = k1 + tid; i < p; i += (int)blockDim.x) {
+      double acc = 0.0;
+      for (int l = k0; l < k1; ++l) acc += L[(int64_t)l * ld + i] * v[l];
+      v[i] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < p; i += (int)blockDim.x) y[i] = v[i];
+}
+
+// Forward, w[i] (+)= sum_k L21[i, k] z[k] over the u update rows (rows p ..
+// p+u-1 of the factor block); grid (row blocks, periods).
+__global__ void __launch_bounds__(256) k_fwd_gemv(const double* __restrict__ Lb, int64_t Lstride, int32_t ld,
+                                                  int32_t p, int32_t u, const double* __restrict__ zb,
+                                                  int64_t zstride, double* __restrict__ wb, int64_t wstride,
+                                                  int32_t accumulate) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= u) return;
+  const double* L = Lb + (int64_t)blockIdx.y * Lstride + p + i;
+  const double* z = zb + (int64_t)blockIdx.y * zstride;
+  double acc = 0.0;
+  for (int k = 0; k < p; ++k) acc += L[(int64_t)k * ld] * z[k];
+  double* w = wb + (int64_t)blockIdx.y * wstride;
+  w[i] = accumulate ? w[i] + acc : acc;
+}
+
+// Backward, v[j] = y[j] - sum_i L21[i, j] x_u[i] for the p pivot columns,
+// one wavefront per column; x_u gathered through rows (or contiguous when
+// rows is NULL).  Grid (column blocks of 4, periods).
+__global__ void __launch_bounds__(256) k_bwd_gemv(const double* __restrict__ Lb, int64_t Lstride, int32_t ld,
+                                                  int32_t p, int32_t u, const int32_t* __restrict__ rows,
+                                                  const double* __restrict__ xb, int64_t xstride,
+                                                  double* __restrict__ yb, int64_t ystride) {
+  const int j = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  if (j >= p) return;
+  const double* col = Lb + (int64_t)blockIdx.y * Lstride + (int64_t)j * ld + p;
+  const double* xs = xb + (int64_t)blockIdx.y * xstride;
+  double acc = 0.0;
+  for (int a = lane; a < u; a += 64) acc += col[a] * xs[rows ? rows[a] : a];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) yb[(int64_t)blockIdx.y * ystride + j] -= acc;
+}
+
+// Backward triangle L11^T x = v on one front per block, blocked by 64
+// columns from the end; dynamic LDS p doubles.
+__global__ void __launch_bounds__(256) k_bwd_tri(const double* __restrict__ Lb, int64_t Lstride, int32_t ld,
+                                                 int32_t p, double* __restrict__ yb, int64_t ystride) {
+  extern __shared__ double v[];
+  const double* L = Lb + (int64_t)blockIdx.x * Lstride;
+  double* y = yb + (int64_t)blockIdx.x * ystride;
+  const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < p; i += (int)blockDim.x) v[i] = y[i];
+  __syncthreads();
+  const int nblk = (p + 63) / 64;
+  for (int bk = nblk - 1; bk >= 0; --bk) {
+    const int k0 = bk * 64, k1 = min(k0 + 64, p);
+    // columns of the block against the solved rows below it
+    if (k1 < p)
+      for (int j = k0 + wv; j < k1; j += 4) {
+        double acc = 0.0;
+        for (int i = k1 + lane; i < p; i += 64) acc += L[(int64_t)j * ld + i] * v[i];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) v[j] -= acc;
+      }
+    __syncthreads();
+    for (int k = k1 - 1; k >= k0; --k) {
+      if (tid == 0) v[k] /= L[(int64_t)k * ld + k];
+      __syncthreads();
+      for (int j = k0 + tid; j < k; j += (int)blockDim.x) v[j] -= L[(int64_t)j * ld + k] * v[k];
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < p; i += (int)blockDim.x) y[i] = v[i];
+}
+
+// Backward, small fronts: gather x at the update rows, v = y - L21^T x_u,
+// then L11^T x = v.
+__global__ void __launch_bounds__(64) k_bwd_small(CDev D, const int32_t* __restrict__ list, int64_t l0,
+                                                  const double* __restrict__ Lf, double* __restrict__ Y) {
+  __shared__ double v[kSmall], xu[kSmall];
+  const int t = (int)blockIdx.y;
+  const int s = list[l0 + blockIdx.x];
+  const int p = D.node_p[s], u = D.node_u[s], f = p + u, fs = D.node_f[s];
+  const int i = (int)threadIdx.x;
+  const double* L = Lf + (int64_t)t * D.lsize + D.node_loff[s];
+  double* Yt = Y + (int64_t)t * D.n_p;
+  const int32_t* rows = D.rows + D.row_ptr[s];
+  if (i < u) xu[i] = Yt[rows[i]];
+  __syncthreads();
+  if (i < p) {
+    double acc = Yt[fs + i];
+    for (int a = 0; a < u; ++a) acc -= L[(int64_t)i * f + p + a] * xu[a];
+    v[i] = acc;
+  }
+  __syncthreads();
+  for (int k = p - 1; k >= 0; --k) {
+    if (i == k) v[k] /= L[(int64_t)k * f + k];
+    __syncthreads();
+    if (i < k) v[i] -= L[(int64_t)i * f + k] * v[k];
+    __syncthreads();
+  }
+  if (i < p) Yt[fs + i] = v[i];
+}
+
+int grid_for(int64_t n, int block) {
+  const int64_t g = (n + block - 1) / block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65535));
+}
+
+}  // namespace
+}  // namespace opf
+
+using namespace opf;
+
+// ------------------------------------------------------------------ object
+namespace {
+
+struct CholInst {
+  CholPlan plan;
+  const InstHost* I = nullptr;
+  CDev dev{};
+  int32_t *d_node_f = nullptr, *d_node_p = nullptr, *d_node_u = nullptr, *d_rel = nullptr, *d_kids = nullptr,
+          *d_rows = nullptr, *d_perm = nullptr, *d_items = nullptr, *d_small = nullptr, *d_roots = nullptr,
+          *d_kpos0 = nullptr, *d_kpos1 = nullptr, *d_ramp = nullptr;
+  int64_t *d_loff = nullptr, *d_uoff = nullptr, *d_woff = nullptr, *d_rowptr = nullptr, *d_kidptr = nullptr,
+          *d_slot = nullptr;
+  double *Lf = nullptr, *Cf = nullptr, *Ar = nullptr, *W = nullptr, *Wc = nullptr, *Y = nullptr;
+  std::vector<int64_t> woff;  // per-front offsets of the forward update vectors
+  int64_t csize = 0, wsize = 0;
+  int32_t chunk = 1, nlarge = 0;
+};
+
+}  // namespace
+
+struct opf_chol {
+  opf_model* model = nullptr;
+  int device = -1;
+  std::vector<CholInst> inst;
+  double* Us = nullptr;  // G x G update block of the pg chain (largest G)
+  std::vector<void*> allocs;
+  double flops = 0.0, flops_int = 0.0;
+  int64_t factor_entries = 0, arena_entries = 0;
+};
+
+namespace {
+
+constexpr int64_t kArenaBudget = 8LL << 30;  // bytes of update-matrix workspace per instance
+
+// Workspace budget: OPF_CHOL_ARENA_BYTES (bytes, > 0) overrides the default.
+int64_t arena_budget() {
+  const char* e = std::getenv("OPF_CHOL_ARENA_BYTES");
+  if (e && *e) {
+    const long long v = std::atoll(e);
+    if (v > 0) return (int64_t)v;
+  }
+  return kArenaBudget;
+}
+
+template <class T>
+int upload(opf_chol* F, const std::vector<T>& h, T** d) {
+  const size_t bytes = std::max<size_t>(1, h.size()) * sizeof(T);
+  if (hipMalloc((void**)d, bytes) != hipSuccess) return api_fail(OPF_ENOMEM, "chol: device allocation failed");
+  F->allocs.push_back(*d);
+  if (!h.empty() && hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return api_fail(OPF_EHIP, "chol: upload failed");
+  return OPF_OK;
+}
+
+int dalloc(opf_chol* F, int64_t n, double** d) {
+  if (hipMalloc((void**)d, (size_t)std::max<int64_t>(1, n) * sizeof(double)) != hipSuccess)
+    return api_fail(OPF_ENOMEM, "chol: device allocation of " + std::to_string(n * 8) + " bytes failed");
+  F->allocs.push_back(*d);
+  return OPF_OK;
+}
+
+void release(opf_chol* F) {
+  for (void* p : F->allocs) (void)hipFree(p);
+  F->allocs.clear();
+}
+
+#define CHK(x)                      \
+  do {                              \
+    int rc_ = (x);                  \
+    if (rc_ != OPF_OK) return rc_;  \
+  } while (0)
+
+#define LAUNCH_OK(what)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = hipGetLastError();                                                        \
+    if (e_ != hipSuccess) return api_fail(OPF_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int setup_device(opf_chol* F, CholInst& C) {
+  const CholPlan& P = C.plan;
+  std::vector<int64_t>& woff = C.woff;
+  woff.assign(P.nnodes, 0);
+  int64_t w = 0;
+  for (int32_t s = 0; s < P.nnodes; ++s) {
+    woff[s] = w;
+    w += P.node_u[s];
+  }
+  C.wsize = std::max<int64_t>(w, 1);
+  std::vector<int32_t> items = P.items;
+  CHK(upload(F, P.node_f, &C.d_node_f));
+  CHK(upload(F, P.node_p, &C.d_node_p));
+  CHK(upload(F, P.node_u, &C.d_node_u));
+  CHK(upload(F, P.rel, &C.d_rel));
+  CHK(upload(F, P.kids, &C.d_kids));
+  CHK(upload(F, P.rows, &C.d_rows));
+  CHK(upload(F, P.perm, &C.d_perm));
+  CHK(upload(F, items, &C.d_items));
+  CHK(upload(F, P.lvl_small, &C.d_small));
+  CHK(upload(F, P.roots, &C.d_roots));
+  CHK(upload(F, P.kpos0, &C.d_kpos0));
+  CHK(upload(F, P.kpos1, &C.d_kpos1));
+  CHK(upload(F, P.ramp_pos, &C.d_ramp));
+  CHK(upload(F, P.node_loff, &C.d_loff));
+  CHK(upload(F, P.node_uoff, &C.d_uoff));
+  CHK(upload(F, woff, &C.d_woff));
+  CHK(upload(F, P.row_ptr, &C.d_rowptr));
+  CHK(upload(F, P.kid_ptr, &C.d_kidptr));
+  CHK(upload(F, P.slot_dst, &C.d_slot));
+  const int64_t T = P.T, G = P.G;
+  C.csize = 2 * G * G;
+  C.chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(T, arena_budget() / (P.usize * 8)));
+  CHK(dalloc(F, P.lsize * T, &C.Lf));
+  CHK(dalloc(F, C.csize * T, &C.Cf));
+  CHK(dalloc(F, P.usize * C.chunk, &C.Ar));
+  CHK(dalloc(F, C.wsize * T, &C.W));
+  CHK(dalloc(F, G * T, &C.Wc));
+  CHK(dalloc(F, (int64_t)P.n_p * T, &C.Y));
+  CDev& D = C.dev;
+  D.node_f = C.d_node_f;
+  D.node_p = C.d_node_p;
+  D.node_u = C.d_node_u;
+  D.rel = C.d_rel;
+  D.kids = C.d_kids;
+  D.rows = C.d_rows;
+  D.node_loff = C.d_loff;
+  D.node_uoff = C.d_uoff;
+  D.node_woff = C.d_woff;
+  D.row_ptr = C.d_rowptr;
+  D.kid_ptr = C.d_kidptr;
+  D.lsize = P.lsize;
+  D.usize = P.usize;
+  D.wsize = C.wsize;
+  D.n_p = P.n_p;
+  D.n_int = P.n_int;
+  D.G = P.G;
+  return OPF_OK;
+}
+
+// Blocked factorization of one front over nt periods.
+int factor_front(const FrontArg& A, int nt, double tol, double repl, int32_t* npert, hipStream_t st) {
+  const int rows = A.p + A.u;
+  for (int k0 = 0; k0 < A.p; k0 += kNB) {
+    const int kb = std::min(kNB, A.p - k0);
+    const int below = rows - k0 - kb;
+    hipLaunchKernelGGL(k_diag, dim3(nt), dim3(64), 0, st, A, k0, kb, tol, repl, npert);
+    LAUNCH_OK("chol diagonal block");
+    if (below > 0) {
+      hipLaunchKernelGGL(k_panel, dim3((below + 255) / 256, nt), dim3(256), 0, st, A, k0, kb);
+      LAUNCH_OK("chol panel");
+      const int64_t tb = (below + kTile - 1) / kTile;
+      const int64_t ntiles = tb * (tb + 1) / 2;
+      if (ntiles > 0x7fffffff) return api_fail(OPF_EINVAL, "chol: front too large");
+      hipLaunchKernelGGL(k_update, dim3((unsigned)ntiles, nt), dim3(256), 0, st, A, k0, kb);
+      LAUNCH_OK("chol update");
+    }
+  }
+  return OPF_OK;
+}
+
+int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double repl, int32_t* npert,
+                hipStream_t st) {
+  const CholPlan& P = C.plan;
+  const InstHost& I = *C.I;
+  const int T = P.T, G = P.G;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(P.lsize * T, 256)), dim3(256), 0, st, C.Lf, P.lsize * T);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(C.csize * T, 256)), dim3(256), 0, st, C.Cf, C.csize * T);
+  LAUNCH_OK("chol fill");
+  const int nslots = (int)P.slot_dst.size();
+  for (int t0 = 0; t0 < T; t0 += C.chunk) {
+    const int nt = std::min(C.chunk, T - t0);
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(nslots, 256), nt), dim3(256), 0, st, kv, I.k_off, I.nnzk_p, G, t0,
+                       nslots, C.d_slot, C.d_kpos0, C.d_kpos1, C.Lf, P.lsize, C.Cf, C.csize);
+    LAUNCH_OK("chol scatter");
+    const int r0 = std::max(t0, 1);
+    if (t0 + nt > r0) {
+      hipLaunchKernelGGL(k_scatter_ramp, dim3(grid_for(G, 256), t0 + nt - r0), dim3(256), 0, st, kv, I.k_off,
+                         I.nnzk_p, G, r0, C.d_ramp, C.Cf, C.csize);
+      LAUNCH_OK("chol ramp scatter");
+    }
+    for (int h = 0; h < P.nlevels; ++h) {
+      const int64_t i0 = P.lvl_items_ptr[h], i1 = P.lvl_items_ptr[h + 1];
+      if (i1 > i0) {
+        hipLaunchKernelGGL(k_extend, dim3((unsigned)(i1 - i0), nt), dim3(256), 0, st, C.dev, C.d_items, i0,
+                           CholOptions().col_block, t0, C.Lf, C.Ar);
+        LAUNCH_OK("chol extend-add");
+      }
+      const int64_t s0 = P.lvl_small_ptr[h], s1 = P.lvl_small_ptr[h + 1];
+      if (s1 > s0) {
+        hipLaunchKernelGGL(k_factor_small, dim3((unsigned)(s1 - s0), nt), dim3(64), 0, st, C.dev, C.d_small, s0, t0,
+                           C.Lf, C.Ar, tol, repl, npert);
+        LAUNCH_OK("chol small fronts");
+      }
+      for (int64_t q = P.lvl_large_ptr[h]; q < P.lvl_large_ptr[h + 1]; ++q) {
+        const int s = P.lvl_large[q];
+        FrontArg A;
+        A.L = C.Lf + (int64_t)t0 * P.lsize + P.node_loff[s];
+        A.Lstride = P.lsize;
+        A.ld = P.node_p[s] + P.node_u[s];
+        A.p = P.node_p[s];
+        A.u = P.node_u[s];
+        A.U = C.Ar + P.node_uoff[s];
+        A.Ustride = P.usize;
+        A.ldU = std::max(1, P.node_u[s]);
+        CHK(factor_front(A, nt, tol, repl, npert, st));
+      }
+    }
+    const int cb = CholOptions().col_block;
+    hipLaunchKernelGGL(k_extend_root, dim3((G + cb - 1) / cb, nt), dim3(256), 0, st, C.dev, C.d_roots,
+                       (int32_t)P.roots.size(), cb, t0, C.Cf, C.csize, C.Ar);
+    LAUNCH_OK("chol pg front assembly");
+  }
+  // the pg chain over the periods
+  for (int t = 0; t < T; ++t) {
+    double* Ct = C.Cf + (int64_t)t * C.csize;
+    if (t >= 1) {
+      hipLaunchKernelGGL(k_add_chain, dim3(grid_for((int64_t)G * G, 256)), dim3(256), 0, st, F->Us, G, Ct);
+      LAUNCH_OK("chol chain add");
+    }
+    const int u = t + 1 < T ? G : 0;
+    if (u) {
+      hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)G * G, 256)), dim3(256), 0, st, F->Us, (int64_t)G * G);
+      LAUNCH_OK("chol chain clear");
+    }
+    FrontArg A;
+    A.L = Ct;
+    A.Lstride = 0;
+    A.ld = 2 * G;
+    A.p = G;
+    A.u = u;
+    A.U = F->Us;
+    A.Ustride = 0;
+    A.ldU = G;
+    CHK(factor_front(A, 1, tol, repl, npert, st));
+  }
+  return OPF_OK;
+}
+
+int solve_inst(CholInst& C, const double* b, double* x, hipStream_t st) {
+  const CholPlan& P = C.plan;
+  const InstHost& I = *C.I;
+  const int T = P.T, G = P.G;
+  const int64_t np = P.n_p;
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(np * T, 256)), dim3(256), 0, st, b + I.x_off, P.n_p, T, C.d_perm, C.Y);
+  LAUNCH_OK("chol gather");
+  // forward through the interior trees, all periods at once
+  for (int h = 0; h < P.nlevels; ++h) {
+    const int64_t s0 = P.lvl_small_ptr[h], s1 = P.lvl_small_ptr[h + 1];
+    if (s1 > s0) {
+      hipLaunchKernelGGL(k_fwd_small, dim3((unsigned)(s1 - s0), T), dim3(64), 0, st, C.dev, C.d_small, s0, C.Lf,
+                         C.Y, C.W);
+      LAUNCH_OK("chol forward small");
+    }
+    for (int64_t q = P.lvl_large_ptr[h]; q < P.lvl_large_ptr[h + 1]; ++q) {
+      const int s = P.lvl_large[q];
+      const int p = P.node_p[s], u = P.node_u[s];
+      const double* L = C.Lf + P.node_loff[s];
+      hipLaunchKernelGGL(k_fwd_pull, dim3(T), dim3(256), 0, st, C.dev, s, C.Y, C.W);
+      hipLaunchKernelGGL(k_fwd_tri, dim3(T), dim3(256), (size_t)p * 8, st, L, P.lsize, p + u, p, C.Y + P.node_f[s],
+                         np, (const double*)nullptr);
+      if (u > 0)
+        hipLaunchKernelGGL(k_fwd_gemv, dim3((u + 255) / 256, T), dim3(256), 0, st, L, P.lsize, p + u, p, u,
+                           (const double*)(C.Y + P.node_f[s]), np, C.W + C.woff[s], C.wsize, 1);
+      LAUNCH_OK("chol forward large");
+    }
+  }
+  hipLaunchKernelGGL(k_fwd_root_pull, dim3(T), dim3(256), 0, st, C.dev, C.d_roots, (int32_t)P.roots.size(), C.Y,
+                     (const double*)C.W);
+  LAUNCH_OK("chol forward roots");
+  // forward along the pg chain
+  for (int t = 0; t < T; ++t) {
+    const double* Ct = C.Cf + (int64_t)t * C.csize;
+    double* yt = C.Y + (int64_t)t * np + P.n_int;
+    hipLaunchKernelGGL(k_fwd_tri, dim3(1), dim3(256), (size_t)G * 8, st, Ct, (int64_t)0, 2 * G, G, yt, (int64_t)0,
+                       t >= 1 ? (const double*)(C.Wc + (int64_t)(t - 1) * G) : (const double*)nullptr);
+    if (t + 1 < T)
+      hipLaunchKernelGGL(k_fwd_gemv, dim3((G + 255) / 256, 1), dim3(256), 0, st, Ct, (int64_t)0, 2 * G, G, G,
+                         (const double*)yt, (int64_t)0, C.Wc + (int64_t)t * G, (int64_t)0, 0);
+    LAUNCH_OK("chol forward chain");
+  }
+  // backward along the pg chain
+  for (int t = T - 1; t >= 0; --t) {
+    const double* Ct = C.Cf + (int64_t)t * C.csize;
+    double* yt = C.Y + (int64_t)t * np + P.n_int;
+    if (t + 1 < T)
+      hipLaunchKernelGGL(k_bwd_gemv, dim3((G + 3) / 4, 1), dim3(256), 0, st, Ct, (int64_t)0, 2 * G, G, G,
+                         (const int32_t*)nullptr, (const double*)(yt + np), (int64_t)0, yt, (int64_t)0);
+    hipLaunchKernelGGL(k_bwd_tri, dim3(1), dim3(256), (size_t)G * 8, st, Ct, (int64_t)0, 2 * G, G, yt, (int64_t)0);
+    LAUNCH_OK("chol backward chain");
+  }
+  // backward through the interior trees, top down
+  for (int h = P.nlevels - 1; h >= 0; --h) {
+    for (int64_t q = P.lvl_large_ptr[h]; q < P.lvl_large_ptr[h + 1]; ++q) {
+      const int s = P.lvl_large[q];
+      const int p = P.node_p[s], u = P.node_u[s];
+      const double* L = C.Lf + P.node_loff[s];
+      if (u > 0)
+        hipLaunchKernelGGL(k_bwd_gemv, dim3((p + 3) / 4, T), dim3(256), 0, st, L, P.lsize, p + u, p, u,
+                           (const int32_t*)(C.d_rows + P.row_ptr[s]), (const double*)C.Y, np, C.Y + P.node_f[s], np);
+      hipLaunchKernelGGL(k_bwd_tri, dim3(T), dim3(256), (size_t)p * 8, st, L, P.lsize, p + u, p, C.Y + P.node_f[s],
+                         np);
+      LAUNCH_OK("chol backward large");
+    }
+    const int64_t s0 = P.lvl_small_ptr[h], s1 = P.lvl_small_ptr[h + 1];
+    if (s1 > s0) {
+      hipLaunchKernelGGL(k_bwd_small, dim3((unsigned)(s1 - s0), T), dim3(64), 0, st, C.dev, C.d_small, s0, C.Lf,
+                         C.Y);
+      LAUNCH_OK("chol backward small");
+    }
+  }
+  hipLaunchKernelGGL(k_scatter_out, dim3(grid_for(np * T, 256)), dim3(256), 0, st, (const double*)C.Y, P.n_p, T,
+                     C.d_perm, x + I.x_off);
+  LAUNCH_OK("chol scatter");
+  return OPF_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+extern "C" {
+
+int opf_chol_analyze(opf_model* model, opf_chol** out) {
+  if (!out) return api_fail(OPF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!model) return api_fail(OPF_EINVAL, "model is NULL");
+  opf_chol* F = nullptr;
+  try {
+    F = new opf_chol();
+    F->model = model;
+    F->device = model_device(model);
+    const auto& insts = model_insts(model);
+    F->inst.resize(insts.size());
+    CholOptions opt;
+    int32_t maxG = 0;
+    for (size_t k = 0; k < insts.size(); ++k) {
+      CholInst& C = F->inst[k];
+      C.I = &insts[k];
+      std::string err;
+      const int rc = chol_plan_build(insts[k], opt, C.plan, err);
+      if (rc != OPF_OK) {
+        delete F;
+        return api_fail(rc, "instance " + std::to_string(k) + ": " + err);
+      }
+      const CholPlan& P = C.plan;
+      for (int32_t s = 0; s < P.nnodes; ++s)
+        if (P.node_p[s] > kMaxPiv) {
+          delete F;
+          return api_fail(OPF_EINVAL, "chol: a front has more than 8192 pivots");
+        }
+      if (P.G > kMaxPiv) {
+        delete F;
+        return api_fail(OPF_EINVAL, "chol: more than 8192 generators in one instance");
+      }
+      C.nlarge = (int32_t)P.lvl_large.size();
+      maxG = std::max(maxG, P.G);
+      F->flops += P.flops_period * P.T + P.flops_chain;
+      F->flops_int += P.flops_period * P.T;
+      F->factor_entries += P.lsize * P.T + 2LL * P.G * P.G * P.T;
+    }
+    if (F->device >= 0) {
+      if (hipSetDevice(F->device) != hipSuccess) {
+        delete F;
+        return api_fail(OPF_EHIP, "chol: hipSetDevice failed");
+      }
+      for (auto& C : F->inst) {
+        const int rc = setup_device(F, C);
+        if (rc != OPF_OK) {
+          release(F);
+          delete F;
+          return rc;
+        }
+        F->arena_entries += C.plan.usize * C.chunk;
+      }
+      const int rc = dalloc(F, (int64_t)maxG * maxG, &F->Us);
+      if (rc != OPF_OK) {
+        release(F);
+        delete F;
+        return rc;
+      }
+    } else {
+      for (auto& C : F->inst) {
+        C.chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(C.plan.T, arena_budget() / (C.plan.usize * 8)));
+        F->arena_entries += C.plan.usize * C.chunk;
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    if (F) {
+      release(F);
+      delete F;
+    }
+    return api_fail(OPF_ENOMEM, "chol: host allocation failed");
+  }
+  *out = F;
+  return OPF_OK;
+}
+
+void opf_chol_destroy(opf_chol* chol) {
+  if (!chol) return;
+  if (chol->device >= 0) (void)hipSetDevice(chol->device);
+  release(chol);
+  delete chol;
+}
+
+int opf_chol_get_info(const opf_chol* F, opf_chol_info* info) {
+  if (!F || !info) return api_fail(OPF_EINVAL, "chol or info is NULL");
+  std::memset(info, 0, sizeof(*info));
+  info->factor_entries = F->factor_entries;
+  info->arena_entries = F->arena_entries;
+  info->flops = F->flops;
+  info->flops_interior = F->flops_int;
+  info->chunk = F->inst.empty() ? 0 : 0x7fffffff;
+  for (const auto& C : F->inst) {
+    info->nodes += C.plan.nnodes;
+    info->levels = std::max(info->levels, C.plan.nlevels);
+    info->chunk = std::min(info->chunk, C.chunk);
+    info->large_nodes += (int32_t)C.plan.lvl_large.size();
+  }
+  return OPF_OK;
+}
+
+int opf_chol_tree_size(const opf_chol* F, int32_t inst, int32_t* nodes, int64_t* rows) {
+  if (!F || !nodes || !rows) return api_fail(OPF_EINVAL, "NULL argument");
+  if (inst < 0 || inst >= (int32_t)F->inst.size()) return api_fail(OPF_EINVAL, "instance out of range");
+  *nodes = F->inst[inst].plan.nnodes;
+  *rows = (int64_t)F->inst[inst].plan.rows.size();
+  return OPF_OK;
+}
+
+int opf_chol_tree(const opf_chol* F, int32_t inst, int32_t* perm, int32_t* first, int32_t* npiv, int32_t* parent,
+                  int64_t* rowptr, int32_t* rows) {
+  if (!F || !perm || !first || !npiv || !parent || !rowptr || !rows) return api_fail(OPF_EINVAL, "NULL argument");
+  if (inst < 0 || inst >= (int32_t)F->inst.size()) return api_fail(OPF_EINVAL, "instance out of range");
+  const CholPlan& P = F->inst[inst].plan;
+  std::copy(P.perm.begin(), P.perm.end(), perm);
+  std::copy(P.node_f.begin(), P.node_f.end(), first);
+  std::copy(P.node_p.begin(), P.node_p.end(), npiv);
+  std::copy(P.node_parent.begin(), P.node_parent.end(), parent);
+  std::copy(P.row_ptr.begin(), P.row_ptr.end(), rowptr);
+  std::copy(P.rows.begin(), P.rows.end(), rows);
+  return OPF_OK;
+}
+
+int opf_chol_factor(opf_chol* F, const double* kvals, double pivot_tol, double pivot_repl, int32_t* npert) {
+  if (!F || !kvals || !npert) return api_fail(OPF_EINVAL, "chol, kvals or npert is NULL");
+  if (F->device < 0) return api_fail(OPF_ENODEV, "model is host-only");
+  if (!(pivot_repl > 0.0) || !std::isfinite(pivot_repl)) return api_fail(OPF_EINVAL, "pivot_repl must be > 0");
+  if (std::isnan(pivot_tol)) return api_fail(OPF_EINVAL, "pivot_tol is NaN");
+  if (hipSetDevice(F->device) != hipSuccess) return api_fail(OPF_EHIP, "hipSetDevice failed");
+  hipStream_t st = model_stream(F->model);
+  if (hipMemsetAsync(npert, 0, sizeof(int32_t), st) != hipSuccess) return api_fail(OPF_EHIP, "clearing npert");
+  for (auto& C : F->inst) CHK(factor_inst(F, C, kvals, pivot_tol, pivot_repl, npert, st));
+  return OPF_OK;
+}
+
+int opf_chol_solve(opf_chol* F, const double* b, double* x) {
+  if (!F || !b || !x) return api_fail(OPF_EINVAL, "chol, b or x is NULL");
+  if (F->device < 0) return api_fail(OPF_ENODEV, "model is host-only");
+  if (hipSetDevice(F->device) != hipSuccess) return api_fail(OPF_EHIP, "hipSetDevice failed");
+  hipStream_t st = model_stream(F->model);
+  for (auto& C : F->inst) CHK(solve_inst(C, b, x, st));
+  return OPF_OK;
+}
+
+}  // extern "C"

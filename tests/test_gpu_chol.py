@@ -1,0 +1,218 @@
+"""Static-pivot sparse Cholesky of the condensed matrix on the GPU (Sec.
+III-B): the GPU builds K with its own kernels and solves K dx = b; the
+oracle builds K with its own code from the same seeded inputs and solves by
+a sparse LU.  Two families of K:
+
+* well conditioned (diag_x ~ U(1, 10), D ~ U(0.5, 2), small multipliers):
+  dx element by element against the oracle's solution;
+* interior-point-like (diag_x, D ~ logU(1e-4, 1e4), objective Hessian only,
+  so K is positive definite but badly conditioned): the backward error of
+  the GPU's dx in the oracle's K.
+
+Tolerances: Cholesky is backward stable, with a backward error of a small
+multiple of (front order) x eps ~ 1e-13 here; K itself agrees between the
+two sides to 1e-12 per entry, so both bounds are 1e-11 (backward) and, for
+the well-conditioned family, 1e-8 on dx relative to its largest entry."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import opf_oracle as O
+from paper_2405_14032_amd import synth
+
+import pins
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "tiny": lambda: [synth.config_network("tiny")],
+    "ragged": lambda: [synth.make_network(301, 517, 63, 7, 41)],
+    "one_bus": lambda: [pins.manual_network(1, [], [], [], [], [], [0], T=3, pd=np.full((3, 1), 0.4))],
+    "parallel": lambda: [pins.manual_network(4, [0, 0, 1, 1, 2], [1, 1, 0, 2, 3], [0.01] * 5,
+                                             [0.1, 0.2, 0.15, 0.1, 0.3], [0.02] * 5, [1, 1, 3], T=3,
+                                             pd=np.full((3, 4), 0.2))],
+    "hub": lambda: [pins.hub_network()],
+    "batched": lambda: [synth.make_network(31, 45, 7, 3, 71), synth.make_network(14, 20, 5, 5, 72),
+                        synth.make_network(57, 80, 11, 2, 73)],
+}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def _inputs(nets, family, seed):
+    """Seeded x, multipliers, sigma, diag_x, D and b per instance."""
+    out = []
+    for k, net in enumerate(nets):
+        pt = synth.make_point(net, seed + k)
+        L = O.Layout(net)
+        rng = np.random.default_rng(1000 + seed + k)
+        if family == "well":
+            lam, dx = 1e-3 * pt.lam, rng.uniform(1.0, 10.0, L.n)
+            d = rng.uniform(0.5, 2.0, L.m)
+        else:
+            lam = np.zeros(L.m)
+            dx = 10.0 ** rng.uniform(-4.0, 4.0, L.n)
+            d = 10.0 ** rng.uniform(-4.0, 4.0, L.m)
+        out.append(dict(x=pt.x, lam=lam, diag_x=dx, dcon=d, b=rng.standard_normal(L.n)))
+    return out
+
+
+def _oracle_k(net, inp):
+    L = O.Layout(net)
+    rp, ci, kv, _ = O.condensed(L.n, O.jacobian(net, inp["x"]), O.hessian(net, inp["x"], inp["lam"], 1.0),
+                                inp["diag_x"], inp["dcon"])
+    return L.n, rp, ci, kv
+
+
+def _gpu_solve(M, F, inps, torch, dev, repeat=1):
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    cat = lambda key: np.concatenate([i[key] for i in inps])
+    X, LAM, DX, D, Bv = (t(cat(k)) for k in ("x", "lam", "diag_x", "dcon", "b"))
+    e = lambda k: torch.empty(k, dtype=torch.float64, device=dev)
+    jv, hv, kv = e(M.nnz_jac), e(M.nnz_hess), e(M.nnz_kkt)
+    M.eval_jhk(X, LAM, 1.0, DX, D, jv, hv, kv)
+    npert = torch.full((1,), -7, dtype=torch.int32, device=dev)
+    xs = torch.full((M.n,), float("nan"), dtype=torch.float64, device=dev)
+    for _ in range(repeat):
+        F.factor(kv, 0.0, 1.0, npert)
+        F.solve(Bv, xs)
+    torch.cuda.synchronize()
+    return xs.cpu().numpy(), int(npert.item())
+
+
+def _check(nets, inps, xg, family, name):
+    xo = 0
+    for k, (net, inp) in enumerate(zip(nets, inps)):
+        n, rp, ci, kv = _oracle_k(net, inp)
+        K = O.kkt_full(n, rp, ci, kv)
+        x = xg[xo:xo + n]
+        b = inp["b"]
+        bwd = np.max(np.abs(K @ x - b)) / (abs(K).max() * np.max(np.abs(x)) + np.max(np.abs(b)))
+        assert bwd <= 1e-11, (name, k, family, bwd)
+        if family == "well":
+            ref = O.kkt_solve(n, rp, ci, kv, b)
+            err = np.max(np.abs(x - ref)) / np.max(np.abs(ref))
+            assert err <= 1e-8, (name, k, err)
+        xo += n
+
+
+@pytest.mark.parametrize("family", ["well", "wide"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_chol_parity(name, family, dev):
+    import torch
+    from paper_2405_14032_amd import capi
+    nets = CASES[name]()
+    print(f"chol case {name} {family}: {[(n.N, n.B, n.G, n.T) for n in nets]}", flush=True)
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    inps = _inputs(nets, family, 11)
+    xg, npert = _gpu_solve(M, F, inps, torch, dev)
+    assert npert == 0
+    _check(nets, inps, xg, family, name)
+    F.close()
+    M.close()
+
+
+def test_chol_mid_backward_error(dev):
+    """The mid grid (422k variables, 24 periods): backward error in the
+    oracle's K for both families."""
+    import torch
+    from paper_2405_14032_amd import capi
+    nets = [synth.config_network("mid")]
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    print("mid chol info", F.info(), flush=True)
+    for family in ("well", "wide"):
+        inps = _inputs(nets, family, 3)
+        xg, npert = _gpu_solve(M, F, inps, torch, dev)
+        assert npert == 0
+        n, rp, ci, kv = _oracle_k(nets[0], inps[0])
+        K = O.kkt_full(n, rp, ci, kv)
+        b = inps[0]["b"]
+        bwd = np.max(np.abs(K @ xg - b)) / (abs(K).max() * np.max(np.abs(xg)) + np.max(np.abs(b)))
+        assert bwd <= 1e-11, (family, bwd)
+    F.close()
+    M.close()
+
+
+def test_chunked_periods_bitwise_equal(dev, monkeypatch):
+    """Factoring the periods one or two at a time (a small workspace budget)
+    gives the same bits as all at once."""
+    import torch
+    from paper_2405_14032_amd import capi
+    nets = [synth.make_network(301, 517, 63, 7, 41)]
+    inps = _inputs(nets, "well", 5)
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    full = F.info()["chunk"]
+    x1, _ = _gpu_solve(M, F, inps, torch, dev)
+    F.close()
+    monkeypatch.setenv("OPF_CHOL_ARENA_BYTES", "1")
+    F = capi.Chol(M)
+    assert F.info()["chunk"] == 1 and full == 7
+    x2, _ = _gpu_solve(M, F, inps, torch, dev)
+    assert np.array_equal(x1, x2)
+    F.close()
+    M.close()
+
+
+def test_indefinite_k_counts_static_pivots(dev):
+    """A K with strongly negative diagonal entries is not positive definite
+    (the oracle's dense Cholesky fails); the factorization replaces and
+    counts pivots instead of failing.  A positive definite K counts none."""
+    import torch
+    from paper_2405_14032_amd import capi
+    nets = [synth.config_network("tiny")]
+    inps = _inputs(nets, "well", 7)
+    bad = [dict(inps[0])]
+    bad[0]["diag_x"] = inps[0]["diag_x"].copy()
+    bad[0]["diag_x"][::5] = -1e6
+    n, rp, ci, kv = _oracle_k(nets[0], bad[0])
+    assert not O.kkt_is_positive_definite(n, rp, ci, kv)
+    n, rp, ci, kv = _oracle_k(nets[0], inps[0])
+    assert O.kkt_is_positive_definite(n, rp, ci, kv)
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    _, npert = _gpu_solve(M, F, bad, torch, dev)
+    assert npert >= 1
+    xg, npert = _gpu_solve(M, F, inps, torch, dev)
+    assert npert == 0
+    _check(nets, inps, xg, "well", "tiny after indefinite")
+    F.close()
+    M.close()
+
+
+def test_refactor_and_solve_in_place(dev):
+    """Two factorizations in a row on one object, the second with other
+    values, and a solve whose right-hand side array receives the solution."""
+    import torch
+    from paper_2405_14032_amd import capi
+    nets = [pins.hub_network()]
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    _gpu_solve(M, F, _inputs(nets, "wide", 1), torch, dev)
+    inps = _inputs(nets, "well", 2)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    e = lambda k: torch.empty(k, dtype=torch.float64, device=dev)
+    jv, hv, kv = e(M.nnz_jac), e(M.nnz_hess), e(M.nnz_kkt)
+    M.eval_jhk(t(inps[0]["x"]), t(inps[0]["lam"]), 1.0, t(inps[0]["diag_x"]), t(inps[0]["dcon"]), jv, hv, kv)
+    npert = torch.zeros(1, dtype=torch.int32, device=dev)
+    F.factor(kv, 0.0, 1.0, npert)
+    bx = t(inps[0]["b"])
+    F.solve(bx, bx)
+    torch.cuda.synchronize()
+    assert int(npert.item()) == 0
+    _check(nets, inps, bx.cpu().numpy(), "well", "hub in place")
+    F.close()
+    M.close()
