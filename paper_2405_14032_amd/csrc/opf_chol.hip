@@ -33,9 +33,8 @@ namespace opf {
 namespace {
 
 constexpr int kSmall = 64;   // largest front factored in LDS by one wavefront
-constexpr int kNB = 32;      // panel width of the blocked fronts
-constexpr int kTile = 64;    // trailing-update tile
-constexpr int kMaxPiv = 8192;  // pivots of one front held in LDS by the solves
+constexpr int kNB = 64;      // panel width of the blocked fronts
+constexpr int kTile = 128;   // trailing-update tile (8 x 8 outputs per thread)
 
 // Device view of one instance's plan.
 struct CDev {
@@ -163,69 +162,80 @@ __device__ __forceinline__ double pivot_sqrt(double d, double tol, double repl, 
   return sqrt(d);
 }
 
-// Small fronts (p + u <= 64): one wavefront per (front, period), the whole
-// lower front in LDS, right-looking elimination of the p pivots.
+// Broadcast of lane l's value to the whole wavefront (l uniform).
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const int2 w = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(w.x, l);
+  r.y = __builtin_amdgcn_readlane(w.y, l);
+  return __builtin_bit_cast(double, r);
+}
+
+// Right-looking elimination of the first p pivots of a front of order f <=
+// 64 held by one wavefront, lane i owning row i in registers (a[j] = entry
+// (i, j) for j <= i).  Pivot d_k is computed by every lane from the
+// broadcast diagonal; entry (j, k) of column k is broadcast from lane j.
+// Fully unrolled so that every register index is a constant.
+__device__ __forceinline__ void chol_rows64(double (&a)[64], int p, int f, double tol, double repl,
+                                            int32_t* npert) {
+  const int i = (int)threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    if (k < p) {
+      const double d = pivot_sqrt(lane_bcast(a[k], k), tol, repl, npert, i == 0);
+      if (i == k) a[k] = d;
+      else if (i > k && i < f) a[k] /= d;
+#pragma unroll
+      for (int j = k + 1; j < 64; ++j) {
+        if (j < f) {
+          const double ljk = lane_bcast(a[k], j);
+          if (i >= j && i < f) a[j] -= a[k] * ljk;
+        }
+      }
+    }
+  }
+}
+
+// Small fronts (p + u <= 64): one wavefront per (front, period), the front
+// in registers (one row per lane).
 __global__ void __launch_bounds__(64) k_factor_small(CDev D, const int32_t* __restrict__ list, int64_t l0,
                                                      int32_t t0, double* __restrict__ Lf, double* __restrict__ Ar,
                                                      double tol, double repl, int32_t* __restrict__ npert) {
-  __shared__ double F[kSmall * (kSmall + 1)];
-  constexpr int S = kSmall + 1;
   const int tt = (int)blockIdx.y;
   const int s = list[l0 + blockIdx.x];
   const int p = D.node_p[s], u = D.node_u[s], f = p + u;
   const int i = (int)threadIdx.x;
   double* L = Lf + (int64_t)(t0 + tt) * D.lsize + D.node_loff[s];
   double* U = Ar + (int64_t)tt * D.usize + D.node_uoff[s];
-  for (int j = 0; j < f; ++j)
-    if (i >= j && i < f) F[j * S + i] = j < p ? L[(int64_t)j * f + i] : U[(int64_t)(j - p) * u + (i - p)];
-  __syncthreads();
-  for (int k = 0; k < p; ++k) {
-    if (i == k) F[k * S + k] = pivot_sqrt(F[k * S + k], tol, repl, npert, true);
-    __syncthreads();
-    if (i > k && i < f) F[k * S + i] /= F[k * S + k];
-    __syncthreads();
-    if (i > k && i < f) {
-      const double aik = F[k * S + i];
-      for (int j = k + 1; j <= i; ++j) F[j * S + i] -= aik * F[k * S + j];
-    }
-    __syncthreads();
+  double a[64];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) {
+    a[j] = 0.0;
+    if (j < f && i >= j && i < f) a[j] = j < p ? L[(int64_t)j * f + i] : U[(int64_t)(j - p) * u + (i - p)];
   }
-  for (int j = 0; j < f; ++j)
-    if (i >= j && i < f) {
-      if (j < p) L[(int64_t)j * f + i] = F[j * S + i];
-      else U[(int64_t)(j - p) * u + (i - p)] = F[j * S + i];
+  chol_rows64(a, p, f, tol, repl, npert);
+#pragma unroll
+  for (int j = 0; j < 64; ++j)
+    if (j < f && i >= j && i < f) {
+      if (j < p) L[(int64_t)j * f + i] = a[j];
+      else U[(int64_t)(j - p) * u + (i - p)] = a[j];
     }
 }
 
 // Blocked front, one panel [k0, k0+kb), step 1: the kb x kb diagonal block
-// factored in place in LDS by one block per period (pivots counted here).
+// factored in place by one wavefront per period (pivots counted here).
 __global__ void __launch_bounds__(64) k_diag(FrontArg A, int32_t k0, int32_t kb, double tol, double repl,
                                              int32_t* __restrict__ npert) {
-  __shared__ double Dg[kNB * (kNB + 1)];
-  constexpr int S = kNB + 1;
   double* L = A.L + (int64_t)blockIdx.x * A.Lstride;
   const int64_t ld = A.ld;
-  const int tid = (int)threadIdx.x;
-  for (int e = tid; e < kb * kb; e += (int)blockDim.x) {
-    const int j = e / kb, i = e % kb;
-    if (i >= j) Dg[j * S + i] = L[(int64_t)(k0 + j) * ld + k0 + i];
-  }
-  __syncthreads();
-  for (int k = 0; k < kb; ++k) {
-    if (tid == k) Dg[k * S + k] = pivot_sqrt(Dg[k * S + k], tol, repl, npert, true);
-    __syncthreads();
-    if (tid > k && tid < kb) Dg[k * S + tid] /= Dg[k * S + k];
-    __syncthreads();
-    if (tid > k && tid < kb) {
-      const double aik = Dg[k * S + tid];
-      for (int j = k + 1; j <= tid; ++j) Dg[j * S + tid] -= aik * Dg[k * S + j];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < kb * kb; e += (int)blockDim.x) {
-    const int j = e / kb, i = e % kb;
-    if (i >= j) L[(int64_t)(k0 + j) * ld + k0 + i] = Dg[j * S + i];
-  }
+  const int i = (int)threadIdx.x;
+  double a[64];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) a[j] = (j < kb && i >= j && i < kb) ? L[(int64_t)(k0 + j) * ld + k0 + i] : 0.0;
+  chol_rows64(a, kb, kb, tol, repl, npert);
+#pragma unroll
+  for (int j = 0; j < 64; ++j)
+    if (j < kb && i >= j && i < kb) L[(int64_t)(k0 + j) * ld + k0 + i] = a[j];
 }
 
 // Step 2: the rows below the panel, L21 = A21 L11^-T, 256 rows per block
@@ -262,10 +272,12 @@ __global__ void __launch_bounds__(256) k_panel(FrontArg A, int32_t k0, int32_t k
 }
 
 // Trailing update after a panel: C -= P P^T on the lower part of rows and
-// columns [r0, p+u), 64 x 64 tiles, 4 x 4 outputs per thread.  Columns < p
-// live in the factor block, the others in the update block.
+// columns [k0+kb, p+u), 128 x 128 tiles, 8 x 8 outputs per thread, the
+// panel staged through LDS 32 columns at a time.  Columns < p live in the
+// factor block, the others in the update block.
 __global__ void __launch_bounds__(256) k_update(FrontArg A, int32_t k0, int32_t kb) {
-  __shared__ double Pi[kNB][kTile + 1], Pj[kNB][kTile + 1];
+  constexpr int KC = 32;
+  __shared__ double Pi[KC][kTile], Pj[KC][kTile];
   const int64_t x = blockIdx.x;
   int64_t ti = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
   while (ti * (ti + 1) / 2 > x) --ti;
@@ -277,32 +289,41 @@ __global__ void __launch_bounds__(256) k_update(FrontArg A, int32_t k0, int32_t 
   const int rows = A.p + A.u, r0 = k0 + kb;
   const int i0 = r0 + (int)ti * kTile, j0 = r0 + (int)tj * kTile;
   const int tid = (int)threadIdx.x;
-  for (int e = tid; e < kNB * kTile; e += (int)blockDim.x) {
-    const int l = e / kTile, rr = e % kTile;
-    Pi[l][rr] = (l < kb && i0 + rr < rows) ? L[(int64_t)(k0 + l) * ld + i0 + rr] : 0.0;
-    Pj[l][rr] = (l < kb && j0 + rr < rows) ? L[(int64_t)(k0 + l) * ld + j0 + rr] : 0.0;
-  }
-  __syncthreads();
   const int tx = tid & 15, ty = tid >> 4;
-  double acc[4][4] = {};
-  for (int l = 0; l < kb; ++l) {
-    double a[4], b[4];
+  double acc[8][8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      a[q] = Pi[l][tx + 16 * q];
-      b[q] = Pj[l][ty + 16 * q];
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[q][c] = 0.0;
+  for (int l0 = 0; l0 < kb; l0 += KC) {
+    const int lb = min(KC, kb - l0);
+    __syncthreads();
+    for (int e = tid; e < KC * kTile; e += (int)blockDim.x) {
+      const int l = e / kTile, rr = e % kTile;
+      const int64_t col = (int64_t)(k0 + l0 + l) * ld;
+      Pi[l][rr] = (l < lb && i0 + rr < rows) ? L[col + i0 + rr] : 0.0;
+      Pj[l][rr] = (l < lb && j0 + rr < rows) ? L[col + j0 + rr] : 0.0;
     }
+    __syncthreads();
+    for (int l = 0; l < lb; ++l) {
+      double a[8], b[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 8; ++q) {
+        a[q] = Pi[l][tx + 16 * q];
+        b[q] = Pj[l][ty + 16 * q];
+      }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[q][c] += a[q] * b[c];
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[q][c] += a[q] * b[c];
+    }
   }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < 8; ++c) {
     const int j = j0 + ty + 16 * c;
     if (j >= rows) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const int i = i0 + tx + 16 * q;
       if (i >= rows || i < j) continue;
       if (j < A.p) L[(int64_t)j * ld + i] -= acc[q][c];
@@ -321,6 +342,10 @@ __global__ void k_add_chain(const double* __restrict__ Us, int32_t G, double* __
 }
 
 // ------------------------------------------------------------------ solves
+__global__ void k_sub(double* __restrict__ y, const double* __restrict__ w, int32_t n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) y[i] -= w[i];
+}
+
 __global__ void k_gather(const double* __restrict__ b, int32_t n_p, int32_t T, const int32_t* __restrict__ perm,
                          double* __restrict__ Y) {
   const int64_t n = (int64_t)n_p * T;
@@ -423,33 +448,46 @@ __global__ void __launch_bounds__(256) k_fwd_root_pull(CDev D, const int32_t* __
   }
 }
 
-// Forward triangle L11 z = y - win on one front per block (y: p entries at
-// stride ystride per block), blocked by 64 columns; dynamic LDS p doubles.
-__global__ void __launch_bounds__(256) k_fwd_tri(const double* __restrict__ Lb, int64_t Lstride, int32_t ld,
-                                                 int32_t p, double* __restrict__ yb, int64_t ystride,
-                                                 const double* __restrict__ win) {
-  extern __shared__ double v[];
-  const double* L = Lb + (int64_t)blockIdx.x * Lstride;
-  double* y = yb + (int64_t)blockIdx.x * ystride;
+// Forward triangle L11 z = y (pivot part of one front), one panel
+// [k0, k0+kb) per launch, grid (row blocks, periods): every block solves
+// the panel's diagonal triangle (staged in LDS, one wavefront, the solved
+// entry broadcast across lanes) from y, block 0 stores the solution in z,
+// and each block subtracts the panel's contribution from its 256 rows of y
+// below the panel.  y's panel entries are only read here and z is only
+// written, so the blocks of one launch never touch an entry another block
+// writes.
+__global__ void __launch_bounds__(256) k_fwd_panel(const double* __restrict__ Lb, int64_t Lstride, int32_t ld,
+                                                   int32_t p, int32_t k0, double* __restrict__ yb,
+                                                   double* __restrict__ zb, int64_t ystride) {
+  __shared__ double Tr[64 * 65];
+  __shared__ double xs[64];
+  const double* L = Lb + (int64_t)blockIdx.y * Lstride;
+  double* y = yb + (int64_t)blockIdx.y * ystride;
+  double* z = zb + (int64_t)blockIdx.y * ystride;
   const int tid = (int)threadIdx.x;
-  for (int i = tid; i < p; i += (int)blockDim.x) v[i] = y[i] - (win ? win[i] : 0.0);
-  __syncthreads();
-  for (int k0 = 0; k0 < p; k0 += 64) {
-    const int k1 = min(k0 + 64, p);
-    for (int k = k0; k < k1; ++k) {
-      if (tid == 0) v[k] /= L[(int64_t)k * ld + k];
-      __syncthreads();
-      for (int i = k + 1 + tid; i < k1; i += (int)blockDim.x) v[i] -= L[(int64_t)k * ld + i] * v[k];
-      __syncthreads();
-    }
-    for (int i = k1 + tid; i < p; i += (int)blockDim.x) {
-      double acc = 0.0;
-      for (int l = k0; l < k1; ++l) acc += L[(int64_t)l * ld + i] * v[l];
-      v[i] -= acc;
-    }
-    __syncthreads();
+  const int kb = min(64, p - k0);
+  for (int e = tid; e < 64 * 64; e += (int)blockDim.x) {
+    const int c = e >> 6, r = e & 63;
+    if (c < kb && r < kb && r >= c) Tr[c * 65 + r] = L[(int64_t)(k0 + c) * ld + k0 + r];
   }
-  for (int i = tid; i < p; i += (int)blockDim.x) y[i] = v[i];
+  __syncthreads();
+  if (tid < 64) {
+    double vi = tid < kb ? y[k0 + tid] : 0.0;
+    for (int k = 0; k < kb; ++k) {
+      const double xk = __shfl(vi, k) / Tr[k * 65 + k];
+      if (tid == k) vi = xk;
+      else if (tid > k && tid < kb) vi -= Tr[k * 65 + tid] * xk;
+    }
+    xs[tid] = vi;
+    if (blockIdx.x == 0 && tid < kb) z[k0 + tid] = vi;
+  }
+  __syncthreads();
+  const int i = k0 + kb + (int)blockIdx.x * (int)blockDim.x + tid;
+  if (i < p) {
+    double acc = 0.0;
+    for (int l = 0; l < kb; ++l) acc += L[(int64_t)(k0 + l) * ld + i] * xs[l];
+    y[i] -= acc;
+  }
 }
 
 // Forward, w[i] (+)= sum_k L21[i, k] z[k] over the u update rows (rows p ..
@@ -486,36 +524,44 @@ __global__ void __launch_bounds__(256) k_bwd_gemv(const double* __restrict__ Lb,
   if (lane == 0) yb[(int64_t)blockIdx.y * ystride + j] -= acc;
 }
 
-// Backward triangle L11^T x = v on one front per block, blocked by 64
-// columns from the end; dynamic LDS p doubles.
-__global__ void __launch_bounds__(256) k_bwd_tri(const double* __restrict__ Lb, int64_t Lstride, int32_t ld,
-                                                 int32_t p, double* __restrict__ yb, int64_t ystride) {
-  extern __shared__ double v[];
-  const double* L = Lb + (int64_t)blockIdx.x * Lstride;
-  double* y = yb + (int64_t)blockIdx.x * ystride;
+// Backward triangle L11^T x = z (pivot part of one front), one panel
+// [k0, k0+kb) per launch, panels from the last: every block solves the
+// panel's triangle from z (panel entries only read here), block 0 stores x
+// in y, and each block's 4 wavefronts subtract the panel's contribution
+// from their columns j < k0 of z (one wavefront per column, lanes over the
+// panel's rows).  Grid (column blocks of 64, periods).
+__global__ void __launch_bounds__(256) k_bwd_panel(const double* __restrict__ Lb, int64_t Lstride, int32_t ld,
+                                                   int32_t p, int32_t k0, double* __restrict__ yb,
+                                                   double* __restrict__ zb, int64_t ystride) {
+  __shared__ double Tr[64 * 65];
+  __shared__ double xs[64];
+  const double* L = Lb + (int64_t)blockIdx.y * Lstride;
+  double* y = yb + (int64_t)blockIdx.y * ystride;
+  double* z = zb + (int64_t)blockIdx.y * ystride;
   const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int i = tid; i < p; i += (int)blockDim.x) v[i] = y[i];
-  __syncthreads();
-  const int nblk = (p + 63) / 64;
-  for (int bk = nblk - 1; bk >= 0; --bk) {
-    const int k0 = bk * 64, k1 = min(k0 + 64, p);
-    // columns of the block against the solved rows below it
-    if (k1 < p)
-      for (int j = k0 + wv; j < k1; j += 4) {
-        double acc = 0.0;
-        for (int i = k1 + lane; i < p; i += 64) acc += L[(int64_t)j * ld + i] * v[i];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) v[j] -= acc;
-      }
-    __syncthreads();
-    for (int k = k1 - 1; k >= k0; --k) {
-      if (tid == 0) v[k] /= L[(int64_t)k * ld + k];
-      __syncthreads();
-      for (int j = k0 + tid; j < k; j += (int)blockDim.x) v[j] -= L[(int64_t)j * ld + k] * v[k];
-      __syncthreads();
-    }
+  const int kb = min(64, p - k0);
+  for (int e = tid; e < 64 * 64; e += (int)blockDim.x) {
+    const int c = e >> 6, r = e & 63;
+    if (c < kb && r < kb && r >= c) Tr[c * 65 + r] = L[(int64_t)(k0 + c) * ld + k0 + r];
   }
-  for (int i = tid; i < p; i += (int)blockDim.x) y[i] = v[i];
+  __syncthreads();
+  if (tid < 64) {
+    double vj = tid < kb ? z[k0 + tid] : 0.0;
+    for (int k = kb - 1; k >= 0; --k) {
+      const double xk = __shfl(vj, k) / Tr[k * 65 + k];
+      if (tid == k) vj = xk;
+      else if (tid < k) vj -= Tr[tid * 65 + k] * xk;
+    }
+    xs[tid] = tid < kb ? vj : 0.0;
+    if (blockIdx.x == 0 && tid < kb) y[k0 + tid] = vj;
+  }
+  __syncthreads();
+  const int jb = (int)blockIdx.x * 64;
+  for (int j = jb + wv; j < min(jb + 64, k0); j += 4) {
+    double acc = lane < kb ? L[(int64_t)j * ld + k0 + lane] * xs[lane] : 0.0;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) z[j] -= acc;
+  }
 }
 
 // Backward, small fronts: gather x at the update rows, v = y - L21^T x_u,
@@ -569,7 +615,7 @@ struct CholInst {
           *d_kpos0 = nullptr, *d_kpos1 = nullptr, *d_ramp = nullptr;
   int64_t *d_loff = nullptr, *d_uoff = nullptr, *d_woff = nullptr, *d_rowptr = nullptr, *d_kidptr = nullptr,
           *d_slot = nullptr;
-  double *Lf = nullptr, *Cf = nullptr, *Ar = nullptr, *W = nullptr, *Wc = nullptr, *Y = nullptr;
+  double *Lf = nullptr, *Cf = nullptr, *Ar = nullptr, *W = nullptr, *Wc = nullptr, *Y = nullptr, *Z = nullptr;
   std::vector<int64_t> woff;  // per-front offsets of the forward update vectors
   int64_t csize = 0, wsize = 0;
   int32_t chunk = 1, nlarge = 0;
@@ -674,6 +720,7 @@ int setup_device(opf_chol* F, CholInst& C) {
   CHK(dalloc(F, C.wsize * T, &C.W));
   CHK(dalloc(F, G * T, &C.Wc));
   CHK(dalloc(F, (int64_t)P.n_p * T, &C.Y));
+  CHK(dalloc(F, (int64_t)P.n_p * T, &C.Z));
   CDev& D = C.dev;
   D.node_f = C.d_node_f;
   D.node_p = C.d_node_p;
@@ -794,6 +841,29 @@ int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double r
   return OPF_OK;
 }
 
+// Forward / backward triangle of one front's pivot block by panels (see
+// k_fwd_panel / k_bwd_panel): y is the right-hand side in, z the forward
+// solution; the backward pass reads z and leaves x in y.
+int fwd_tri(const double* L, int64_t Ls, int ld, int p, double* y, double* z, int64_t ys, int nper,
+            hipStream_t st) {
+  for (int k0 = 0; k0 < p; k0 += 64) {
+    const int below = p - k0 - std::min(64, p - k0);
+    hipLaunchKernelGGL(k_fwd_panel, dim3(std::max(1, (below + 255) / 256), nper), dim3(256), 0, st, L, Ls, ld, p,
+                       k0, y, z, ys);
+  }
+  LAUNCH_OK("chol forward triangle");
+  return OPF_OK;
+}
+
+int bwd_tri(const double* L, int64_t Ls, int ld, int p, double* y, double* z, int64_t ys, int nper,
+            hipStream_t st) {
+  for (int k0 = ((p - 1) / 64) * 64; k0 >= 0; k0 -= 64)
+    hipLaunchKernelGGL(k_bwd_panel, dim3(std::max(1, (k0 + 63) / 64), nper), dim3(256), 0, st, L, Ls, ld, p, k0, y,
+                       z, ys);
+  LAUNCH_OK("chol backward triangle");
+  return OPF_OK;
+}
+
 int solve_inst(CholInst& C, const double* b, double* x, hipStream_t st) {
   const CholPlan& P = C.plan;
   const InstHost& I = *C.I;
@@ -801,7 +871,8 @@ int solve_inst(CholInst& C, const double* b, double* x, hipStream_t st) {
   const int64_t np = P.n_p;
   hipLaunchKernelGGL(k_gather, dim3(grid_for(np * T, 256)), dim3(256), 0, st, b + I.x_off, P.n_p, T, C.d_perm, C.Y);
   LAUNCH_OK("chol gather");
-  // forward through the interior trees, all periods at once
+  // forward through the interior trees, all periods at once (small fronts
+  // leave their forward solution in Y, large ones in Z)
   for (int h = 0; h < P.nlevels; ++h) {
     const int64_t s0 = P.lvl_small_ptr[h], s1 = P.lvl_small_ptr[h + 1];
     if (s1 > s0) {
@@ -811,14 +882,13 @@ int solve_inst(CholInst& C, const double* b, double* x, hipStream_t st) {
     }
     for (int64_t q = P.lvl_large_ptr[h]; q < P.lvl_large_ptr[h + 1]; ++q) {
       const int s = P.lvl_large[q];
-      const int p = P.node_p[s], u = P.node_u[s];
+      const int p = P.node_p[s], u = P.node_u[s], fs = P.node_f[s];
       const double* L = C.Lf + P.node_loff[s];
       hipLaunchKernelGGL(k_fwd_pull, dim3(T), dim3(256), 0, st, C.dev, s, C.Y, C.W);
-      hipLaunchKernelGGL(k_fwd_tri, dim3(T), dim3(256), (size_t)p * 8, st, L, P.lsize, p + u, p, C.Y + P.node_f[s],
-                         np, (const double*)nullptr);
+      CHK(fwd_tri(L, P.lsize, p + u, p, C.Y + fs, C.Z + fs, np, T, st));
       if (u > 0)
         hipLaunchKernelGGL(k_fwd_gemv, dim3((u + 255) / 256, T), dim3(256), 0, st, L, P.lsize, p + u, p, u,
-                           (const double*)(C.Y + P.node_f[s]), np, C.W + C.woff[s], C.wsize, 1);
+                           (const double*)(C.Z + fs), np, C.W + C.woff[s], C.wsize, 1);
       LAUNCH_OK("chol forward large");
     }
   }
@@ -828,35 +898,34 @@ int solve_inst(CholInst& C, const double* b, double* x, hipStream_t st) {
   // forward along the pg chain
   for (int t = 0; t < T; ++t) {
     const double* Ct = C.Cf + (int64_t)t * C.csize;
-    double* yt = C.Y + (int64_t)t * np + P.n_int;
-    hipLaunchKernelGGL(k_fwd_tri, dim3(1), dim3(256), (size_t)G * 8, st, Ct, (int64_t)0, 2 * G, G, yt, (int64_t)0,
-                       t >= 1 ? (const double*)(C.Wc + (int64_t)(t - 1) * G) : (const double*)nullptr);
+    const int64_t o = (int64_t)t * np + P.n_int;
+    if (t >= 1) hipLaunchKernelGGL(k_sub, dim3((G + 255) / 256), dim3(256), 0, st, C.Y + o, (const double*)(C.Wc + (int64_t)(t - 1) * G), G);
+    CHK(fwd_tri(Ct, 0, 2 * G, G, C.Y + o, C.Z + o, 0, 1, st));
     if (t + 1 < T)
       hipLaunchKernelGGL(k_fwd_gemv, dim3((G + 255) / 256, 1), dim3(256), 0, st, Ct, (int64_t)0, 2 * G, G, G,
-                         (const double*)yt, (int64_t)0, C.Wc + (int64_t)t * G, (int64_t)0, 0);
+                         (const double*)(C.Z + o), (int64_t)0, C.Wc + (int64_t)t * G, (int64_t)0, 0);
     LAUNCH_OK("chol forward chain");
   }
   // backward along the pg chain
   for (int t = T - 1; t >= 0; --t) {
     const double* Ct = C.Cf + (int64_t)t * C.csize;
-    double* yt = C.Y + (int64_t)t * np + P.n_int;
+    const int64_t o = (int64_t)t * np + P.n_int;
     if (t + 1 < T)
       hipLaunchKernelGGL(k_bwd_gemv, dim3((G + 3) / 4, 1), dim3(256), 0, st, Ct, (int64_t)0, 2 * G, G, G,
-                         (const int32_t*)nullptr, (const double*)(yt + np), (int64_t)0, yt, (int64_t)0);
-    hipLaunchKernelGGL(k_bwd_tri, dim3(1), dim3(256), (size_t)G * 8, st, Ct, (int64_t)0, 2 * G, G, yt, (int64_t)0);
+                         (const int32_t*)nullptr, (const double*)(C.Y + o + np), (int64_t)0, C.Z + o, (int64_t)0);
+    CHK(bwd_tri(Ct, 0, 2 * G, G, C.Y + o, C.Z + o, 0, 1, st));
     LAUNCH_OK("chol backward chain");
   }
   // backward through the interior trees, top down
   for (int h = P.nlevels - 1; h >= 0; --h) {
     for (int64_t q = P.lvl_large_ptr[h]; q < P.lvl_large_ptr[h + 1]; ++q) {
       const int s = P.lvl_large[q];
-      const int p = P.node_p[s], u = P.node_u[s];
+      const int p = P.node_p[s], u = P.node_u[s], fs = P.node_f[s];
       const double* L = C.Lf + P.node_loff[s];
       if (u > 0)
         hipLaunchKernelGGL(k_bwd_gemv, dim3((p + 3) / 4, T), dim3(256), 0, st, L, P.lsize, p + u, p, u,
-                           (const int32_t*)(C.d_rows + P.row_ptr[s]), (const double*)C.Y, np, C.Y + P.node_f[s], np);
-      hipLaunchKernelGGL(k_bwd_tri, dim3(T), dim3(256), (size_t)p * 8, st, L, P.lsize, p + u, p, C.Y + P.node_f[s],
-                         np);
+                           (const int32_t*)(C.d_rows + P.row_ptr[s]), (const double*)C.Y, np, C.Z + fs, np);
+      CHK(bwd_tri(L, P.lsize, p + u, p, C.Y + fs, C.Z + fs, np, T, st));
       LAUNCH_OK("chol backward large");
     }
     const int64_t s0 = P.lvl_small_ptr[h], s1 = P.lvl_small_ptr[h + 1];
@@ -900,15 +969,6 @@ int opf_chol_analyze(opf_model* model, opf_chol** out) {
         return api_fail(rc, "instance " + std::to_string(k) + ": " + err);
       }
       const CholPlan& P = C.plan;
-      for (int32_t s = 0; s < P.nnodes; ++s)
-        if (P.node_p[s] > kMaxPiv) {
-          delete F;
-          return api_fail(OPF_EINVAL, "chol: a front has more than 8192 pivots");
-        }
-      if (P.G > kMaxPiv) {
-        delete F;
-        return api_fail(OPF_EINVAL, "chol: more than 8192 generators in one instance");
-      }
       C.nlarge = (int32_t)P.lvl_large.size();
       maxG = std::max(maxG, P.G);
       F->flops += P.flops_period * P.T + P.flops_chain;
