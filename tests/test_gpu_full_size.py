@@ -190,3 +190,51 @@ def test_condensation_calls_paper_scale(dev):
     ref, mags = O.recover_step(net, st, c, dxv, with_mag=True)
     for what, g, r, mg in zip(("ds", "dy", "dzl", "dzu", "dvl", "dvu"), outs, ref, mags):
         GC.assert_close(h(g), r, mg, GC.TOL, "paper " + what)
+
+
+@pytest.mark.timeout(900)
+def test_chol_paper_scale_residual(dev):
+    """The sparse Cholesky at the benchmark's paper-scale configuration
+    (12.8M unknowns, 168 periods, ten periods per chunk): no static pivots
+    on a positive definite K, and the solution's backward error in that K
+    (a property that holds at any size) at the level Cholesky guarantees."""
+    import torch
+    import scipy.sparse as sp
+    from paper_2405_14032_amd import capi
+    net = synth.config_network("paper")
+    pt = synth.make_point(net, 3)
+    M = capi.Model([net], device=0)
+    M.use_current_torch_stream()
+    rng = np.random.default_rng(17)
+    X = _t(torch, dev, pt.x)
+    LAM = torch.zeros(M.m, dtype=torch.float64, device=dev)
+    DX, D = _t(torch, dev, 10.0 ** rng.uniform(-4, 4, M.n)), _t(torch, dev, 10.0 ** rng.uniform(-4, 4, M.m))
+    e = lambda k: torch.empty(k, dtype=torch.float64, device=dev)
+    jv, hv, kv = e(M.nnz_jac), e(M.nnz_hess), e(M.nnz_kkt)
+    M.eval_jhk(X, LAM, 1.0, DX, D, jv, hv, kv)
+    del jv, hv
+    F = capi.Chol(M)
+    print("paper chol", F.info(), flush=True)
+    npert = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    B, XS = _t(torch, dev, rng.standard_normal(M.n)), e(M.n)
+    F.factor(kv, 0.0, 1.0, npert)
+    F.solve(B, XS)
+    rp = torch.empty(M.n + 1, dtype=torch.int64, device=dev)
+    ci = torch.empty(M.nnz_kkt, dtype=torch.int32, device=dev)
+    M.kkt_structure(rp, ci)
+    torch.cuda.synchronize()
+    assert int(npert.item()) == 0
+    n = M.n
+    rows = np.repeat(np.arange(n), np.diff(rp.cpu().numpy()))
+    Lo = sp.csr_matrix((kv.cpu().numpy(), (rows, ci.cpu().numpy())), shape=(n, n))
+    K = (Lo + sp.tril(Lo, -1).T).tocsr()
+    x, b = XS.cpu().numpy(), B.cpu().numpy()
+    r = K @ x - b
+    # normwise backward error, and the residual relative to |K| |x| + |b|
+    # row by row (componentwise backward error)
+    bwd = np.max(np.abs(r)) / (abs(K).max() * np.max(np.abs(x)) + np.max(np.abs(b)))
+    comp = np.max(np.abs(r) / (abs(K) @ np.abs(x) + np.abs(b)))
+    print("backward errors", bwd, comp, flush=True)
+    assert bwd <= 1e-11 and comp <= 1e-8
+    F.close()
+    M.close()
