@@ -173,9 +173,10 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 
 // Right-looking elimination of the first p pivots of a front of order f <=
 // 64 held by one wavefront, lane i owning row i in registers (a[j] = entry
-// (i, j) for j <= i).  Pivot d_k is computed by every lane from the
-// broadcast diagonal; entry (j, k) of column k is broadcast from lane j.
-// Fully unrolled so that every register index is a constant.
+// (i, j) for j <= i; the entries above the diagonal are scratch that no
+// valid entry ever reads, so the updates run unmasked).  Pivot d_k comes
+// from the broadcast diagonal; entry (j, k) of column k is broadcast from
+// lane j.  Fully unrolled so that every register index is a constant.
 __device__ __forceinline__ void chol_rows64(double (&a)[64], int p, int f, double tol, double repl,
                                             int32_t* npert) {
   const int i = (int)threadIdx.x;
@@ -183,14 +184,11 @@ __device__ __forceinline__ void chol_rows64(double (&a)[64], int p, int f, doubl
   for (int k = 0; k < 64; ++k) {
     if (k < p) {
       const double d = pivot_sqrt(lane_bcast(a[k], k), tol, repl, npert, i == 0);
-      if (i == k) a[k] = d;
-      else if (i > k && i < f) a[k] /= d;
+      const double rd = 1.0 / d;
+      a[k] = i > k ? a[k] * rd : (i == k ? d : a[k]);
 #pragma unroll
       for (int j = k + 1; j < 64; ++j) {
-        if (j < f) {
-          const double ljk = lane_bcast(a[k], j);
-          if (i >= j && i < f) a[j] -= a[k] * ljk;
-        }
+        if (j < f) a[j] = fma(-a[k], lane_bcast(a[k], j), a[j]);
       }
     }
   }
@@ -272,29 +270,49 @@ __global__ void __launch_bounds__(256) k_panel(FrontArg A, int32_t k0, int32_t k
 }
 
 // Trailing update after a panel: C -= P P^T on the lower part of rows and
-// columns [k0+kb, p+u), 128 x 128 tiles, 8 x 8 outputs per thread, the
-// panel staged through LDS 32 columns at a time.  Columns < p live in the
-// factor block, the others in the update block.
-__global__ void __launch_bounds__(256) k_update(FrontArg A, int32_t k0, int32_t kb) {
-  constexpr int KC = 32;
+// columns [k0+kb, p+u), 128 x 128 tiles on the FP64 matrix cores: each of
+// the 4 wavefronts accumulates a 64 x 64 quarter as 4 x 4 products of
+// 16 x 16 x 4 (v_mfma_f64_16x16x4: lane l supplies A(l%16, l/16) and
+// B(l/16, l%16) and holds D(l/16 + 4r, l%16), r < 4).  The product is
+// formed transposed (rows of the tile along the lanes) so that each lane
+// group writes 16 consecutive rows of a column of the column-major front.
+// The panel is staged through LDS 16 columns at a time.  Columns < p live
+// in the factor block, the others in the update block.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Region: rows [r0, p+u) x columns [r0, min(cmax, p+u)), lower part, in
+// 128 x 128 tiles enumerated column by column; panel columns [k0, k0+kb),
+// kb <= 128.  With dnext > 0, block 0 (the tile holding rows and columns
+// [r0, r0+128)) then factors the next diagonal block [r0, r0+dnext) in
+// place, which the next panel needs.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_update(FrontArg A, int32_t k0, int32_t kb, int32_t r0, int32_t cmax, int32_t dnext, double tol, double repl,
+         int32_t* __restrict__ npert) {
+  constexpr int KC = 16;
   __shared__ double Pi[KC][kTile], Pj[KC][kTile];
-  const int64_t x = blockIdx.x;
-  int64_t ti = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-  while (ti * (ti + 1) / 2 > x) --ti;
-  while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
-  const int64_t tj = x - ti * (ti + 1) / 2;
+  const int rows = A.p + A.u;
+  const int R = (rows - r0 + kTile - 1) / kTile;
+  int x = (int)blockIdx.x, tj = 0;
+  while (x >= R - tj) {
+    x -= R - tj;
+    ++tj;
+  }
+  const int ti = tj + x;
+  const int cend = min(cmax, rows);
   double* L = A.L + (int64_t)blockIdx.y * A.Lstride;
   double* U = A.U + (int64_t)blockIdx.y * A.Ustride;
   const int64_t ld = A.ld;
-  const int rows = A.p + A.u, r0 = k0 + kb;
-  const int i0 = r0 + (int)ti * kTile, j0 = r0 + (int)tj * kTile;
-  const int tid = (int)threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  double acc[8][8];
+  const int i0 = r0 + ti * kTile, j0 = r0 + tj * kTile;
+  const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = wv & 1, wc = wv >> 1;  // the wavefront's 64-row / 64-column quarter
+  // a quarter wholly above the diagonal or right of the region contributes nothing
+  const bool skip = i0 + wr * 64 + 63 < j0 + wc * 64 || j0 + wc * 64 >= cend;
+  dbl4 acc[4][4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q)
+  for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[q][c] = 0.0;
+    for (int r = 0; r < 4; ++r) acc[c][r] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  const int lr = lane & 15, lk = lane >> 4;
   for (int l0 = 0; l0 < kb; l0 += KC) {
     const int lb = min(KC, kb - l0);
     __syncthreads();
@@ -302,32 +320,50 @@ __global__ void __launch_bounds__(256) k_update(FrontArg A, int32_t k0, int32_t 
       const int l = e / kTile, rr = e % kTile;
       const int64_t col = (int64_t)(k0 + l0 + l) * ld;
       Pi[l][rr] = (l < lb && i0 + rr < rows) ? L[col + i0 + rr] : 0.0;
-      Pj[l][rr] = (l < lb && j0 + rr < rows) ? L[col + j0 + rr] : 0.0;
+      Pj[l][rr] = (l < lb && j0 + rr < cend) ? L[col + j0 + rr] : 0.0;
     }
     __syncthreads();
-    for (int l = 0; l < lb; ++l) {
-      double a[8], b[8];
+    if (!skip) {
+      for (int k4 = 0; k4 < lb; k4 += 4) {
+        double aj[4], bi[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        a[q] = Pi[l][tx + 16 * q];
-        b[q] = Pj[l][ty + 16 * q];
+        for (int q = 0; q < 4; ++q) {
+          aj[q] = Pj[k4 + lk][wc * 64 + q * 16 + lr];
+          bi[q] = Pi[k4 + lk][wr * 64 + q * 16 + lr];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[c], bi[r], acc[c][r], 0, 0, 0);
       }
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc[q][c] += a[q] * b[c];
     }
   }
+  if (!skip) {
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int j = j0 + ty + 16 * c;
-    if (j >= rows) continue;
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = i0 + tx + 16 * q;
-      if (i >= rows || i < j) continue;
-      if (j < A.p) L[(int64_t)j * ld + i] -= acc[q][c];
-      else U[(int64_t)(j - A.p) * A.ldU + (i - A.p)] -= acc[q][c];
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 64 + r * 16 + lr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = j0 + wc * 64 + c * 16 + lk + 4 * e;
+          if (i >= rows || j >= cend || i < j) continue;
+          if (j < A.p) L[(int64_t)j * ld + i] -= acc[c][r][e];
+          else U[(int64_t)(j - A.p) * A.ldU + (i - A.p)] -= acc[c][r][e];
+        }
+      }
+  }
+  if (dnext > 0 && blockIdx.x == 0) {
+    __syncthreads();
+    if (wv == 0) {
+      double a[64];
+#pragma unroll
+      for (int j = 0; j < 64; ++j)
+        a[j] = (j < dnext && lane >= j && lane < dnext) ? L[(int64_t)(r0 + j) * ld + r0 + lane] : 0.0;
+      chol_rows64(a, dnext, dnext, tol, repl, npert);
+#pragma unroll
+      for (int j = 0; j < 64; ++j)
+        if (j < dnext && lane >= j && lane < dnext) L[(int64_t)(r0 + j) * ld + r0 + lane] = a[j];
     }
   }
 }
@@ -742,23 +778,53 @@ int setup_device(opf_chol* F, CholInst& C) {
   return OPF_OK;
 }
 
-// Blocked factorization of one front over nt periods.
+// Blocked factorization of one front over nt periods: 128-column steps of
+// two 64-column sub-panels (diagonal block, rows below; the first
+// sub-panel's update of the second's columns in between), then one
+// trailing update with the 128-wide panel.  Each update launch also factors
+// the next diagonal block.
+int launch_update(const FrontArg& A, int nt, int k0, int kb, int r0, int cmax, int dnext, double tol, double repl,
+                  int32_t* npert, hipStream_t st) {
+  const int rows = A.p + A.u;
+  const int cend = std::min(cmax, rows);
+  if (r0 >= rows || cend <= r0) {
+    if (dnext > 0) {
+      hipLaunchKernelGGL(k_diag, dim3(nt), dim3(64), 0, st, A, r0, dnext, tol, repl, npert);
+      LAUNCH_OK("chol diagonal block");
+    }
+    return OPF_OK;
+  }
+  const int64_t R = (rows - r0 + kTile - 1) / kTile, Cn = (cend - r0 + kTile - 1) / kTile;
+  const int64_t ntiles = Cn * R - Cn * (Cn - 1) / 2;
+  if (ntiles > 0x7fffffff) return api_fail(OPF_EINVAL, "chol: front too large");
+  hipLaunchKernelGGL(k_update, dim3((unsigned)ntiles, nt), dim3(256), 0, st, A, k0, kb, r0, cmax, dnext, tol, repl,
+                     npert);
+  LAUNCH_OK("chol update");
+  return OPF_OK;
+}
+
 int factor_front(const FrontArg& A, int nt, double tol, double repl, int32_t* npert, hipStream_t st) {
   const int rows = A.p + A.u;
-  for (int k0 = 0; k0 < A.p; k0 += kNB) {
-    const int kb = std::min(kNB, A.p - k0);
-    const int below = rows - k0 - kb;
-    hipLaunchKernelGGL(k_diag, dim3(nt), dim3(64), 0, st, A, k0, kb, tol, repl, npert);
-    LAUNCH_OK("chol diagonal block");
-    if (below > 0) {
-      hipLaunchKernelGGL(k_panel, dim3((below + 255) / 256, nt), dim3(256), 0, st, A, k0, kb);
+  hipLaunchKernelGGL(k_diag, dim3(nt), dim3(64), 0, st, A, 0, std::min(64, A.p), tol, repl, npert);
+  LAUNCH_OK("chol diagonal block");
+  for (int k0 = 0; k0 < A.p; k0 += 128) {
+    const int ka = std::min(64, A.p - k0);
+    const int kbB = std::min(64, A.p - k0 - ka);  // second sub-panel (0 if none)
+    if (rows > k0 + ka) {
+      hipLaunchKernelGGL(k_panel, dim3((rows - k0 - ka + 255) / 256, nt), dim3(256), 0, st, A, k0, ka);
       LAUNCH_OK("chol panel");
-      const int64_t tb = (below + kTile - 1) / kTile;
-      const int64_t ntiles = tb * (tb + 1) / 2;
-      if (ntiles > 0x7fffffff) return api_fail(OPF_EINVAL, "chol: front too large");
-      hipLaunchKernelGGL(k_update, dim3((unsigned)ntiles, nt), dim3(256), 0, st, A, k0, kb);
-      LAUNCH_OK("chol update");
     }
+    if (kbB > 0) {
+      const int r1 = k0 + ka;
+      CHK(launch_update(A, nt, k0, ka, r1, r1 + kbB, kbB, tol, repl, npert, st));
+      if (rows > r1 + kbB) {
+        hipLaunchKernelGGL(k_panel, dim3((rows - r1 - kbB + 255) / 256, nt), dim3(256), 0, st, A, r1, kbB);
+        LAUNCH_OK("chol panel");
+      }
+    }
+    const int kb = ka + kbB, r0 = k0 + kb;
+    const int dnext = r0 < A.p ? std::min(64, A.p - r0) : 0;
+    CHK(launch_update(A, nt, k0, kb, r0, rows, dnext, tol, repl, npert, st));
   }
   return OPF_OK;
 }
