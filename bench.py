@@ -467,6 +467,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="skip the batched and adjoint legs")
     ap.add_argument("--no-chol", action="store_true", help="skip the sparse Cholesky leg")
+    ap.add_argument("--chol-only", action="store_true",
+                    help="run only the sparse Cholesky leg and print its JSON object (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -487,6 +489,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.chol_only:
+        print(json.dumps({"chol": bench_chol(torch, dev, args)}), flush=True)
+        return
     res = bench_plain(torch, dev, args)
     log(f"plain sweep: {res['ms_per_step']:.3f} ms/step")
     line = {"metric": METRIC, "value": res["value"], "unit": "nnz/s", "n_gpus": 1, "steps": args.steps,
