@@ -722,3 +722,149 @@ def kkt_is_positive_definite(n, rowptr, colind, vals):
         return True
     except np.linalg.LinAlgError:
         return False
+
+
+# ----------------------------------------------------------------------------
+# the lifted-KKT interior-point loop (Sec. III-B around the condensed system)
+# ----------------------------------------------------------------------------
+def ipm_start(net, relax=1e-4):
+    """Starting iterate: flat voltages (vm = 1, va = 0), generation at the
+    middle of its box, flows equal to the flows of that voltage profile (the
+    flow rows hold), every bounded entry moved at least 1e-2 max(1, |bound|)
+    (at most half the box) inside its bounds; slacks = c(x) moved inside the
+    relaxed row bounds the same way; y = 0; bound multipliers 1 where the
+    bound is finite."""
+    L = Layout(net)
+    xl, xu, cl, cu = bounds(net)
+    eq = cl == cu
+    sl = np.where(eq, cl - relax, cl)
+    su = np.where(eq, cu + relax, cu)
+    X = np.zeros((net.T, L.n_p))
+    X[:, L.vm:L.vm + net.N] = 1.0
+    X[:, L.pg:L.pg + net.G] = 0.5 * (net.pmin + net.pmax)
+    X[:, L.qg:L.qg + net.G] = 0.5 * (net.qmin + net.qmax)
+    C0 = constraints(net, X.reshape(-1))[:net.T * L.m_p].reshape(net.T, L.m_p)
+    for k in range(4):
+        X[:, L.flow[k]:L.flow[k] + net.B] = -C0[:, L.cflow[k]:L.cflow[k] + net.B]
+
+    def inside(v, lo, hi):
+        with np.errstate(invalid="ignore"):
+            half = 0.5 * (hi - lo)
+            pl = np.where(np.isfinite(lo), 1e-2 * np.maximum(1.0, np.abs(lo)), 0.0)
+            pu = np.where(np.isfinite(hi), 1e-2 * np.maximum(1.0, np.abs(hi)), 0.0)
+            pl = np.where(np.isfinite(half), np.minimum(pl, half), pl)
+            pu = np.where(np.isfinite(half), np.minimum(pu, half), pu)
+            v = np.where(np.isfinite(lo), np.maximum(v, lo + pl), v)
+            return np.where(np.isfinite(hi), np.minimum(v, hi - pu), v)
+
+    x = inside(X.reshape(-1), xl, xu)
+    s = inside(constraints(net, x), sl, su)
+    fin = lambda b: np.where(np.isfinite(b), 1.0, 0.0)
+    return dict(x=x, s=s, y=np.zeros(L.m), zl=fin(xl), zu=fin(xu), vl=fin(sl), vu=fin(su),
+                xl=xl, xu=xu, sl=sl, su=su)
+
+
+def ipm_residuals(net, w, mu):
+    """Residuals of the lifted KKT conditions at iterate w (Sec. III-B):
+    p_x = grad f - J^T y - zl + zu, p_s = -vl + vu + y, q_y = c - s and the
+    complementarity products of the finite bounds minus mu (absent bounds
+    contribute nothing).  Returns (rd, rs, rp, gaps, c, grad)."""
+    x, s = w["x"], w["s"]
+    hl, hu, gl, gu = (np.isfinite(w[k]) for k in ("xl", "xu", "sl", "su"))
+    grad, c = gradient(net, x), constraints(net, x)
+    jr, jc, jv = jacobian(net, x)
+    Jty = np.zeros(x.size)
+    np.add.at(Jty, jc, jv * w["y"][jr])
+    rd = grad - Jty - np.where(hl, w["zl"], 0.0) + np.where(hu, w["zu"], 0.0)
+    rs = -np.where(gl, w["vl"], 0.0) + np.where(gu, w["vu"], 0.0) + w["y"]
+    rp = c - s
+    gaps = np.concatenate([w["zl"][hl] * (x[hl] - w["xl"][hl]), w["zu"][hu] * (w["xu"][hu] - x[hu]),
+                           w["vl"][gl] * (s[gl] - w["sl"][gl]), w["vu"][gu] * (w["su"][gu] - s[gu])])
+    return rd, rs, rp, gaps, c, grad
+
+
+def ipm_solve(net, tol=1e-4, max_iter=100, relax=1e-4, sigma=0.1, tau=0.99995, delta_c=1e-8, dw_first=1e-4,
+              dw_grow=8.0, dw_max=1e10):
+    """Primal-dual interior-point method on the lifted formulation of
+    Sec. III-B: the rows c(x) are relaxed to sl <= s <= su with c(x) - s = 0
+    (equality rows widened by +-relax), each iteration solves the condensed
+    system K dx = rhs (condensed_rhs, the condensed matrix of the Hessian of
+    the Lagrangian with lambda = -y, kkt_solve) and recovers the other step
+    components (recover_step).  The paper leaves the outer algorithm to its
+    solver; this one takes:
+
+    * barrier parameter mu = sigma * (mean complementarity product);
+    * inertia correction: delta_w = 0, else dw_first, growing by dw_grow,
+      until K is positive definite (the condition static pivoting needs);
+    * the Newton step is the negated (dx, ds, dzl, dzu, dvl, dvu) with +dy
+      (the condensed system is written for the residuals, not their negative);
+    * step lengths by the fraction-to-the-boundary rule (tau) alone, one
+      for the primal (x, s) and one for the dual (bound multipliers) part; y
+      moves with the dual length;
+    * stop when max(|p_x| / sd, |p_s| / sd, |c - s|, complementarity) <= tol,
+      sd = max(1, mean |multiplier| / 100).
+
+    Returns a dict: the iterate, objective, iterations, factorizations,
+    converged, and the per-iteration history (err, mu, delta_w, alpha_p,
+    alpha_d)."""
+    L = Layout(net)
+    n, m = L.n, L.m
+    w = ipm_start(net, relax)
+    hl, hu, gl, gu = (np.isfinite(w[k]) for k in ("xl", "xu", "sl", "su"))
+    hist, nfact = [], 0
+
+    for it in range(max_iter + 1):
+        rd, rs, rp, gaps, c, grad = ipm_residuals(net, w, 0.0)
+        mult = (np.abs(w["y"]).sum() + w["zl"].sum() + w["zu"].sum() + w["vl"].sum() + w["vu"].sum())
+        sd = max(1.0, mult / (m + 2 * n) / 100.0)
+        err = max(np.abs(rd).max() / sd, np.abs(rs).max() / sd, np.abs(rp).max(),
+                  gaps.max() if gaps.size else 0.0)
+        if err <= tol or it == max_iter:
+            break
+        mu = sigma * gaps.sum() / max(gaps.size, 1)
+        jac = jacobian(net, w["x"])
+        hess = hessian(net, w["x"], -w["y"], 1.0)
+        dw = 0.0
+        while True:
+            st = synth_state(w, mu, dw, delta_c)
+            diag_x, D, rhs = condensed_rhs(net, st, grad, c)
+            rp_, ci_, kv_, _ = condensed(n, jac, hess, diag_x, D)
+            nfact += 1
+            if kkt_is_positive_definite(n, rp_, ci_, kv_):
+                break
+            dw = dw_first if dw == 0.0 else dw * dw_grow
+            if dw > dw_max:
+                raise RuntimeError("inertia correction failed")
+        dx = kkt_solve(n, rp_, ci_, kv_, rhs)
+        ds, dy, dzl, dzu, dvl, dvu = recover_step(net, st, c, dx)
+        step = dict(x=-dx, s=-ds, y=dy, zl=-dzl, zu=-dzu, vl=-dvl, vu=-dvu)
+        ap = min(_max_step(w["x"], step["x"], w["xl"], hl, tau, False),
+                 _max_step(w["x"], step["x"], w["xu"], hu, tau, True),
+                 _max_step(w["s"], step["s"], w["sl"], gl, tau, False),
+                 _max_step(w["s"], step["s"], w["su"], gu, tau, True))
+        ad = min(_max_step(w[k], step[k], np.zeros(w[k].size), msk, tau, False)
+                 for k, msk in (("zl", hl), ("zu", hu), ("vl", gl), ("vu", gu)))
+        w = dict(w)
+        for k in ("x", "s"):
+            w[k] = w[k] + ap * step[k]
+        for k in ("y", "zl", "zu", "vl", "vu"):
+            w[k] = w[k] + ad * step[k]
+        hist.append(dict(err=err, mu=mu, delta_w=dw, alpha_p=ap, alpha_d=ad))
+    return dict(w=w, x=w["x"], objective=objective(net, w["x"]), iterations=it, factorizations=nfact,
+                converged=err <= tol, err=err, history=hist)
+
+
+def _max_step(v, dv, b, mask, tau, upper):
+    """Largest alpha <= 1 with v + alpha dv at least (1 - tau) of the way
+    from the bound b (fraction to the boundary), over the masked entries."""
+    sel = mask & ((dv > 0) if upper else (dv < 0))
+    if not sel.any():
+        return 1.0
+    return float(min(1.0, np.min(tau * (b[sel] - v[sel]) / dv[sel])))
+
+
+def synth_state(w, mu, delta_w, delta_c):
+    """The iterate as the condensation routines take it."""
+    from types import SimpleNamespace
+    return SimpleNamespace(x=w["x"], s=w["s"], y=w["y"], zl=w["zl"], zu=w["zu"], vl=w["vl"], vu=w["vu"],
+                           xl=w["xl"], xu=w["xu"], sl=w["sl"], su=w["su"], mu=mu, delta_w=delta_w, delta_c=delta_c)

@@ -386,3 +386,84 @@ def test_planted_doubled_diagonal(monkeypatch):
     monkeypatch.setattr(O, "kkt_full", wrong)
     with pytest.raises(AssertionError):
         test_kkt_solve_grid_against_dense_system()
+
+
+# ---------------------------------------------------------------- IPM loop
+def _trust_constr_objective(net, relax=1e-4):
+    """The relaxed problem solved by scipy's trust-region constrained method
+    (an independent solver; only the model functions are shared)."""
+    import scipy.optimize as so
+    import scipy.sparse as sp
+    L = O.Layout(net)
+    n, m = L.n, L.m
+    xl, xu, cl, cu = O.bounds(net)
+    eq = cl == cu
+    sl, su = np.where(eq, cl - relax, cl), np.where(eq, cu + relax, cu)
+
+    def jac(x):
+        r, c, v = O.jacobian(net, x)
+        return sp.csr_matrix((v, (r, c)), shape=(m, n))
+
+    x0 = np.zeros(n)
+    X = x0.reshape(net.T, L.n_p)
+    X[:, :net.N] = 1.0
+    nl = so.NonlinearConstraint(lambda x: O.constraints(net, x), sl, su, jac=jac,
+                                hess=lambda x, lam: O.hessian_dense(n, O.hessian(net, x, lam, 0.0)))
+    r = so.minimize(lambda x: O.objective(net, x), x0, jac=lambda x: O.gradient(net, x),
+                    hess=lambda x: O.hessian_dense(n, O.hessian(net, x, np.zeros(m), 1.0)), method="trust-constr",
+                    constraints=[nl], bounds=so.Bounds(xl, xu), options=dict(maxiter=3000, gtol=1e-10, xtol=1e-12))
+    assert r.constr_violation <= 1e-8
+    return r.fun
+
+
+def test_ipm_tiny_objective_matches_independent_solver():
+    net = synth.config_network("tiny")
+    r = O.ipm_solve(net)
+    assert r["converged"] and r["iterations"] < 40
+    ref = _trust_constr_objective(net)
+    assert abs(r["objective"] - ref) <= 1e-6 * abs(ref), (r["objective"], ref)
+
+
+def test_ipm_tiny_solution_satisfies_kkt():
+    # first-order conditions at the returned point with a Jacobian by
+    # central differences (not the oracle's analytic one)
+    net = synth.config_network("tiny")
+    r = O.ipm_solve(net)
+    w = r["w"]
+    Jd = pins.dense_jac(net, w["x"]) if hasattr(pins, "dense_jac") else None
+    h = 1e-6
+    n = w["x"].size
+    J = np.zeros((w["y"].size, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = h
+        J[:, k] = (O.constraints(net, w["x"] + e) - O.constraints(net, w["x"] - e)) / (2 * h)
+    if Jd is not None:
+        assert np.max(np.abs(J - Jd)) <= 1e-6
+    fin = lambda b, v: np.where(np.isfinite(b), v, 0.0)
+    g = np.zeros(n)
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = h
+        g[k] = (O.objective(net, w["x"] + e) - O.objective(net, w["x"] - e)) / (2 * h)
+    rd = g - J.T @ w["y"] - fin(w["xl"], w["zl"]) + fin(w["xu"], w["zu"])
+    assert np.max(np.abs(rd)) <= 1e-3
+    assert np.max(np.abs(O.constraints(net, w["x"]) - w["s"])) <= 1e-4
+    with np.errstate(invalid="ignore"):
+        assert np.all(w["x"] >= np.where(np.isfinite(w["xl"]), w["xl"], -np.inf))
+        assert np.all(w["x"] <= np.where(np.isfinite(w["xu"]), w["xu"], np.inf))
+        assert np.all(w["s"] >= w["sl"]) and np.all(w["s"] <= w["su"])
+
+
+def test_planted_wrong_multiplier_step(monkeypatch):
+    # the y step taken with the wrong sign stops the method from converging
+    orig = O.recover_step
+
+    def flipped(net, st, c, dx, with_mag=False):
+        out = list(orig(net, st, c, dx))
+        out[1] = -out[1]
+        return tuple(out)
+
+    monkeypatch.setattr(O, "recover_step", flipped)
+    r = O.ipm_solve(synth.config_network("tiny"), max_iter=40)
+    assert not r["converged"]
