@@ -340,6 +340,41 @@ def bench_chol(torch, dev, args):
     return res
 
 
+def bench_ipm(torch, dev, args):
+    """The lifted-KKT interior-point loop (opf_ipm_solve): a whole solve to
+    1e-4 of a 301-bus, 2-period synthetic grid (where the loop's plain step
+    rule converges), and the cost of one iteration at paper scale (three
+    iterations timed; evaluation + condensation, factorization, solve +
+    recovery)."""
+    from paper_2405_14032_amd import capi, synth
+    out = {}
+    net = synth.make_network(301, 517, 63, 2, 41)
+    M = capi.Model([net], device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    x = torch.empty(M.n, dtype=torch.float64, device=dev)
+    r = capi.ipm_solve(M, F, x)
+    out["whole_solve"] = {"workload": "N=301 B=517 G=63 T=2 (seed 41), tol 1e-4", "n": M.n, "m": M.m,
+                          "converged": bool(r["converged"]), "iterations": r["iterations"],
+                          "seconds": round(r["seconds"], 4), "objective": r["objective"]}
+    F.close()
+    M.close()
+    net = synth.config_network("paper")
+    M = capi.Model([net], device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    x = torch.empty(M.n, dtype=torch.float64, device=dev)
+    r = capi.ipm_solve(M, F, x, max_iter=3)
+    k = max(1, r["iterations"])
+    out["paper_iteration"] = {"workload": "paper-scale grid, first 3 iterations", "n": M.n, "m": M.m,
+                              "s_per_iteration": round(r["seconds"] / k, 3),
+                              "eval_condense_s": round(r["t_eval"] / k, 4), "factor_s": round(r["t_factor"] / k, 3),
+                              "solve_recover_s": round(r["t_solve"] / k, 3)}
+    F.close()
+    M.close()
+    return out
+
+
 def bench_batched(torch, dev, args):
     from paper_2405_14032_amd import capi, synth
     nets = synth.batched_networks(64)
@@ -506,6 +541,8 @@ def main():
     if not args.no_chol:
         line["chol"] = bench_chol(torch, dev, args)
         log(f"chol: {line['chol']}")
+        line["ipm"] = bench_ipm(torch, dev, args)
+        log(f"ipm: {line['ipm']}")
     if not args.only_plain:
         line["batched"] = bench_batched(torch, dev, args)
         log(f"batched: {line['batched']}")

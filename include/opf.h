@@ -358,6 +358,58 @@ int opf_chol_factor(opf_chol *chol, const double *kvals, double pivot_tol,
  * object's work vectors, so solves on one object must not overlap. */
 int opf_chol_solve(opf_chol *chol, const double *b, double *x);
 
+/* ---- the lifted-KKT interior-point loop (Sec. III-B) ----
+ *
+ * Solves the multi-period AC OPF of the model (all instances jointly) to
+ * tolerance by a primal-dual interior-point method on the lifted
+ * formulation: rows relaxed to sl <= s <= su with c(x) - s = 0 (equality
+ * rows widened by +-relax), each iteration condensing (opf_condensed_rhs),
+ * building K at lambda = -y (opf_eval_jhk), factoring with the static-pivot
+ * Cholesky and correcting the inertia (delta_w = 0, then dw_first, times
+ * dw_grow, while the factorization reports static pivots), solving and
+ * recovering the step (opf_recover_step).  The paper leaves the outer
+ * algorithm to its solver; this one takes mu = sigma * (mean
+ * complementarity product), step lengths by the fraction-to-the-boundary
+ * rule (one primal, one dual; y moves with the dual length), and stops when
+ * max(|p_x| / sd, |p_s| / sd, |c - s|, complementarity) <= tol with
+ * sd = max(1, mean |multiplier| / 100).  Start: flat voltages, generation at
+ * the middle of its box, consistent flows, every bounded entry pushed
+ * 1e-2 max(1, |bound|) inside; y = 0, bound multipliers 1. */
+typedef struct {
+  double tol;      /* stopping tolerance (1e-4)                          */
+  int32_t max_iter; /* iteration limit (100)                             */
+  double relax;    /* half-width of the relaxed equality rows (1e-4)     */
+  double sigma;    /* centring factor of mu (0.1)                        */
+  double tau;      /* fraction to the boundary (0.99995)                 */
+  double delta_c;  /* dual regularisation (1e-8)                         */
+  double dw_first, dw_grow, dw_max; /* inertia correction (1e-4, 8, 1e10) */
+  double pivot_tol; /* static pivot threshold of the factorization (0)   */
+  int32_t verbose;  /* 1: progress lines per iteration on stderr, 2: also
+                       each factorization's delta_w and static pivots (0) */
+} opf_ipm_options;
+
+typedef struct {
+  int32_t converged;      /* 1 if the tolerance was met                  */
+  int32_t iterations;     /* Newton steps taken                           */
+  int32_t factorizations; /* including inertia-correction refactorizations */
+  double objective;       /* sum over instances                           */
+  double err;             /* final value of the stopping measure          */
+  double seconds;         /* wall time of the call                        */
+  double t_eval, t_factor, t_solve; /* evaluation + condensation, factorization, solve + recovery + step */
+} opf_ipm_result;
+
+void opf_ipm_default_options(opf_ipm_options *opt);
+/* chol: opf_chol_analyze of the same model.  x_out: device [n], receives
+ * the final primal point; y_out: device [m] or NULL, the final multipliers
+ * of c(x) - s = 0.  opt NULL = defaults.  Allocates its work vectors on the
+ * model's device for the duration of the call and synchronises the model's
+ * stream once per iteration.  Returns OPF_OK also when the iteration limit
+ * stops it (res->converged = 0); OPF_EINVAL on bad options, a non-finite
+ * iterate (any non-finite residual) or a failed inertia correction;
+ * OPF_ENODEV on a host-only model. */
+int opf_ipm_solve(opf_model *model, opf_chol *chol, const opf_ipm_options *opt,
+                  double *x_out, double *y_out, opf_ipm_result *res);
+
 /* Last error message of the calling thread ("" if none). */
 const char *opf_last_error(void);
 

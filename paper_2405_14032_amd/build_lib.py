@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/opf_capi.hip", "csrc/opf_kernels.hip", "csrc/opf_symbolic.cpp", "csrc/opf_chol.hip",
-           "csrc/opf_chol_symbolic.cpp"]
+           "csrc/opf_chol_symbolic.cpp", "csrc/opf_ipm.hip"]
 LIB = os.path.join(HERE, "libopf.so")
 
 

@@ -71,6 +71,18 @@ class opf_chol_info(C.Structure):
                 ("chunk", C.c_int32), ("large_nodes", C.c_int32)]
 
 
+class opf_ipm_options(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("relax", C.c_double), ("sigma", C.c_double),
+                ("tau", C.c_double), ("delta_c", C.c_double), ("dw_first", C.c_double), ("dw_grow", C.c_double),
+                ("dw_max", C.c_double), ("pivot_tol", C.c_double), ("verbose", C.c_int32)]
+
+
+class opf_ipm_result(C.Structure):
+    _fields_ = [("converged", C.c_int32), ("iterations", C.c_int32), ("factorizations", C.c_int32),
+                ("objective", C.c_double), ("err", C.c_double), ("seconds", C.c_double), ("t_eval", C.c_double),
+                ("t_factor", C.c_double), ("t_solve", C.c_double)]
+
+
 class opf_ipm_state(C.Structure):
     _fields_ = [("x", C.c_void_p), ("s", C.c_void_p), ("y", C.c_void_p),
                 ("zl", C.c_void_p), ("zu", C.c_void_p), ("vl", C.c_void_p), ("vu", C.c_void_p),
@@ -113,6 +125,8 @@ _SIGS = {
     "opf_chol_tree": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "opf_chol_factor": (C.c_int, [_vp, _vp, C.c_double, C.c_double, _vp]),
     "opf_chol_solve": (C.c_int, [_vp, _vp, _vp]),
+    "opf_ipm_default_options": (None, [C.POINTER(opf_ipm_options)]),
+    "opf_ipm_solve": (C.c_int, [_vp, _vp, C.POINTER(opf_ipm_options), _vp, _vp, C.POINTER(opf_ipm_result)]),
     "opf_set_timing": (C.c_int, [_vp, C.c_int]),
     "opf_kernel_stats": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]),
@@ -398,3 +412,21 @@ class Chol:
 
     def solve(self, b, x):
         check(opf_chol_solve(self.h, _ptr(b), _ptr(x)), "opf_chol_solve")
+
+
+def ipm_options(**kw) -> opf_ipm_options:
+    """Default interior-point options with the given fields replaced."""
+    o = opf_ipm_options()
+    opf_ipm_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def ipm_solve(model: Model, chol: Chol, x_out, y_out=None, **opts) -> dict:
+    """Runs the lifted-KKT interior-point loop (opf_ipm_solve); x_out (and
+    y_out) are device arrays receiving the final point (multipliers)."""
+    o = ipm_options(**opts)
+    r = opf_ipm_result()
+    check(opf_ipm_solve(model.h, chol.h, C.byref(o), _ptr(x_out), _ptr(y_out), C.byref(r)), "opf_ipm_solve")
+    return {k: getattr(r, k) for k, _ in opf_ipm_result._fields_}

@@ -1,0 +1,443 @@
+// The lifted-KKT interior-point loop (Sec. III-B around the condensed
+// system): element-wise and reduction kernels of the outer iteration and the
+// opf_ipm_solve driver, which calls the library's own evaluation,
+// condensation, factorization, solve and recovery entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/opf.h"
+#include "opf_api_internal.h"
+
+namespace opf {
+namespace {
+
+constexpr int kRedBlock = 256;
+constexpr int kRedGrid = 512;
+
+__device__ __forceinline__ bool fin(double v) { return isfinite(v); }
+
+// Flat start of one instance: vm = 1, va = 0, pg and qg at the middle of
+// their boxes, flows 0 (set from c next).
+__global__ void k_start_flat(double* __restrict__ x, const double* __restrict__ xl, const double* __restrict__ xu,
+                             int64_t n_p, int32_t N, int32_t G, int32_t T) {
+  const int64_t n = n_p * T;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n_p;
+    double v = 0.0;
+    if (i < N) v = 1.0;
+    else if (i >= 2 * N && i < 2 * N + 2 * G) v = 0.5 * (xl[e] + xu[e]);
+    x[e] = v;
+  }
+}
+
+// Flows equal to the flows of the current voltages: the flow rows read
+// c = x_flow - phi(V) with x_flow = 0, so x_flow = -c.
+__global__ void k_start_flows(double* __restrict__ x, const double* __restrict__ c, int64_t n_p, int64_t m_p,
+                              int32_t N, int32_t B, int32_t G, int32_t T) {
+  const int64_t n = 4LL * B * T;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = e / (4LL * B), r = e % (4LL * B);
+    x[t * n_p + 2 * N + 2 * G + r] = -c[t * m_p + 2 * N + 1 + r];
+  }
+}
+
+// Moves v at least 1e-2 max(1, |bound|) (at most half the box) inside its
+// finite bounds.
+__device__ __forceinline__ double inside(double v, double lo, double hi) {
+  const bool fl = fin(lo), fh = fin(hi);
+  double pl = fl ? 1e-2 * fmax(1.0, fabs(lo)) : 0.0, pu = fh ? 1e-2 * fmax(1.0, fabs(hi)) : 0.0;
+  if (fl && fh) {
+    pl = fmin(pl, 0.5 * (hi - lo));
+    pu = fmin(pu, 0.5 * (hi - lo));
+  }
+  if (fl) v = fmax(v, lo + pl);
+  if (fh) v = fmin(v, hi - pu);
+  return v;
+}
+
+__global__ void k_push_inside(double* __restrict__ v, const double* __restrict__ src, const double* __restrict__ lo,
+                              const double* __restrict__ hi, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = inside(src[i], lo[i], hi[i]);
+}
+
+// Relaxed row bounds (equality rows widened by +-relax) and the starting
+// multipliers: y = 0, bound multipliers 1 where the bound is finite.
+__global__ void k_start_rows(const double* __restrict__ cl, const double* __restrict__ cu, double relax,
+                             double* __restrict__ sl, double* __restrict__ su, double* __restrict__ y,
+                             double* __restrict__ ly, double* __restrict__ vl, double* __restrict__ vu, int64_t m) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool eq = cl[i] == cu[i];
+    const double a = eq ? cl[i] - relax : cl[i], b = eq ? cu[i] + relax : cu[i];
+    sl[i] = a;
+    su[i] = b;
+    y[i] = 0.0;
+    ly[i] = 0.0;
+    vl[i] = fin(a) ? 1.0 : 0.0;
+    vu[i] = fin(b) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void k_start_vars(const double* __restrict__ xl, const double* __restrict__ xu, double* __restrict__ zl,
+                             double* __restrict__ zu, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    zl[i] = fin(xl[i]) ? 1.0 : 0.0;
+    zu[i] = fin(xu[i]) ? 1.0 : 0.0;
+  }
+}
+
+struct Iter {
+  double *x, *s, *y, *ly, *zl, *zu, *vl, *vu;
+  const double *xl, *xu, *sl, *su;
+};
+
+// Per-block partials of the residual measures: [0] max |p_x|, [1] max |p_s|,
+// [2] max |c - s|, [3] max complementarity product, [4] their sum, [5]
+// their count, [6] sum of |multipliers|, [7] number of non-finite terms
+// (fmax would drop a NaN, so they are counted instead).
+constexpr int kNR = 8;
+
+__device__ __forceinline__ void block_reduce(double* sh, int op, double& v) {
+  // op 0: max, 1: sum, 2: min
+  const int tid = (int)threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      const double a = sh[tid], b = sh[tid + off];
+      sh[tid] = op == 0 ? fmax(a, b) : (op == 1 ? a + b : fmin(a, b));
+    }
+    __syncthreads();
+  }
+  v = sh[0];
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_resid(Iter w, const double* __restrict__ grad,
+                                                     const double* __restrict__ jtv, const double* __restrict__ c,
+                                                     int64_t n, int64_t m, double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  double rd = 0.0, rs = 0.0, rp = 0.0, gmax = 0.0, gsum = 0.0, gcnt = 0.0, msum = 0.0, bad = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const bool hl = fin(w.xl[i]), hu = fin(w.xu[i]);
+    const double zl = hl ? w.zl[i] : 0.0, zu = hu ? w.zu[i] : 0.0;
+    const double r = grad[i] - jtv[i] - zl + zu;
+    if (!fin(r) || !fin(w.x[i])) bad += 1.0;
+    rd = fmax(rd, fabs(r));
+    if (hl) {
+      const double g = zl * (w.x[i] - w.xl[i]);
+      gmax = fmax(gmax, g);
+      gsum += g;
+      gcnt += 1.0;
+    }
+    if (hu) {
+      const double g = zu * (w.xu[i] - w.x[i]);
+      gmax = fmax(gmax, g);
+      gsum += g;
+      gcnt += 1.0;
+    }
+    msum += zl + zu;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) {
+    const bool gl = fin(w.sl[i]), gu = fin(w.su[i]);
+    const double vl = gl ? w.vl[i] : 0.0, vu = gu ? w.vu[i] : 0.0;
+    const double a = -vl + vu + w.y[i], b = c[i] - w.s[i];
+    if (!fin(a) || !fin(b)) bad += 1.0;
+    rs = fmax(rs, fabs(a));
+    rp = fmax(rp, fabs(b));
+    if (gl) {
+      const double g = vl * (w.s[i] - w.sl[i]);
+      gmax = fmax(gmax, g);
+      gsum += g;
+      gcnt += 1.0;
+    }
+    if (gu) {
+      const double g = vu * (w.su[i] - w.s[i]);
+      gmax = fmax(gmax, g);
+      gsum += g;
+      gcnt += 1.0;
+    }
+    msum += vl + vu + fabs(w.y[i]);
+  }
+  block_reduce(sh, 0, rd);
+  block_reduce(sh, 0, rs);
+  block_reduce(sh, 0, rp);
+  block_reduce(sh, 0, gmax);
+  block_reduce(sh, 1, gsum);
+  block_reduce(sh, 1, gcnt);
+  block_reduce(sh, 1, msum);
+  block_reduce(sh, 1, bad);
+  if (threadIdx.x == 0) {
+    double* o = part + (int64_t)blockIdx.x * kNR;
+    o[0] = rd;
+    o[1] = rs;
+    o[2] = rp;
+    o[3] = gmax;
+    o[4] = gsum;
+    o[5] = gcnt;
+    o[6] = msum;
+    o[7] = bad;
+  }
+}
+
+struct Step {
+  const double *dx, *ds, *dy, *dzl, *dzu, *dvl, *dvu;  // as the condensed solve returns them
+};
+
+// Fraction to the boundary: the Newton step is (-dx, -ds, +dy, -dz, -dv).
+// Per-block partials [0] primal length, [1] dual length.
+__device__ __forceinline__ double ftb(double v, double d, double b, bool upper, double tau) {
+  if (upper ? d > 0.0 : d < 0.0) return fmin(1.0, tau * (b - v) / d);
+  return 1.0;
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_steplen(Iter w, Step st, double tau, int64_t n, int64_t m,
+                                                       double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  double ap = 1.0, ad = 1.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double dx = -st.dx[i];
+    if (fin(w.xl[i])) {
+      ap = fmin(ap, ftb(w.x[i], dx, w.xl[i], false, tau));
+      ad = fmin(ad, ftb(w.zl[i], -st.dzl[i], 0.0, false, tau));
+    }
+    if (fin(w.xu[i])) {
+      ap = fmin(ap, ftb(w.x[i], dx, w.xu[i], true, tau));
+      ad = fmin(ad, ftb(w.zu[i], -st.dzu[i], 0.0, false, tau));
+    }
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) {
+    const double ds = -st.ds[i];
+    if (fin(w.sl[i])) {
+      ap = fmin(ap, ftb(w.s[i], ds, w.sl[i], false, tau));
+      ad = fmin(ad, ftb(w.vl[i], -st.dvl[i], 0.0, false, tau));
+    }
+    if (fin(w.su[i])) {
+      ap = fmin(ap, ftb(w.s[i], ds, w.su[i], true, tau));
+      ad = fmin(ad, ftb(w.vu[i], -st.dvu[i], 0.0, false, tau));
+    }
+  }
+  block_reduce(sh, 2, ap);
+  block_reduce(sh, 2, ad);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ap;
+    part[2 * blockIdx.x + 1] = ad;
+  }
+}
+
+__global__ void k_update(Iter w, Step st, double ap, double ad, int64_t n, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    w.x[i] -= ap * st.dx[i];
+    if (fin(w.xl[i])) w.zl[i] -= ad * st.dzl[i];
+    if (fin(w.xu[i])) w.zu[i] -= ad * st.dzu[i];
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) {
+    w.s[i] -= ap * st.ds[i];
+    w.y[i] += ad * st.dy[i];
+    w.ly[i] = -w.y[i];
+    if (fin(w.sl[i])) w.vl[i] -= ad * st.dvl[i];
+    if (fin(w.su[i])) w.vu[i] -= ad * st.dvu[i];
+  }
+}
+
+int grid_of(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
+
+#define IPM_CHK(x)                    \
+  do {                                \
+    const int rc_ = (x);              \
+    if (rc_ != OPF_OK) return rc_;    \
+  } while (0)
+
+#define IPM_HIP(call, what)                                                                   \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return api_fail(OPF_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Buffers {
+  std::vector<void*> p;
+  ~Buffers() {
+    for (void* q : p) (void)hipFree(q);
+  }
+  int get(int64_t count, double** out) {
+    if (hipMalloc((void**)out, (size_t)std::max<int64_t>(1, count) * sizeof(double)) != hipSuccess)
+      return api_fail(OPF_ENOMEM, "ipm: device allocation failed");
+    p.push_back(*out);
+    return OPF_OK;
+  }
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+}  // namespace opf
+
+using namespace opf;
+
+extern "C" {
+
+void opf_ipm_default_options(opf_ipm_options* o) {
+  if (!o) return;
+  o->tol = 1e-4;
+  o->max_iter = 100;
+  o->relax = 1e-4;
+  o->sigma = 0.1;
+  o->tau = 0.99995;
+  o->delta_c = 1e-8;
+  o->dw_first = 1e-4;
+  o->dw_grow = 8.0;
+  o->dw_max = 1e10;
+  o->pivot_tol = 0.0;
+  o->verbose = 0;
+}
+
+int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, double* x_out, double* y_out,
+                  opf_ipm_result* res) {
+  if (!M || !F || !x_out || !res) return api_fail(OPF_EINVAL, "ipm: model, chol, x or result is NULL");
+  if (model_device(M) < 0) return api_fail(OPF_ENODEV, "model is host-only");
+  opf_ipm_options opt;
+  if (opt_in) opt = *opt_in;
+  else opf_ipm_default_options(&opt);
+  if (!(opt.tol > 0.0) || opt.max_iter < 0 || !(opt.relax >= 0.0) || !(opt.sigma > 0.0 && opt.sigma < 1.0) ||
+      !(opt.tau > 0.0 && opt.tau < 1.0) || !(opt.delta_c >= 0.0) || !(opt.dw_first > 0.0) || !(opt.dw_grow > 1.0) ||
+      !(opt.dw_max >= opt.dw_first) || !std::isfinite(opt.pivot_tol))
+    return api_fail(OPF_EINVAL, "ipm: invalid options");
+  std::memset(res, 0, sizeof(*res));
+  const double t_start = now_s();
+  hipStream_t st = model_stream(M);
+  opf_dims d;
+  IPM_CHK(opf_model_dims(M, &d));
+  const int64_t n = d.n, m = d.m;
+  Buffers B;
+  double *x, *s, *y, *ly, *zl, *zu, *vl, *vu, *xl, *xu, *cl, *cu, *sl, *su;
+  double *grad, *c, *jtv, *diag_x, *dcon, *rhs, *dx, *ds, *dy, *dzl, *dzu, *dvl, *dvu, *jv, *hv, *kv, *part, *fobj;
+  // variable-length (n) and row-length (m) work vectors
+  for (double** p : {&x, &xl, &xu, &zl, &zu, &grad, &jtv, &diag_x, &rhs, &dx, &dzl, &dzu}) IPM_CHK(B.get(n, p));
+  for (double** p : {&s, &y, &ly, &vl, &vu, &cl, &cu, &sl, &su, &c, &dcon, &ds, &dy, &dvl, &dvu}) IPM_CHK(B.get(m, p));
+  IPM_CHK(B.get(d.nnz_jac, &jv));
+  IPM_CHK(B.get(d.nnz_hess, &hv));
+  IPM_CHK(B.get(d.nnz_kkt, &kv));
+  IPM_CHK(B.get((int64_t)kRedGrid * kNR, &part));
+  IPM_CHK(B.get(d.ninst, &fobj));
+  int32_t* npert = nullptr;
+  IPM_HIP(hipMalloc((void**)&npert, sizeof(int32_t)), "ipm: allocation");
+  B.p.push_back(npert);
+
+  // starting iterate
+  IPM_CHK(opf_bounds(M, xl, xu, cl, cu));
+  const auto& insts = model_insts(M);
+  for (const auto& I : insts)
+    hipLaunchKernelGGL(k_start_flat, dim3(grid_of(I.n)), dim3(256), 0, st, x + I.x_off, xl + I.x_off, xu + I.x_off,
+                       I.n_p, I.N, I.G, I.T);
+  IPM_CHK(opf_eval_cons(M, x, c));
+  for (const auto& I : insts)
+    hipLaunchKernelGGL(k_start_flows, dim3(grid_of(4LL * I.B * I.T)), dim3(256), 0, st, x + I.x_off, c + I.c_off,
+                       I.n_p, I.m_p, I.N, I.B, I.G, I.T);
+  hipLaunchKernelGGL(k_push_inside, dim3(grid_of(n)), dim3(256), 0, st, x, x, xl, xu, n);
+  hipLaunchKernelGGL(k_start_rows, dim3(grid_of(m)), dim3(256), 0, st, cl, cu, opt.relax, sl, su, y, ly, vl, vu, m);
+  hipLaunchKernelGGL(k_start_vars, dim3(grid_of(n)), dim3(256), 0, st, xl, xu, zl, zu, n);
+  IPM_CHK(opf_eval_cons(M, x, c));
+  hipLaunchKernelGGL(k_push_inside, dim3(grid_of(m)), dim3(256), 0, st, s, c, sl, su, m);
+  IPM_HIP(hipGetLastError(), "ipm: start kernels");
+
+  Iter w{x, s, y, ly, zl, zu, vl, vu, xl, xu, sl, su};
+  Step stp{dx, ds, dy, dzl, dzu, dvl, dvu};
+  std::vector<double> hp((size_t)kRedGrid * kNR);
+  double t_eval = 0, t_fac = 0, t_sol = 0;
+  int it = 0, nfact = 0;
+  double err = 0.0;
+  for (;; ++it) {
+    double t0 = now_s();
+    IPM_CHK(opf_eval_grad(M, x, grad));
+    IPM_CHK(opf_eval_cons(M, x, c));
+    IPM_CHK(opf_jtprod(M, x, y, jtv));
+    hipLaunchKernelGGL(k_resid, dim3(kRedGrid), dim3(kRedBlock), 0, st, w, (const double*)grad, (const double*)jtv,
+                       (const double*)c, n, m, part);
+    IPM_HIP(hipGetLastError(), "ipm: residual kernel");
+    IPM_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st), "ipm: copy");
+    IPM_HIP(hipStreamSynchronize(st), "ipm: sync");
+    t_eval += now_s() - t0;
+    double r[kNR] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < kRedGrid; ++b)
+      for (int k = 0; k < kNR; ++k) r[k] = k <= 3 ? std::max(r[k], hp[b * kNR + k]) : r[k] + hp[b * kNR + k];
+    const double sd = std::max(1.0, r[6] / (double)(m + 2 * n) / 100.0);
+    err = std::max({r[0] / sd, r[1] / sd, r[2], r[3]});
+    if (r[7] > 0.0 || !std::isfinite(err))
+      return api_fail(OPF_EINVAL, "ipm: the iterate is not finite at iteration " + std::to_string(it));
+    if (opt.verbose)
+      std::fprintf(stderr, "ipm %3d  err %.3e  |p_x| %.3e  |p_s| %.3e  |c-s| %.3e  compl %.3e  mu %.3e\n", it, err,
+                   r[0], r[1], r[2], r[3], opt.sigma * r[4] / std::max(1.0, r[5]));
+    if (err <= opt.tol || it >= opt.max_iter) break;
+    const double mu = opt.sigma * r[4] / std::max(1.0, r[5]);
+    // inertia-corrected condensed system
+    double dw = 0.0;
+    opf_ipm_state ist{x, s, y, zl, zu, vl, vu, xl, xu, sl, su, mu, dw, opt.delta_c};
+    for (;;) {
+      ist.delta_w = dw;
+      t0 = now_s();
+      IPM_CHK(opf_condensed_rhs(M, &ist, grad, c, diag_x, dcon, rhs));
+      IPM_CHK(opf_eval_jhk(M, x, ly, 1.0, diag_x, dcon, jv, hv, kv));
+      IPM_HIP(hipStreamSynchronize(st), "ipm: sync");
+      t_eval += now_s() - t0;
+      t0 = now_s();
+      IPM_CHK(opf_chol_factor(F, kv, opt.pivot_tol, 1.0, npert));
+      int32_t hn = 0;
+      IPM_HIP(hipMemcpyAsync(&hn, npert, sizeof(int32_t), hipMemcpyDeviceToHost, st), "ipm: copy");
+      IPM_HIP(hipStreamSynchronize(st), "ipm: sync");
+      t_fac += now_s() - t0;
+      ++nfact;
+      if (opt.verbose > 1) std::fprintf(stderr, "      factorization  delta_w %.1e  static pivots %d\n", dw, hn);
+      if (hn == 0) break;
+      dw = dw == 0.0 ? opt.dw_first : dw * opt.dw_grow;
+      if (dw > opt.dw_max) return api_fail(OPF_EINVAL, "ipm: inertia correction failed");
+    }
+    t0 = now_s();
+    IPM_CHK(opf_chol_solve(F, rhs, dx));
+    IPM_CHK(opf_recover_step(M, &ist, c, dx, ds, dy, dzl, dzu, dvl, dvu));
+    hipLaunchKernelGGL(k_steplen, dim3(kRedGrid), dim3(kRedBlock), 0, st, w, stp, opt.tau, n, m, part);
+    IPM_HIP(hipGetLastError(), "ipm: step kernel");
+    IPM_HIP(hipMemcpyAsync(hp.data(), part, 2 * kRedGrid * sizeof(double), hipMemcpyDeviceToHost, st), "ipm: copy");
+    IPM_HIP(hipStreamSynchronize(st), "ipm: sync");
+    double ap = 1.0, ad = 1.0;
+    for (int b = 0; b < kRedGrid; ++b) {
+      ap = std::min(ap, hp[2 * b]);
+      ad = std::min(ad, hp[2 * b + 1]);
+    }
+    if (opt.verbose) std::fprintf(stderr, "      delta_w %.1e  alpha_p %.3e  alpha_d %.3e\n", ist.delta_w, ap, ad);
+    hipLaunchKernelGGL(k_update, dim3(grid_of(std::max(n, m))), dim3(256), 0, st, w, stp, ap, ad, n, m);
+    IPM_HIP(hipGetLastError(), "ipm: update kernel");
+    t_sol += now_s() - t0;
+  }
+  IPM_CHK(opf_eval_obj(M, x, fobj));
+  std::vector<double> fh(d.ninst);
+  IPM_HIP(hipMemcpyAsync(fh.data(), fobj, d.ninst * sizeof(double), hipMemcpyDeviceToHost, st), "ipm: copy");
+  IPM_HIP(hipMemcpyAsync(x_out, x, n * sizeof(double), hipMemcpyDeviceToDevice, st), "ipm: copy");
+  if (y_out) IPM_HIP(hipMemcpyAsync(y_out, y, m * sizeof(double), hipMemcpyDeviceToDevice, st), "ipm: copy");
+  IPM_HIP(hipStreamSynchronize(st), "ipm: sync");
+  double fsum = 0.0;
+  for (double v : fh) fsum += v;
+  res->converged = err <= opt.tol ? 1 : 0;
+  res->iterations = it;
+  res->factorizations = nfact;
+  res->objective = fsum;
+  res->err = err;
+  res->seconds = now_s() - t_start;
+  res->t_eval = t_eval;
+  res->t_factor = t_fac;
+  res->t_solve = t_sol;
+  return OPF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+"""The lifted-KKT interior-point loop on the GPU (opf_ipm_solve) against the
+oracle's loop (the same algorithm written plainly on the CPU with a sparse LU
+and a dense positive-definiteness test): both converge to the stopping
+tolerance 1e-4 and reach the same point.  Iterates agree to rounding at
+first and the rounding is amplified along the iterations, so the comparison
+is of the converged solutions: objective to 1e-6 relative, x to 1e-3, and
+iteration counts within 2."""
+import numpy as np
+import pytest
+
+from oracle import opf_oracle as O
+from paper_2405_14032_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def _gpu_ipm(nets, torch, dev, **opts):
+    from paper_2405_14032_amd import capi
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    x = torch.full((M.n,), float("nan"), dtype=torch.float64, device=dev)
+    y = torch.full((M.m,), float("nan"), dtype=torch.float64, device=dev)
+    r = capi.ipm_solve(M, F, x, y, **opts)
+    torch.cuda.synchronize()
+    out = (r, x.cpu().numpy(), y.cpu().numpy(), list(M.x_off))
+    F.close()
+    M.close()
+    return out
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged_small"])
+def test_ipm_matches_oracle(name, dev):
+    import torch
+    net = synth.config_network("tiny") if name == "tiny" else synth.make_network(301, 517, 63, 2, 41)
+    print(f"ipm case {name}: {(net.N, net.B, net.G, net.T)}", flush=True)
+    r, x, _, _ = _gpu_ipm([net], torch, dev)
+    print("gpu", r, flush=True)
+    ref = O.ipm_solve(net)
+    assert r["converged"] == 1 and ref["converged"]
+    assert abs(r["iterations"] - ref["iterations"]) <= 2, (r["iterations"], ref["iterations"])
+    assert abs(r["objective"] - ref["objective"]) <= 1e-6 * abs(ref["objective"])
+    assert abs(O.objective(net, x) - r["objective"]) <= 1e-9 * abs(r["objective"])
+    assert np.max(np.abs(x - ref["x"])) <= 1e-3
+
+
+def test_ipm_batch_solves_each_instance(dev):
+    """Two instances solved jointly: each instance's part is that
+    instance's optimum (the oracle solving it alone)."""
+    import torch
+    nets = [synth.config_network("tiny"), synth.make_network(20, 30, 6, 3, 12)]
+    r, x, _, offs = _gpu_ipm(nets, torch, dev)
+    assert r["converged"] == 1
+    total = 0.0
+    for k, net in enumerate(nets):
+        ref = O.ipm_solve(net)
+        assert ref["converged"]
+        xk = x[offs[k]:offs[k + 1]]
+        assert abs(O.objective(net, xk) - ref["objective"]) <= 1e-5 * abs(ref["objective"]), k
+        total += ref["objective"]
+    assert abs(r["objective"] - total) <= 1e-5 * abs(total)
+
+
+def test_ipm_inertia_correction_path(dev):
+    """A static pivot threshold (5) above some of the tiny grid's pivots makes
+    the first factorization of many iterations report static pivots: the
+    loop raises delta_w until none is reported (more factorizations than
+    iterations) and keeps making progress.  The threshold distorts the
+    method (a regularised step every iteration), so only the first 15
+    iterations are run."""
+    import torch
+    net = synth.config_network("tiny")
+    r, x, _, _ = _gpu_ipm([net], torch, dev, pivot_tol=5.0, max_iter=15)
+    assert r["iterations"] == 15 and r["factorizations"] >= r["iterations"] + 5
+    assert r["err"] < 1.0  # from 40 at the start
+
+
+def test_ipm_rejects_bad_options(dev):
+    import torch
+    from paper_2405_14032_amd import capi
+    net = synth.config_network("tiny")
+    M = capi.Model([net], device=0)
+    F = capi.Chol(M)
+    x = torch.empty(M.n, dtype=torch.float64, device=dev)
+    for bad in (dict(tol=0.0), dict(sigma=1.5), dict(tau=1.0), dict(dw_grow=1.0)):
+        with pytest.raises(capi.OpfError):
+            capi.ipm_solve(M, F, x, **bad)
+    F.close()
+    M.close()
