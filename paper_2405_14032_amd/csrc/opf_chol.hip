@@ -664,6 +664,10 @@ struct opf_chol {
   int device = -1;
   std::vector<CholInst> inst;
   double* Us = nullptr;  // G x G update block of the pg chain (largest G)
+  // the pg chain runs on a stream of its own, chunk by chunk, behind the
+  // interior fronts of the next chunk (events order the two)
+  hipStream_t cs = nullptr;
+  std::vector<hipEvent_t> evs;
   std::vector<void*> allocs;
   double flops = 0.0, flops_int = 0.0;
   int64_t factor_entries = 0, arena_entries = 0;
@@ -837,18 +841,21 @@ int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double r
   hipLaunchKernelGGL(k_fill, dim3(grid_for(P.lsize * T, 256)), dim3(256), 0, st, C.Lf, P.lsize * T);
   hipLaunchKernelGGL(k_fill, dim3(grid_for(C.csize * T, 256)), dim3(256), 0, st, C.Cf, C.csize * T);
   LAUNCH_OK("chol fill");
+  // every ramp pair up front: they land in the pg front of the period
+  // before, which the chain stream may be factoring while a later chunk's
+  // interior runs
+  if (T > 1) {
+    hipLaunchKernelGGL(k_scatter_ramp, dim3(grid_for(G, 256), T - 1), dim3(256), 0, st, kv, I.k_off, I.nnzk_p, G, 1,
+                       C.d_ramp, C.Cf, C.csize);
+    LAUNCH_OK("chol ramp scatter");
+  }
   const int nslots = (int)P.slot_dst.size();
-  for (int t0 = 0; t0 < T; t0 += C.chunk) {
+  int chunk_id = 0;
+  for (int t0 = 0; t0 < T; t0 += C.chunk, ++chunk_id) {
     const int nt = std::min(C.chunk, T - t0);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(nslots, 256), nt), dim3(256), 0, st, kv, I.k_off, I.nnzk_p, G, t0,
                        nslots, C.d_slot, C.d_kpos0, C.d_kpos1, C.Lf, P.lsize, C.Cf, C.csize);
     LAUNCH_OK("chol scatter");
-    const int r0 = std::max(t0, 1);
-    if (t0 + nt > r0) {
-      hipLaunchKernelGGL(k_scatter_ramp, dim3(grid_for(G, 256), t0 + nt - r0), dim3(256), 0, st, kv, I.k_off,
-                         I.nnzk_p, G, r0, C.d_ramp, C.Cf, C.csize);
-      LAUNCH_OK("chol ramp scatter");
-    }
     for (int h = 0; h < P.nlevels; ++h) {
       const int64_t i0 = P.lvl_items_ptr[h], i1 = P.lvl_items_ptr[h + 1];
       if (i1 > i0) {
@@ -880,30 +887,36 @@ int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double r
     hipLaunchKernelGGL(k_extend_root, dim3((G + cb - 1) / cb, nt), dim3(256), 0, st, C.dev, C.d_roots,
                        (int32_t)P.roots.size(), cb, t0, C.Cf, C.csize, C.Ar);
     LAUNCH_OK("chol pg front assembly");
-  }
-  // the pg chain over the periods
-  for (int t = 0; t < T; ++t) {
-    double* Ct = C.Cf + (int64_t)t * C.csize;
-    if (t >= 1) {
-      hipLaunchKernelGGL(k_add_chain, dim3(grid_for((int64_t)G * G, 256)), dim3(256), 0, st, F->Us, G, Ct);
-      LAUNCH_OK("chol chain add");
+    // the chunk's periods along the pg chain, on the chain stream
+    if (hipEventRecord(F->evs[chunk_id], st) != hipSuccess || hipStreamWaitEvent(F->cs, F->evs[chunk_id], 0) != hipSuccess)
+      return api_fail(OPF_EHIP, "chol: chain stream ordering");
+    for (int t = t0; t < t0 + nt; ++t) {
+      double* Ct = C.Cf + (int64_t)t * C.csize;
+      if (t >= 1) {
+        hipLaunchKernelGGL(k_add_chain, dim3(grid_for((int64_t)G * G, 256)), dim3(256), 0, F->cs, F->Us, G, Ct);
+        LAUNCH_OK("chol chain add");
+      }
+      const int u = t + 1 < T ? G : 0;
+      if (u) {
+        hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)G * G, 256)), dim3(256), 0, F->cs, F->Us, (int64_t)G * G);
+        LAUNCH_OK("chol chain clear");
+      }
+      FrontArg A;
+      A.L = Ct;
+      A.Lstride = 0;
+      A.ld = 2 * G;
+      A.p = G;
+      A.u = u;
+      A.U = F->Us;
+      A.Ustride = 0;
+      A.ldU = G;
+      CHK(factor_front(A, 1, tol, repl, npert, F->cs));
     }
-    const int u = t + 1 < T ? G : 0;
-    if (u) {
-      hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)G * G, 256)), dim3(256), 0, st, F->Us, (int64_t)G * G);
-      LAUNCH_OK("chol chain clear");
-    }
-    FrontArg A;
-    A.L = Ct;
-    A.Lstride = 0;
-    A.ld = 2 * G;
-    A.p = G;
-    A.u = u;
-    A.U = F->Us;
-    A.Ustride = 0;
-    A.ldU = G;
-    CHK(factor_front(A, 1, tol, repl, npert, st));
   }
+  // the model's stream waits for the chain
+  hipEvent_t done = F->evs.back();
+  if (hipEventRecord(done, F->cs) != hipSuccess || hipStreamWaitEvent(st, done, 0) != hipSuccess)
+    return api_fail(OPF_EHIP, "chol: chain stream join");
   return OPF_OK;
 }
 
@@ -1061,6 +1074,19 @@ int opf_chol_analyze(opf_model* model, opf_chol** out) {
         delete F;
         return rc;
       }
+      // default priority, no implicit ordering with the null stream
+      int nev = 1;
+      for (auto& C : F->inst) nev = std::max(nev, (C.plan.T + C.chunk - 1) / C.chunk + 1);
+      bool ok = hipStreamCreateWithFlags(&F->cs, hipStreamNonBlocking) == hipSuccess;
+      for (int k = 0; ok && k < nev; ++k) {
+        hipEvent_t e = nullptr;
+        ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        if (ok) F->evs.push_back(e);
+      }
+      if (!ok) {
+        opf_chol_destroy(F);
+        return api_fail(OPF_EHIP, "chol: stream or event creation failed");
+      }
     } else {
       for (auto& C : F->inst) {
         C.chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(C.plan.T, arena_budget() / (C.plan.usize * 8)));
@@ -1081,6 +1107,9 @@ int opf_chol_analyze(opf_model* model, opf_chol** out) {
 void opf_chol_destroy(opf_chol* chol) {
   if (!chol) return;
   if (chol->device >= 0) (void)hipSetDevice(chol->device);
+  if (chol->cs) (void)hipStreamSynchronize(chol->cs);
+  for (hipEvent_t e : chol->evs) (void)hipEventDestroy(e);
+  if (chol->cs) (void)hipStreamDestroy(chol->cs);
   release(chol);
   delete chol;
 }
