@@ -357,6 +357,11 @@ int opf_chol_factor(opf_chol *chol, const double *kvals, double pivot_tol,
  * the same array).  Enqueued on the model's stream; uses the factor
  * object's work vectors, so solves on one object must not overlap. */
 int opf_chol_solve(opf_chol *chol, const double *b, double *x);
+/* By default a solve is recorded once into a HIP graph per (b, x) pointer
+ * pair and replayed (the launch sequence is fixed for the object; the
+ * graph reads the factor's current values).  enable = 0 launches the
+ * kernels one by one instead. */
+int opf_chol_set_graph(opf_chol *chol, int enable);
 
 /* ---- the lifted-KKT interior-point loop (Sec. III-B) ----
  *

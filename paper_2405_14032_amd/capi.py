@@ -125,6 +125,7 @@ _SIGS = {
     "opf_chol_tree": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "opf_chol_factor": (C.c_int, [_vp, _vp, C.c_double, C.c_double, _vp]),
     "opf_chol_solve": (C.c_int, [_vp, _vp, _vp]),
+    "opf_chol_set_graph": (C.c_int, [_vp, C.c_int]),
     "opf_ipm_default_options": (None, [C.POINTER(opf_ipm_options)]),
     "opf_ipm_solve": (C.c_int, [_vp, _vp, C.POINTER(opf_ipm_options), _vp, _vp, C.POINTER(opf_ipm_result)]),
     "opf_set_timing": (C.c_int, [_vp, C.c_int]),
@@ -412,6 +413,9 @@ class Chol:
 
     def solve(self, b, x):
         check(opf_chol_solve(self.h, _ptr(b), _ptr(x)), "opf_chol_solve")
+
+    def set_graph(self, enable: bool):
+        check(opf_chol_set_graph(self.h, int(enable)), "opf_chol_set_graph")
 
 
 def ipm_options(**kw) -> opf_ipm_options:

@@ -35,6 +35,7 @@ namespace {
 constexpr int kSmall = 64;   // largest front factored in LDS by one wavefront
 constexpr int kNB = 64;      // panel width of the blocked fronts
 constexpr int kTile = 128;   // trailing-update tile (8 x 8 outputs per thread)
+constexpr int kChainCols = 128;  // column chunk of the chain's L21 z
 
 // Device view of one instance's plan.
 struct CDev {
@@ -240,6 +241,7 @@ __global__ void __launch_bounds__(64) k_diag(FrontArg A, int32_t k0, int32_t kb,
 // against the factored diagonal block (read-only here).
 __global__ void __launch_bounds__(256) k_panel(FrontArg A, int32_t k0, int32_t kb) {
   __shared__ double Dg[kNB * (kNB + 1)];
+  __shared__ double rdg[kNB];
   constexpr int S = kNB + 1;
   double* L = A.L + (int64_t)blockIdx.y * A.Lstride;
   const int64_t ld = A.ld;
@@ -249,6 +251,7 @@ __global__ void __launch_bounds__(256) k_panel(FrontArg A, int32_t k0, int32_t k
     const int j = e / kb, i = e % kb;
     if (i >= j) Dg[j * S + i] = L[(int64_t)(k0 + j) * ld + k0 + i];
   }
+  if (tid < kb) rdg[tid] = 1.0 / L[(int64_t)(k0 + tid) * ld + k0 + tid];
   __syncthreads();
   const int r = k0 + kb + (int)blockIdx.x * (int)blockDim.x + tid;
   if (r >= rows) return;
@@ -261,7 +264,7 @@ __global__ void __launch_bounds__(256) k_panel(FrontArg A, int32_t k0, int32_t k
       double sacc = x[j];
 #pragma unroll
       for (int l = 0; l < j; ++l) sacc -= x[l] * Dg[l * S + j];
-      x[j] = sacc / Dg[j * S + j];
+      x[j] = sacc * rdg[j];
     }
   }
 #pragma unroll
@@ -508,9 +511,12 @@ __global__ void __launch_bounds__(256) k_fwd_panel(const double* __restrict__ Lb
   }
   __syncthreads();
   if (tid < 64) {
+    // lane i holds entry i and the reciprocal of its diagonal; step k
+    // broadcasts entry k and its reciprocal (uniform lane reads)
     double vi = tid < kb ? y[k0 + tid] : 0.0;
+    const double ri = tid < kb ? 1.0 / Tr[tid * 65 + tid] : 0.0;
     for (int k = 0; k < kb; ++k) {
-      const double xk = __shfl(vi, k) / Tr[k * 65 + k];
+      const double xk = lane_bcast(vi, k) * lane_bcast(ri, k);
       if (tid == k) vi = xk;
       else if (tid > k && tid < kb) vi -= Tr[k * 65 + tid] * xk;
     }
@@ -524,6 +530,27 @@ __global__ void __launch_bounds__(256) k_fwd_panel(const double* __restrict__ Lb
     for (int l = 0; l < kb; ++l) acc += L[(int64_t)(k0 + l) * ld + i] * xs[l];
     y[i] -= acc;
   }
+}
+
+// w = L21 z with the columns split over chunks of cc (grid: row blocks x
+// chunks); partial sums part[chunk][u], summed in chunk order next.
+__global__ void __launch_bounds__(256) k_gemv_part(const double* __restrict__ L, int32_t ld, int32_t p, int32_t u,
+                                                   const double* __restrict__ z, int32_t cc,
+                                                   double* __restrict__ part) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= u) return;
+  const int k0 = (int)blockIdx.y * cc, k1 = min(p, k0 + cc);
+  double acc = 0.0;
+  for (int k = k0; k < k1; ++k) acc += L[(int64_t)k * ld + p + i] * z[k];
+  part[(int64_t)blockIdx.y * u + i] = acc;
+}
+
+__global__ void k_gemv_sum(const double* __restrict__ part, int32_t nch, int32_t u, double* __restrict__ w) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= u) return;
+  double acc = 0.0;
+  for (int c = 0; c < nch; ++c) acc += part[(int64_t)c * u + i];
+  w[i] = acc;
 }
 
 // Forward, w[i] (+)= sum_k L21[i, k] z[k] over the u update rows (rows p ..
@@ -583,8 +610,9 @@ __global__ void __launch_bounds__(256) k_bwd_panel(const double* __restrict__ Lb
   __syncthreads();
   if (tid < 64) {
     double vj = tid < kb ? z[k0 + tid] : 0.0;
+    const double rj = tid < kb ? 1.0 / Tr[tid * 65 + tid] : 0.0;
     for (int k = kb - 1; k >= 0; --k) {
-      const double xk = __shfl(vj, k) / Tr[k * 65 + k];
+      const double xk = lane_bcast(vj, k) * lane_bcast(rj, k);
       if (tid == k) vj = xk;
       else if (tid < k) vj -= Tr[tid * 65 + k] * xk;
     }
@@ -652,6 +680,7 @@ struct CholInst {
   int64_t *d_loff = nullptr, *d_uoff = nullptr, *d_woff = nullptr, *d_rowptr = nullptr, *d_kidptr = nullptr,
           *d_slot = nullptr;
   double *Lf = nullptr, *Cf = nullptr, *Ar = nullptr, *W = nullptr, *Wc = nullptr, *Y = nullptr, *Z = nullptr;
+  double* Gp = nullptr;  // column-chunk partials of the chain's L21 z
   std::vector<int64_t> woff;  // per-front offsets of the forward update vectors
   int64_t csize = 0, wsize = 0;
   int32_t chunk = 1, nlarge = 0;
@@ -668,6 +697,13 @@ struct opf_chol {
   // interior fronts of the next chunk (events order the two)
   hipStream_t cs = nullptr;
   std::vector<hipEvent_t> evs;
+  // the solve recorded once into a HIP graph per (b, x) pair and replayed
+  // on the model's stream (its launch sequence is fixed for the object)
+  hipStream_t gs = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const double* gb = nullptr;
+  double* gx = nullptr;
+  bool use_graph = true;
   std::vector<void*> allocs;
   double flops = 0.0, flops_int = 0.0;
   int64_t factor_entries = 0, arena_entries = 0;
@@ -761,6 +797,7 @@ int setup_device(opf_chol* F, CholInst& C) {
   CHK(dalloc(F, G * T, &C.Wc));
   CHK(dalloc(F, (int64_t)P.n_p * T, &C.Y));
   CHK(dalloc(F, (int64_t)P.n_p * T, &C.Z));
+  CHK(dalloc(F, (int64_t)((G + kChainCols - 1) / kChainCols) * G, &C.Gp));
   CDev& D = C.dev;
   D.node_f = C.d_node_f;
   D.node_p = C.d_node_p;
@@ -980,9 +1017,13 @@ int solve_inst(CholInst& C, const double* b, double* x, hipStream_t st) {
     const int64_t o = (int64_t)t * np + P.n_int;
     if (t >= 1) hipLaunchKernelGGL(k_sub, dim3((G + 255) / 256), dim3(256), 0, st, C.Y + o, (const double*)(C.Wc + (int64_t)(t - 1) * G), G);
     CHK(fwd_tri(Ct, 0, 2 * G, G, C.Y + o, C.Z + o, 0, 1, st));
-    if (t + 1 < T)
-      hipLaunchKernelGGL(k_fwd_gemv, dim3((G + 255) / 256, 1), dim3(256), 0, st, Ct, (int64_t)0, 2 * G, G, G,
-                         (const double*)(C.Z + o), (int64_t)0, C.Wc + (int64_t)t * G, (int64_t)0, 0);
+    if (t + 1 < T) {
+      const int nch = (G + kChainCols - 1) / kChainCols;
+      hipLaunchKernelGGL(k_gemv_part, dim3((G + 255) / 256, nch), dim3(256), 0, st, Ct, 2 * G, G, G,
+                         (const double*)(C.Z + o), kChainCols, C.Gp);
+      hipLaunchKernelGGL(k_gemv_sum, dim3((G + 255) / 256), dim3(256), 0, st, (const double*)C.Gp, nch, G,
+                         C.Wc + (int64_t)t * G);
+    }
     LAUNCH_OK("chol forward chain");
   }
   // backward along the pg chain
@@ -1077,7 +1118,8 @@ int opf_chol_analyze(opf_model* model, opf_chol** out) {
       // default priority, no implicit ordering with the null stream
       int nev = 1;
       for (auto& C : F->inst) nev = std::max(nev, (C.plan.T + C.chunk - 1) / C.chunk + 1);
-      bool ok = hipStreamCreateWithFlags(&F->cs, hipStreamNonBlocking) == hipSuccess;
+      bool ok = hipStreamCreateWithFlags(&F->cs, hipStreamNonBlocking) == hipSuccess &&
+                hipStreamCreateWithFlags(&F->gs, hipStreamNonBlocking) == hipSuccess;
       for (int k = 0; ok && k < nev; ++k) {
         hipEvent_t e = nullptr;
         ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
@@ -1108,8 +1150,11 @@ void opf_chol_destroy(opf_chol* chol) {
   if (!chol) return;
   if (chol->device >= 0) (void)hipSetDevice(chol->device);
   if (chol->cs) (void)hipStreamSynchronize(chol->cs);
+  if (chol->device >= 0) (void)hipDeviceSynchronize();
+  if (chol->gexec) (void)hipGraphExecDestroy(chol->gexec);
   for (hipEvent_t e : chol->evs) (void)hipEventDestroy(e);
   if (chol->cs) (void)hipStreamDestroy(chol->cs);
+  if (chol->gs) (void)hipStreamDestroy(chol->gs);
   release(chol);
   delete chol;
 }
@@ -1170,7 +1215,44 @@ int opf_chol_solve(opf_chol* F, const double* b, double* x) {
   if (F->device < 0) return api_fail(OPF_ENODEV, "model is host-only");
   if (hipSetDevice(F->device) != hipSuccess) return api_fail(OPF_EHIP, "hipSetDevice failed");
   hipStream_t st = model_stream(F->model);
-  for (auto& C : F->inst) CHK(solve_inst(C, b, x, st));
+  if (!F->use_graph) {
+    for (auto& C : F->inst) CHK(solve_inst(C, b, x, st));
+    return OPF_OK;
+  }
+  if (!F->gexec || F->gb != b || F->gx != x) {
+    if (F->gexec) {
+      (void)hipStreamSynchronize(st);
+      (void)hipGraphExecDestroy(F->gexec);
+      F->gexec = nullptr;
+    }
+    if (hipStreamBeginCapture(F->gs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return api_fail(OPF_EHIP, "chol: solve capture");
+    int rc = OPF_OK;
+    for (auto& C : F->inst)
+      if (rc == OPF_OK) rc = solve_inst(C, b, x, F->gs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(F->gs, &g);
+    if (rc != OPF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess || !g) return api_fail(OPF_EHIP, "chol: solve capture end");
+    const hipError_t ei = hipGraphInstantiate(&F->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      F->gexec = nullptr;
+      return api_fail(OPF_EHIP, std::string("chol: solve graph: ") + hipGetErrorString(ei));
+    }
+    F->gb = b;
+    F->gx = x;
+  }
+  if (hipGraphLaunch(F->gexec, st) != hipSuccess) return api_fail(OPF_EHIP, "chol: solve graph launch");
+  return OPF_OK;
+}
+
+int opf_chol_set_graph(opf_chol* F, int enable) {
+  if (!F) return api_fail(OPF_EINVAL, "chol is NULL");
+  F->use_graph = enable != 0;
   return OPF_OK;
 }
 

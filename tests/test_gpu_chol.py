@@ -216,3 +216,45 @@ def test_refactor_and_solve_in_place(dev):
     _check(nets, inps, bx.cpu().numpy(), "well", "hub in place")
     F.close()
     M.close()
+
+
+def test_solve_graph_replays_match_eager(dev):
+    """The solve replayed from its HIP graph (the default) five times, with
+    eager work and a refactorization between replays, each bitwise equal to
+    the eager solve of the same factor; a new (b, x) pair re-records."""
+    import torch
+    from paper_2405_14032_amd import capi
+    nets = [synth.make_network(301, 517, 63, 3, 41)]
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    B = torch.empty(M.n, dtype=torch.float64, device=dev)
+    xg = torch.empty(M.n, dtype=torch.float64, device=dev)
+    xe = torch.empty(M.n, dtype=torch.float64, device=dev)
+    for rep in range(5):
+        inps = _inputs(nets, "well" if rep % 2 == 0 else "wide", 40 + rep)
+        e = lambda k: torch.empty(k, dtype=torch.float64, device=dev)
+        jv, hv, kv = e(M.nnz_jac), e(M.nnz_hess), e(M.nnz_kkt)
+        M.eval_jhk(t(inps[0]["x"]), t(inps[0]["lam"]), 1.0, t(inps[0]["diag_x"]), t(inps[0]["dcon"]), jv, hv, kv)
+        npert = torch.zeros(1, dtype=torch.int32, device=dev)
+        F.factor(kv, 0.0, 1.0, npert)
+        B.copy_(t(inps[0]["b"]))
+        xg.fill_(float("nan"))
+        F.set_graph(True)
+        F.solve(B, xg)  # recorded on the first pass, replayed after
+        _ = (B * 2.0).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        xe.fill_(float("nan"))
+        F.set_graph(False)
+        F.solve(B, xe)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe), rep
+    # a different output array re-records the graph
+    F.set_graph(True)
+    x2 = torch.empty(M.n, dtype=torch.float64, device=dev)
+    F.solve(B, x2)
+    torch.cuda.synchronize()
+    assert torch.equal(x2, xe)
+    F.close()
+    M.close()
