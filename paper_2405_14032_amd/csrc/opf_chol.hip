@@ -292,7 +292,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_update(FrontArg A, int32_t k0, int32_t kb, int32_t r0, int32_t cmax, int32_t dnext, double tol, double repl,
          int32_t* __restrict__ npert) {
   constexpr int KC = 16;
-  __shared__ double Pi[KC][kTile], Pj[KC][kTile];
+  constexpr int NLD = KC * kTile / 256;  // panel values per thread per chunk and side
+  // two LDS buffers: the next chunk is loaded into registers while the
+  // matrix cores work on the current one
+  __shared__ double Pi[2][KC][kTile], Pj[2][KC][kTile];
   const int rows = A.p + A.u;
   const int R = (rows - r0 + kTile - 1) / kTile;
   int x = (int)blockIdx.x, tj = 0;
@@ -316,23 +319,41 @@ k_update(FrontArg A, int32_t k0, int32_t kb, int32_t r0, int32_t cmax, int32_t d
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[c][r] = (dbl4){0.0, 0.0, 0.0, 0.0};
   const int lr = lane & 15, lk = lane >> 4;
-  for (int l0 = 0; l0 < kb; l0 += KC) {
+  double ri[NLD], rj[NLD];
+  auto fetch = [&](int l0) {
     const int lb = min(KC, kb - l0);
-    __syncthreads();
-    for (int e = tid; e < KC * kTile; e += (int)blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int e = tid + q * 256;
       const int l = e / kTile, rr = e % kTile;
       const int64_t col = (int64_t)(k0 + l0 + l) * ld;
-      Pi[l][rr] = (l < lb && i0 + rr < rows) ? L[col + i0 + rr] : 0.0;
-      Pj[l][rr] = (l < lb && j0 + rr < cend) ? L[col + j0 + rr] : 0.0;
+      ri[q] = (l < lb && i0 + rr < rows) ? L[col + i0 + rr] : 0.0;
+      rj[q] = (l < lb && j0 + rr < cend) ? L[col + j0 + rr] : 0.0;
     }
-    __syncthreads();
+  };
+  auto park = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int e = tid + q * 256;
+      Pi[buf][e / kTile][e % kTile] = ri[q];
+      Pj[buf][e / kTile][e % kTile] = rj[q];
+    }
+  };
+  fetch(0);
+  park(0);
+  __syncthreads();
+  int buf = 0;
+  for (int l0 = 0; l0 < kb; l0 += KC) {
+    const int lb = min(KC, kb - l0);
+    const bool more = l0 + KC < kb;
+    if (more) fetch(l0 + KC);
     if (!skip) {
       for (int k4 = 0; k4 < lb; k4 += 4) {
         double aj[4], bi[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          aj[q] = Pj[k4 + lk][wc * 64 + q * 16 + lr];
-          bi[q] = Pi[k4 + lk][wr * 64 + q * 16 + lr];
+          aj[q] = Pj[buf][k4 + lk][wc * 64 + q * 16 + lr];
+          bi[q] = Pi[buf][k4 + lk][wr * 64 + q * 16 + lr];
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -340,6 +361,9 @@ k_update(FrontArg A, int32_t k0, int32_t kb, int32_t r0, int32_t cmax, int32_t d
           for (int r = 0; r < 4; ++r) acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj[c], bi[r], acc[c][r], 0, 0, 0);
       }
     }
+    if (more) park(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
   if (!skip) {
 #pragma unroll
