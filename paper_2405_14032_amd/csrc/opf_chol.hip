@@ -298,15 +298,23 @@ k_update(FrontArg A, int32_t k0, int32_t kb, int32_t r0, int32_t cmax, int32_t d
   __shared__ double Pi[2][KC][kTile], Pj[2][KC][kTile];
   const int rows = A.p + A.u;
   const int R = (rows - r0 + kTile - 1) / kTile;
-  int x = (int)blockIdx.x, tj = 0;
+  // blocks are dealt round-robin to the 8 XCDs in launch order; give each
+  // XCD a contiguous run of (period, tile) items so that neighbouring tiles,
+  // which share panel slices, meet in the same L2
+  const int ntl = (int)gridDim.x, total = ntl * (int)gridDim.y;
+  int item = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  const int q8 = total >> 3;
+  if (item < (q8 << 3)) item = (item & 7) * q8 + (item >> 3);
+  const int per = item / ntl;
+  int x = item % ntl, tj = 0;
   while (x >= R - tj) {
     x -= R - tj;
     ++tj;
   }
   const int ti = tj + x;
   const int cend = min(cmax, rows);
-  double* L = A.L + (int64_t)blockIdx.y * A.Lstride;
-  double* U = A.U + (int64_t)blockIdx.y * A.Ustride;
+  double* L = A.L + (int64_t)per * A.Lstride;
+  double* U = A.U + (int64_t)per * A.Ustride;
   const int64_t ld = A.ld;
   const int i0 = r0 + ti * kTile, j0 = r0 + tj * kTile;
   const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -380,7 +388,7 @@ k_update(FrontArg A, int32_t k0, int32_t kb, int32_t r0, int32_t cmax, int32_t d
         }
       }
   }
-  if (dnext > 0 && blockIdx.x == 0) {
+  if (dnext > 0 && x == 0 && tj == 0) {
     __syncthreads();
     if (wv == 0) {
       double a[64];
