@@ -120,11 +120,26 @@ __global__ void __launch_bounds__(256) k_extend(CDev D, const int32_t* __restric
     const int b0 = lower_bound_i32(rel, uc, c0), b1 = lower_bound_i32(rel, uc, c1);
     for (int b = b0; b < b1; ++b) {
       const int j = rel[b];
-      for (int a = b + (int)threadIdx.x; a < uc; a += (int)blockDim.x) {
-        const int i = rel[a];
-        const double v = Uc[(int64_t)b * uc + a];
-        if (j < p) L[(int64_t)j * ld + i] += v;
-        else U[(int64_t)(j - p) * u + (i - p)] += v;
+      double* dcol = j < p ? L + (int64_t)j * ld : U + (int64_t)(j - p) * u - p;  // row i at dcol[i]
+      const double* scol = Uc + (int64_t)b * uc;
+      // four entries per lane in flight: every load before any store (the
+      // child's entries of one column land on distinct parent entries)
+      constexpr int UN = 4;
+      const int bd = (int)blockDim.x;
+      for (int a = b + (int)threadIdx.x; a < uc; a += UN * bd) {
+        int ii[UN];
+        double vv[UN], pv[UN];
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+          const int aa = a + k * bd;
+          ii[k] = aa < uc ? rel[aa] : -1;
+          vv[k] = aa < uc ? scol[aa] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < UN; ++k) pv[k] = ii[k] >= 0 ? dcol[ii[k]] : 0.0;
+#pragma unroll
+        for (int k = 0; k < UN; ++k)
+          if (ii[k] >= 0) dcol[ii[k]] = pv[k] + vv[k];
       }
     }
     __syncthreads();
