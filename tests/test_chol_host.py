@@ -14,6 +14,9 @@ CASES = {
     "tiny": lambda: synth.config_network("tiny"),
     "ragged": lambda: synth.make_network(301, 517, 63, 2, 41),
     "hub": lambda: pins.hub_network(),
+    "single_period": lambda: synth.make_network(57, 80, 11, 1, 73),
+    "isolated_bus": lambda: pins.manual_network(4, [0, 1], [1, 2], [0.01, 0.02], [0.1, 0.2], [0.02, 0.01], [0, 2], T=3,
+                                                pd=np.full((3, 4), 0.3)),
     "one_bus": lambda: pins.manual_network(1, [], [], [], [], [], [0], T=3, pd=np.full((3, 1), 0.4)),
     "parallel": lambda: pins.manual_network(4, [0, 0, 1, 1, 2], [1, 1, 0, 2, 3], [0.01] * 5,
                                             [0.1, 0.2, 0.15, 0.1, 0.3], [0.02] * 5, [1, 1, 3], T=3,

@@ -33,6 +33,9 @@ CASES = {
                                              [0.1, 0.2, 0.15, 0.1, 0.3], [0.02] * 5, [1, 1, 3], T=3,
                                              pd=np.full((3, 4), 0.2))],
     "hub": lambda: [pins.hub_network()],
+    "single_period": lambda: [synth.make_network(57, 80, 11, 1, 73)],
+    "isolated_bus": lambda: [pins.manual_network(4, [0, 1], [1, 2], [0.01, 0.02], [0.1, 0.2], [0.02, 0.01], [0, 2], T=3,
+                                                 pd=np.full((3, 4), 0.3))],
     "batched": lambda: [synth.make_network(31, 45, 7, 3, 71), synth.make_network(14, 20, 5, 5, 72),
                         synth.make_network(57, 80, 11, 2, 73)],
 }
