@@ -300,7 +300,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // Region: rows [r0, p+u) x columns [r0, min(cmax, p+u)), lower part, in
 // 128 x 128 tiles enumerated column by column; panel columns [k0, k0+kb),
-// kb <= 128.  With dnext > 0, block 0 (the tile holding rows and columns
+// kb <= 256.  With dnext > 0, block 0 (the tile holding rows and columns
 // [r0, r0+128)) then factors the next diagonal block [r0, r0+dnext) in
 // place, which the next panel needs.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
@@ -891,26 +891,45 @@ int launch_update(const FrontArg& A, int nt, int k0, int kb, int r0, int cmax, i
   return OPF_OK;
 }
 
+// 128 columns [k, k+128) whose diagonal block [k, k+64) is factored: two
+// 64-column sub-panels with the first's update of the second's columns in
+// between (the second's diagonal factored by that update).
+int sub_panel128(const FrontArg& A, int nt, int k, double tol, double repl, int32_t* npert, hipStream_t st) {
+  const int rows = A.p + A.u;
+  const int ka = std::min(64, A.p - k);
+  const int kbB = std::min(64, A.p - k - ka);
+  if (rows > k + ka) {
+    hipLaunchKernelGGL(k_panel, dim3((rows - k - ka + 255) / 256, nt), dim3(256), 0, st, A, k, ka);
+    LAUNCH_OK("chol panel");
+  }
+  if (kbB > 0) {
+    const int r1 = k + ka;
+    CHK(launch_update(A, nt, k, ka, r1, r1 + kbB, kbB, tol, repl, npert, st));
+    if (rows > r1 + kbB) {
+      hipLaunchKernelGGL(k_panel, dim3((rows - r1 - kbB + 255) / 256, nt), dim3(256), 0, st, A, r1, kbB);
+      LAUNCH_OK("chol panel");
+    }
+  }
+  return OPF_OK;
+}
+
 int factor_front(const FrontArg& A, int nt, double tol, double repl, int32_t* npert, hipStream_t st) {
   const int rows = A.p + A.u;
   hipLaunchKernelGGL(k_diag, dim3(nt), dim3(64), 0, st, A, 0, std::min(64, A.p), tol, repl, npert);
   LAUNCH_OK("chol diagonal block");
-  for (int k0 = 0; k0 < A.p; k0 += 128) {
-    const int ka = std::min(64, A.p - k0);
-    const int kbB = std::min(64, A.p - k0 - ka);  // second sub-panel (0 if none)
-    if (rows > k0 + ka) {
-      hipLaunchKernelGGL(k_panel, dim3((rows - k0 - ka + 255) / 256, nt), dim3(256), 0, st, A, k0, ka);
-      LAUNCH_OK("chol panel");
+  // 256-column steps: two 128-column halves (the first's update of the
+  // second's columns in between), then one trailing update with the
+  // 256-wide panel; every update launch also factors the next diagonal block
+  for (int k0 = 0; k0 < A.p; k0 += 256) {
+    CHK(sub_panel128(A, nt, k0, tol, repl, npert, st));
+    const int kh = std::min(128, A.p - k0);
+    const int kc2 = std::min(128, A.p - k0 - kh);
+    if (kc2 > 0) {
+      const int r1 = k0 + kh;
+      CHK(launch_update(A, nt, k0, kh, r1, r1 + kc2, std::min(64, kc2), tol, repl, npert, st));
+      CHK(sub_panel128(A, nt, r1, tol, repl, npert, st));
     }
-    if (kbB > 0) {
-      const int r1 = k0 + ka;
-      CHK(launch_update(A, nt, k0, ka, r1, r1 + kbB, kbB, tol, repl, npert, st));
-      if (rows > r1 + kbB) {
-        hipLaunchKernelGGL(k_panel, dim3((rows - r1 - kbB + 255) / 256, nt), dim3(256), 0, st, A, r1, kbB);
-        LAUNCH_OK("chol panel");
-      }
-    }
-    const int kb = ka + kbB, r0 = k0 + kb;
+    const int kb = kh + kc2, r0 = k0 + kb;
     const int dnext = r0 < A.p ? std::min(64, A.p - r0) : 0;
     CHK(launch_update(A, nt, k0, kb, r0, rows, dnext, tol, repl, npert, st));
   }
