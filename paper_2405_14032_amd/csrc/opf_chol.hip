@@ -36,6 +36,7 @@ constexpr int kSmall = 64;   // largest front factored in LDS by one wavefront
 constexpr int kNB = 64;      // panel width of the blocked fronts
 constexpr int kTile = 128;   // trailing-update tile (8 x 8 outputs per thread)
 constexpr int kChainCols = 128;  // column chunk of the chain's L21 z
+constexpr int kStep = 1024;      // columns per trailing update of a blocked front
 
 // Device view of one instance's plan.
 struct CDev {
@@ -300,7 +301,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // Region: rows [r0, p+u) x columns [r0, min(cmax, p+u)), lower part, in
 // 128 x 128 tiles enumerated column by column; panel columns [k0, k0+kb),
-// kb <= 256.  With dnext > 0, block 0 (the tile holding rows and columns
+// kb <= 1024.  With dnext > 0, block 0 (the tile holding rows and columns
 // [r0, r0+128)) then factors the next diagonal block [r0, r0+dnext) in
 // place, which the next panel needs.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
@@ -891,24 +892,31 @@ int launch_update(const FrontArg& A, int nt, int k0, int kb, int r0, int cmax, i
   return OPF_OK;
 }
 
-// 128 columns [k, k+128) whose diagonal block [k, k+64) is factored: two
-// 64-column sub-panels with the first's update of the second's columns in
-// between (the second's diagonal factored by that update).
-int sub_panel128(const FrontArg& A, int nt, int k, double tol, double repl, int32_t* npert, hipStream_t st) {
+// Columns [k, k+w) of a front whose diagonal block [k, k+64) is factored
+// already, w a power of two >= 64: recursively the first half, the first
+// half's update of the second half's columns (which also factors the second
+// half's first diagonal block), the second half.  The rows below the block
+// get their share of the panel through the panel kernels; the trailing
+// columns are left to the caller.
+int factor_cols(const FrontArg& A, int nt, int k, int w, double tol, double repl, int32_t* npert, hipStream_t st) {
   const int rows = A.p + A.u;
-  const int ka = std::min(64, A.p - k);
-  const int kbB = std::min(64, A.p - k - ka);
-  if (rows > k + ka) {
-    hipLaunchKernelGGL(k_panel, dim3((rows - k - ka + 255) / 256, nt), dim3(256), 0, st, A, k, ka);
-    LAUNCH_OK("chol panel");
-  }
-  if (kbB > 0) {
-    const int r1 = k + ka;
-    CHK(launch_update(A, nt, k, ka, r1, r1 + kbB, kbB, tol, repl, npert, st));
-    if (rows > r1 + kbB) {
-      hipLaunchKernelGGL(k_panel, dim3((rows - r1 - kbB + 255) / 256, nt), dim3(256), 0, st, A, r1, kbB);
+  if (k >= A.p) return OPF_OK;
+  if (w == 64) {
+    const int kb = std::min(64, A.p - k);
+    if (rows > k + kb) {
+      hipLaunchKernelGGL(k_panel, dim3((rows - k - kb + 255) / 256, nt), dim3(256), 0, st, A, k, kb);
       LAUNCH_OK("chol panel");
     }
+    return OPF_OK;
+  }
+  const int h = w / 2;
+  CHK(factor_cols(A, nt, k, h, tol, repl, npert, st));
+  const int kh = std::min(h, A.p - k);
+  const int k2 = std::min(h, A.p - k - kh);
+  if (k2 > 0) {
+    const int r1 = k + kh;
+    CHK(launch_update(A, nt, k, kh, r1, r1 + k2, std::min(64, k2), tol, repl, npert, st));
+    CHK(factor_cols(A, nt, r1, h, tol, repl, npert, st));
   }
   return OPF_OK;
 }
@@ -917,19 +925,12 @@ int factor_front(const FrontArg& A, int nt, double tol, double repl, int32_t* np
   const int rows = A.p + A.u;
   hipLaunchKernelGGL(k_diag, dim3(nt), dim3(64), 0, st, A, 0, std::min(64, A.p), tol, repl, npert);
   LAUNCH_OK("chol diagonal block");
-  // 256-column steps: two 128-column halves (the first's update of the
-  // second's columns in between), then one trailing update with the
-  // 256-wide panel; every update launch also factors the next diagonal block
-  for (int k0 = 0; k0 < A.p; k0 += 256) {
-    CHK(sub_panel128(A, nt, k0, tol, repl, npert, st));
-    const int kh = std::min(128, A.p - k0);
-    const int kc2 = std::min(128, A.p - k0 - kh);
-    if (kc2 > 0) {
-      const int r1 = k0 + kh;
-      CHK(launch_update(A, nt, k0, kh, r1, r1 + kc2, std::min(64, kc2), tol, repl, npert, st));
-      CHK(sub_panel128(A, nt, r1, tol, repl, npert, st));
-    }
-    const int kb = kh + kc2, r0 = k0 + kb;
+  // kStep-column steps, each factored recursively, then one trailing update
+  // with the kStep-wide panel; every update launch also factors the next
+  // diagonal block
+  for (int k0 = 0; k0 < A.p; k0 += kStep) {
+    CHK(factor_cols(A, nt, k0, kStep, tol, repl, npert, st));
+    const int kb = std::min(kStep, A.p - k0), r0 = k0 + kb;
     const int dnext = r0 < A.p ? std::min(64, A.p - r0) : 0;
     CHK(launch_update(A, nt, k0, kb, r0, rows, dnext, tol, repl, npert, st));
   }
