@@ -37,6 +37,7 @@ constexpr int kNB = 64;      // panel width of the blocked fronts
 constexpr int kTile = 128;   // trailing-update tile (8 x 8 outputs per thread)
 constexpr int kChainCols = 128;  // column chunk of the chain's L21 z
 constexpr int kStep = 1024;      // columns per trailing update of a blocked front
+constexpr int kBwdCols = 16;     // earlier columns updated per block of a backward panel
 
 // Device view of one instance's plan.
 struct CDev {
@@ -640,7 +641,7 @@ __global__ void __launch_bounds__(256) k_bwd_gemv(const double* __restrict__ Lb,
 // panel's triangle from z (panel entries only read here), block 0 stores x
 // in y, and each block's 4 wavefronts subtract the panel's contribution
 // from their columns j < k0 of z (one wavefront per column, lanes over the
-// panel's rows).  Grid (column blocks of 64, periods).
+// panel's rows).  Grid (column blocks of kBwdCols, periods).
 __global__ void __launch_bounds__(256) k_bwd_panel(const double* __restrict__ Lb, int64_t Lstride, int32_t ld,
                                                    int32_t p, int32_t k0, double* __restrict__ yb,
                                                    double* __restrict__ zb, int64_t ystride) {
@@ -668,8 +669,8 @@ __global__ void __launch_bounds__(256) k_bwd_panel(const double* __restrict__ Lb
     if (blockIdx.x == 0 && tid < kb) y[k0 + tid] = vj;
   }
   __syncthreads();
-  const int jb = (int)blockIdx.x * 64;
-  for (int j = jb + wv; j < min(jb + 64, k0); j += 4) {
+  const int jb = (int)blockIdx.x * kBwdCols;
+  for (int j = jb + wv; j < min(jb + kBwdCols, k0); j += 4) {
     double acc = lane < kb ? L[(int64_t)j * ld + k0 + lane] * xs[lane] : 0.0;
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) z[j] -= acc;
@@ -1041,8 +1042,8 @@ int fwd_tri(const double* L, int64_t Ls, int ld, int p, double* y, double* z, in
 int bwd_tri(const double* L, int64_t Ls, int ld, int p, double* y, double* z, int64_t ys, int nper,
             hipStream_t st) {
   for (int k0 = ((p - 1) / 64) * 64; k0 >= 0; k0 -= 64)
-    hipLaunchKernelGGL(k_bwd_panel, dim3(std::max(1, (k0 + 63) / 64), nper), dim3(256), 0, st, L, Ls, ld, p, k0, y,
-                       z, ys);
+    hipLaunchKernelGGL(k_bwd_panel, dim3(std::max(1, (k0 + kBwdCols - 1) / kBwdCols), nper), dim3(256), 0, st, L,
+                       Ls, ld, p, k0, y, z, ys);
   LAUNCH_OK("chol backward triangle");
   return OPF_OK;
 }
