@@ -347,9 +347,12 @@ int opf_chol_tree(const opf_chol *chol, int32_t inst, int32_t *perm,
  * order of opf_kkt_structure).  A pivot d (the diagonal entry after the
  * updates of the columns before it) with !(d > pivot_tol) is replaced by
  * pivot_repl (> 0) and counted into *npert (device int32, overwritten).
- * Enqueued on the model's stream; the factor stays in the opf_chol object.
- * Errors: OPF_EINVAL (NULL, pivot_repl not > 0), OPF_ENODEV (host-only
- * model), OPF_EHIP. */
+ * Enqueued on the model's stream: the work of the call starts after what
+ * is already queued there and later work queued there sees the finished
+ * factor (internally the pg chain runs on a stream of the object's own,
+ * ordered by events and joined back into the model's stream).  The factor
+ * stays in the opf_chol object.  Errors: OPF_EINVAL (NULL, pivot_repl not
+ * > 0), OPF_ENODEV (host-only model), OPF_EHIP. */
 int opf_chol_factor(opf_chol *chol, const double *kvals, double pivot_tol,
                     double pivot_repl, int32_t *npert);
 
