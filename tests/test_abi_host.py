@@ -211,3 +211,19 @@ def test_host_kkt_pattern_hub():
     rp, ci = M.kkt_structure_host()
     orp, oci = _oracle_pattern(net, 62)
     assert np.array_equal(rp, orp) and np.array_equal(ci.astype(np.int64), oci)
+
+
+def test_host_only_model_refuses_the_interior_point_loop():
+    # the loop needs a device; the host-only model reports it before any
+    # pointer is touched, and the analysis itself works without one
+    net = synth.config_network("tiny")
+    M = capi.Model([net], device=-1)
+    F = capi.Chol(M)
+    import torch
+    with pytest.raises(capi.OpfError) as e:
+        capi.ipm_solve(M, F, torch.empty(M.n, dtype=torch.float64))
+    assert e.value.code == -5
+    o = capi.ipm_options()
+    assert o.tol == 1e-4 and o.max_iter == 100 and o.tau == 0.99995 and o.verbose == 0
+    F.close()
+    M.close()
