@@ -509,7 +509,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the evaluation path has no "
-              "multi-GPU mode in this build", file=sys.stderr)
+              "multi-GPU mode", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

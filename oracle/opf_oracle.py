@@ -11,7 +11,7 @@ of that form, while the device path uses an expanded real trigonometric
 form.  Every routine is written for clarity, vectorised with numpy over
 elements, never blocked or fused.
 
-Model (Sec. II, eq. (1a)-(1k)), with the readings this build takes where the
+Model (Sec. II, eq. (1a)-(1k)), with the readings taken where the
 paper is silent or its printed formula is garbled:
 
 * branch l = (i -> j) is a pi-model line with series admittance
