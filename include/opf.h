@@ -349,8 +349,9 @@ int opf_chol_tree(const opf_chol *chol, int32_t inst, int32_t *perm,
  * pivot_repl (> 0) and counted into *npert (device int32, overwritten).
  * Enqueued on the model's stream: the work of the call starts after what
  * is already queued there and later work queued there sees the finished
- * factor (internally the pg chain runs on a stream of the object's own,
- * ordered by events and joined back into the model's stream).  The factor
+ * factor (internally the pg chain, and every other large front of a level,
+ * run on two streams of the object's own, ordered by events and joined back
+ * into the model's stream).  The factor
  * stays in the opf_chol object.  Errors: OPF_EINVAL (NULL, pivot_repl not
  * > 0), OPF_ENODEV (host-only model), OPF_EHIP. */
 int opf_chol_factor(opf_chol *chol, const double *kvals, double pivot_tol,
