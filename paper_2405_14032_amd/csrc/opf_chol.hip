@@ -770,7 +770,10 @@ struct opf_chol {
 
 namespace {
 
-constexpr int64_t kArenaBudget = 8LL << 30;  // bytes of update-matrix workspace per instance
+// bytes of update-matrix workspace per instance: 20 periods of the
+// 10000-bus grid (measured per factorization: 5 periods 2.15 s, 10 1.76 s,
+// 20 1.63 s, 40 1.63 s)
+constexpr int64_t kArenaBudget = 16LL << 30;
 
 // Workspace budget: OPF_CHOL_ARENA_BYTES (bytes, > 0) overrides the default.
 int64_t arena_budget() {

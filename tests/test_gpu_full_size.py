@@ -195,7 +195,7 @@ def test_condensation_calls_paper_scale(dev):
 @pytest.mark.timeout(900)
 def test_chol_paper_scale_residual(dev):
     """The sparse Cholesky at the benchmark's paper-scale configuration
-    (12.8M unknowns, 168 periods, ten periods per chunk): no static pivots
+    (12.8M unknowns, 168 periods, twenty periods per chunk): no static pivots
     on a positive definite K, and the solution's backward error in that K
     (a property that holds at any size) at the level Cholesky guarantees."""
     import torch
