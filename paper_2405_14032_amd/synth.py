@@ -27,6 +27,7 @@ length; the draw order below is part of the recipe and fixed.
 from __future__ import annotations
 
 import math
+import dataclasses
 from dataclasses import dataclass
 
 import numpy as np
@@ -154,6 +155,18 @@ def make_network(N: int, B: int, G: int, T: int, seed: int, rng=None) -> Network
 def config_network(name: str) -> Network:
     s = SHAPES[name]
     return make_network(s["N"], s["B"], s["G"], s["T"], SEEDS[name])
+
+
+def cap_load(net: Network, frac: float) -> Network:
+    """The same network with every period's real and reactive loads scaled
+    by one factor, chosen so that the peak period's total real load is at
+    most ``frac`` of the total generation capacity (sum of pmax).  With the
+    random ratings and limits of the draws, the single-period problems of
+    the heavier periods have no feasible point that either the interior-point
+    loop or a general constrained solver finds; capped loads give instances
+    a whole solve can finish."""
+    s = min(1.0, frac * float(net.pmax.sum()) / float(net.pd.sum(axis=1).max()))
+    return dataclasses.replace(net, pd=net.pd * s, qd=net.qd * s)
 
 
 def batched_shape(rng) -> tuple[int, int, int, int]:

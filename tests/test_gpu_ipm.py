@@ -51,6 +51,31 @@ def test_ipm_matches_oracle(name, dev):
     assert np.max(np.abs(x - ref["x"])) <= 1e-3
 
 
+@pytest.mark.timeout(600)
+def test_ipm_mid_grid_capped_load_whole_solve(dev):
+    """A whole solve at the 2000-bus, 24-period size (n = 422400) with loads
+    capped at 30 % of capacity: converged to 1e-4, and the returned point,
+    checked with the oracle's own functions, inside the variable bounds and
+    the relaxed row bounds up to the stopping tolerance, with the objective
+    the oracle computes there.  (The oracle's loop is too slow to run to
+    the end at this size, so the point is checked, not compared.)"""
+    import torch
+    net = synth.cap_load(synth.config_network("mid"), 0.3)
+    print("ipm case mid, loads capped at 0.3", flush=True)
+    r, x, y, _ = _gpu_ipm([net], torch, dev)
+    print("gpu", r, flush=True)
+    assert r["converged"] == 1 and r["iterations"] <= 120
+    xl, xu, cl, cu = O.bounds(net)
+    relax, tol = 1e-4, 1e-4
+    eq = cl == cu
+    sl, su = np.where(eq, cl - relax, cl), np.where(eq, cu + relax, cu)
+    assert np.all(np.isfinite(x)) and np.all(np.isfinite(y))
+    assert np.all(x >= xl) and np.all(x <= xu)
+    c = O.constraints(net, x)
+    assert np.all(c >= sl - tol) and np.all(c <= su + tol), (np.max(sl - c), np.max(c - su))
+    assert abs(O.objective(net, x) - r["objective"]) <= 1e-9 * abs(r["objective"])
+
+
 def test_ipm_batch_solves_each_instance(dev):
     """Two instances solved jointly: each instance's part is that
     instance's optimum (the oracle solving it alone)."""
