@@ -227,3 +227,21 @@ def test_host_only_model_refuses_the_interior_point_loop():
     assert o.tol == 1e-4 and o.max_iter == 100 and o.tau == 0.99995 and o.verbose == 0
     F.close()
     M.close()
+
+
+def test_cap_load_scales_to_the_capacity_fraction():
+    """synth.cap_load: the peak period's total real load becomes the given
+    fraction of the generation capacity, real and reactive loads scale by
+    the same factor, a network already below the cap is left unchanged, and
+    nothing else in the network moves."""
+    net = synth.config_network("mid")
+    cap = synth.cap_load(net, 0.3)
+    s = cap.pd.sum() / net.pd.sum()
+    assert 0.0 < s < 1.0
+    assert abs(cap.pd.sum(axis=1).max() - 0.3 * net.pmax.sum()) <= 1e-12 * net.pmax.sum()
+    np.testing.assert_allclose(cap.pd, s * net.pd, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(cap.qd, s * net.qd, rtol=1e-13, atol=0)
+    for k in ("rate", "pmax", "pmin", "qmax", "qmin", "ramp", "vmin", "vmax", "f_bus", "t_bus"):
+        assert np.array_equal(getattr(cap, k), getattr(net, k)), k
+    same = synth.cap_load(net, 10.0)
+    assert np.array_equal(same.pd, net.pd) and np.array_equal(same.qd, net.qd)
