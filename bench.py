@@ -345,8 +345,9 @@ def bench_ipm(torch, dev, args):
     1e-4 of the 2000-bus, 24-period grid with its loads capped at 30 % of
     the generation capacity (synth.cap_load: the heavier uncapped periods
     have no feasible point found), timed after one warm-up solve, and the
-    cost of one iteration at paper scale (three iterations timed; evaluation
-    + condensation, factorization, solve + recovery)."""
+    same grid over 168 periods (one solve), and the cost of one iteration at
+    paper scale (three iterations timed; evaluation + condensation,
+    factorization, solve + recovery)."""
     from paper_2405_14032_amd import capi, synth
     out = {}
     net = synth.cap_load(synth.config_network("mid"), 0.3)
@@ -360,6 +361,20 @@ def bench_ipm(torch, dev, args):
                           "n": M.n, "m": M.m, "converged": bool(r["converged"]), "iterations": r["iterations"],
                           "seconds": round(r["seconds"], 4), "s_per_iteration": round(r["seconds"] / max(1, r["iterations"]), 4),
                           "objective": r["objective"]}
+    F.close()
+    M.close()
+    # the same grid over a week of hourly periods (n = 2956800), one solve
+    net = synth.cap_load(synth.make_network(2000, 3200, 400, 168, 2), 0.3)
+    M = capi.Model([net], device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    x = torch.empty(M.n, dtype=torch.float64, device=dev)
+    r = capi.ipm_solve(M, F, x)
+    out["whole_solve_week"] = {"workload": "N=2000 B=3200 G=400 T=168 (seed 2), loads capped at 0.3 of capacity, tol 1e-4",
+                               "n": M.n, "m": M.m, "converged": bool(r["converged"]), "iterations": r["iterations"],
+                               "seconds": round(r["seconds"], 3), "factor_s": round(r["t_factor"], 3),
+                               "solve_recover_s": round(r["t_solve"], 3), "objective": r["objective"]}
+    log(f"ipm week solve: {out['whole_solve_week']}")
     F.close()
     M.close()
     net = synth.config_network("paper")
