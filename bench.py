@@ -393,6 +393,30 @@ def bench_ipm(torch, dev, args):
     return out
 
 
+def bench_paper_solve(torch, dev, cap):
+    """A whole interior-point solve (tol 1e-4) of the paper-scale grid with
+    every period's loads scaled so that the peak period draws ``cap`` of the
+    generation capacity (synth.cap_load); one progress line per iteration on
+    stderr."""
+    from paper_2405_14032_amd import capi, synth
+    net = synth.cap_load(synth.config_network("paper"), cap)
+    t0 = time.perf_counter()
+    M = capi.Model([net], device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    setup_s = time.perf_counter() - t0
+    x = torch.empty(M.n, dtype=torch.float64, device=dev)
+    r = capi.ipm_solve(M, F, x, max_iter=200, verbose=1)
+    out = {"workload": f"paper-scale grid N=10000 B=13000 G=2000 T=168 (seed 3), loads capped at {cap} of capacity, "
+                       "tol 1e-4", "n": M.n, "m": M.m, "setup_s": round(setup_s, 2), "converged": bool(r["converged"]),
+           "iterations": r["iterations"], "seconds": round(r["seconds"], 2), "eval_s": round(r["t_eval"], 2),
+           "factor_s": round(r["t_factor"], 2), "solve_recover_s": round(r["t_solve"], 2),
+           "objective": r["objective"], "err": r["err"]}
+    F.close()
+    M.close()
+    return out
+
+
 def bench_batched(torch, dev, args):
     from paper_2405_14032_amd import capi, synth
     nets = synth.batched_networks(64)
@@ -522,6 +546,9 @@ def main():
     ap.add_argument("--no-chol", action="store_true", help="skip the sparse Cholesky leg")
     ap.add_argument("--chol-only", action="store_true",
                     help="run only the sparse Cholesky leg and print its JSON object (for profiling)")
+    ap.add_argument("--paper-solve", type=float, default=None, metavar="CAP",
+                    help="run only a whole interior-point solve of the paper-scale grid with its loads capped at "
+                         "CAP of the generation capacity (several minutes) and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -544,6 +571,9 @@ def main():
         del src, dst
     if args.chol_only:
         print(json.dumps({"chol": bench_chol(torch, dev, args)}), flush=True)
+        return
+    if args.paper_solve is not None:
+        print(json.dumps({"paper_solve": bench_paper_solve(torch, dev, args.paper_solve)}), flush=True)
         return
     res = bench_plain(torch, dev, args)
     log(f"plain sweep: {res['ms_per_step']:.3f} ms/step")
