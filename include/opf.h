@@ -14,7 +14,10 @@
  * Conventions
  *  - Indices are 0-based.  Value arrays are double.  Index arrays are int32,
  *    CSR row pointers int64.  Creation fails with OPF_ERANGE if any global
- *    row or column index would not fit int32.
+ *    row or column index would not fit int32, or if one period's block of
+ *    x, c, J, H or K (or of the line scratch, 22 doubles per line) would
+ *    exceed 4 GiB (the kernels address inside a block by 32-bit byte
+ *    offsets; at most 2^29 - 1 doubles per block).
  *  - Status: every function returns OPF_OK (0) or a negative code; the
  *    thread-local message of the last failure is opf_last_error().  No C++
  *    exception crosses this boundary.
@@ -120,8 +123,9 @@ typedef struct {
 } opf_sweep_args;
 
 /* Checks a descriptor array on the host (no device needed): sizes, index
- * ranges, f != t, NULL pointers, finite admittances, int32 index limits.
- * Returns OPF_OK, OPF_EINVAL or OPF_ERANGE. */
+ * ranges, f != t, NULL pointers, finite admittances, int32 index limits,
+ * per-period blocks within 4 GiB (the K block is checked at creation, once
+ * its pattern is known).  Returns OPF_OK, OPF_EINVAL or OPF_ERANGE. */
 int opf_validate(const opf_instance_desc *desc, int32_t ninst);
 
 /* Builds a model of ninst instances.  device >= 0: element tables, the
@@ -172,7 +176,11 @@ int opf_eval_obj(opf_model *model, const double *x, double *f);
 int opf_eval_grad(opf_model *model, const double *x, double *g);
 /* All rows c(x) in canonical order (eq. (1b)-(1f), (1j), (1k), ref). [m] */
 int opf_eval_cons(opf_model *model, const double *x, double *c);
-/* Jacobian values in the canonical COO order. [nnz_jac] */
+/* Jacobian values of the rows of eq. (1b)-(1f), (1j), (1k) and the ref row,
+ * in the canonical COO order (Sec. III-A: each pattern's sparsity analysed
+ * once and expanded over the data; the order is that of
+ * opf_jac_structure).  x: device [n]; jvals: device [nnz_jac], overwritten.
+ * Errors: OPF_EINVAL (NULL), OPF_ENODEV (host-only model), OPF_EHIP. */
 int opf_eval_jac(opf_model *model, const double *x, double *jvals);
 /* Lower COO values of sigma Hess f + sum_i lambda_i Hess c_i (Sec. III-B:
  * W, the Hessian of the Lagrangian; an IPM written with p_x = grad f -

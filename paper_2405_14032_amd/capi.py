@@ -208,6 +208,33 @@ def _ptr(t) -> int | None:
     return t.data_ptr()
 
 
+def _dev_arg(t, device: int, count: int, dtype: str, what: str, optional: bool = False) -> int | None:
+    """Device address of a torch tensor after checking that the library can
+    use it: a contiguous tensor of the given dtype ("f64", "i32" or "i64") on
+    the model's HIP device with at least ``count`` elements.  None passes NULL
+    where the call allows it.  Raises before anything reaches the C ABI, so
+    a wrong argument never becomes an out-of-bounds device access."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{what}: a tensor is required")
+    import torch
+    want = {"f64": torch.float64, "i32": torch.int32, "i64": torch.int64}[dtype]
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != want:
+        raise TypeError(f"{what}: dtype {t.dtype}, expected {want}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+    if t.numel() < count:
+        raise ValueError(f"{what}: {t.numel()} elements, need {count}")
+    if device < 0:
+        raise ValueError(f"{what}: the model is host-only (created with device < 0)")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{what}: tensor on {t.device}, the model is on cuda:{device}")
+    return t.data_ptr()
+
+
 class Model:
     """Owns an opf_model handle.  device >= 0 puts it on that HIP device;
     device < 0 makes a host-only model (dims, offsets, host KKT pattern)."""
@@ -230,7 +257,11 @@ class Model:
         offs = [np.zeros(k, dtype=np.int64) for _ in range(5)]
         check(opf_instance_offsets(self.h, *[o.ctypes.data_as(_lp) for o in offs]), "opf_instance_offsets")
         self.x_off, self.c_off, self.j_off, self.h_off, self.k_off = offs
+        self.nload = int(sum(int(net.T) * int(net.N) for net in self.nets))
         self._stream = None
+
+    def _a(self, t, count, what, dtype="f64", optional=False):
+        return _dev_arg(t, self.device, count, dtype, what, optional)
 
     def close(self):
         if getattr(self, "h", None):
@@ -254,16 +285,23 @@ class Model:
 
     # structure --------------------------------------------------------------
     def bounds(self, lv, uv, lc, uc):
-        check(opf_bounds(self.h, _ptr(lv), _ptr(uv), _ptr(lc), _ptr(uc)), "opf_bounds")
+        n, m = self.n, self.m
+        check(opf_bounds(self.h, self._a(lv, n, "lvar"), self._a(uv, n, "uvar"), self._a(lc, m, "lcon"),
+                         self._a(uc, m, "ucon")), "opf_bounds")
 
     def jac_structure(self, rows, cols):
-        check(opf_jac_structure(self.h, _ptr(rows), _ptr(cols)), "opf_jac_structure")
+        k = self.nnz_jac
+        check(opf_jac_structure(self.h, self._a(rows, k, "rows", "i32"), self._a(cols, k, "cols", "i32")),
+              "opf_jac_structure")
 
     def hess_structure(self, rows, cols):
-        check(opf_hess_structure(self.h, _ptr(rows), _ptr(cols)), "opf_hess_structure")
+        k = self.nnz_hess
+        check(opf_hess_structure(self.h, self._a(rows, k, "rows", "i32"), self._a(cols, k, "cols", "i32")),
+              "opf_hess_structure")
 
     def kkt_structure(self, rowptr, colind):
-        check(opf_kkt_structure(self.h, _ptr(rowptr), _ptr(colind)), "opf_kkt_structure")
+        check(opf_kkt_structure(self.h, self._a(rowptr, self.n + 1, "rowptr", "i64"),
+                                self._a(colind, self.nnz_kkt, "colind", "i32")), "opf_kkt_structure")
 
     def kkt_structure_host(self):
         """Host-only models: the K pattern as numpy arrays."""
@@ -274,66 +312,84 @@ class Model:
 
     # evaluation -------------------------------------------------------------
     def eval_obj(self, x, f):
-        check(opf_eval_obj(self.h, _ptr(x), _ptr(f)), "opf_eval_obj")
+        check(opf_eval_obj(self.h, self._a(x, self.n, "x"), self._a(f, self.ninst, "f")), "opf_eval_obj")
 
     def eval_grad(self, x, g):
-        check(opf_eval_grad(self.h, _ptr(x), _ptr(g)), "opf_eval_grad")
+        check(opf_eval_grad(self.h, self._a(x, self.n, "x"), self._a(g, self.n, "grad")), "opf_eval_grad")
 
     def eval_cons(self, x, c):
-        check(opf_eval_cons(self.h, _ptr(x), _ptr(c)), "opf_eval_cons")
+        check(opf_eval_cons(self.h, self._a(x, self.n, "x"), self._a(c, self.m, "c")), "opf_eval_cons")
 
     def eval_jac(self, x, jv):
-        check(opf_eval_jac(self.h, _ptr(x), _ptr(jv)), "opf_eval_jac")
+        check(opf_eval_jac(self.h, self._a(x, self.n, "x"), self._a(jv, self.nnz_jac, "jvals")), "opf_eval_jac")
 
     def eval_hess(self, x, lam, sigma, hv):
-        check(opf_eval_hess(self.h, _ptr(x), _ptr(lam), float(sigma), _ptr(hv)), "opf_eval_hess")
+        check(opf_eval_hess(self.h, self._a(x, self.n, "x"), self._a(lam, self.m, "lambda"), float(sigma),
+                            self._a(hv, self.nnz_hess, "hvals")), "opf_eval_hess")
 
     def jtprod(self, x, v, out):
-        check(opf_jtprod(self.h, _ptr(x), _ptr(v), _ptr(out)), "opf_jtprod")
+        check(opf_jtprod(self.h, self._a(x, self.n, "x"), self._a(v, self.m, "v"), self._a(out, self.n, "jtv")),
+              "opf_jtprod")
 
     def set_load(self, pd, qd):
-        check(opf_set_load(self.h, _ptr(pd), _ptr(qd)), "opf_set_load")
+        check(opf_set_load(self.h, self._a(pd, self.nload, "pd"), self._a(qd, self.nload, "qd")), "opf_set_load")
 
     def load_adjoint(self, lam, gpd, gqd):
-        check(opf_load_adjoint(self.h, _ptr(lam), _ptr(gpd), _ptr(gqd)), "opf_load_adjoint")
+        check(opf_load_adjoint(self.h, self._a(lam, self.m, "lambda"), self._a(gpd, self.nload, "gpd"),
+                               self._a(gqd, self.nload, "gqd")), "opf_load_adjoint")
 
     def assemble_condensed(self, hv, jv, diag_x, dcon, kv):
-        check(opf_assemble_condensed(self.h, _ptr(hv), _ptr(jv), _ptr(diag_x), _ptr(dcon), _ptr(kv)),
-              "opf_assemble_condensed")
+        check(opf_assemble_condensed(self.h, self._a(hv, self.nnz_hess, "hvals"), self._a(jv, self.nnz_jac, "jvals"),
+                                     self._a(diag_x, self.n, "diag_x", optional=True), self._a(dcon, self.m, "dcon"),
+                                     self._a(kv, self.nnz_kkt, "kvals")), "opf_assemble_condensed")
 
     def eval_jhk(self, x, lam, sigma, diag_x, dcon, jv, hv, kv):
-        check(opf_eval_jhk(self.h, _ptr(x), _ptr(lam), float(sigma), _ptr(diag_x), _ptr(dcon), _ptr(jv),
-                           _ptr(hv), _ptr(kv)), "opf_eval_jhk")
+        check(opf_eval_jhk(self.h, self._a(x, self.n, "x"), self._a(lam, self.m, "lambda"), float(sigma),
+                           self._a(diag_x, self.n, "diag_x", optional=True), self._a(dcon, self.m, "dcon"),
+                           self._a(jv, self.nnz_jac, "jvals"), self._a(hv, self.nnz_hess, "hvals"),
+                           self._a(kv, self.nnz_kkt, "kvals")), "opf_eval_jhk")
 
     def jprod(self, x, v, out):
-        check(opf_jprod(self.h, _ptr(x), _ptr(v), _ptr(out)), "opf_jprod")
+        check(opf_jprod(self.h, self._a(x, self.n, "x"), self._a(v, self.n, "v"), self._a(out, self.m, "jv")),
+              "opf_jprod")
 
-    @staticmethod
-    def ipm_state(x, s, y, zl, zu, vl, vu, xl, xu, sl, su, mu, delta_w, delta_c) -> opf_ipm_state:
+    def ipm_state(self, x, s, y, zl, zu, vl, vu, xl, xu, sl, su, mu, delta_w, delta_c) -> opf_ipm_state:
         """The C state struct over device tensors (the tensors must outlive
         the calls that use it)."""
+        n, m = self.n, self.m
         st = opf_ipm_state()
-        st.x, st.s, st.y = _ptr(x), _ptr(s), _ptr(y)
-        st.zl, st.zu, st.vl, st.vu = _ptr(zl), _ptr(zu), _ptr(vl), _ptr(vu)
-        st.xl, st.xu, st.sl, st.su = _ptr(xl), _ptr(xu), _ptr(sl), _ptr(su)
+        st.x, st.s, st.y = self._a(x, n, "x"), self._a(s, m, "s"), self._a(y, m, "y")
+        st.zl, st.zu = self._a(zl, n, "zl"), self._a(zu, n, "zu")
+        st.vl, st.vu = self._a(vl, m, "vl"), self._a(vu, m, "vu")
+        st.xl, st.xu = self._a(xl, n, "xl"), self._a(xu, n, "xu")
+        st.sl, st.su = self._a(sl, m, "sl"), self._a(su, m, "su")
         st.mu, st.delta_w, st.delta_c = float(mu), float(delta_w), float(delta_c)
         return st
 
     def condensed_rhs(self, st, grad, c, diag_x, dcon, rhs):
-        check(opf_condensed_rhs(self.h, C.byref(st), _ptr(grad), _ptr(c), _ptr(diag_x), _ptr(dcon), _ptr(rhs)),
+        n, m = self.n, self.m
+        check(opf_condensed_rhs(self.h, C.byref(st), self._a(grad, n, "grad"), self._a(c, m, "c"),
+                                self._a(diag_x, n, "diag_x"), self._a(dcon, m, "dcon"), self._a(rhs, n, "rhs")),
               "opf_condensed_rhs")
 
     def recover_step(self, st, c, dx, ds, dy, dzl, dzu, dvl, dvu):
-        check(opf_recover_step(self.h, C.byref(st), _ptr(c), _ptr(dx), _ptr(ds), _ptr(dy), _ptr(dzl), _ptr(dzu),
-                               _ptr(dvl), _ptr(dvu)), "opf_recover_step")
+        n, m = self.n, self.m
+        check(opf_recover_step(self.h, C.byref(st), self._a(c, m, "c"), self._a(dx, n, "dx"), self._a(ds, m, "ds"),
+                               self._a(dy, m, "dy"), self._a(dzl, n, "dzl"), self._a(dzu, n, "dzu"),
+                               self._a(dvl, m, "dvl"), self._a(dvu, m, "dvu")), "opf_recover_step")
 
-    @staticmethod
-    def sweep_args(x=None, lam=None, sigma=1.0, v=None, diag_x=None, dcon=None, f=None, grad=None, c=None,
+    def sweep_args(self, x=None, lam=None, sigma=1.0, v=None, diag_x=None, dcon=None, f=None, grad=None, c=None,
                    jvals=None, hvals=None, jtv=None, kvals=None) -> opf_sweep_args:
+        """The sweep's argument struct; every tensor given is checked, an
+        argument left None passes NULL (the C side decides which may be)."""
+        n, m = self.n, self.m
         a = opf_sweep_args()
-        a.x, a.lambda_, a.sigma, a.v = _ptr(x), _ptr(lam), float(sigma), _ptr(v)
-        a.diag_x, a.dcon, a.f, a.grad, a.c = _ptr(diag_x), _ptr(dcon), _ptr(f), _ptr(grad), _ptr(c)
-        a.jvals, a.hvals, a.jtv, a.kvals = _ptr(jvals), _ptr(hvals), _ptr(jtv), _ptr(kvals)
+        o = dict(optional=True)
+        a.x, a.lambda_, a.sigma = self._a(x, n, "x", **o), self._a(lam, m, "lambda", **o), float(sigma)
+        a.v, a.diag_x, a.dcon = self._a(v, m, "v", **o), self._a(diag_x, n, "diag_x", **o), self._a(dcon, m, "dcon", **o)
+        a.f, a.grad, a.c = self._a(f, self.ninst, "f", **o), self._a(grad, n, "grad", **o), self._a(c, m, "c", **o)
+        a.jvals, a.hvals = self._a(jvals, self.nnz_jac, "jvals", **o), self._a(hvals, self.nnz_hess, "hvals", **o)
+        a.jtv, a.kvals = self._a(jtv, n, "jtv", **o), self._a(kvals, self.nnz_kkt, "kvals", **o)
         return a
 
     def sweep(self, args: opf_sweep_args):
@@ -408,11 +464,13 @@ class Chol:
         return dict(perm=perm, first=first, npiv=npiv, parent=parent, rowptr=rowptr, rows=rows[:nr.value])
 
     def factor(self, kvals, pivot_tol: float, pivot_repl: float, npert):
-        check(opf_chol_factor(self.h, _ptr(kvals), float(pivot_tol), float(pivot_repl), _ptr(npert)),
-              "opf_chol_factor")
+        M = self.model
+        check(opf_chol_factor(self.h, M._a(kvals, M.nnz_kkt, "kvals"), float(pivot_tol), float(pivot_repl),
+                              M._a(npert, 1, "npert", "i32", optional=True)), "opf_chol_factor")
 
     def solve(self, b, x):
-        check(opf_chol_solve(self.h, _ptr(b), _ptr(x)), "opf_chol_solve")
+        M = self.model
+        check(opf_chol_solve(self.h, M._a(b, M.n, "b"), M._a(x, M.n, "x")), "opf_chol_solve")
 
     def set_graph(self, enable: bool):
         check(opf_chol_set_graph(self.h, int(enable)), "opf_chol_set_graph")
@@ -430,7 +488,10 @@ def ipm_options(**kw) -> opf_ipm_options:
 def ipm_solve(model: Model, chol: Chol, x_out, y_out=None, **opts) -> dict:
     """Runs the lifted-KKT interior-point loop (opf_ipm_solve); x_out (and
     y_out) are device arrays receiving the final point (multipliers)."""
+    if chol.model is not model:
+        raise ValueError("chol was analysed from another model")
     o = ipm_options(**opts)
     r = opf_ipm_result()
-    check(opf_ipm_solve(model.h, chol.h, C.byref(o), _ptr(x_out), _ptr(y_out), C.byref(r)), "opf_ipm_solve")
+    check(opf_ipm_solve(model.h, chol.h, C.byref(o), model._a(x_out, model.n, "x_out"),
+                        model._a(y_out, model.m, "y_out", optional=True), C.byref(r)), "opf_ipm_solve")
     return {k: getattr(r, k) for k, _ in opf_ipm_result._fields_}

@@ -18,4 +18,5 @@ hipStream_t model_stream(const opf_model* M);
 const std::vector<InstHost>& model_insts(const opf_model* M);
 int64_t model_n(const opf_model* M);
 int64_t model_nnzk(const opf_model* M);
+const opf_model* chol_model(const opf_chol* F);  // the model F was analysed from
 }  // namespace opf

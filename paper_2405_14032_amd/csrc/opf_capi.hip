@@ -22,6 +22,8 @@
 
 using namespace opf;
 
+static_assert(kScratchPerLine == kLineScratchDoubles, "line scratch layout of the device and the host checks");
+
 namespace {
 
 thread_local std::string g_err;

@@ -768,6 +768,8 @@ struct opf_chol {
   int64_t factor_entries = 0, arena_entries = 0;
 };
 
+const opf_model* opf::chol_model(const opf_chol* F) { return F ? F->model : nullptr; }
+
 namespace {
 
 // bytes of update-matrix workspace per instance: 20 periods of the

@@ -11,6 +11,14 @@
 
 namespace opf {
 
+// Doubles of line scratch per line and period (the device layout: two
+// 64-byte end records, the shared cross pair, four J^T v hand-off values).
+constexpr int64_t kLineScratchDoubles = 22;
+// Largest block of doubles that a 32-bit byte offset addresses; the kernels
+// reach each per-period block of x, c, J, H, K and the line scratch, and
+// each per-instance line table, through such an offset from the block base.
+constexpr int64_t kMaxBlockDoubles = (int64_t(1) << 29) - 1;
+
 // Slot source codes in the per-period condensed-matrix template.
 constexpr int32_t kSrcNone = -2;     // slot filled from the owner's own data
 constexpr int32_t kSrcThermal = -1;  // (qf,pf) / (qt,pt) pair of a thermal row

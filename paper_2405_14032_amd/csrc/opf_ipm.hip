@@ -307,6 +307,7 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
                   opf_ipm_result* res) {
   if (!M || !F || !x_out || !res) return api_fail(OPF_EINVAL, "ipm: model, chol, x or result is NULL");
   if (model_device(M) < 0) return api_fail(OPF_ENODEV, "model is host-only");
+  if (chol_model(F) != M) return api_fail(OPF_EINVAL, "ipm: chol was analysed from another model");
   opf_ipm_options opt;
   if (opt_in) opt = *opt_in;
   else opf_ipm_default_options(&opt);

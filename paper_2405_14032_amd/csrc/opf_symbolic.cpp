@@ -62,6 +62,14 @@ int validate_descs(const opf_instance_desc* desc, int32_t ninst, std::string& er
       err = where + "per-period sizes exceed int32";
       return OPF_ERANGE;
     }
+    // every block a kernel addresses through a 32-bit byte offset (x, c, J,
+    // H of one period, the line scratch of one period) stays below 4 GiB
+    const int64_t blocks[] = {n_p, m_p, 2 * G + 30 * B + 1, G + 40 * B, kLineScratchDoubles * B};
+    for (int64_t e : blocks)
+      if (e > kMaxBlockDoubles) {
+        err = where + "a per-period block exceeds the 4 GiB a 32-bit byte offset addresses";
+        return OPF_ERANGE;
+      }
     tot_n += n;
     tot_m += m;
     if (tot_n > kI32Max || tot_m > kI32Max) {
@@ -303,6 +311,10 @@ int build_instance(const opf_instance_desc& d, InstHost& I, std::string& err) {
   }
   if ((int64_t)I.kcol.size() > kI32Max) {
     err = "condensed-matrix template exceeds int32";
+    return OPF_ERANGE;
+  }
+  if ((int64_t)I.kcol.size() + G > kMaxBlockDoubles) {
+    err = "a period's block of the condensed matrix exceeds the 4 GiB a 32-bit byte offset addresses";
     return OPF_ERANGE;
   }
   I.nnzk_p = (int64_t)I.kcol.size();

@@ -220,9 +220,11 @@ def test_host_only_model_refuses_the_interior_point_loop():
     M = capi.Model([net], device=-1)
     F = capi.Chol(M)
     import torch
-    with pytest.raises(capi.OpfError) as e:
-        capi.ipm_solve(M, F, torch.empty(M.n, dtype=torch.float64))
-    assert e.value.code == -5
+    x = torch.empty(M.n, dtype=torch.float64)
+    with pytest.raises(ValueError, match="host-only"):
+        capi.ipm_solve(M, F, x)
+    r = capi.opf_ipm_result()
+    assert capi.opf_ipm_solve(M.h, F.h, None, x.data_ptr(), None, C.byref(r)) == -5
     o = capi.ipm_options()
     assert o.tol == 1e-4 and o.max_iter == 100 and o.tau == 0.99995 and o.verbose == 0
     F.close()
@@ -245,3 +247,74 @@ def test_cap_load_scales_to_the_capacity_fraction():
         assert np.array_equal(getattr(cap, k), getattr(net, k)), k
     same = synth.cap_load(net, 10.0)
     assert np.array_equal(same.pd, net.pd) and np.array_equal(same.qd, net.qd)
+
+
+@pytest.mark.parametrize("B,G,T", [(13_421_773, 1, 1), (24_403_000, 1, 2)])
+def test_validate_rejects_blocks_beyond_32bit_byte_offsets(B, G, T):
+    # one period's H block (G + 40 B doubles) or line scratch (22 B doubles)
+    # beyond 2^29 doubles cannot be addressed by a 32-bit byte offset: the
+    # descriptor is refused before any line array is read (the arrays here
+    # are untouched zero pages)
+    N = 4
+    net = synth.make_network(N, 3, 1, 1, 3)
+    descs, keep = _one(net)
+    d = descs[0]
+    d.nbranch, d.ngen, d.nperiod = B, G, T
+    big_i = np.zeros(B, dtype=np.int32)
+    big_d = np.zeros(B)
+    keep += [big_i, big_d]
+    for name in ("f_bus", "t_bus"):
+        setattr(d, name, big_i.ctypes.data_as(C.POINTER(C.c_int32)))
+    for name in ("r", "x", "b_charge", "rate", "angmin", "angmax", "tap", "shift"):
+        setattr(d, name, big_d.ctypes.data_as(C.POINTER(C.c_double)))
+    assert capi.opf_validate(descs, 1) == capi.OPF_ERANGE
+    assert b"4 GiB" in capi.opf_last_error()
+
+
+def test_validate_accepts_largest_addressable_lines():
+    # G + 40 B just at 2^29 - 1 doubles passes the size checks (the first
+    # line, a self loop of zero pages, is then what stops validation)
+    B = ((1 << 29) - 1 - 1) // 40
+    net = synth.make_network(4, 3, 1, 1, 3)
+    descs, keep = _one(net)
+    d = descs[0]
+    d.nbranch = B
+    big_i = np.zeros(B, dtype=np.int32)
+    big_d = np.zeros(B)
+    keep += [big_i, big_d]
+    for name in ("f_bus", "t_bus"):
+        setattr(d, name, big_i.ctypes.data_as(C.POINTER(C.c_int32)))
+    for name in ("r", "x", "b_charge", "rate", "angmin", "angmax", "tap", "shift"):
+        setattr(d, name, big_d.ctypes.data_as(C.POINTER(C.c_double)))
+    assert capi.opf_validate(descs, 1) == capi.OPF_EINVAL
+    assert b"f == t" in capi.opf_last_error()
+
+
+def test_binding_rejects_wrong_tensors_before_the_abi():
+    # the binding checks dtype, contiguity, length and device of every tensor
+    # before a pointer reaches the C ABI
+    torch = pytest.importorskip("torch")
+    n = 10
+    f64 = torch.zeros(n, dtype=torch.float64)
+    with pytest.raises(TypeError, match="dtype"):
+        capi._dev_arg(torch.zeros(n, dtype=torch.float32), 0, n, "f64", "x")
+    with pytest.raises(TypeError, match="dtype"):
+        capi._dev_arg(torch.zeros(n, dtype=torch.int64), 0, n, "i32", "rows")
+    with pytest.raises(ValueError, match="contiguous"):
+        capi._dev_arg(torch.zeros((n, 2), dtype=torch.float64)[:, 0], 0, n, "f64", "x")
+    with pytest.raises(ValueError, match="need 11"):
+        capi._dev_arg(f64, 0, n + 1, "f64", "x")
+    with pytest.raises(ValueError, match="cuda:0"):
+        capi._dev_arg(f64, 0, n, "f64", "x")
+    with pytest.raises(ValueError, match="required"):
+        capi._dev_arg(None, 0, n, "f64", "x")
+    assert capi._dev_arg(None, 0, n, "f64", "x", optional=True) is None
+    with pytest.raises(TypeError, match="torch tensor"):
+        capi._dev_arg(np.zeros(n), 0, n, "f64", "x")
+    # a host-only model refuses device calls in the binding too
+    M = capi.Model([synth.config_network("tiny")], device=-1)
+    with pytest.raises(ValueError, match="host-only"):
+        M.eval_cons(torch.zeros(M.n, dtype=torch.float64), torch.zeros(M.m, dtype=torch.float64))
+    with pytest.raises(ValueError, match="need"):
+        M.eval_cons(torch.zeros(M.n - 1, dtype=torch.float64), torch.zeros(M.m, dtype=torch.float64))
+    M.close()

@@ -119,3 +119,24 @@ def test_ipm_rejects_bad_options(dev):
             capi.ipm_solve(M, F, x, **bad)
     F.close()
     M.close()
+
+
+def test_ipm_rejects_chol_of_another_model(dev):
+    # the factor object must come from the same model: the binding refuses
+    # the pair, and so does the C ABI itself (OPF_EINVAL, nothing enqueued)
+    import ctypes as C
+    import torch
+    from paper_2405_14032_amd import capi
+    net = synth.config_network("tiny")
+    M1 = capi.Model([net], device=0)
+    M2 = capi.Model([net], device=0)
+    F2 = capi.Chol(M2)
+    x = torch.empty(M1.n, dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError, match="another model"):
+        capi.ipm_solve(M1, F2, x)
+    r = capi.opf_ipm_result()
+    assert capi.opf_ipm_solve(M1.h, F2.h, None, x.data_ptr(), None, C.byref(r)) == capi.OPF_EINVAL
+    assert b"another model" in capi.opf_last_error()
+    F2.close()
+    M2.close()
+    M1.close()
