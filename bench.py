@@ -88,17 +88,30 @@ def sweep_kernel_bytes(net, model, kbus):
 
 
 def event_time(torch, fn, reps):
-    """Average milliseconds of fn() over reps, HIP events on the current stream."""
+    """Median milliseconds of fn() over reps (one warm-up first), a HIP event
+    pair per repetition on the current stream."""
     s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     fn()
     torch.cuda.synchronize()
-    e0.record(s)
-    for _ in range(reps):
+    for e0, e1 in ev:
+        e0.record(s)
         fn()
-    e1.record(s)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / reps
+        e1.record(s)
+    ev[-1][1].synchronize()
+    return float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+
+def copy_peak(torch, dev, reps=5):
+    """Measured HBM rate of a plain 1 GiB device-to-device copy (1 GiB read
+    + 1 GiB written per copy), median of ``reps`` after a warm-up: the
+    practical peak next to the 8 TB/s of the data sheet."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    ms = event_time(torch, lambda: dst.copy_(src), reps)
+    nbytes = 2 * src.numel() * 8
+    del src, dst
+    return {"bytes_per_copy": nbytes, "ms": round(ms, 4), "gbs": round(nbytes / ms / 1e6, 1)}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "sweep_paper_scale.txt")
@@ -132,27 +145,97 @@ def profiled_traffic(kernel):
     return None
 
 
-def cpu_baseline(periods: int = 96):
-    """The oracle as it stands, on the paper-scale grid over a shorter
-    horizon (a bounded sample), one full sweep; nnz/s like the GPU value."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_chunk_worker(chunk, periods, conn):
+    """One worker of the CPU baseline: builds its share of the paper-scale
+    horizon once, then runs one whole oracle sweep per request and reports
+    the J + H + K nnz it produced."""
     from oracle import opf_oracle as O
     from paper_2405_14032_amd import synth
-    net = synth.make_network(10000, 13000, 2000, periods, 3)
-    pt = synth.make_point(net, 3)
+    t0, t1 = chunk
+    full = synth.make_network(10000, 13000, 2000, periods, 3)
+    net = synth.make_network(10000, 13000, 2000, t1 - t0, 3)
+    net.pd, net.qd = full.pd[t0:t1].copy(), full.qd[t0:t1].copy()
+    pt = synth.make_point(net, 3 + t0)
     L = O.Layout(net)
-    t0 = time.perf_counter()
-    O.objective(net, pt.x)
-    O.gradient(net, pt.x)
-    O.constraints(net, pt.x)
-    jac = O.jacobian(net, pt.x)
-    hess = O.hessian(net, pt.x, pt.lam, pt.sigma)
-    O.jtprod(net, pt.x, pt.lam)
-    rp, _, _, _ = O.condensed(L.n, jac, hess, pt.diag_x, pt.dcon)
-    dt = time.perf_counter() - t0
-    nnz = len(jac[0]) + len(hess[0]) + int(rp[-1])
-    return {"value": nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full sweep of the paper-scale grid (N=10000, B=13000, G=2000) over T={periods} "
-                      f"periods: {nnz} J+H+K nnz in {dt:.2f} s, numpy/scipy single thread"}
+    conn.send("ready")
+    while conn.recv() == "run":
+        O.objective(net, pt.x)
+        O.gradient(net, pt.x)
+        O.constraints(net, pt.x)
+        jac = O.jacobian(net, pt.x)
+        hess = O.hessian(net, pt.x, pt.lam, pt.sigma)
+        O.jtprod(net, pt.x, pt.lam)
+        rp, _, _, _ = O.condensed(L.n, jac, hess, pt.diag_x, pt.dcon)
+        conn.send(len(jac[0]) + len(hess[0]) + int(rp[-1]))
+
+
+def cpu_baseline(periods: int = 96, reps: int = 5, max_workers: int = 16):
+    """The oracle as it stands, timed on the host cores: the paper-scale grid
+    over a horizon of ``periods`` (a bounded sample) split into one
+    contiguous period range per worker process (each range its own horizon,
+    so the ramp rows at the range boundaries are the only thing missing),
+    all workers sweeping at once; one warm-up, then the median wall time of
+    ``reps`` sweeps; nnz/s like the GPU value.  Call it before anything
+    initialises the GPU: the workers are fresh interpreters (spawn)."""
+    import multiprocessing as mp
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    workers = max(1, min(max_workers, avail, periods))
+    bounds = [round(k * periods / workers) for k in range(workers + 1)]
+    ctx = mp.get_context("spawn")
+    procs, conns = [], []
+    # one thread per worker: the workers inherit this environment
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    os.environ.update({k: "1" for k in saved})
+    try:
+        for k in range(workers):
+            a, b = ctx.Pipe()
+            p = ctx.Process(target=_oracle_chunk_worker, args=((bounds[k], bounds[k + 1]), periods, b), daemon=True)
+            p.start()
+            procs.append(p)
+            conns.append(a)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    for c in conns:
+        assert c.recv() == "ready"
+    times, nnz = [], 0
+    for r in range(reps + 1):
+        t0 = time.perf_counter()
+        for c in conns:
+            c.send("run")
+        nnz = sum(c.recv() for c in conns)
+        dt = time.perf_counter() - t0
+        if r > 0:
+            times.append(dt)
+    for c in conns:
+        c.send("stop")
+    for p in procs:
+        p.join(timeout=30)
+    med = float(np.median(times))
+    return {"value": nnz / med, "unit": "nnz/s", "cores": workers, "kind": "oracle",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": avail,
+            "median_s": round(med, 3), "times_s": [round(t, 3) for t in times],
+            "sample": f"one full sweep (f, grad, c, J, H, J^T v, K) of the paper-scale grid (N=10000, B=13000, "
+                      f"G=2000) over T={periods} periods, split into {workers} contiguous period ranges swept "
+                      f"at once by {workers} worker processes (numpy/scipy, one thread each): {nnz} J+H+K nnz; "
+                      f"median of {reps} after one warm-up"}
 
 
 def make_inputs(torch, dev, net, pt):
@@ -191,20 +274,26 @@ def bench_plain(torch, dev, args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = 1e3 * dt / args.steps
+    # the same replays one by one between HIP events: the median step
+    median_step_ms = event_time(torch, lambda: M.sweep_graph(sa), args.steps)
     # the same steps launched eagerly, every kernel bracketed by HIP events on
-    # the model's stream: the per-kernel durations of the roofline
+    # the model's stream: the per-kernel durations of the roofline (median
+    # over the steps, one launch of each kernel per step)
     for _ in range(args.warmup):
         M.sweep(sa)
     torch.cuda.synchronize()
-    M.set_timing(True)
+    per_kernel = {}
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        M.set_timing(True)
         M.sweep(sa)
+        for k, (c, t) in M.kernel_stats().items():
+            per_kernel.setdefault(k, []).append(t / c)
     torch.cuda.synchronize()
     eager_ms = 1e3 * (time.perf_counter() - t0) / args.steps
-    kstats = M.kernel_stats()
     M.set_timing(False)
-    kernels = {k: {"launches": c, "avg_ms": round(t / c, 4)} for k, (c, t) in kstats.items()}
+    kernels = {k: {"launches": len(v), "median_ms": round(float(np.median(v)), 4),
+                   "mean_ms": round(float(np.mean(v)), 4)} for k, v in per_kernel.items()}
     nnz = M.nnz_jac + M.nnz_hess + M.nnz_kkt
     by = call_bytes(net, M)
     # K slots in the bus (vm, va) rows: written by the bus pass of the sweep
@@ -266,28 +355,43 @@ def bench_plain(torch, dev, args):
         "hbm_gbs": sweep_bytes / (ms / 1e3) / 1e9,
         "sweep_bytes": sweep_bytes,
         "graph_sweep_ms": round(graph_ms, 4),
+        "median_step_ms": round(median_step_ms, 4),
         "eager_sweep_ms": round(eager_ms, 4),
-        # Jacobian + Hessian + condensed matrix alone (opf_eval_jhk): nnz/s and
-        # the rate in the separate pipeline's algorithmic bytes (J and H
-        # written, read back by the condensation: 3.56 GB)
+        # Jacobian + Hessian + condensed matrix alone (opf_eval_jhk): nnz/s,
+        # its rate in its own algorithmic bytes (what the fused pass must
+        # move), and the effective rate in the separate pipeline's bytes (J
+        # and H written, then read back by the condensation: 3.56 GB, which
+        # the fused pass never moves)
         "jhk": {"ms": jhk_ms, "nnz_per_s": nnz / (jhk_ms / 1e3),
+                "own_bytes": by["jhk"], "own_frac_of_peak": round(by["jhk"] / jhk_ms / 1e6 / HBM_PEAK_GBS, 4),
                 "separate_pipeline_bytes": by["jac"] + by["hess"] + by["condensed"],
-                "separate_pipeline_frac_of_peak": round((by["jac"] + by["hess"] + by["condensed"]) / jhk_ms / 1e6
-                                                        / HBM_PEAK_GBS, 4)},
+                "separate_pipeline_effective_frac": round((by["jac"] + by["hess"] + by["condensed"]) / jhk_ms
+                                                          / 1e6 / HBM_PEAK_GBS, 4)},
         "calls": per,
         "separate_jhk_ms": round(per["jac"]["ms"] + per["hess"]["ms"] + per["condensed"]["ms"], 4),
         "kernels": kernels,
         "symbolic": symbolic,
     }
-    kt = kernels["sweep_a"]["avg_ms"]
+    cp = args.copy_peak
+    kt = kernels["sweep_a"]["median_ms"]
+    ach = kb["sweep_a"] / kt / 1e6
     res["roofline"] = {"bound": "hbm", "kernel": "k_sweep_a (lines and generators of the fused sweep)",
-                       "achieved": round(kb["sweep_a"] / kt / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(kb["sweep_a"] / kt / 1e6 / HBM_PEAK_GBS, 4),
-                       "algorithmic_bytes": kb["sweep_a"], "avg_ms": kt, "traffic": profiled_traffic("k_sweep_a"),
+                       "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(ach / HBM_PEAK_GBS, 4),
+                       "measured_copy_gbs": cp["gbs"], "frac_of_measured_copy": round(ach / cp["gbs"], 4),
+                       "algorithmic_bytes": kb["sweep_a"], "median_ms": kt, "traffic": profiled_traffic("k_sweep_a"),
                        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
-    kt_b = kernels["sweep_b"]["avg_ms"]
+    kt_b = kernels["sweep_b"]["median_ms"]
     res["roofline_bus"] = {"kernel": "k_sweep_b", "achieved": round(kb["sweep_b"] / kt_b / 1e6, 1),
-                           "algorithmic_bytes": kb["sweep_b"], "avg_ms": kt_b}
+                           "frac": round(kb["sweep_b"] / kt_b / 1e6 / HBM_PEAK_GBS, 4),
+                           "algorithmic_bytes": kb["sweep_b"], "median_ms": kt_b,
+                           "traffic": profiled_traffic("k_sweep_b")}
+    sweep_gbs = sweep_bytes / (median_step_ms / 1e3) / 1e9
+    res["sweep_roofline"] = {"algorithmic_bytes": sweep_bytes, "median_step_ms": round(median_step_ms, 4),
+                             "achieved": round(sweep_gbs, 1), "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
+                             "frac_of_measured_copy": round(sweep_gbs / cp["gbs"], 4),
+                             "jhk_separate_pipeline_effective_frac": round(
+                                 (by["jac"] + by["hess"] + by["condensed"]) / median_step_ms / 1e6 / HBM_PEAK_GBS, 4)}
     M.close()
     return res
 
@@ -550,25 +654,29 @@ def main():
                     help="run only a whole interior-point solve of the paper-scale grid with its loads capped at "
                          "CAP of the generation capacity (several minutes) and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 1 GiB device-to-device copy (reference kernel for HBM counters)")
+                    help="accepted for older profiling commands; the 1 GiB copy now always runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the evaluation path has no "
               "multi-GPU mode", file=sys.stderr)
         sys.exit(2)
+    cpu = None
+    if not (args.no_cpu_baseline or args.chol_only or args.paper_solve is not None):
+        # before anything initialises the GPU: the oracle's workers are fresh
+        # interpreters started from this process
+        log("cpu baseline (oracle on the host cores) ...")
+        cpu = cpu_baseline()
+        log(f"cpu baseline: {cpu['value']:.3e} nnz/s on {cpu['cores']} cores ({cpu['cpu_model']})")
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
     os.makedirs(os.path.dirname(args.tune_cache), exist_ok=True)
-    if args.copy_calibration:
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    # the plain 1 GiB copy: the measured HBM peak, and the reference kernel
+    # of the counter calibration (its FETCH_SIZE / WRITE_SIZE per dispatch)
+    args.copy_peak = copy_peak(torch, dev)
+    log(f"1 GiB device copy: {args.copy_peak}")
     if args.chol_only:
         print(json.dumps({"chol": bench_chol(torch, dev, args)}), flush=True)
         return
@@ -582,7 +690,9 @@ def main():
             "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic (seeded grids standing in for the paper's public cases)",
             "config": res["config"], "hbm_gbs": res["hbm_gbs"], "sweep_bytes": res["sweep_bytes"],
-            "graph_sweep_ms": res["graph_sweep_ms"], "eager_sweep_ms": res["eager_sweep_ms"],
+            "graph_sweep_ms": res["graph_sweep_ms"], "median_step_ms": res["median_step_ms"],
+            "eager_sweep_ms": res["eager_sweep_ms"], "hbm_copy": args.copy_peak,
+            "sweep_roofline": res["sweep_roofline"],
             "jhk": res["jhk"], "separate_jhk_ms": res["separate_jhk_ms"],
             "calls": res["calls"], "kernels": res["kernels"], "symbolic": res["symbolic"], "roofline": res["roofline"],
             "roofline_bus": res["roofline_bus"]}
@@ -596,9 +706,8 @@ def main():
         log(f"batched: {line['batched']}")
         line["adjoint"] = bench_adjoint(torch, dev, args)
         log(f"adjoint: {line['adjoint']}")
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline()
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 
