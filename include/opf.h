@@ -276,6 +276,22 @@ int opf_sweep(opf_model *model, const opf_sweep_args *args);
 /* The same sweep recorded once into a HIP graph (re-recorded when the
  * argument set changes) and replayed with a single graph launch. */
 int opf_sweep_graph(opf_model *model, const opf_sweep_args *args);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sweep as opf_sweep, with the same kernels and bitwise identical results,
+ * but its scratch (the line -> bus hand-off records and the objective's
+ * partial sums) lives in a static device array of the library, 32 MiB per
+ * device, instead of the model's buffers.  The call itself allocates nothing
+ * (no hipMalloc, no event creation) and only enqueues kernels on the model's
+ * stream; the model is still created beforehand with opf_model_create.
+ * Returns OPF_ERANGE when the model needs more scratch than the static array
+ * holds (22 doubles per line-period plus one per objective tile: e.g. 2000
+ * buses / 3200 lines over 24 periods fit, the 13000-line grid over 168
+ * periods does not).  Every call on one device shares that array and it
+ * keeps the last call's contents: calls that overlap on one device (two
+ * streams, two models, two threads) race and must be serialised by the
+ * caller.  Per-kernel timing (opf_set_timing) does not cover this call. */
+int opf_sweep_noalloc(opf_model *model, const opf_sweep_args *args);
 
 /* Per-kernel timing.  opf_set_timing(model, 1) clears the statistics and
  * brackets every later kernel launch of the model with HIP events on the

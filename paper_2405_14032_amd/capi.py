@@ -114,6 +114,7 @@ _SIGS = {
     "opf_eval_jhk": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _vp, _vp, _vp, _vp]),
     "opf_sweep": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
     "opf_sweep_graph": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
+    "opf_sweep_noalloc": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
     "opf_jprod": (C.c_int, [_vp, _vp, _vp, _vp]),
     "opf_condensed_rhs": (C.c_int, [_vp, C.POINTER(opf_ipm_state), _vp, _vp, _vp, _vp, _vp]),
     "opf_recover_step": (C.c_int, [_vp, C.POINTER(opf_ipm_state), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -397,6 +398,9 @@ class Model:
 
     def sweep_graph(self, args: opf_sweep_args):
         check(opf_sweep_graph(self.h, C.byref(args)), "opf_sweep_graph")
+
+    def sweep_noalloc(self, args: opf_sweep_args):
+        check(opf_sweep_noalloc(self.h, C.byref(args)), "opf_sweep_noalloc")
 
     def set_timing(self, enable: bool):
         check(opf_set_timing(self.h, 1 if enable else 0), "opf_set_timing")

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -92,6 +93,40 @@ constexpr size_t kMaxSmem = 64 * 1024;
 
 }  // namespace
 
+// ---------------------------------------------------------------- static scratch
+// Device scratch of opf_sweep_noalloc (hand-off records, then the objective
+// partials): a file-scope array, so that call needs no allocation.  Every
+// device the library runs on holds its own copy until the process ends.  In
+// host code the name below is only a stand-in: kernels get the device
+// address looked up per device by static_scratch_lookup.
+constexpr int64_t kStaticScratchBytes = 32LL << 20;
+constexpr int64_t kStaticScratchDoubles = kStaticScratchBytes / (int64_t)sizeof(double);
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+double* g_static_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of the static scratch array; the
+// device must be current.  Looked up once per device (at model creation).
+int static_scratch_lookup(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return OPF_EINVAL;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return OPF_EHIP;
+    g_static_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_static_ptr[device];
+  return OPF_OK;
+}
+
+}  // namespace
+
 struct opf_model {
   int device = -1;
   int n_cu = 256;
@@ -103,6 +138,7 @@ struct opf_model {
   InstDev* d_inst = nullptr;
   std::vector<InstDev> h_dev;  // host mirror of d_inst
   double* scratch = nullptr;
+  int64_t scratch_doubles = 0;  // size of scratch (the hand-off records)
   double* wbuf = nullptr;  // [m]: row vector of the condensation calls
   double* obj_partial = nullptr;
   int obj_partial_cap = 0;
@@ -571,33 +607,43 @@ struct DeviceGuard {
   } while (0)
 
 // ---------------------------------------------------------------- enqueue helpers
-int enq_obj(opf_model* M, const double* x, double* f) {
-  { TimerScope ts_(M, OP_OBJ); OPF_LAUNCHED(launch_obj_partial(launch_of(M, OP_OBJ), x, M->obj_partial), "objective kernel"); }
+// Device scratch of one enqueue: the line -> bus hand-off records and the
+// objective's per-tile partial sums.  Normally the model's own buffers; the
+// allocation-free sweep passes slices of the library's static array.
+struct Work {
+  double* scr;
+  double* partial;
+};
+
+Work model_work(const opf_model* M) { return Work{M->scratch, M->obj_partial}; }
+
+int enq_obj(opf_model* M, const Work& w, const double* x, double* f) {
+  { TimerScope ts_(M, OP_OBJ); OPF_LAUNCHED(launch_obj_partial(launch_of(M, OP_OBJ), x, w.partial), "objective kernel"); }
   {
     TimerScope ts_(M, kTimeObjFinal);
-    OPF_LAUNCHED(launch_obj_final(M->d_obj_begin, (int)M->inst.size(), M->obj_partial, f, M->stream),
+    OPF_LAUNCHED(launch_obj_final(M->d_obj_begin, (int)M->inst.size(), w.partial, f, M->stream),
                  "objective reduction kernel");
   }
   return OPF_OK;
 }
 
-int enq_jt(opf_model* M, const double* x, const double* v, double* out) {
-  { TimerScope ts_(M, OP_JTA); OPF_LAUNCHED(launch_jt_a(launch_of(M, OP_JTA), x, v, out, M->scratch), "J^T v line kernel"); }
-  { TimerScope ts_(M, OP_JTB); OPF_LAUNCHED(launch_jt_b(launch_of(M, OP_JTB), v, out, M->scratch), "J^T v bus kernel"); }
+int enq_jt(opf_model* M, const Work& w, const double* x, const double* v, double* out) {
+  { TimerScope ts_(M, OP_JTA); OPF_LAUNCHED(launch_jt_a(launch_of(M, OP_JTA), x, v, out, w.scr), "J^T v line kernel"); }
+  { TimerScope ts_(M, OP_JTB); OPF_LAUNCHED(launch_jt_b(launch_of(M, OP_JTB), v, out, w.scr), "J^T v bus kernel"); }
   return OPF_OK;
 }
 
-int enq_kkt(opf_model* M, const double* h, const double* j, const double* dx, const double* d, double* k) {
-  { TimerScope ts_(M, OP_KKA); OPF_LAUNCHED(launch_kkt_a(launch_of(M, OP_KKA), h, j, dx, d, k, M->scratch), "condensed line kernel"); }
-  { TimerScope ts_(M, OP_KKB); OPF_LAUNCHED(launch_kkt_b(launch_of(M, OP_KKB), j, dx, d, k, M->scratch), "condensed bus kernel"); }
+int enq_kkt(opf_model* M, const Work& w, const double* h, const double* j, const double* dx, const double* d, double* k) {
+  { TimerScope ts_(M, OP_KKA); OPF_LAUNCHED(launch_kkt_a(launch_of(M, OP_KKA), h, j, dx, d, k, w.scr), "condensed line kernel"); }
+  { TimerScope ts_(M, OP_KKB); OPF_LAUNCHED(launch_kkt_b(launch_of(M, OP_KKB), j, dx, d, k, w.scr), "condensed bus kernel"); }
   return OPF_OK;
 }
 
-int enq_jhk(opf_model* M, const double* x, const double* lam, double sigma, const double* dx, const double* d,
+int enq_jhk(opf_model* M, const Work& w, const double* x, const double* lam, double sigma, const double* dx, const double* d,
             double* j, double* h, double* k) {
-  { TimerScope ts_(M, OP_JHKA); OPF_LAUNCHED(launch_jhk_a(launch_of(M, OP_JHKA), x, lam, sigma, h, j, dx, d, k, M->scratch),
+  { TimerScope ts_(M, OP_JHKA); OPF_LAUNCHED(launch_jhk_a(launch_of(M, OP_JHKA), x, lam, sigma, h, j, dx, d, k, w.scr),
                "fused J/H/condensed line kernel"); }
-  { TimerScope ts_(M, OP_KKB); OPF_LAUNCHED(launch_kkt_b(launch_of(M, OP_KKB), j, dx, d, k, M->scratch), "condensed bus kernel"); }
+  { TimerScope ts_(M, OP_KKB); OPF_LAUNCHED(launch_kkt_b(launch_of(M, OP_KKB), j, dx, d, k, w.scr), "condensed bus kernel"); }
   return OPF_OK;
 }
 
@@ -612,24 +658,24 @@ int check_sweep_args(const opf_sweep_args* a) {
   return OPF_OK;
 }
 
-int enq_sweep(opf_model* M, const opf_sweep_args* a) {
+int enq_sweep(opf_model* M, const Work& w, const opf_sweep_args* a) {
   int rc;
   // every per-element output requested: two fused passes (lines and
   // generators, then buses) plus the objective reduction
   if (a->grad && a->c && a->jvals && a->hvals && a->jtv && a->kvals) {
     { TimerScope ts_(M, OP_SWA); OPF_LAUNCHED(launch_sweep_a(launch_of(M, OP_SWA), a->x, a->lambda, a->sigma, a->v, a->hvals, a->jvals, a->diag_x,
-                                a->dcon, a->kvals, a->c, a->jtv, a->grad, M->scratch),
+                                a->dcon, a->kvals, a->c, a->jtv, a->grad, w.scr),
                  "sweep line kernel"); }
     { TimerScope ts_(M, OP_SWB); OPF_LAUNCHED(launch_sweep_b(launch_of(M, OP_SWB), a->x, a->v, a->jvals, a->diag_x, a->dcon, a->kvals, a->c,
-                                a->jtv, a->grad, M->scratch),
+                                a->jtv, a->grad, w.scr),
                  "sweep bus kernel"); }
-    if (a->f && (rc = enq_obj(M, a->x, a->f)) != OPF_OK) return rc;
+    if (a->f && (rc = enq_obj(M, w, a->x, a->f)) != OPF_OK) return rc;
     return OPF_OK;
   }
   // J, H and K together: the fused pass (K from the J / H values in registers)
   const bool fused = a->jvals && a->hvals && a->kvals;
   if (fused) {
-    if ((rc = enq_jhk(M, a->x, a->lambda, a->sigma, a->diag_x, a->dcon, a->jvals, a->hvals, a->kvals)) != OPF_OK)
+    if ((rc = enq_jhk(M, w, a->x, a->lambda, a->sigma, a->diag_x, a->dcon, a->jvals, a->hvals, a->kvals)) != OPF_OK)
       return rc;
   } else {
     if (a->jvals) { TimerScope ts_(M, OP_JAC); OPF_LAUNCHED(launch_jac(launch_of(M, OP_JAC), a->x, a->jvals), "Jacobian kernel"); }
@@ -638,8 +684,8 @@ int enq_sweep(opf_model* M, const opf_sweep_args* a) {
   }
   if (a->c) { TimerScope ts_(M, OP_CONS); OPF_LAUNCHED(launch_cons(launch_of(M, OP_CONS), a->x, a->c), "constraint kernel"); }
   if (a->grad) { TimerScope ts_(M, OP_GRAD); OPF_LAUNCHED(launch_grad(launch_of(M, OP_GRAD), a->x, a->grad), "gradient kernel"); }
-  if (a->f && (rc = enq_obj(M, a->x, a->f)) != OPF_OK) return rc;
-  if (a->jtv && (rc = enq_jt(M, a->x, a->v, a->jtv)) != OPF_OK) return rc;
+  if (a->f && (rc = enq_obj(M, w, a->x, a->f)) != OPF_OK) return rc;
+  if (a->jtv && (rc = enq_jt(M, w, a->x, a->v, a->jtv)) != OPF_OK) return rc;
   return OPF_OK;
 }
 
@@ -726,6 +772,14 @@ int opf_model_create(const opf_instance_desc* desc, int32_t ninst, int device, o
     }
     size_t scr = 0;
     for (const auto& I : M->inst) scr += (size_t)(kScratchPerLine * (int64_t)I.B * I.T + 7) / 8 * 8;
+    M->scratch_doubles = (int64_t)scr;
+    if (device < kMaxDevices) {
+      double* sp = nullptr;
+      if (static_scratch_lookup(device, &sp) != OPF_OK) {
+        release(M);
+        return fail(OPF_EHIP, "static scratch: hipGetSymbolAddress failed");
+      }
+    }
     if (hipMalloc(&M->scratch, std::max<size_t>(scr, 1) * sizeof(double)) != hipSuccess) {
       M->scratch = nullptr;
       release(M);
@@ -852,7 +906,7 @@ int opf_eval_obj(opf_model* M, const double* x, double* f) {
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(x && f, "x / f");
   DeviceGuard g(M->device);
-  return enq_obj(M, x, f);
+  return enq_obj(M, model_work(M), x, f);
 }
 
 int opf_eval_grad(opf_model* M, const double* x, double* gr) {
@@ -891,7 +945,7 @@ int opf_jtprod(opf_model* M, const double* x, const double* v, double* out) {
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(x && v && out, "x / v / jtv");
   DeviceGuard g(M->device);
-  return enq_jt(M, x, v, out);
+  return enq_jt(M, model_work(M), x, v, out);
 }
 
 int opf_set_load(opf_model* M, const double* pd, const double* qd) {
@@ -947,7 +1001,7 @@ int opf_condensed_rhs(opf_model* M, const opf_ipm_state* st, const double* grad,
   OPF_CHECK_MODEL(M);
   DeviceGuard g(M->device);
   { TimerScope ts_(M, OP_RHSR); OPF_LAUNCHED(launch_rhs_rows(Flat{M->m, M->stream}, d, c, dcon, M->wbuf), "condensed rhs row kernel"); }
-  if ((rc = enq_jt(M, st->x, M->wbuf, rhs)) != OPF_OK) return rc;
+  if ((rc = enq_jt(M, model_work(M), st->x, M->wbuf, rhs)) != OPF_OK) return rc;
   { TimerScope ts_(M, OP_RHSV); OPF_LAUNCHED(launch_rhs_vars(Flat{M->n, M->stream}, d, grad, diag_x, rhs), "condensed rhs variable kernel"); }
   return OPF_OK;
 }
@@ -972,7 +1026,7 @@ int opf_assemble_condensed(opf_model* M, const double* hv, const double* jv, con
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(hv && jv && d && kv, "hvals / jvals / dcon / kvals");
   DeviceGuard g(M->device);
-  return enq_kkt(M, hv, jv, dx, d, kv);
+  return enq_kkt(M, model_work(M), hv, jv, dx, d, kv);
 }
 
 int opf_eval_jhk(opf_model* M, const double* x, const double* lam, double sigma, const double* dx, const double* d,
@@ -980,7 +1034,7 @@ int opf_eval_jhk(opf_model* M, const double* x, const double* lam, double sigma,
   OPF_CHECK_MODEL(M);
   OPF_REQUIRE(x && lam && d && jv && hv && kv, "x / lambda / dcon / jvals / hvals / kvals");
   DeviceGuard g(M->device);
-  return enq_jhk(M, x, lam, sigma, dx, d, jv, hv, kv);
+  return enq_jhk(M, model_work(M), x, lam, sigma, dx, d, jv, hv, kv);
 }
 
 int opf_set_timing(opf_model* M, int enable) {
@@ -1011,7 +1065,7 @@ int opf_sweep(opf_model* M, const opf_sweep_args* a) {
   int rc = check_sweep_args(a);
   if (rc != OPF_OK) return rc;
   DeviceGuard g(M->device);
-  return enq_sweep(M, a);
+  return enq_sweep(M, model_work(M), a);
 }
 
 int opf_sweep_graph(opf_model* M, const opf_sweep_args* a) {
@@ -1028,7 +1082,7 @@ int opf_sweep_graph(opf_model* M, const opf_sweep_args* a) {
     hipStream_t keep = M->stream;
     M->stream = M->cap_stream;
     OPF_HIP(hipStreamBeginCapture(M->cap_stream, hipStreamCaptureModeThreadLocal));
-    rc = enq_sweep(M, a);
+    rc = enq_sweep(M, model_work(M), a);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(M->cap_stream, &graph);
     M->stream = keep;
@@ -1048,6 +1102,30 @@ int opf_sweep_graph(opf_model* M, const opf_sweep_args* a) {
   }
   OPF_HIP(hipGraphLaunch(M->gexec, M->stream));
   return OPF_OK;
+}
+
+int opf_sweep_noalloc(opf_model* M, const opf_sweep_args* a) {
+  OPF_CHECK_MODEL(M);
+  int rc = check_sweep_args(a);
+  if (rc != OPF_OK) return rc;
+  const int64_t parts = ((int64_t)M->lists[OP_OBJ].n + 31) / 32 * 32;
+  const int64_t need = M->scratch_doubles + parts;
+  if (need > kStaticScratchDoubles)
+    return fail(OPF_ERANGE, "opf_sweep_noalloc: the model needs " + std::to_string(need * 8) +
+                                " bytes of scratch, the static buffer holds " + std::to_string(kStaticScratchBytes));
+  double* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (M->device < kMaxDevices) base = g_static_ptr[M->device];
+  }
+  if (!base) return fail(OPF_EHIP, "opf_sweep_noalloc: no static scratch on this device");
+  DeviceGuard g(M->device);
+  // no timing events here: their pool may have to create events
+  const bool timing = M->timing;
+  M->timing = false;
+  rc = enq_sweep(M, Work{base, base + M->scratch_doubles}, a);
+  M->timing = timing;
+  return rc;
 }
 
 }  // extern "C"
