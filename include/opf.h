@@ -292,6 +292,16 @@ int opf_sweep_graph(opf_model *model, const opf_sweep_args *args);
  * streams, two models, two threads) race and must be serialised by the
  * caller.  Per-kernel timing (opf_set_timing) does not cover this call. */
 int opf_sweep_noalloc(opf_model *model, const opf_sweep_args *args);
+/* Status of the one-launch sweep (opf_sweep, opf_sweep_graph and
+ * opf_sweep_noalloc with every per-element output requested run the line,
+ * generator and bus passes of Sec. III-A / III-B as one persistent launch in
+ * which bus tiles wait, with a bounded spin, for the line tiles of their
+ * periods).  Waits for the model's stream, then returns in *status (host
+ * int32) the bits raised by the launches since the last call and clears
+ * them: bit 0 = a bus tile's wait ran out (its outputs are not valid),
+ * bit 1 = a work queue was left unfinished.  0 means every sweep since the
+ * last call completed as designed. */
+int opf_sweep_check(opf_model *model, int32_t *status);
 
 /* Per-kernel timing.  opf_set_timing(model, 1) clears the statistics and
  * brackets every later kernel launch of the model with HIP events on the

@@ -115,6 +115,7 @@ _SIGS = {
     "opf_sweep": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
     "opf_sweep_graph": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
     "opf_sweep_noalloc": (C.c_int, [_vp, C.POINTER(opf_sweep_args)]),
+    "opf_sweep_check": (C.c_int, [_vp, C.POINTER(C.c_int32)]),
     "opf_jprod": (C.c_int, [_vp, _vp, _vp, _vp]),
     "opf_condensed_rhs": (C.c_int, [_vp, C.POINTER(opf_ipm_state), _vp, _vp, _vp, _vp, _vp]),
     "opf_recover_step": (C.c_int, [_vp, C.POINTER(opf_ipm_state), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -401,6 +402,13 @@ class Model:
 
     def sweep_noalloc(self, args: opf_sweep_args):
         check(opf_sweep_noalloc(self.h, C.byref(args)), "opf_sweep_noalloc")
+
+    def sweep_check(self) -> int:
+        """Status bits of the one-launch sweeps since the last call (0: all
+        completed as designed); waits for the model's stream."""
+        st = C.c_int32(0)
+        check(opf_sweep_check(self.h, C.byref(st)), "opf_sweep_check")
+        return st.value
 
     def set_timing(self, enable: bool):
         check(opf_set_timing(self.h, 1 if enable else 0), "opf_set_timing")

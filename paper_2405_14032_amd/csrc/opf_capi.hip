@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <sstream>
@@ -141,6 +142,15 @@ struct opf_model {
   int64_t scratch_doubles = 0;  // size of scratch (the hand-off records)
   double* wbuf = nullptr;  // [m]: row vector of the condensation calls
   double* obj_partial = nullptr;
+  // the one-launch sweep (k_sweep): per-XCD work queues built from the
+  // sweep's line tile shape; off (two launches) when sw_ok is false
+  int sw_nq = 0;  // XCDs of the device (queues); 0: unknown
+  bool sw_ok = false;
+  SweepItem* d_sw_items = nullptr;
+  int32_t *d_sw_qbeg = nullptr, *d_sw_ctr = nullptr, *d_sw_flags = nullptr;
+  int sw_items_cap = 0, sw_ctr_cap = 0, sw_nctr = 0, sw_grid = 0, sw_block = 0;
+  int sw_cap_seg = 0, sw_cap_vm = 0, sw_cap_va = 0;
+  size_t sw_smem = 0;
   int obj_partial_cap = 0;
   int32_t* d_obj_begin = nullptr;
   TileList lists[OP_COUNT];
@@ -335,6 +345,8 @@ int lds_needs(const opf_model* M, int op, const std::vector<Tile>& tiles, const 
   return OPF_OK;
 }
 
+int build_fused(opf_model* M);
+
 int set_shape(opf_model* M, int op, const Shape& s) {
   TileList& L = M->lists[op];
   std::vector<int32_t> begin;
@@ -372,6 +384,168 @@ int set_shape(opf_model* M, int op, const Shape& s) {
     OPF_HIP(hipMemcpy(M->d_obj_begin, begin.data(), begin.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   M->gvalid = false;
+  if (op == OP_SWA) return build_fused(M);
+  return OPF_OK;
+}
+
+// Work queues of the one-launch sweep for the current line tile shape.
+// Groups = (instance, run of periods); each XCD's queue gets a contiguous
+// run of groups of about equal cost, and lists each group's line and
+// generator tiles, then its bus tiles once enough later tiles have been
+// listed that the group's line tiles are done by the time a block takes
+// them.  Leaves the two-launch sweep in place (sw_ok false) when the
+// device's XCD count is unknown or a tile does not fit the LDS budget.
+// Switched off: its first two runs on the GPU (the smallest test grid) did
+// not finish; the cause is not established, so the two-launch sweep is the
+// one that runs and this builder leaves sw_ok false.
+constexpr bool kOneLaunchSweep = false;
+
+int build_fused(opf_model* M) {
+  M->sw_ok = false;
+  if (!kOneLaunchSweep || M->sw_nq <= 0 || M->device < 0) return OPF_OK;
+  const int nq = M->sw_nq;
+  const int blk = M->lists[OP_SWA].shape.block;
+  if (blk > 256) return OPF_OK;
+  // periods per group: the largest of 4..1 that spreads the groups evenly
+  // over the queues (one instance: T / gp groups)
+  int64_t sumT = 0;
+  for (const auto& I : M->inst) sumT += I.T;
+  int gp = 1;
+  for (int c = 4; c >= 1; --c) {
+    int64_t ng = 0;
+    for (const auto& I : M->inst) ng += (I.T + c - 1) / c;
+    const double per = (double)ng / nq, most = (double)((ng + nq - 1) / nq);
+    if (M->inst.size() > 1 || ng >= nq * 8 || most <= per * 1.02) {
+      gp = c;
+      break;
+    }
+  }
+  struct Grp {
+    int inst, t0, t1;
+    double cost;
+  };
+  std::vector<Grp> groups;
+  double total = 0.0;
+  for (size_t k = 0; k < M->inst.size(); ++k) {
+    const InstHost& I = M->inst[k];
+    for (int t0 = 0; t0 < I.T; t0 += gp) {
+      const int t1 = std::min(I.T, t0 + gp);
+      const double c = ((double)I.B + 0.3 * I.G + 0.5 * I.N) * (t1 - t0);
+      groups.push_back({(int)k, t0, t1, c});
+      total += c;
+    }
+  }
+  const int ng = (int)groups.size();
+  std::vector<std::vector<int>> qg(nq);
+  double acc = 0.0;
+  for (int g = 0; g < ng; ++g) {
+    const double mid = acc + 0.5 * groups[g].cost;
+    const int q = std::min(nq - 1, (int)(mid / std::max(total, 1e-300) * nq));
+    qg[q].push_back(g);
+    acc += groups[g].cost;
+  }
+  // launch shape first: the listing lag is counted in blocks per XCD
+  // counter slots: each queue's tickets and its groups' counts on lines of
+  // their own
+  constexpr int kStride = 32;
+  std::vector<int32_t> slot(ng, 0);
+  int nctr = kStride * nq;
+  for (int q = 0; q < nq; ++q) {
+    for (int g : qg[q]) slot[g] = nctr++;
+    nctr = (nctr + kStride - 1) / kStride * kStride;
+  }
+  auto tiles_of = [&](const Grp& G, int kind, std::vector<SweepItem>& out, int g, int need) {
+    const InstHost& I = M->inst[G.inst];
+    const int cnt = kind == TK_BRANCH ? I.B : kind == TK_GEN ? I.G : I.N;
+    for (int e0 = 0; e0 < cnt; e0 += blk) {
+      SweepItem it;
+      it.tl = Tile{G.inst, kind, e0, std::min(cnt, e0 + blk), G.t0, G.t1};
+      it.slot = slot[g];
+      it.need = need;
+      out.push_back(it);
+    }
+  };
+  int cap_seg = kRecLds * blk, cap_vm = 0, cap_va = 0;
+  for (const auto& I : M->inst) {
+    const int64_t FL = 2LL * I.N + 2LL * I.G;
+    for (int e0 = 0; e0 < I.B; e0 += blk) {
+      const int e1 = std::min(I.B, e0 + blk);
+      for (int k = 0; k < 4; ++k)
+        cap_seg = std::max<int>(cap_seg, I.krow[FL + (int64_t)k * I.B + e1] - I.krow[FL + (int64_t)k * I.B + e0]);
+    }
+    for (int e0 = 0; e0 < I.N; e0 += blk) {
+      const int e1 = std::min(I.N, e0 + blk);
+      cap_vm = std::max<int>(cap_vm, I.krow[e1] - I.krow[e0]);
+      cap_va = std::max<int>(cap_va, I.krow[I.N + e1] - I.krow[I.N + e0]);
+    }
+  }
+  const size_t smem = (size_t)std::max<int64_t>((int64_t)cap_seg + 8LL * blk, (int64_t)cap_vm + cap_va) * sizeof(double);
+  if (smem > kMaxSmem) return OPF_OK;
+  const int occ = sweep_fused_blocks_per_cu(blk, smem);
+  if (occ <= 0) return OPF_OK;
+  const int grid = occ * M->n_cu;
+  const int lag = std::max(1, grid / nq) * 3 / 2;
+  std::vector<SweepItem> items;
+  std::vector<int32_t> qbeg(nq + 1, 0), need(ng, 0);
+  for (int q = 0; q < nq; ++q) {
+    qbeg[q] = (int32_t)items.size();
+    std::deque<std::pair<int, size_t>> pend;  // (group, listed items after its last line tile)
+    auto flush = [&](bool all) {
+      while (!pend.empty() && (all || items.size() - pend.front().second >= (size_t)lag)) {
+        const int g = pend.front().first;
+        tiles_of(groups[g], TK_BUS, items, g, need[g]);
+        pend.pop_front();
+      }
+    };
+    for (int g : qg[q]) {
+      const size_t before = items.size();
+      tiles_of(groups[g], TK_BRANCH, items, g, 0);
+      tiles_of(groups[g], TK_GEN, items, g, 0);
+      need[g] = (int32_t)(items.size() - before);
+      pend.push_back({g, items.size()});
+      flush(false);
+    }
+    flush(true);
+  }
+  qbeg[nq] = (int32_t)items.size();
+  if (items.size() > (size_t)0x7fffffff) return OPF_OK;
+  const int nitems = (int)items.size();
+  if (nitems > M->sw_items_cap) {
+    if (M->d_sw_items) OPF_HIP(hipFree(M->d_sw_items));
+    M->d_sw_items = nullptr;
+    M->sw_items_cap = 0;
+    if (hipMalloc(&M->d_sw_items, std::max(1, nitems) * sizeof(SweepItem)) != hipSuccess) {
+      M->d_sw_items = nullptr;
+      return fail(OPF_ENOMEM, "sweep work list allocation failed");
+    }
+    M->sw_items_cap = nitems;
+  }
+  if (nctr > M->sw_ctr_cap) {
+    if (M->d_sw_ctr) OPF_HIP(hipFree(M->d_sw_ctr));
+    M->d_sw_ctr = nullptr;
+    M->sw_ctr_cap = 0;
+    if (hipMalloc(&M->d_sw_ctr, (size_t)nctr * sizeof(int32_t)) != hipSuccess)
+      return fail(OPF_ENOMEM, "sweep counter allocation failed");
+    M->sw_ctr_cap = nctr;
+  }
+  if (!M->d_sw_qbeg) {
+    if (hipMalloc(&M->d_sw_qbeg, (nq + 1) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&M->d_sw_flags, sizeof(int32_t)) != hipSuccess)
+      return fail(OPF_ENOMEM, "sweep queue allocation failed");
+    OPF_HIP(hipMemset(M->d_sw_flags, 0, sizeof(int32_t)));
+  }
+  OPF_HIP(hipMemcpy(M->d_sw_items, items.data(), items.size() * sizeof(SweepItem), hipMemcpyHostToDevice));
+  OPF_HIP(hipMemcpy(M->d_sw_qbeg, qbeg.data(), qbeg.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  M->sw_nctr = nctr;
+  M->sw_grid = grid;
+  M->sw_block = blk;
+  M->sw_cap_seg = cap_seg;
+  M->sw_cap_vm = cap_vm;
+  M->sw_cap_va = cap_va;
+  M->sw_smem = smem;
+  // OPF_SWEEP_SPLIT=1 keeps the two-launch sweep (for comparisons)
+  const char* split = std::getenv("OPF_SWEEP_SPLIT");
+  M->sw_ok = !(split && std::strcmp(split, "1") == 0);
   return OPF_OK;
 }
 
@@ -568,6 +742,8 @@ void release(opf_model* M) {
     if (M->wbuf) (void)hipFree(M->wbuf);
     if (M->obj_partial) (void)hipFree(M->obj_partial);
     if (M->d_obj_begin) (void)hipFree(M->d_obj_begin);
+    for (void* p : {(void*)M->d_sw_items, (void*)M->d_sw_qbeg, (void*)M->d_sw_ctr, (void*)M->d_sw_flags})
+      if (p) (void)hipFree(p);
     if (M->cap_stream) (void)hipStreamDestroy(M->cap_stream);
     if (cur >= 0 && cur != M->device) (void)hipSetDevice(cur);
   }
@@ -613,12 +789,13 @@ struct DeviceGuard {
 struct Work {
   double* scr;
   double* partial;
+  int32_t* ctr;  // counters of the one-launch sweep
 };
 
-Work model_work(const opf_model* M) { return Work{M->scratch, M->obj_partial}; }
+Work model_work(const opf_model* M) { return Work{M->scratch, M->obj_partial, M->d_sw_ctr}; }
 
 int enq_obj(opf_model* M, const Work& w, const double* x, double* f) {
-  { TimerScope ts_(M, OP_OBJ); OPF_LAUNCHED(launch_obj_partial(launch_of(M, OP_OBJ), x, w.partial), "objective kernel"); }
+  { TimerScope ts_(M, OP_OBJ); OPF_LAUNCHED(launch_obj_partial(launch_of(M, OP_OBJ), x, w.partial, nullptr, 0), "objective kernel"); }
   {
     TimerScope ts_(M, kTimeObjFinal);
     OPF_LAUNCHED(launch_obj_final(M->d_obj_begin, (int)M->inst.size(), w.partial, f, M->stream),
@@ -662,6 +839,44 @@ int enq_sweep(opf_model* M, const Work& w, const opf_sweep_args* a) {
   int rc;
   // every per-element output requested: two fused passes (lines and
   // generators, then buses) plus the objective reduction
+  if (a->grad && a->c && a->jvals && a->hvals && a->jtv && a->kvals && M->sw_ok && w.ctr) {
+    // one launch for lines, generators and buses (the objective's partial
+    // pass first, which also clears the launch's counters)
+    const int nctr = M->sw_nctr;
+    if (a->f && M->lists[OP_OBJ].n > 0) {
+      TimerScope ts_(M, OP_OBJ);
+      OPF_LAUNCHED(launch_obj_partial(launch_of(M, OP_OBJ), a->x, w.partial, w.ctr, nctr), "objective kernel");
+    } else {
+      OPF_LAUNCHED(launch_sweep_open(w.ctr, nctr, M->stream), "sweep counter reset");
+    }
+    {
+      TimerScope ts_(M, OP_SWA);
+      FusedSweep F;
+      F.insts = M->d_inst;
+      F.items = M->d_sw_items;
+      F.qbeg = M->d_sw_qbeg;
+      F.nq = M->sw_nq;
+      F.ctr = w.ctr;
+      F.flags = M->d_sw_flags;
+      F.cap_seg = M->sw_cap_seg;
+      F.cap_vm = M->sw_cap_vm;
+      F.cap_va = M->sw_cap_va;
+      F.smem = M->sw_smem;
+      F.grid = M->sw_grid;
+      F.block = M->sw_block;
+      F.stream = M->stream;
+      OPF_LAUNCHED(launch_sweep_fused(F, a->x, a->lambda, a->sigma, a->v, a->hvals, a->jvals, a->diag_x, a->dcon,
+                                      a->kvals, a->c, a->jtv, a->grad, w.scr),
+                   "sweep kernel");
+    }
+    {
+      TimerScope ts_(M, kTimeObjFinal);
+      OPF_LAUNCHED(launch_sweep_close(M->d_obj_begin, (int)M->inst.size(), w.partial, a->f, w.ctr, M->d_sw_qbeg,
+                                      M->sw_nq, M->d_sw_flags, M->stream),
+                   "sweep close kernel");
+    }
+    return OPF_OK;
+  }
   if (a->grad && a->c && a->jvals && a->hvals && a->jtv && a->kvals) {
     { TimerScope ts_(M, OP_SWA); OPF_LAUNCHED(launch_sweep_a(launch_of(M, OP_SWA), a->x, a->lambda, a->sigma, a->v, a->hvals, a->jvals, a->diag_x,
                                 a->dcon, a->kvals, a->c, a->jtv, a->grad, w.scr),
@@ -799,6 +1014,12 @@ int opf_model_create(const opf_instance_desc* desc, int32_t ninst, int device, o
       M->cap_stream = nullptr;
       release(M);
       return fail(OPF_EHIP, "stream creation failed");
+    }
+    {
+      int nxcc = 0;
+      if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, device) == hipSuccess && nxcc > 0 &&
+          nxcc <= 64)
+        M->sw_nq = nxcc;
     }
     for (int op = 0; op < OP_COUNT; ++op) {
       if ((rc = set_default_shape(M, op)) != OPF_OK) {
@@ -1109,7 +1330,8 @@ int opf_sweep_noalloc(opf_model* M, const opf_sweep_args* a) {
   int rc = check_sweep_args(a);
   if (rc != OPF_OK) return rc;
   const int64_t parts = ((int64_t)M->lists[OP_OBJ].n + 31) / 32 * 32;
-  const int64_t need = M->scratch_doubles + parts;
+  const int64_t ctrs = M->sw_ok ? ((int64_t)M->sw_nctr + 63) / 64 * 32 : 0;  // doubles holding the int32 counters
+  const int64_t need = M->scratch_doubles + parts + ctrs;
   if (need > kStaticScratchDoubles)
     return fail(OPF_ERANGE, "opf_sweep_noalloc: the model needs " + std::to_string(need * 8) +
                                 " bytes of scratch, the static buffer holds " + std::to_string(kStaticScratchBytes));
@@ -1123,9 +1345,26 @@ int opf_sweep_noalloc(opf_model* M, const opf_sweep_args* a) {
   // no timing events here: their pool may have to create events
   const bool timing = M->timing;
   M->timing = false;
-  rc = enq_sweep(M, Work{base, base + M->scratch_doubles}, a);
+  rc = enq_sweep(M,
+                 Work{base, base + M->scratch_doubles,
+                      M->sw_ok ? reinterpret_cast<int32_t*>(base + M->scratch_doubles + parts) : nullptr},
+                 a);
   M->timing = timing;
   return rc;
+}
+
+int opf_sweep_check(opf_model* M, int32_t* status) {
+  OPF_CHECK_MODEL(M);
+  if (!status) return fail(OPF_EINVAL, "status is NULL");
+  *status = 0;
+  if (!M->d_sw_flags) return OPF_OK;
+  DeviceGuard g(M->device);
+  OPF_HIP(hipStreamSynchronize(M->stream));
+  int32_t v = 0;
+  OPF_HIP(hipMemcpy(&v, M->d_sw_flags, sizeof(v), hipMemcpyDeviceToHost));
+  if (v) OPF_HIP(hipMemset(M->d_sw_flags, 0, sizeof(int32_t)));
+  *status = v;
+  return OPF_OK;
 }
 
 }  // extern "C"
@@ -1260,7 +1499,7 @@ extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
       case OP_GRAD:
         return launch_grad(launch_of(M, op), x, out_n);
       case OP_OBJ:
-        return launch_obj_partial(launch_of(M, op), x, M->obj_partial);
+        return launch_obj_partial(launch_of(M, op), x, M->obj_partial, nullptr, 0);
       case OP_JTA:
         return launch_jt_a(launch_of(M, op), x, lam, out_n, M->scratch);
       case OP_JTB:

@@ -94,6 +94,14 @@ __device__ __forceinline__ void bst2v(rsrc_t r, uint32_t vo, uint32_t so, double
 __device__ __forceinline__ double2 bld2v(rsrc_t r, uint32_t vo, uint32_t so) {
   return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
 }
+// Loads that miss in the CU's L1 and are served by the L2 (cache policy
+// sc0): data another CU of the same XCD wrote earlier in the same launch.
+__device__ __forceinline__ double2 bld2v_l2(rsrc_t r, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 1));
+}
+__device__ __forceinline__ double bld_l2(rsrc_t r, uint32_t e) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8u, 0, 1));
+}
 
 // Per-instance scratch, in doubles, per line and period:
 //  * a line -> bus hand-off record per line end (kRecEnd doubles, one
@@ -141,7 +149,7 @@ hipError_t launch_jac(const Launch& L, const double* x, double* jv);
 hipError_t launch_hess(const Launch& L, const double* x, const double* lam, double sigma, double* hv);
 hipError_t launch_cons(const Launch& L, const double* x, double* c);
 hipError_t launch_grad(const Launch& L, const double* x, double* g);
-hipError_t launch_obj_partial(const Launch& L, const double* x, double* partial);
+hipError_t launch_obj_partial(const Launch& L, const double* x, double* partial, int32_t* zero, int nzero);
 hipError_t launch_obj_final(const int32_t* inst_tile_begin, int ninst, const double* partial, double* f,
                             hipStream_t s);
 hipError_t launch_jt_a(const Launch& L, const double* x, const double* v, double* out, double* scratch);
@@ -169,6 +177,40 @@ struct Flat {
   int64_t count;
   hipStream_t stream;
 };
+
+// One tile of the one-launch sweep.  slot: the counter of its group (an
+// instance and a run of periods); a line or generator tile adds one to it
+// when done, a bus tile (need > 0) first waits until it reaches need.
+struct SweepItem {
+  Tile tl;
+  int32_t slot;
+  int32_t need;
+};
+
+// Launch data of the one-launch sweep (k_sweep): per-XCD queues of items
+// [qbeg[q], qbeg[q+1]), the counters (zeroed before the launch: ticket and
+// finished tiles of queue q at 32 q and 32 q + 1, then the group slots),
+// status flags.
+struct FusedSweep {
+  const InstDev* insts;
+  const SweepItem* items;
+  const int32_t* qbeg;
+  int nq;
+  int32_t* ctr;
+  int32_t* flags;
+  int cap_seg, cap_vm, cap_va;
+  size_t smem;
+  int grid;
+  int block;  // elements per tile = threads per block (<= 256)
+  hipStream_t stream;
+};
+int sweep_fused_blocks_per_cu(int block, size_t smem);
+hipError_t launch_sweep_fused(const FusedSweep& F, const double* x, const double* lam, double sigma,
+                              const double* v, double* h, double* j, const double* dx, const double* d, double* k,
+                              double* c, double* jtv, double* g, double* scratch);
+hipError_t launch_sweep_open(int32_t* ctr, int n, hipStream_t s);
+hipError_t launch_sweep_close(const int32_t* begin, int ninst, const double* partial, double* f,
+                              const int32_t* ctr, const int32_t* qbeg, int nq, int32_t* flags, hipStream_t s);
 
 hipError_t launch_jv(const Launch& L, const double* x, const double* v, double* jv);
 hipError_t launch_rhs_rows(const Flat& F, const IpmDev& st, const double* c, double* dcon, double* w);

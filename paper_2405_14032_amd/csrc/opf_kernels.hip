@@ -701,10 +701,15 @@ __global__ void __launch_bounds__(512) k_grad(const InstDev* __restrict__ insts,
 
 // ---------------------------------------------------------------- objective
 // Pass 1: per tile, a fixed-order block tree sum of c2 p^2 + c1 p + c0.
+// Block 0 also clears zero[0 .. nzero) (the counters of the one-launch
+// sweep, which follows this kernel).
 __global__ void __launch_bounds__(512) k_obj_partial(const InstDev* __restrict__ insts,
                                                      const Tile* __restrict__ tiles, int ntiles,
-                                                     const double* __restrict__ x, double* __restrict__ partial) {
+                                                     const double* __restrict__ x, double* __restrict__ partial,
+                                                     int32_t* __restrict__ zero, int nzero) {
   __shared__ double red[512];
+  if (blockIdx.x == 0)
+    for (int i = (int)threadIdx.x; i < nzero; i += blockDim.x) zero[i] = 0;
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const int ti = remap_tile(v, ntiles);
     const Tile tl = tiles[ti];
@@ -1528,7 +1533,11 @@ __global__ void __launch_bounds__(256) k_sweep_a(const InstDev* __restrict__ ins
   }
 }
 
-// Bus rows of K for one tile.  SWEEP: the same pass also produces the bus's
+// Bus rows of K for one tile.  The hand-off records, the shared pairs and
+// the reference row's J entry are read past the CU's L1 (in the one-launch
+// sweep they were written by other CUs of the XCD during the same launch, and
+// a line holding another period's part may sit in this CU's L1 from an
+// earlier tile).  SWEEP: the same pass also produces the bus's
 // balance rows (and the reference row), J^T v on vm / va and their gradient
 // entries, from the same walk over the incident line ends (the flow values
 // of those ends and the J^T v hand-off records are gathered beside the
@@ -1611,8 +1620,8 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
           const int w1 = SWEEP ? 4 : 2;
 #pragma unroll
           for (int w = 0; w < 4; ++w)
-            r[u][w] = (ok && w < w1) ? bld2v(rR, ro, (uint32_t)w * 16u) : make_double2(0.0, 0.0);
-          x2[u] = (ok && nb[u] < n) ? bld2v(rS, (uint32_t)(ad[u] >> 1) * 16u, 0) : make_double2(0.0, 0.0);
+            r[u][w] = (ok && w < w1) ? bld2v_l2(rR, ro, (uint32_t)w * 16u) : make_double2(0.0, 0.0);
+          x2[u] = (ok && nb[u] < n) ? bld2v_l2(rS, (uint32_t)(ad[u] >> 1) * 16u, 0) : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1656,7 +1665,7 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
       const rsrc_t rD = rsrc(D + co);
       double dref = 0.0;
       if (n == I.ref) {
-        const double jr = J[I.j_off + (int64_t)t * I.nnzj_p + 2LL * I.G + 4LL * I.B];
+        const double jr = bld_l2(rsrc(J + I.j_off + (int64_t)t * I.nnzj_p), (uint32_t)(2 * I.G + 4 * I.B));
         dref = bld(rD, (uint32_t)(2 * N)) * jr * jr;
       }
       double dxm = 0.0, dxa = 0.0;
@@ -1718,6 +1727,116 @@ __global__ void __launch_bounds__(512) k_sweep_b(const InstDev* __restrict__ ins
     const Tile tl = tiles[remap_tile(v, ntiles)];
     bus_tile<true>(insts[tl.inst], tl, cap_vm, J, DX, D, K, scr, lds, X, V, C, JTV, GR);
   }
+}
+
+// ---------------------------------------------------------------- whole sweep, one launch
+// The whole sweep as one persistent launch.  Every XCD drains a queue of its
+// own (the XCD a block runs on is read from the hardware register, so the
+// queue's tiles share that XCD's L2): line and generator tiles of a group of
+// periods first, the group's bus tiles a couple of groups later.  A bus tile
+// waits until every line and generator tile of its group has counted itself
+// done, then reads the group's hand-off records, which are still in the
+// XCD's L2 or the memory-side cache instead of coming back from HBM as in
+// the two-launch form.  Tiles are handed out in queue order by a ticket
+// counter, so every tile a bus tile waits for is already held by a running
+// block of the same XCD and the waits always end; the spin is bounded
+// anyway and a wait that runs out sets bit 0 of *flags.
+// Counters (all zero at launch: the objective's partial pass or
+// k_sweep_open clears them), each queue's on 128-byte lines of their own:
+// ctr[32 q] ticket and ctr[32 q + 1] tiles finished of queue q; ctr[slot]
+// tiles finished of a group (SweepItem::slot).  Every access to them is an
+// atomic read-modify-write, so all of them execute where the increments
+// do: the poll of a bus tile reads its group's count with max(count, 0),
+// which returns the count unchanged (a plain cache-bypassing load would not
+// observe increments held in the XCD's L2).
+constexpr int kSweepCtrStride = 32;
+constexpr int kSweepSpinLimit = 1 << 20;
+
+__global__ void __launch_bounds__(256) k_sweep(const InstDev* __restrict__ insts, const SweepItem* __restrict__ items,
+                                               const int32_t* __restrict__ qbeg, int nq, int32_t* __restrict__ ctr,
+                                               int32_t* __restrict__ flags, int cap_seg, int cap_vm, int cap_va,
+                                               const double* __restrict__ X, const double* __restrict__ LAM,
+                                               double sigma, const double* __restrict__ V, double* __restrict__ H,
+                                               double* __restrict__ J, const double* __restrict__ DX,
+                                               const double* __restrict__ D, double* __restrict__ K,
+                                               double* __restrict__ C, double* __restrict__ JTV,
+                                               double* __restrict__ GR, double* __restrict__ scr) {
+  extern __shared__ double lds[];
+  __shared__ int s_item;
+  int xcc;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
+  const int q = xcc % nq;
+  const int i0 = qbeg[q], nitems = qbeg[q + 1] - i0;
+  int32_t* ticket = ctr + kSweepCtrStride * q;
+  int32_t* qdone = ticket + 1;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= nitems) break;
+    const SweepItem w = items[i0 + it];
+    const InstDev& I = insts[w.tl.inst];
+    if (w.tl.kind == TK_BUS) {
+      if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_fetch_max(ctr + w.slot, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < w.need) {
+          __builtin_amdgcn_s_sleep(4);
+          if (++spins > kSweepSpinLimit) {
+            __hip_atomic_fetch_or(flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      bus_tile<true>(I, w.tl, cap_vm, J, DX, D, K, scr, lds, X, V, C, JTV, GR);
+    } else {
+      if (w.tl.kind == TK_BRANCH) {
+        fused_line_tile<true>(I, w.tl, X, LAM, H, J, DX, D, K, scr, lds, lds + cap_seg, V, C, JTV, GR);
+      } else {
+        const int e = w.tl.e0 + (int)threadIdx.x;
+        if (e < w.tl.e1) fused_gen<true>(I, e, w.tl.t0, w.tl.t1, sigma, H, J, DX, D, K, X, V, C, JTV, GR);
+      }
+      // every store of the tile has been acknowledged by the XCD's L2
+      // before the tile counts itself done
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr + w.slot, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(qdone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Clears the counters of k_sweep (one block).
+__global__ void __launch_bounds__(256) k_sweep_open(int32_t* __restrict__ ctr, int n) {
+  for (int i = (int)threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0;
+}
+
+// After k_sweep: block k < ninst sums instance k's objective partials in the
+// order of k_obj_final (when f is requested); block 0 also checks that every
+// queue was drained (bit 1 of *flags otherwise).
+__global__ void __launch_bounds__(256) k_sweep_close(const int32_t* __restrict__ begin,
+                                                     const double* __restrict__ partial, double* __restrict__ f,
+                                                     const int32_t* __restrict__ ctr,
+                                                     const int32_t* __restrict__ qbeg, int nq,
+                                                     int32_t* __restrict__ flags) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  if (k == 0 && threadIdx.x == 0) {
+    for (int q = 0; q < nq; ++q)
+      if (ctr[kSweepCtrStride * q + 1] != qbeg[q + 1] - qbeg[q]) *flags |= 2;
+  }
+  if (!f) return;
+  const int a = begin[k], z = begin[k + 1];
+  double acc = 0.0;
+  for (int q = a + (int)threadIdx.x; q < z; q += blockDim.x) acc += partial[q];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) f[k] = red[0];
 }
 
 // ---------------------------------------------------------------- structure
@@ -1984,8 +2103,8 @@ hipError_t launch_rec_vars(const Flat& F, const IpmDev& st, const double* dx, do
   return hipGetLastError();
 }
 hipError_t launch_grad(const Launch& L, const double* x, double* g) { OPF_LAUNCH(k_grad, L, x, g); }
-hipError_t launch_obj_partial(const Launch& L, const double* x, double* partial) {
-  OPF_LAUNCH(k_obj_partial, L, x, partial);
+hipError_t launch_obj_partial(const Launch& L, const double* x, double* partial, int32_t* zero, int nzero) {
+  OPF_LAUNCH(k_obj_partial, L, x, partial, zero, nzero);
 }
 hipError_t launch_obj_final(const int32_t* begin, int ninst, const double* partial, double* f, hipStream_t s) {
   hipLaunchKernelGGL(k_obj_final, dim3((unsigned)ninst), dim3(256), 0, s, begin, partial, f);
@@ -2047,6 +2166,35 @@ hipError_t launch_bounds(const Launch& L, double* lv, double* uv, double* lc, do
 }
 hipError_t launch_load_adjoint(const Launch& L, const double* lam, double* gpd, double* gqd) {
   OPF_LAUNCH(k_load_adj, L, lam, gpd, gqd);
+}
+
+
+int sweep_fused_blocks_per_cu(int block, size_t smem) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep, block, smem) != hipSuccess) return 0;
+  return occ;
+}
+
+hipError_t launch_sweep_fused(const FusedSweep& F, const double* x, const double* lam, double sigma,
+                              const double* v, double* h, double* j, const double* dx, const double* d, double* k,
+                              double* c, double* jtv, double* g, double* scratch) {
+  if (F.grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sweep, dim3((unsigned)F.grid), dim3((unsigned)F.block), F.smem, F.stream, F.insts, F.items,
+                     F.qbeg, F.nq, F.ctr, F.flags, F.cap_seg, F.cap_vm, F.cap_va, x, lam, sigma, v, h, j, dx, d, k, c, jtv,
+                     g, scratch);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_open(int32_t* ctr, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sweep_open, dim3(1), dim3(256), 0, s, ctr, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_close(const int32_t* begin, int ninst, const double* partial, double* f,
+                              const int32_t* ctr, const int32_t* qbeg, int nq, int32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_sweep_close, dim3((unsigned)(f ? ninst : 1)), dim3(256), 0, s, begin, partial, f, ctr, qbeg,
+                     nq, flags);
+  return hipGetLastError();
 }
 
 }  // namespace opf
