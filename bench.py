@@ -445,15 +445,29 @@ def bench_chol(torch, dev, args):
 
 
 def bench_ipm(torch, dev, args):
-    """The lifted-KKT interior-point loop (opf_ipm_solve): a whole solve to
-    1e-4 of the 2000-bus, 24-period grid with its loads capped at 30 % of
-    the generation capacity (synth.cap_load: the heavier uncapped periods
-    have no feasible point found), timed after one warm-up solve, and the
-    same grid over 168 periods (one solve), and the cost of one iteration at
-    paper scale (three iterations timed; evaluation + condensation,
-    factorization, solve + recovery)."""
+    """The lifted-KKT interior-point loop (opf_ipm_solve, filter line
+    search): a whole solve to 1e-4 of the 2000-bus, 24-period grid with its
+    loads capped at 30 % of the generation capacity (synth.cap_load), timed
+    after one warm-up solve; the same grid with its loads as drawn (the
+    loop's status: converged or stalled); the capped grid over 168 periods
+    (one solve); and the cost of one iteration at paper scale (three
+    iterations timed; evaluation + condensation, factorization, solve +
+    recovery)."""
     from paper_2405_14032_amd import capi, synth
     out = {}
+    net = synth.config_network("mid")
+    M = capi.Model([net], device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    x = torch.empty(M.n, dtype=torch.float64, device=dev)
+    r = capi.ipm_solve(M, F, x, max_iter=150)
+    out["whole_solve_uncapped"] = {"workload": "N=2000 B=3200 G=400 T=24 (seed 2), loads as drawn, tol 1e-4",
+                                   "n": M.n, "m": M.m, "status": r["status_name"], "iterations": r["iterations"],
+                                   "seconds": round(r["seconds"], 3), "theta": r["theta"], "err": r["err"],
+                                   "objective": r["objective"]}
+    log(f"ipm uncapped mid solve: {out['whole_solve_uncapped']}")
+    F.close()
+    M.close()
     net = synth.cap_load(synth.config_network("mid"), 0.3)
     M = capi.Model([net], device=0)
     M.use_current_torch_stream()
@@ -462,8 +476,8 @@ def bench_ipm(torch, dev, args):
     capi.ipm_solve(M, F, x)
     r = capi.ipm_solve(M, F, x)
     out["whole_solve"] = {"workload": "N=2000 B=3200 G=400 T=24 (seed 2), loads capped at 0.3 of capacity, tol 1e-4",
-                          "n": M.n, "m": M.m, "converged": bool(r["converged"]), "iterations": r["iterations"],
-                          "seconds": round(r["seconds"], 4), "s_per_iteration": round(r["seconds"] / max(1, r["iterations"]), 4),
+                          "n": M.n, "m": M.m, "converged": bool(r["converged"]), "status": r["status_name"],
+                          "iterations": r["iterations"], "seconds": round(r["seconds"], 4), "s_per_iteration": round(r["seconds"] / max(1, r["iterations"]), 4),
                           "objective": r["objective"]}
     F.close()
     M.close()
@@ -475,7 +489,8 @@ def bench_ipm(torch, dev, args):
     x = torch.empty(M.n, dtype=torch.float64, device=dev)
     r = capi.ipm_solve(M, F, x)
     out["whole_solve_week"] = {"workload": "N=2000 B=3200 G=400 T=168 (seed 2), loads capped at 0.3 of capacity, tol 1e-4",
-                               "n": M.n, "m": M.m, "converged": bool(r["converged"]), "iterations": r["iterations"],
+                               "n": M.n, "m": M.m, "converged": bool(r["converged"]), "status": r["status_name"],
+                               "iterations": r["iterations"],
                                "seconds": round(r["seconds"], 3), "factor_s": round(r["t_factor"], 3),
                                "solve_recover_s": round(r["t_solve"], 3), "objective": r["objective"]}
     log(f"ipm week solve: {out['whole_solve_week']}")
@@ -513,7 +528,8 @@ def bench_paper_solve(torch, dev, cap):
     r = capi.ipm_solve(M, F, x, max_iter=200, verbose=1)
     out = {"workload": f"paper-scale grid N=10000 B=13000 G=2000 T=168 (seed 3), loads capped at {cap} of capacity, "
                        "tol 1e-4", "n": M.n, "m": M.m, "setup_s": round(setup_s, 2), "converged": bool(r["converged"]),
-           "iterations": r["iterations"], "seconds": round(r["seconds"], 2), "eval_s": round(r["t_eval"], 2),
+           "status": r["status_name"], "iterations": r["iterations"], "seconds": round(r["seconds"], 2),
+           "eval_s": round(r["t_eval"], 2),
            "factor_s": round(r["t_factor"], 2), "solve_recover_s": round(r["t_solve"], 2),
            "objective": r["objective"], "err": r["err"]}
     F.close()

@@ -410,26 +410,54 @@ int opf_chol_set_graph(opf_chol *chol, int enable);
  * building K at lambda = -y (opf_eval_jhk), factoring with the static-pivot
  * Cholesky and correcting the inertia (delta_w = 0, then dw_first, times
  * dw_grow, while the factorization reports static pivots), solving and
- * recovering the step (opf_recover_step).  The paper leaves the outer
- * algorithm to its solver; this one takes mu = sigma * (mean
- * complementarity product), step lengths by the fraction-to-the-boundary
- * rule (one primal, one dual; y moves with the dual length), and stops when
- * max(|p_x| / sd, |p_s| / sd, |c - s|, complementarity) <= tol with
- * sd = max(1, mean |multiplier| / 100).  Start: flat voltages, generation at
- * the middle of its box, consistent flows, every bounded entry pushed
- * 1e-2 max(1, |bound|) inside; y = 0, bound multipliers 1. */
+ * recovering the step (opf_recover_step).  Sec. III-B takes the inertia
+ * correction from the filter interior-point method of Waechter and Biegler
+ * (2006) and says a line search chooses the step length; with line_search
+ * (the default) this loop takes that method's filter line search: a
+ * monotone barrier parameter (mu_init; while the barrier problem's error is
+ * at most kappa_eps mu, mu = max(tol / 10, min(kappa_mu mu, mu^theta_mu))
+ * and the filter is emptied), fraction to the boundary
+ * tau_k = max(tau_min, 1 - mu), then backtracking (halving) on the barrier
+ * function phi = f - mu sum ln(distance to each finite bound) and the
+ * violation theta = |c(x) - s|_1 with the filter, switching (delta,
+ * s_theta, s_phi), Armijo (eta_phi) and sufficient-decrease (gamma_theta,
+ * gamma_phi) tests of that method; y moves with the accepted primal length
+ * and each bound multiplier is kept within [mu / (kappa_sigma gap),
+ * kappa_sigma mu / gap].  When no length above alpha_min (gamma_alpha times
+ * the smallest length at which a decrease can still be required) is
+ * accepted, or theta has not fallen below 0.9 of its best value for
+ * stall_iter iterations while max |c - s| > tol (steps accepted, no progress
+ * towards feasibility), the loop stops with status OPF_IPM_STALLED (the
+ * method's restoration phase is not implemented: a stall reports the
+ * instance as not solved, e.g. infeasible).  Without line_search: mu = sigma * (mean
+ * complementarity product) and the fraction-to-the-boundary lengths (tau,
+ * one primal, one dual; y moves with the dual length) are taken as they
+ * are.  Both stop when max(|p_x| / sd, |p_s| / sd, |c - s|,
+ * complementarity) <= tol with sd = max(1, mean |multiplier| / 100).
+ * Start: flat voltages, generation at the middle of its box, consistent
+ * flows, every bounded entry pushed 1e-2 max(1, |bound|) inside; y = 0,
+ * bound multipliers 1. */
 typedef struct {
   double tol;      /* stopping tolerance (1e-4)                          */
   int32_t max_iter; /* iteration limit (100)                             */
   double relax;    /* half-width of the relaxed equality rows (1e-4)     */
-  double sigma;    /* centring factor of mu (0.1)                        */
-  double tau;      /* fraction to the boundary (0.99995)                 */
+  double sigma;    /* centring factor of mu without line search (0.1)    */
+  double tau;      /* fraction to the boundary without line search (0.99995) */
   double delta_c;  /* dual regularisation (1e-8)                         */
   double dw_first, dw_grow, dw_max; /* inertia correction (1e-4, 8, 1e10) */
   double pivot_tol; /* static pivot threshold of the factorization (0)   */
   int32_t verbose;  /* 1: progress lines per iteration on stderr, 2: also
                        each factorization's delta_w and static pivots (0) */
+  int32_t line_search; /* 1: filter line search, monotone mu (1)         */
+  double mu_init, kappa_eps, kappa_mu, theta_mu, tau_min; /* (0.1, 10, 0.2, 1.5, 0.99) */
+  double gamma_theta, gamma_phi, eta_phi, s_theta, s_phi, delta; /* (1e-5, 1e-8, 1e-8, 1.1, 2.3, 1) */
+  double gamma_alpha, kappa_sigma; /* (0.05, 1e10)                       */
+  int32_t stall_iter; /* line search: stop as stalled when theta has not
+                         fallen below 0.9 of its best for this many
+                         iterations while max |c - s| > tol; 0: never (25) */
 } opf_ipm_options;
+
+enum { OPF_IPM_CONVERGED = 0, OPF_IPM_MAX_ITER = 1, OPF_IPM_STALLED = 2 };
 
 typedef struct {
   int32_t converged;      /* 1 if the tolerance was met                  */
@@ -439,6 +467,9 @@ typedef struct {
   double err;             /* final value of the stopping measure          */
   double seconds;         /* wall time of the call                        */
   double t_eval, t_factor, t_solve; /* evaluation + condensation, factorization, solve + recovery + step */
+  int32_t status;         /* OPF_IPM_CONVERGED / _MAX_ITER / _STALLED      */
+  int32_t trials;         /* line-search trial points evaluated           */
+  double theta;           /* final |c(x) - s|_1                           */
 } opf_ipm_result;
 
 void opf_ipm_default_options(opf_ipm_options *opt);
@@ -446,8 +477,9 @@ void opf_ipm_default_options(opf_ipm_options *opt);
  * the final primal point; y_out: device [m] or NULL, the final multipliers
  * of c(x) - s = 0.  opt NULL = defaults.  Allocates its work vectors on the
  * model's device for the duration of the call and synchronises the model's
- * stream once per iteration.  Returns OPF_OK also when the iteration limit
- * stops it (res->converged = 0); OPF_EINVAL on bad options, a non-finite
+ * stream once per iteration (and once per line-search trial).  Returns
+ * OPF_OK also when the iteration limit or a stall stops it
+ * (res->converged = 0, res->status says which); OPF_EINVAL on bad options, a non-finite
  * iterate (any non-finite residual) or a failed inertia correction;
  * OPF_ENODEV on a host-only model. */
 int opf_ipm_solve(opf_model *model, opf_chol *chol, const opf_ipm_options *opt,

@@ -784,44 +784,100 @@ def ipm_residuals(net, w, mu):
 
 
 def ipm_solve(net, tol=1e-4, max_iter=100, relax=1e-4, sigma=0.1, tau=0.99995, delta_c=1e-8, dw_first=1e-4,
-              dw_grow=8.0, dw_max=1e10):
+              dw_grow=8.0, dw_max=1e10, line_search=True, mu_init=0.1, kappa_eps=10.0, kappa_mu=0.2,
+              theta_mu=1.5, tau_min=0.99, gamma_theta=1e-5, gamma_phi=1e-8, eta_phi=1e-8, s_theta=1.1,
+              s_phi=2.3, delta=1.0, gamma_alpha=0.05, kappa_sigma=1e10, stall_iter=25):
     """Primal-dual interior-point method on the lifted formulation of
     Sec. III-B: the rows c(x) are relaxed to sl <= s <= su with c(x) - s = 0
     (equality rows widened by +-relax), each iteration solves the condensed
     system K dx = rhs (condensed_rhs, the condensed matrix of the Hessian of
     the Lagrangian with lambda = -y, kkt_solve) and recovers the other step
-    components (recover_step).  The paper leaves the outer algorithm to its
-    solver; this one takes:
+    components (recover_step).  Sec. III-B takes the inertia correction from
+    the filter interior-point method of Waechter and Biegler (2006) and says
+    that a line search chooses the step length without naming one; the
+    reading taken here is that method's filter line search:
 
-    * barrier parameter mu = sigma * (mean complementarity product);
     * inertia correction: delta_w = 0, else dw_first, growing by dw_grow,
       until K is positive definite (the condition static pivoting needs);
     * the Newton step is the negated (dx, ds, dzl, dzu, dvl, dvu) with +dy
       (the condensed system is written for the residuals, not their negative);
-    * step lengths by the fraction-to-the-boundary rule (tau) alone, one
-      for the primal (x, s) and one for the dual (bound multipliers) part; y
+    * fraction to the boundary, tau_k = max(tau_min, 1 - mu), one length for
+      the primal (x, s) part and one for the bound multipliers;
+    * with ``line_search`` (the default): a monotone barrier parameter
+      (start mu_init; while the barrier problem's error -- the stopping
+      measure with the complementarity products taken minus mu -- is at most
+      kappa_eps mu, mu = max(tol / 10, min(kappa_mu mu, mu^theta_mu)) and the
+      filter is emptied), and a backtracking line search (halving from the
+      fraction-to-the-boundary length) on the barrier function
+      phi = f - mu sum ln(distance to each finite bound) and the violation
+      theta = |c(x) - s|_1: a trial point must not be dominated by a filter
+      entry nor exceed theta_max = 1e4 max(1, theta_0); when phi decreases
+      along the step (switching condition alpha (-phi'd)^s_phi >
+      delta theta^s_theta) and theta <= theta_min = 1e-4 max(1, theta_0) it
+      must satisfy the Armijo condition on phi (eta_phi), otherwise it must
+      reduce theta by the factor (1 - gamma_theta) or phi by gamma_phi theta,
+      and then (gamma_theta theta, phi - gamma_phi theta) joins the filter.
+      The multipliers y move with the accepted primal length; afterwards each
+      bound multiplier is kept within [mu / (kappa_sigma gap),
+      kappa_sigma mu / gap].  When the length falls below alpha_min (gamma_alpha
+      times the smallest length at which a decrease can still be required)
+      the loop stops with status "stalled": the method's restoration phase,
+      which would look for a less infeasible point, is not implemented, so a
+      stall reports the instance as not solved (infeasible or too hard from
+      this start).  The same status ends a run whose violation theta has not
+      fallen below 0.9 of its best value for stall_iter iterations while
+      max |c - s| > tol (steps still accepted, but no progress towards
+      feasibility: what would send the method into restoration);
+    * without ``line_search``: mu = sigma * (mean complementarity product) and
+      the fraction-to-the-boundary lengths (tau) are taken as they are; y
       moves with the dual length;
     * stop when max(|p_x| / sd, |p_s| / sd, |c - s|, complementarity) <= tol,
       sd = max(1, mean |multiplier| / 100).
 
     Returns a dict: the iterate, objective, iterations, factorizations,
-    converged, and the per-iteration history (err, mu, delta_w, alpha_p,
-    alpha_d)."""
+    converged, status ("converged", "stalled", "max_iter"), the final
+    violation theta, and the per-iteration history (err, mu, delta_w,
+    alpha_p, alpha_d, trials)."""
     L = Layout(net)
     n, m = L.n, L.m
     w = ipm_start(net, relax)
     hl, hu, gl, gu = (np.isfinite(w[k]) for k in ("xl", "xu", "sl", "su"))
     hist, nfact = [], 0
+    status = "max_iter"
+    mu = mu_init
+    filt = []
+    th0 = _violation(net, w["x"], w["s"])
+    theta_max, theta_min = 1e4 * max(1.0, th0), 1e-4 * max(1.0, th0)
+    th_best, it_best = th0, 0
 
     for it in range(max_iter + 1):
         rd, rs, rp, gaps, c, grad = ipm_residuals(net, w, 0.0)
         mult = (np.abs(w["y"]).sum() + w["zl"].sum() + w["zu"].sum() + w["vl"].sum() + w["vu"].sum())
         sd = max(1.0, mult / (m + 2 * n) / 100.0)
-        err = max(np.abs(rd).max() / sd, np.abs(rs).max() / sd, np.abs(rp).max(),
-                  gaps.max() if gaps.size else 0.0)
-        if err <= tol or it == max_iter:
+        base = max(np.abs(rd).max() / sd, np.abs(rs).max() / sd, np.abs(rp).max())
+        err = max(base, gaps.max() if gaps.size else 0.0)
+        if err <= tol:
+            status = "converged"
             break
-        mu = sigma * gaps.sum() / max(gaps.size, 1)
+        if it == max_iter:
+            break
+        if line_search:
+            th = _violation(net, w["x"], w["s"])
+            if th < 0.9 * th_best:
+                th_best, it_best = th, it
+            if stall_iter > 0 and it - it_best >= stall_iter and np.abs(rp).max() > tol:
+                status = "stalled"
+                break
+            while mu > tol / 10.0:
+                err_mu = max(base, np.abs(gaps - mu).max() if gaps.size else 0.0)
+                if err_mu > kappa_eps * mu:
+                    break
+                mu = max(tol / 10.0, min(kappa_mu * mu, mu ** theta_mu))
+                filt = []
+            tau_k = max(tau_min, 1.0 - mu)
+        else:
+            mu = sigma * gaps.sum() / max(gaps.size, 1)
+            tau_k = tau
         jac = jacobian(net, w["x"])
         hess = hessian(net, w["x"], -w["y"], 1.0)
         dw = 0.0
@@ -838,20 +894,98 @@ def ipm_solve(net, tol=1e-4, max_iter=100, relax=1e-4, sigma=0.1, tau=0.99995, d
         dx = kkt_solve(n, rp_, ci_, kv_, rhs)
         ds, dy, dzl, dzu, dvl, dvu = recover_step(net, st, c, dx)
         step = dict(x=-dx, s=-ds, y=dy, zl=-dzl, zu=-dzu, vl=-dvl, vu=-dvu)
-        ap = min(_max_step(w["x"], step["x"], w["xl"], hl, tau, False),
-                 _max_step(w["x"], step["x"], w["xu"], hu, tau, True),
-                 _max_step(w["s"], step["s"], w["sl"], gl, tau, False),
-                 _max_step(w["s"], step["s"], w["su"], gu, tau, True))
-        ad = min(_max_step(w[k], step[k], np.zeros(w[k].size), msk, tau, False)
+        ap = min(_max_step(w["x"], step["x"], w["xl"], hl, tau_k, False),
+                 _max_step(w["x"], step["x"], w["xu"], hu, tau_k, True),
+                 _max_step(w["s"], step["s"], w["sl"], gl, tau_k, False),
+                 _max_step(w["s"], step["s"], w["su"], gu, tau_k, True))
+        ad = min(_max_step(w[k], step[k], np.zeros(w[k].size), msk, tau_k, False)
                  for k, msk in (("zl", hl), ("zu", hu), ("vl", gl), ("vu", gu)))
+        trials, ay = 1, ad
+        if line_search:
+            ph = _barrier(net, w, w["x"], w["s"], mu)
+            dph = _barrier_slope(grad, w, step["x"], step["s"], mu)
+            if dph < 0.0:
+                amin = gamma_alpha * min(gamma_theta, gamma_phi * th / -dph, delta * th ** s_theta / (-dph) ** s_phi)
+            else:
+                amin = gamma_alpha * gamma_theta
+            a, kind = ap, None
+            while True:
+                xt, stt = w["x"] + a * step["x"], w["s"] + a * step["s"]
+                tht, pht = _violation(net, xt, stt), _barrier(net, w, xt, stt, mu)
+                if tht <= theta_max and all(tht < tj or pht < pj for tj, pj in filt):
+                    switching = dph < 0.0 and a * (-dph) ** s_phi > delta * th ** s_theta
+                    if switching and th <= theta_min:
+                        if pht <= ph + eta_phi * a * dph:
+                            kind = "f"
+                    elif tht <= (1.0 - gamma_theta) * th or pht <= ph - gamma_phi * th:
+                        kind = "h"
+                if kind is not None:
+                    break
+                a *= 0.5
+                trials += 1
+                if a < amin:
+                    break
+            if kind is None:
+                hist.append(dict(err=err, mu=mu, delta_w=dw, alpha_p=0.0, alpha_d=0.0, trials=trials))
+                status = "stalled"
+                break
+            if kind == "h":
+                filt.append(((1.0 - gamma_theta) * th, ph - gamma_phi * th))
+            ap, ay = a, a
         w = dict(w)
         for k in ("x", "s"):
             w[k] = w[k] + ap * step[k]
-        for k in ("y", "zl", "zu", "vl", "vu"):
+        w["y"] = w["y"] + ay * step["y"]
+        for k in ("zl", "zu", "vl", "vu"):
             w[k] = w[k] + ad * step[k]
-        hist.append(dict(err=err, mu=mu, delta_w=dw, alpha_p=ap, alpha_d=ad))
+        if line_search:
+            _safeguard(w, mu, kappa_sigma)
+        hist.append(dict(err=err, mu=mu, delta_w=dw, alpha_p=ap, alpha_d=ad, trials=trials))
     return dict(w=w, x=w["x"], objective=objective(net, w["x"]), iterations=it, factorizations=nfact,
-                converged=err <= tol, err=err, history=hist)
+                converged=status == "converged", status=status, err=err,
+                theta=_violation(net, w["x"], w["s"]), history=hist)
+
+
+def _violation(net, x, s):
+    """theta = |c(x) - s|_1, the violation the filter measures."""
+    return float(np.abs(constraints(net, x) - s).sum())
+
+
+def _barrier(net, w, x, s, mu):
+    """phi_mu = f(x) - mu * (sum of ln(distance to each finite bound)) over
+    the variable bounds and the relaxed row bounds."""
+    out = objective(net, x)
+    for v, key, upper in ((x, "xl", False), (x, "xu", True), (s, "sl", False), (s, "su", True)):
+        b = w[key]
+        sel = np.isfinite(b)
+        gap = (b[sel] - v[sel]) if upper else (v[sel] - b[sel])
+        out -= mu * np.log(gap).sum()
+    return float(out)
+
+
+def _barrier_slope(grad, w, px, ps, mu):
+    """Directional derivative of phi_mu along the primal step (px, ps)."""
+    out = float(np.dot(grad, px))
+    for v, p, key, upper in ((w["x"], px, "xl", False), (w["x"], px, "xu", True), (w["s"], ps, "sl", False),
+                             (w["s"], ps, "su", True)):
+        b = w[key]
+        sel = np.isfinite(b)
+        gap = (b[sel] - v[sel]) if upper else (v[sel] - b[sel])
+        out += mu * (p[sel] / gap).sum() if upper else -mu * (p[sel] / gap).sum()
+    return out
+
+
+def _safeguard(w, mu, kappa_sigma):
+    """Keeps every bound multiplier within [mu / (kappa_sigma gap),
+    kappa_sigma mu / gap] of its bound's distance (gap)."""
+    for z, v, key, upper in (("zl", "x", "xl", False), ("zu", "x", "xu", True), ("vl", "s", "sl", False),
+                             ("vu", "s", "su", True)):
+        b = w[key]
+        sel = np.isfinite(b)
+        gap = (b[sel] - w[v][sel]) if upper else (w[v][sel] - b[sel])
+        zz = w[z].copy()
+        zz[sel] = np.maximum(np.minimum(zz[sel], kappa_sigma * mu / gap), mu / (kappa_sigma * gap))
+        w[z] = zz
 
 
 def _max_step(v, dv, b, mask, tau, upper):

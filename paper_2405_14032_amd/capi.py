@@ -30,6 +30,8 @@ if not os.path.exists(LIB_PATH):
 lib = C.CDLL(LIB_PATH)
 
 OPF_OK, OPF_EINVAL, OPF_ERANGE, OPF_ENOMEM, OPF_EHIP, OPF_ENODEV = 0, -1, -2, -3, -4, -5
+OPF_IPM_CONVERGED, OPF_IPM_MAX_ITER, OPF_IPM_STALLED = 0, 1, 2
+IPM_STATUS = {OPF_IPM_CONVERGED: "converged", OPF_IPM_MAX_ITER: "max_iter", OPF_IPM_STALLED: "stalled"}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -74,13 +76,19 @@ class opf_chol_info(C.Structure):
 class opf_ipm_options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("relax", C.c_double), ("sigma", C.c_double),
                 ("tau", C.c_double), ("delta_c", C.c_double), ("dw_first", C.c_double), ("dw_grow", C.c_double),
-                ("dw_max", C.c_double), ("pivot_tol", C.c_double), ("verbose", C.c_int32)]
+                ("dw_max", C.c_double), ("pivot_tol", C.c_double), ("verbose", C.c_int32),
+                ("line_search", C.c_int32), ("mu_init", C.c_double), ("kappa_eps", C.c_double),
+                ("kappa_mu", C.c_double), ("theta_mu", C.c_double), ("tau_min", C.c_double),
+                ("gamma_theta", C.c_double), ("gamma_phi", C.c_double), ("eta_phi", C.c_double),
+                ("s_theta", C.c_double), ("s_phi", C.c_double), ("delta", C.c_double), ("gamma_alpha", C.c_double),
+                ("kappa_sigma", C.c_double), ("stall_iter", C.c_int32)]
 
 
 class opf_ipm_result(C.Structure):
     _fields_ = [("converged", C.c_int32), ("iterations", C.c_int32), ("factorizations", C.c_int32),
                 ("objective", C.c_double), ("err", C.c_double), ("seconds", C.c_double), ("t_eval", C.c_double),
-                ("t_factor", C.c_double), ("t_solve", C.c_double)]
+                ("t_factor", C.c_double), ("t_solve", C.c_double), ("status", C.c_int32), ("trials", C.c_int32),
+                ("theta", C.c_double)]
 
 
 class opf_ipm_state(C.Structure):
@@ -506,4 +514,6 @@ def ipm_solve(model: Model, chol: Chol, x_out, y_out=None, **opts) -> dict:
     r = opf_ipm_result()
     check(opf_ipm_solve(model.h, chol.h, C.byref(o), model._a(x_out, model.n, "x_out"),
                         model._a(y_out, model.m, "y_out", optional=True), C.byref(r)), "opf_ipm_solve")
-    return {k: getattr(r, k) for k, _ in opf_ipm_result._fields_}
+    out = {k: getattr(r, k) for k, _ in opf_ipm_result._fields_}
+    out["status_name"] = IPM_STATUS.get(out["status"], str(out["status"]))
+    return out

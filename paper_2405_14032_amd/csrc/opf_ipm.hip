@@ -101,8 +101,9 @@ struct Iter {
 // Per-block partials of the residual measures: [0] max |p_x|, [1] max |p_s|,
 // [2] max |c - s|, [3] max complementarity product, [4] their sum, [5]
 // their count, [6] sum of |multipliers|, [7] number of non-finite terms
-// (fmax would drop a NaN, so they are counted instead).
-constexpr int kNR = 8;
+// (fmax would drop a NaN, so they are counted instead), [8] min
+// complementarity product (with [3]: max |product - mu| for any mu).
+constexpr int kNR = 9;
 
 __device__ __forceinline__ void block_reduce(double* sh, int op, double& v) {
   // op 0: max, 1: sum, 2: min
@@ -124,7 +125,7 @@ __global__ void __launch_bounds__(kRedBlock) k_resid(Iter w, const double* __res
                                                      const double* __restrict__ jtv, const double* __restrict__ c,
                                                      int64_t n, int64_t m, double* __restrict__ part) {
   __shared__ double sh[kRedBlock];
-  double rd = 0.0, rs = 0.0, rp = 0.0, gmax = 0.0, gsum = 0.0, gcnt = 0.0, msum = 0.0, bad = 0.0;
+  double rd = 0.0, rs = 0.0, rp = 0.0, gmax = 0.0, gsum = 0.0, gcnt = 0.0, msum = 0.0, bad = 0.0, gmin = INFINITY;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
     const bool hl = fin(w.xl[i]), hu = fin(w.xu[i]);
@@ -135,12 +136,14 @@ __global__ void __launch_bounds__(kRedBlock) k_resid(Iter w, const double* __res
     if (hl) {
       const double g = zl * (w.x[i] - w.xl[i]);
       gmax = fmax(gmax, g);
+      gmin = fmin(gmin, g);
       gsum += g;
       gcnt += 1.0;
     }
     if (hu) {
       const double g = zu * (w.xu[i] - w.x[i]);
       gmax = fmax(gmax, g);
+      gmin = fmin(gmin, g);
       gsum += g;
       gcnt += 1.0;
     }
@@ -156,12 +159,14 @@ __global__ void __launch_bounds__(kRedBlock) k_resid(Iter w, const double* __res
     if (gl) {
       const double g = vl * (w.s[i] - w.sl[i]);
       gmax = fmax(gmax, g);
+      gmin = fmin(gmin, g);
       gsum += g;
       gcnt += 1.0;
     }
     if (gu) {
       const double g = vu * (w.su[i] - w.s[i]);
       gmax = fmax(gmax, g);
+      gmin = fmin(gmin, g);
       gsum += g;
       gcnt += 1.0;
     }
@@ -175,8 +180,10 @@ __global__ void __launch_bounds__(kRedBlock) k_resid(Iter w, const double* __res
   block_reduce(sh, 1, gcnt);
   block_reduce(sh, 1, msum);
   block_reduce(sh, 1, bad);
+  block_reduce(sh, 2, gmin);
   if (threadIdx.x == 0) {
     double* o = part + (int64_t)blockIdx.x * kNR;
+    o[8] = gmin;
     o[0] = rd;
     o[1] = rs;
     o[2] = rp;
@@ -250,6 +257,93 @@ __global__ void k_update(Iter w, Step st, double ap, double ad, int64_t n, int64
   }
 }
 
+// The filter line search: per-block partials of the violation
+// theta = sum |c - s| ([0]) and of sum ln(distance to each finite bound)
+// ([1]) at the point (x, s); c = c(x).
+__global__ void __launch_bounds__(kRedBlock) k_barrier(Iter w, const double* __restrict__ x,
+                                                       const double* __restrict__ s, const double* __restrict__ c,
+                                                       int64_t n, int64_t m, double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  double th = 0.0, lg = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (fin(w.xl[i])) lg += log(x[i] - w.xl[i]);
+    if (fin(w.xu[i])) lg += log(w.xu[i] - x[i]);
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) {
+    th += fabs(c[i] - s[i]);
+    if (fin(w.sl[i])) lg += log(s[i] - w.sl[i]);
+    if (fin(w.su[i])) lg += log(w.su[i] - s[i]);
+  }
+  block_reduce(sh, 1, th);
+  block_reduce(sh, 1, lg);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = th;
+    part[2 * blockIdx.x + 1] = lg;
+  }
+}
+
+// Per-block partials of the barrier function's slope along the primal step
+// (-dx, -ds): [0] grad f . (-dx), [1] sum over finite bounds of
+// -step / (v - lo) and +step / (hi - v) (times mu on the host).
+__global__ void __launch_bounds__(kRedBlock) k_slope(Iter w, Step st, const double* __restrict__ grad, int64_t n,
+                                                     int64_t m, double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  double gd = 0.0, bd = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double p = -st.dx[i];
+    gd += grad[i] * p;
+    if (fin(w.xl[i])) bd -= p / (w.x[i] - w.xl[i]);
+    if (fin(w.xu[i])) bd += p / (w.xu[i] - w.x[i]);
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) {
+    const double p = -st.ds[i];
+    if (fin(w.sl[i])) bd -= p / (w.s[i] - w.sl[i]);
+    if (fin(w.su[i])) bd += p / (w.su[i] - w.s[i]);
+  }
+  block_reduce(sh, 1, gd);
+  block_reduce(sh, 1, bd);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = gd;
+    part[2 * blockIdx.x + 1] = bd;
+  }
+}
+
+// Trial point x + a (-dx), s + a (-ds).
+__global__ void k_trial(Iter w, Step st, double a, double* __restrict__ xt, double* __restrict__ stl, int64_t n,
+                        int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) xt[i] = w.x[i] - a * st.dx[i];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) stl[i] = w.s[i] - a * st.ds[i];
+}
+
+// Accepts the trial point: x, s from (xt, st), y with the primal length a,
+// the bound multipliers with the dual length ad, then each bound multiplier
+// kept within [mu / (ks gap), ks mu / gap].
+__device__ __forceinline__ double guard(double z, double gap, double mu, double ks) {
+  return fmax(fmin(z, ks * mu / gap), mu / (ks * gap));
+}
+
+__global__ void k_accept(Iter w, Step st, const double* __restrict__ xt, const double* __restrict__ stl, double a,
+                         double ad, double mu, double ks, int64_t n, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double x = xt[i];
+    w.x[i] = x;
+    if (fin(w.xl[i])) w.zl[i] = guard(w.zl[i] - ad * st.dzl[i], x - w.xl[i], mu, ks);
+    if (fin(w.xu[i])) w.zu[i] = guard(w.zu[i] - ad * st.dzu[i], w.xu[i] - x, mu, ks);
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) {
+    const double s = stl[i];
+    w.s[i] = s;
+    w.y[i] += a * st.dy[i];
+    w.ly[i] = -w.y[i];
+    if (fin(w.sl[i])) w.vl[i] = guard(w.vl[i] - ad * st.dvl[i], s - w.sl[i], mu, ks);
+    if (fin(w.su[i])) w.vu[i] = guard(w.vu[i] - ad * st.dvu[i], w.su[i] - s, mu, ks);
+  }
+}
+
 int grid_of(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
 
 #define IPM_CHK(x)                    \
@@ -301,6 +395,21 @@ void opf_ipm_default_options(opf_ipm_options* o) {
   o->dw_max = 1e10;
   o->pivot_tol = 0.0;
   o->verbose = 0;
+  o->line_search = 1;
+  o->mu_init = 0.1;
+  o->kappa_eps = 10.0;
+  o->kappa_mu = 0.2;
+  o->theta_mu = 1.5;
+  o->tau_min = 0.99;
+  o->gamma_theta = 1e-5;
+  o->gamma_phi = 1e-8;
+  o->eta_phi = 1e-8;
+  o->s_theta = 1.1;
+  o->s_phi = 2.3;
+  o->delta = 1.0;
+  o->gamma_alpha = 0.05;
+  o->kappa_sigma = 1e10;
+  o->stall_iter = 25;
 }
 
 int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, double* x_out, double* y_out,
@@ -315,6 +424,12 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
       !(opt.tau > 0.0 && opt.tau < 1.0) || !(opt.delta_c >= 0.0) || !(opt.dw_first > 0.0) || !(opt.dw_grow > 1.0) ||
       !(opt.dw_max >= opt.dw_first) || !std::isfinite(opt.pivot_tol))
     return api_fail(OPF_EINVAL, "ipm: invalid options");
+  if (opt.line_search &&
+      (!(opt.mu_init > 0.0) || !(opt.kappa_eps > 0.0) || !(opt.kappa_mu > 0.0 && opt.kappa_mu < 1.0) ||
+       !(opt.theta_mu > 1.0) || !(opt.tau_min > 0.0 && opt.tau_min < 1.0) || !(opt.gamma_theta > 0.0) ||
+       !(opt.gamma_phi > 0.0) || !(opt.eta_phi > 0.0) || !(opt.s_theta > 1.0) || !(opt.s_phi > 1.0) ||
+       !(opt.delta > 0.0) || !(opt.gamma_alpha > 0.0) || !(opt.kappa_sigma >= 1.0) || opt.stall_iter < 0))
+    return api_fail(OPF_EINVAL, "ipm: invalid line-search options");
   std::memset(res, 0, sizeof(*res));
   const double t_start = now_s();
   hipStream_t st = model_stream(M);
@@ -324,9 +439,11 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
   Buffers B;
   double *x, *s, *y, *ly, *zl, *zu, *vl, *vu, *xl, *xu, *cl, *cu, *sl, *su;
   double *grad, *c, *jtv, *diag_x, *dcon, *rhs, *dx, *ds, *dy, *dzl, *dzu, *dvl, *dvu, *jv, *hv, *kv, *part, *fobj;
+  double *xt, *stl, *ct;  // line-search trial point and its constraints
   // variable-length (n) and row-length (m) work vectors
-  for (double** p : {&x, &xl, &xu, &zl, &zu, &grad, &jtv, &diag_x, &rhs, &dx, &dzl, &dzu}) IPM_CHK(B.get(n, p));
-  for (double** p : {&s, &y, &ly, &vl, &vu, &cl, &cu, &sl, &su, &c, &dcon, &ds, &dy, &dvl, &dvu}) IPM_CHK(B.get(m, p));
+  for (double** p : {&x, &xl, &xu, &zl, &zu, &grad, &jtv, &diag_x, &rhs, &dx, &dzl, &dzu, &xt}) IPM_CHK(B.get(n, p));
+  for (double** p : {&s, &y, &ly, &vl, &vu, &cl, &cu, &sl, &su, &c, &dcon, &ds, &dy, &dvl, &dvu, &stl, &ct})
+    IPM_CHK(B.get(m, p));
   IPM_CHK(B.get(d.nnz_jac, &jv));
   IPM_CHK(B.get(d.nnz_hess, &hv));
   IPM_CHK(B.get(d.nnz_kkt, &kv));
@@ -356,9 +473,46 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
   Iter w{x, s, y, ly, zl, zu, vl, vu, xl, xu, sl, su};
   Step stp{dx, ds, dy, dzl, dzu, dvl, dvu};
   std::vector<double> hp((size_t)kRedGrid * kNR);
+  std::vector<double> fh(d.ninst);
   double t_eval = 0, t_fac = 0, t_sol = 0;
-  int it = 0, nfact = 0;
+  int it = 0, nfact = 0, trials = 0;
   double err = 0.0;
+  int status = OPF_IPM_MAX_ITER;
+  // theta = |c - s|_1, f and sum ln(gaps) at (xx, ss), so that
+  // phi = f - mu sum ln(gaps); cc = c(xx) (computed here when eval_c)
+  auto theta_phi = [&](const double* xx, const double* ss, double* cc, bool eval_c, double& th, double& fv,
+                       double& lgv) -> int {
+    if (eval_c) IPM_CHK(opf_eval_cons(M, xx, cc));
+    IPM_CHK(opf_eval_obj(M, xx, fobj));
+    hipLaunchKernelGGL(k_barrier, dim3(kRedGrid), dim3(kRedBlock), 0, st, w, xx, ss, (const double*)cc, n, m, part);
+    IPM_HIP(hipGetLastError(), "ipm: barrier kernel");
+    IPM_HIP(hipMemcpyAsync(hp.data(), part, 2 * kRedGrid * sizeof(double), hipMemcpyDeviceToHost, st), "ipm: copy");
+    IPM_HIP(hipMemcpyAsync(fh.data(), fobj, d.ninst * sizeof(double), hipMemcpyDeviceToHost, st), "ipm: copy");
+    IPM_HIP(hipStreamSynchronize(st), "ipm: sync");
+    double t = 0.0, lg = 0.0, f = 0.0;
+    for (int b = 0; b < kRedGrid; ++b) {
+      t += hp[2 * b];
+      lg += hp[2 * b + 1];
+    }
+    for (double v : fh) f += v;
+    th = t;
+    fv = f;
+    lgv = lg;
+    return OPF_OK;
+  };
+  // filter line search state (monotone mu, filter emptied when mu changes)
+  const bool ls = opt.line_search != 0;
+  double mu = opt.mu_init;
+  std::vector<std::pair<double, double>> filt;
+  double theta_max = 0.0, theta_min = 0.0, th_best = 0.0;
+  int it_best = 0;
+  if (ls) {
+    double th0 = 0.0, f0 = 0.0, lg0 = 0.0;
+    IPM_CHK(theta_phi(x, s, c, false, th0, f0, lg0));
+    theta_max = 1e4 * std::max(1.0, th0);
+    theta_min = 1e-4 * std::max(1.0, th0);
+    th_best = th0;
+  }
   for (;; ++it) {
     double t0 = now_s();
     IPM_CHK(opf_eval_grad(M, x, grad));
@@ -370,18 +524,50 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
     IPM_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st), "ipm: copy");
     IPM_HIP(hipStreamSynchronize(st), "ipm: sync");
     t_eval += now_s() - t0;
-    double r[kNR] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double r[kNR] = {0, 0, 0, 0, 0, 0, 0, 0, INFINITY};
     for (int b = 0; b < kRedGrid; ++b)
-      for (int k = 0; k < kNR; ++k) r[k] = k <= 3 ? std::max(r[k], hp[b * kNR + k]) : r[k] + hp[b * kNR + k];
+      for (int k = 0; k < kNR; ++k) {
+        const double v = hp[b * kNR + k];
+        r[k] = k <= 3 ? std::max(r[k], v) : (k == 8 ? std::min(r[k], v) : r[k] + v);
+      }
     const double sd = std::max(1.0, r[6] / (double)(m + 2 * n) / 100.0);
-    err = std::max({r[0] / sd, r[1] / sd, r[2], r[3]});
+    const double base = std::max({r[0] / sd, r[1] / sd, r[2]});
+    err = std::max(base, r[3]);
     if (r[7] > 0.0 || !std::isfinite(err))
       return api_fail(OPF_EINVAL, "ipm: the iterate is not finite at iteration " + std::to_string(it));
     if (opt.verbose)
       std::fprintf(stderr, "ipm %3d  err %.3e  |p_x| %.3e  |p_s| %.3e  |c-s| %.3e  compl %.3e  mu %.3e\n", it, err,
-                   r[0], r[1], r[2], r[3], opt.sigma * r[4] / std::max(1.0, r[5]));
-    if (err <= opt.tol || it >= opt.max_iter) break;
-    const double mu = opt.sigma * r[4] / std::max(1.0, r[5]);
+                   r[0], r[1], r[2], r[3], ls ? mu : opt.sigma * r[4] / std::max(1.0, r[5]));
+    if (err <= opt.tol) {
+      status = OPF_IPM_CONVERGED;
+      break;
+    }
+    if (it >= opt.max_iter) break;
+    double tau_k = opt.tau;
+    double th = 0.0, fcur = 0.0, lgcur = 0.0;
+    if (ls) {
+      // no progress towards feasibility for stall_iter iterations: stalled
+      IPM_CHK(theta_phi(x, s, c, false, th, fcur, lgcur));
+      if (th < 0.9 * th_best) {
+        th_best = th;
+        it_best = it;
+      }
+      if (opt.stall_iter > 0 && it - it_best >= opt.stall_iter && r[2] > opt.tol) {
+        status = OPF_IPM_STALLED;
+        break;
+      }
+      // monotone mu: lowered while the barrier problem is solved to
+      // kappa_eps mu (its error: the complementarity products minus mu)
+      while (mu > opt.tol / 10.0) {
+        const double err_mu = std::max(base, r[5] > 0.0 ? std::max(r[3] - mu, mu - r[8]) : 0.0);
+        if (err_mu > opt.kappa_eps * mu) break;
+        mu = std::max(opt.tol / 10.0, std::min(opt.kappa_mu * mu, std::pow(mu, opt.theta_mu)));
+        filt.clear();
+      }
+      tau_k = std::max(opt.tau_min, 1.0 - mu);
+    } else {
+      mu = opt.sigma * r[4] / std::max(1.0, r[5]);
+    }
     // inertia-corrected condensed system
     double dw = 0.0;
     opf_ipm_state ist{x, s, y, zl, zu, vl, vu, xl, xu, sl, su, mu, dw, opt.delta_c};
@@ -407,7 +593,7 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
     t0 = now_s();
     IPM_CHK(opf_chol_solve(F, rhs, dx));
     IPM_CHK(opf_recover_step(M, &ist, c, dx, ds, dy, dzl, dzu, dvl, dvu));
-    hipLaunchKernelGGL(k_steplen, dim3(kRedGrid), dim3(kRedBlock), 0, st, w, stp, opt.tau, n, m, part);
+    hipLaunchKernelGGL(k_steplen, dim3(kRedGrid), dim3(kRedBlock), 0, st, w, stp, tau_k, n, m, part);
     IPM_HIP(hipGetLastError(), "ipm: step kernel");
     IPM_HIP(hipMemcpyAsync(hp.data(), part, 2 * kRedGrid * sizeof(double), hipMemcpyDeviceToHost, st), "ipm: copy");
     IPM_HIP(hipStreamSynchronize(st), "ipm: sync");
@@ -416,20 +602,83 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
       ap = std::min(ap, hp[2 * b]);
       ad = std::min(ad, hp[2 * b + 1]);
     }
-    if (opt.verbose) std::fprintf(stderr, "      delta_w %.1e  alpha_p %.3e  alpha_d %.3e\n", ist.delta_w, ap, ad);
-    hipLaunchKernelGGL(k_update, dim3(grid_of(std::max(n, m))), dim3(256), 0, st, w, stp, ap, ad, n, m);
-    IPM_HIP(hipGetLastError(), "ipm: update kernel");
+    if (!ls) {
+      if (opt.verbose) std::fprintf(stderr, "      delta_w %.1e  alpha_p %.3e  alpha_d %.3e\n", ist.delta_w, ap, ad);
+      hipLaunchKernelGGL(k_update, dim3(grid_of(std::max(n, m))), dim3(256), 0, st, w, stp, ap, ad, n, m);
+      IPM_HIP(hipGetLastError(), "ipm: update kernel");
+      t_sol += now_s() - t0;
+      continue;
+    }
+    // filter line search from the fraction-to-the-boundary length
+    const double ph = fcur - mu * lgcur;
+    hipLaunchKernelGGL(k_slope, dim3(kRedGrid), dim3(kRedBlock), 0, st, w, stp, (const double*)grad, n, m, part);
+    IPM_HIP(hipGetLastError(), "ipm: slope kernel");
+    IPM_HIP(hipMemcpyAsync(hp.data(), part, 2 * kRedGrid * sizeof(double), hipMemcpyDeviceToHost, st), "ipm: copy");
+    IPM_HIP(hipStreamSynchronize(st), "ipm: sync");
+    double gd = 0.0, bd = 0.0;
+    for (int b = 0; b < kRedGrid; ++b) {
+      gd += hp[2 * b];
+      bd += hp[2 * b + 1];
+    }
+    const double dph = gd + mu * bd;
+    const double amin = dph < 0.0 ? opt.gamma_alpha * std::min({opt.gamma_theta, opt.gamma_phi * th / -dph,
+                                                                 opt.delta * std::pow(th, opt.s_theta) /
+                                                                     std::pow(-dph, opt.s_phi)})
+                                  : opt.gamma_alpha * opt.gamma_theta;
+    double a = ap;
+    int kind = 0;  // 1: Armijo on phi, 2: sufficient decrease (the point joins the filter)
+    for (;;) {
+      hipLaunchKernelGGL(k_trial, dim3(grid_of(std::max(n, m))), dim3(256), 0, st, w, stp, a, xt, stl, n, m);
+      IPM_HIP(hipGetLastError(), "ipm: trial kernel");
+      double tht = 0.0, ft = 0.0, lgt = 0.0;
+      IPM_CHK(theta_phi(xt, stl, ct, true, tht, ft, lgt));
+      const double pht = ft - mu * lgt;
+      ++trials;
+      bool ok = tht <= theta_max;
+      for (const auto& e : filt)
+        if (!(tht < e.first || pht < e.second)) ok = false;
+      if (ok) {
+        const bool switching = dph < 0.0 && a * std::pow(-dph, opt.s_phi) > opt.delta * std::pow(th, opt.s_theta);
+        if (switching && th <= theta_min) {
+          if (pht <= ph + opt.eta_phi * a * dph) kind = 1;
+        } else if (tht <= (1.0 - opt.gamma_theta) * th || pht <= ph - opt.gamma_phi * th) {
+          kind = 2;
+        }
+      }
+      if (kind) break;
+      a *= 0.5;
+      if (a < amin) break;
+    }
+    if (opt.verbose)
+      std::fprintf(stderr, "      delta_w %.1e  alpha_p %.3e (of %.3e)  alpha_d %.3e  theta %.3e  %s\n", ist.delta_w,
+                   kind ? a : 0.0, ap, ad, th, kind == 1 ? "armijo" : (kind == 2 ? "filter" : "no step"));
+    if (!kind) {
+      status = OPF_IPM_STALLED;
+      t_sol += now_s() - t0;
+      break;
+    }
+    if (kind == 2) filt.push_back({(1.0 - opt.gamma_theta) * th, ph - opt.gamma_phi * th});
+    hipLaunchKernelGGL(k_accept, dim3(grid_of(std::max(n, m))), dim3(256), 0, st, w, stp, (const double*)xt,
+                       (const double*)stl, a, ad, mu, opt.kappa_sigma, n, m);
+    IPM_HIP(hipGetLastError(), "ipm: accept kernel");
     t_sol += now_s() - t0;
   }
   IPM_CHK(opf_eval_obj(M, x, fobj));
-  std::vector<double> fh(d.ninst);
   IPM_HIP(hipMemcpyAsync(fh.data(), fobj, d.ninst * sizeof(double), hipMemcpyDeviceToHost, st), "ipm: copy");
   IPM_HIP(hipMemcpyAsync(x_out, x, n * sizeof(double), hipMemcpyDeviceToDevice, st), "ipm: copy");
   if (y_out) IPM_HIP(hipMemcpyAsync(y_out, y, m * sizeof(double), hipMemcpyDeviceToDevice, st), "ipm: copy");
   IPM_HIP(hipStreamSynchronize(st), "ipm: sync");
   double fsum = 0.0;
   for (double v : fh) fsum += v;
-  res->converged = err <= opt.tol ? 1 : 0;
+  res->converged = status == OPF_IPM_CONVERGED ? 1 : 0;
+  res->status = status;
+  res->trials = trials;
+  {
+    double th = 0.0, fv = 0.0, lgv = 0.0;
+    IPM_CHK(opf_eval_cons(M, x, c));
+    IPM_CHK(theta_phi(x, s, c, false, th, fv, lgv));
+    res->theta = th;
+  }
   res->iterations = it;
   res->factorizations = nfact;
   res->objective = fsum;

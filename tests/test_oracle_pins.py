@@ -416,12 +416,53 @@ def _trust_constr_objective(net, relax=1e-4):
     return r.fun
 
 
-def test_ipm_tiny_objective_matches_independent_solver():
+@pytest.mark.parametrize("line_search", [True, False])
+def test_ipm_tiny_objective_matches_independent_solver(line_search):
+    # the stopping tolerance of the default (1e-4) leaves the objective ~1e-5
+    # from the optimum, so the comparison with the independent solver runs
+    # the loop to 1e-8
     net = synth.config_network("tiny")
-    r = O.ipm_solve(net)
+    r = O.ipm_solve(net, tol=1e-8, max_iter=200, line_search=line_search)
     assert r["converged"] and r["iterations"] < 40
     ref = _trust_constr_objective(net)
-    assert abs(r["objective"] - ref) <= 1e-6 * abs(ref), (r["objective"], ref)
+    assert abs(r["objective"] - ref) <= 1e-7 * abs(ref), (r["objective"], ref)
+    assert r["status"] == "converged"
+
+
+def _overloaded(factor=30.0):
+    # every period's load is above the total generating capacity (losses are
+    # non-negative, so generation must cover the load): no feasible point
+    import dataclasses
+    net = synth.config_network("tiny")
+    big = dataclasses.replace(net, pd=net.pd * factor, qd=net.qd * factor)
+    assert np.all(big.pd.sum(axis=1) > net.pmax.sum())
+    return big
+
+
+def test_ipm_line_search_stops_on_infeasible_instance():
+    r = O.ipm_solve(_overloaded(), max_iter=100)
+    assert r["status"] == "stalled" and not r["converged"]
+    assert r["iterations"] <= 20
+    assert r["theta"] > 1.0  # the stall leaves the rows far from satisfied
+    # without the line search the same instance runs into the iteration limit
+    r0 = O.ipm_solve(_overloaded(), max_iter=40, line_search=False)
+    assert r0["status"] == "max_iter"
+
+
+@pytest.mark.parametrize("factor", [3.0, 5.0, 12.0])
+def test_ipm_stops_on_overloaded_instances(factor):
+    # loads above capacity in every period: either no step is acceptable or
+    # the violation stops falling; both end as "stalled" well inside the limit
+    r = O.ipm_solve(_overloaded(factor), max_iter=100)
+    assert r["status"] == "stalled" and r["iterations"] <= 60, (r["status"], r["iterations"])
+
+
+def test_planted_blind_violation_measure(monkeypatch):
+    # a filter that cannot see the violation accepts every step, so the
+    # infeasible instance is no longer reported as stalled
+    monkeypatch.setattr(O, "_violation", lambda net, x, s: 0.0)
+    with pytest.raises(AssertionError):
+        test_ipm_line_search_stops_on_infeasible_instance()
 
 
 def test_ipm_tiny_solution_satisfies_kkt():
