@@ -477,7 +477,8 @@ def bench_ipm(torch, dev, args):
     r = capi.ipm_solve(M, F, x)
     out["whole_solve"] = {"workload": "N=2000 B=3200 G=400 T=24 (seed 2), loads capped at 0.3 of capacity, tol 1e-4",
                           "n": M.n, "m": M.m, "converged": bool(r["converged"]), "status": r["status_name"],
-                          "iterations": r["iterations"], "seconds": round(r["seconds"], 4), "s_per_iteration": round(r["seconds"] / max(1, r["iterations"]), 4),
+                          "iterations": r["iterations"], "factorizations": r["factorizations"],
+                          "seconds": round(r["seconds"], 4), "s_per_iteration": round(r["seconds"] / max(1, r["iterations"]), 4),
                           "objective": r["objective"]}
     F.close()
     M.close()
@@ -490,7 +491,7 @@ def bench_ipm(torch, dev, args):
     r = capi.ipm_solve(M, F, x)
     out["whole_solve_week"] = {"workload": "N=2000 B=3200 G=400 T=168 (seed 2), loads capped at 0.3 of capacity, tol 1e-4",
                                "n": M.n, "m": M.m, "converged": bool(r["converged"]), "status": r["status_name"],
-                               "iterations": r["iterations"],
+                               "iterations": r["iterations"], "factorizations": r["factorizations"],
                                "seconds": round(r["seconds"], 3), "factor_s": round(r["t_factor"], 3),
                                "solve_recover_s": round(r["t_solve"], 3), "objective": r["objective"]}
     log(f"ipm week solve: {out['whole_solve_week']}")
@@ -528,7 +529,8 @@ def bench_paper_solve(torch, dev, cap):
     r = capi.ipm_solve(M, F, x, max_iter=200, verbose=1)
     out = {"workload": f"paper-scale grid N=10000 B=13000 G=2000 T=168 (seed 3), loads capped at {cap} of capacity, "
                        "tol 1e-4", "n": M.n, "m": M.m, "setup_s": round(setup_s, 2), "converged": bool(r["converged"]),
-           "status": r["status_name"], "iterations": r["iterations"], "seconds": round(r["seconds"], 2),
+           "status": r["status_name"], "iterations": r["iterations"], "factorizations": r["factorizations"],
+           "seconds": round(r["seconds"], 2),
            "eval_s": round(r["t_eval"], 2),
            "factor_s": round(r["t_factor"], 2), "solve_recover_s": round(r["t_solve"], 2),
            "objective": r["objective"], "err": r["err"]}

@@ -410,7 +410,8 @@ int opf_chol_set_graph(opf_chol *chol, int enable);
  * building K at lambda = -y (opf_eval_jhk), factoring with the static-pivot
  * Cholesky and correcting the inertia (delta_w = 0, then dw_first, times
  * dw_grow, while the factorization reports static pivots), solving and
- * recovering the step (opf_recover_step).  Sec. III-B takes the inertia
+ * recovering the step (opf_recover_step; with line_search the correction
+ * starts from the last delta_w used, see dw_shrink).  Sec. III-B takes the inertia
  * correction from the filter interior-point method of Waechter and Biegler
  * (2006) and says a line search chooses the step length; with line_search
  * (the default) this loop takes that method's filter line search: a
@@ -455,6 +456,12 @@ typedef struct {
   int32_t stall_iter; /* line search: stop as stalled when theta has not
                          fallen below 0.9 of its best for this many
                          iterations while max |c - s| > tol; 0: never (25) */
+  double dw_grow_first, dw_shrink, dw_min; /* inertia correction with the
+                         line search: first nonzero delta_w = dw_first if no
+                         earlier iteration needed one, else
+                         max(dw_min, dw_shrink * last); growth dw_grow_first
+                         while none was needed before, else dw_grow
+                         (100, 1/3, 1e-20) */
 } opf_ipm_options;
 
 enum { OPF_IPM_CONVERGED = 0, OPF_IPM_MAX_ITER = 1, OPF_IPM_STALLED = 2 };

@@ -786,7 +786,8 @@ def ipm_residuals(net, w, mu):
 def ipm_solve(net, tol=1e-4, max_iter=100, relax=1e-4, sigma=0.1, tau=0.99995, delta_c=1e-8, dw_first=1e-4,
               dw_grow=8.0, dw_max=1e10, line_search=True, mu_init=0.1, kappa_eps=10.0, kappa_mu=0.2,
               theta_mu=1.5, tau_min=0.99, gamma_theta=1e-5, gamma_phi=1e-8, eta_phi=1e-8, s_theta=1.1,
-              s_phi=2.3, delta=1.0, gamma_alpha=0.05, kappa_sigma=1e10, stall_iter=25):
+              s_phi=2.3, delta=1.0, gamma_alpha=0.05, kappa_sigma=1e10, stall_iter=25, dw_grow_first=100.0,
+              dw_shrink=1.0 / 3.0, dw_min=1e-20):
     """Primal-dual interior-point method on the lifted formulation of
     Sec. III-B: the rows c(x) are relaxed to sl <= s <= su with c(x) - s = 0
     (equality rows widened by +-relax), each iteration solves the condensed
@@ -797,8 +798,12 @@ def ipm_solve(net, tol=1e-4, max_iter=100, relax=1e-4, sigma=0.1, tau=0.99995, d
     that a line search chooses the step length without naming one; the
     reading taken here is that method's filter line search:
 
-    * inertia correction: delta_w = 0, else dw_first, growing by dw_grow,
-      until K is positive definite (the condition static pivoting needs);
+    * inertia correction: delta_w = 0, else growing until K is positive
+      definite (the condition static pivoting needs) -- without the line
+      search from dw_first by dw_grow; with it as in that method: the first
+      nonzero try is dw_first when no earlier iteration needed a correction,
+      else max(dw_min, dw_shrink * the last one used), growing by
+      dw_grow_first while no earlier iteration needed one, else by dw_grow;
     * the Newton step is the negated (dx, ds, dzl, dzu, dvl, dvu) with +dy
       (the condensed system is written for the residuals, not their negative);
     * fraction to the boundary, tau_k = max(tau_min, 1 - mu), one length for
@@ -849,6 +854,7 @@ def ipm_solve(net, tol=1e-4, max_iter=100, relax=1e-4, sigma=0.1, tau=0.99995, d
     th0 = _violation(net, w["x"], w["s"])
     theta_max, theta_min = 1e4 * max(1.0, th0), 1e-4 * max(1.0, th0)
     th_best, it_best = th0, 0
+    dw_last = 0.0
 
     for it in range(max_iter + 1):
         rd, rs, rp, gaps, c, grad = ipm_residuals(net, w, 0.0)
@@ -888,9 +894,16 @@ def ipm_solve(net, tol=1e-4, max_iter=100, relax=1e-4, sigma=0.1, tau=0.99995, d
             nfact += 1
             if kkt_is_positive_definite(n, rp_, ci_, kv_):
                 break
-            dw = dw_first if dw == 0.0 else dw * dw_grow
+            if not line_search:
+                dw = dw_first if dw == 0.0 else dw * dw_grow
+            elif dw == 0.0:
+                dw = dw_first if dw_last == 0.0 else max(dw_min, dw_shrink * dw_last)
+            else:
+                dw *= dw_grow_first if dw_last == 0.0 else dw_grow
             if dw > dw_max:
                 raise RuntimeError("inertia correction failed")
+        if line_search and dw > 0.0:
+            dw_last = dw
         dx = kkt_solve(n, rp_, ci_, kv_, rhs)
         ds, dy, dzl, dzu, dvl, dvu = recover_step(net, st, c, dx)
         step = dict(x=-dx, s=-ds, y=dy, zl=-dzl, zu=-dzu, vl=-dvl, vu=-dvu)

@@ -81,7 +81,8 @@ class opf_ipm_options(C.Structure):
                 ("kappa_mu", C.c_double), ("theta_mu", C.c_double), ("tau_min", C.c_double),
                 ("gamma_theta", C.c_double), ("gamma_phi", C.c_double), ("eta_phi", C.c_double),
                 ("s_theta", C.c_double), ("s_phi", C.c_double), ("delta", C.c_double), ("gamma_alpha", C.c_double),
-                ("kappa_sigma", C.c_double), ("stall_iter", C.c_int32)]
+                ("kappa_sigma", C.c_double), ("stall_iter", C.c_int32), ("dw_grow_first", C.c_double),
+                ("dw_shrink", C.c_double), ("dw_min", C.c_double)]
 
 
 class opf_ipm_result(C.Structure):

@@ -410,6 +410,9 @@ void opf_ipm_default_options(opf_ipm_options* o) {
   o->gamma_alpha = 0.05;
   o->kappa_sigma = 1e10;
   o->stall_iter = 25;
+  o->dw_grow_first = 100.0;
+  o->dw_shrink = 1.0 / 3.0;
+  o->dw_min = 1e-20;
 }
 
 int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, double* x_out, double* y_out,
@@ -428,7 +431,8 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
       (!(opt.mu_init > 0.0) || !(opt.kappa_eps > 0.0) || !(opt.kappa_mu > 0.0 && opt.kappa_mu < 1.0) ||
        !(opt.theta_mu > 1.0) || !(opt.tau_min > 0.0 && opt.tau_min < 1.0) || !(opt.gamma_theta > 0.0) ||
        !(opt.gamma_phi > 0.0) || !(opt.eta_phi > 0.0) || !(opt.s_theta > 1.0) || !(opt.s_phi > 1.0) ||
-       !(opt.delta > 0.0) || !(opt.gamma_alpha > 0.0) || !(opt.kappa_sigma >= 1.0) || opt.stall_iter < 0))
+       !(opt.delta > 0.0) || !(opt.gamma_alpha > 0.0) || !(opt.kappa_sigma >= 1.0) || opt.stall_iter < 0 ||
+       !(opt.dw_grow_first > 1.0) || !(opt.dw_shrink > 0.0 && opt.dw_shrink < 1.0) || !(opt.dw_min > 0.0)))
     return api_fail(OPF_EINVAL, "ipm: invalid line-search options");
   std::memset(res, 0, sizeof(*res));
   const double t_start = now_s();
@@ -504,7 +508,7 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
   const bool ls = opt.line_search != 0;
   double mu = opt.mu_init;
   std::vector<std::pair<double, double>> filt;
-  double theta_max = 0.0, theta_min = 0.0, th_best = 0.0;
+  double theta_max = 0.0, theta_min = 0.0, th_best = 0.0, dw_last = 0.0;
   int it_best = 0;
   if (ls) {
     double th0 = 0.0, f0 = 0.0, lg0 = 0.0;
@@ -587,9 +591,15 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
       ++nfact;
       if (opt.verbose > 1) std::fprintf(stderr, "      factorization  delta_w %.1e  static pivots %d\n", dw, hn);
       if (hn == 0) break;
-      dw = dw == 0.0 ? opt.dw_first : dw * opt.dw_grow;
+      if (!ls)
+        dw = dw == 0.0 ? opt.dw_first : dw * opt.dw_grow;
+      else if (dw == 0.0)
+        dw = dw_last == 0.0 ? opt.dw_first : std::max(opt.dw_min, opt.dw_shrink * dw_last);
+      else
+        dw *= dw_last == 0.0 ? opt.dw_grow_first : opt.dw_grow;
       if (dw > opt.dw_max) return api_fail(OPF_EINVAL, "ipm: inertia correction failed");
     }
+    if (ls && dw > 0.0) dw_last = dw;
     t0 = now_s();
     IPM_CHK(opf_chol_solve(F, rhs, dx));
     IPM_CHK(opf_recover_step(M, &ist, c, dx, ds, dy, dzl, dzu, dvl, dvu));
