@@ -408,8 +408,6 @@ int build_fused(opf_model* M) {
   if (blk > 256) return OPF_OK;
   // periods per group: the largest of 4..1 that spreads the groups evenly
   // over the queues (one instance: T / gp groups)
-  int64_t sumT = 0;
-  for (const auto& I : M->inst) sumT += I.T;
   int gp = 1;
   for (int c = 4; c >= 1; --c) {
     int64_t ng = 0;
