@@ -76,3 +76,45 @@ def test_noalloc_sweep_rejects_models_beyond_static_scratch():
     torch.cuda.synchronize()
     assert torch.isnan(out["kvals"]).all(), "a rejected call must enqueue nothing"
     M.close()
+
+
+def test_noalloc_sweep_under_graph_capture():
+    """The call the entry point is for: recorded into a HIP graph (torch's
+    capture on a side stream, which refuses allocations during capture) and
+    replayed three times with eager work in between (every output refilled
+    with NaN first); each replay equals the plain sweep bitwise."""
+    import torch
+    from paper_2405_14032_amd import capi
+    dev = torch.device("cuda:0")
+    net = synth.make_network(300, 450, 60, 5, 805)
+    print("noalloc sweep under graph capture: N=300 B=450 T=5", flush=True)
+    M = capi.Model([net], device=0)
+    inp = _inputs(torch, dev, M, net, 806)
+    ref = _buffers(torch, dev, M, FULL)
+    M.use_current_torch_stream()
+    M.sweep(M.sweep_args(**inp, **ref))
+    torch.cuda.synchronize()
+    out = _buffers(torch, dev, M, FULL)
+    args = M.sweep_args(**inp, **out)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        M.use_current_torch_stream()
+        M.sweep_noalloc(args)  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        M.use_current_torch_stream()
+        M.sweep_noalloc(args)
+    M.use_current_torch_stream()
+    for rep in range(3):
+        for k in FULL:
+            out[k].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in FULL:
+            assert torch.equal(out[k], ref[k]), f"replay {rep}: {k} differs from opf_sweep"
+    del g
+    M.close()
