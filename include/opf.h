@@ -400,6 +400,16 @@ int opf_chol_solve(opf_chol *chol, const double *b, double *x);
  * graph reads the factor's current values).  enable = 0 launches the
  * kernels one by one instead. */
 int opf_chol_set_graph(opf_chol *chol, int enable);
+/* enable != 0: opf_chol_factor stops at its first static pivot -- every
+ * later kernel of that factorization returns at once, *npert is then >= 1
+ * (not the full count) and the factor is not usable.  For callers that
+ * discard a factorization with static pivots, as the inertia correction of
+ * Sec. III-B does (opf_ipm_solve turns it on for its own factorizations and
+ * restores the setting afterwards).  A factorization without static pivots
+ * is unchanged, bitwise.  Default 0. */
+int opf_chol_set_stop_on_pivot(opf_chol *chol, int enable);
+/* The current setting (0 or 1; 0 for NULL). */
+int opf_chol_stop_on_pivot(const opf_chol *chol);
 
 /* ---- the lifted-KKT interior-point loop (Sec. III-B) ----
  *

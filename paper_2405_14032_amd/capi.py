@@ -137,6 +137,8 @@ _SIGS = {
     "opf_chol_factor": (C.c_int, [_vp, _vp, C.c_double, C.c_double, _vp]),
     "opf_chol_solve": (C.c_int, [_vp, _vp, _vp]),
     "opf_chol_set_graph": (C.c_int, [_vp, C.c_int]),
+    "opf_chol_set_stop_on_pivot": (C.c_int, [_vp, C.c_int]),
+    "opf_chol_stop_on_pivot": (C.c_int, [_vp]),
     "opf_ipm_default_options": (None, [C.POINTER(opf_ipm_options)]),
     "opf_ipm_solve": (C.c_int, [_vp, _vp, C.POINTER(opf_ipm_options), _vp, _vp, C.POINTER(opf_ipm_result)]),
     "opf_set_timing": (C.c_int, [_vp, C.c_int]),
@@ -492,6 +494,9 @@ class Chol:
     def solve(self, b, x):
         M = self.model
         check(opf_chol_solve(self.h, M._a(b, M.n, "b"), M._a(x, M.n, "x")), "opf_chol_solve")
+
+    def set_stop_on_pivot(self, enable: bool):
+        check(opf_chol_set_stop_on_pivot(self.h, 1 if enable else 0), "opf_chol_set_stop_on_pivot")
 
     def set_graph(self, enable: bool):
         check(opf_chol_set_graph(self.h, int(enable)), "opf_chol_set_graph")

@@ -45,6 +45,7 @@ struct CDev {
   const int64_t *node_loff, *node_uoff, *node_woff, *row_ptr, *kid_ptr;
   int64_t lsize, usize, wsize;
   int32_t n_p, n_int, G;
+  const int32_t* stop;  // the static-pivot count when the factor stops at the first one, else NULL
 };
 
 // One front as the blocked kernels see it: factor block (ld x p, first p
@@ -56,7 +57,21 @@ struct FrontArg {
   double* U;
   int64_t Ustride;
   int32_t ldU;
+  const int32_t* stop;  // as CDev::stop
 };
+
+// Whether the factorization stops at its first static pivot and one has
+// been counted: the count read once per block by its first thread and
+// shared, so every thread of the block takes the same branch.  A count
+// raised by a concurrent kernel may be seen one launch late; the factor is
+// then only discarded later.
+__device__ __forceinline__ bool stopped(const int32_t* stop) {
+  if (!stop) return false;
+  __shared__ int32_t seen;
+  if (threadIdx.x == 0) seen = *reinterpret_cast<const volatile int32_t*>(stop);
+  __syncthreads();
+  return seen > 0;
+}
 
 __device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int v) {
   int lo = 0, hi = n;
@@ -105,6 +120,7 @@ __global__ void k_scatter_ramp(const double* __restrict__ kv, int64_t k_off, int
 __global__ void __launch_bounds__(256) k_extend(CDev D, const int32_t* __restrict__ items, int64_t item0,
                                                 int32_t cb, int32_t t0, double* __restrict__ Lf,
                                                 double* __restrict__ Ar) {
+  if (stopped(D.stop)) return;
   const int tt = (int)blockIdx.y;
   const int s = items[2 * (item0 + blockIdx.x)], c0 = items[2 * (item0 + blockIdx.x) + 1];
   const int p = D.node_p[s], u = D.node_u[s], ld = p + u;
@@ -152,6 +168,7 @@ __global__ void __launch_bounds__(256) k_extend(CDev D, const int32_t* __restric
 __global__ void __launch_bounds__(256) k_extend_root(CDev D, const int32_t* __restrict__ roots, int32_t nroots,
                                                      int32_t cb, int32_t t0, double* __restrict__ Cf, int64_t csize,
                                                      const double* __restrict__ Ar) {
+  if (stopped(D.stop)) return;
   const int tt = (int)blockIdx.y;
   const int c0 = (int)blockIdx.x * cb, c1 = min(c0 + cb, D.G);
   double* L = Cf + (int64_t)(t0 + tt) * csize;
@@ -217,6 +234,7 @@ __device__ __forceinline__ void chol_rows64(double (&a)[64], int p, int f, doubl
 __global__ void __launch_bounds__(64) k_factor_small(CDev D, const int32_t* __restrict__ list, int64_t l0,
                                                      int32_t t0, double* __restrict__ Lf, double* __restrict__ Ar,
                                                      double tol, double repl, int32_t* __restrict__ npert) {
+  if (stopped(D.stop)) return;
   const int tt = (int)blockIdx.y;
   const int s = list[l0 + blockIdx.x];
   const int p = D.node_p[s], u = D.node_u[s], f = p + u;
@@ -242,6 +260,7 @@ __global__ void __launch_bounds__(64) k_factor_small(CDev D, const int32_t* __re
 // factored in place by one wavefront per period (pivots counted here).
 __global__ void __launch_bounds__(64) k_diag(FrontArg A, int32_t k0, int32_t kb, double tol, double repl,
                                              int32_t* __restrict__ npert) {
+  if (stopped(A.stop)) return;
   double* L = A.L + (int64_t)blockIdx.x * A.Lstride;
   const int64_t ld = A.ld;
   const int i = (int)threadIdx.x;
@@ -260,6 +279,7 @@ __global__ void __launch_bounds__(256) k_panel(FrontArg A, int32_t k0, int32_t k
   __shared__ double Dg[kNB * (kNB + 1)];
   __shared__ double rdg[kNB];
   constexpr int S = kNB + 1;
+  if (stopped(A.stop)) return;
   double* L = A.L + (int64_t)blockIdx.y * A.Lstride;
   const int64_t ld = A.ld;
   const int rows = A.p + A.u;
@@ -313,6 +333,7 @@ k_update(FrontArg A, int32_t k0, int32_t kb, int32_t r0, int32_t cmax, int32_t d
   // two LDS buffers: the next chunk is loaded into registers while the
   // matrix cores work on the current one
   __shared__ double Pi[2][KC][kTile], Pj[2][KC][kTile];
+  if (stopped(A.stop)) return;
   const int rows = A.p + A.u;
   const int R = (rows - r0 + kTile - 1) / kTile;
   // blocks are dealt round-robin to the 8 XCDs in launch order; give each
@@ -763,6 +784,7 @@ struct opf_chol {
   const double* gb = nullptr;
   double* gx = nullptr;
   bool use_graph = true;
+  bool stop_on_pivot = false;  // skip the rest of a factorization after its first static pivot
   std::vector<void*> allocs;
   double flops = 0.0, flops_int = 0.0;
   int64_t factor_entries = 0, arena_entries = 0;
@@ -1010,6 +1032,7 @@ int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double r
         A.U = C.Ar + P.node_uoff[s];
         A.Ustride = P.usize;
         A.ldU = std::max(1, P.node_u[s]);
+        A.stop = C.dev.stop;
         CHK(factor_front(A, nt, tol, repl, npert, fst));
       }
       for (int k = 0; k < nfs; ++k)
@@ -1044,6 +1067,7 @@ int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double r
       A.U = F->Us;
       A.Ustride = 0;
       A.ldU = G;
+      A.stop = C.dev.stop;
       CHK(factor_front(A, 1, tol, repl, npert, F->cs));
     }
   }
@@ -1312,7 +1336,10 @@ int opf_chol_factor(opf_chol* F, const double* kvals, double pivot_tol, double p
   if (hipSetDevice(F->device) != hipSuccess) return api_fail(OPF_EHIP, "hipSetDevice failed");
   hipStream_t st = model_stream(F->model);
   if (hipMemsetAsync(npert, 0, sizeof(int32_t), st) != hipSuccess) return api_fail(OPF_EHIP, "clearing npert");
-  for (auto& C : F->inst) CHK(factor_inst(F, C, kvals, pivot_tol, pivot_repl, npert, st));
+  for (auto& C : F->inst) {
+    C.dev.stop = F->stop_on_pivot ? npert : nullptr;
+    CHK(factor_inst(F, C, kvals, pivot_tol, pivot_repl, npert, st));
+  }
   return OPF_OK;
 }
 
@@ -1355,6 +1382,14 @@ int opf_chol_solve(opf_chol* F, const double* b, double* x) {
   if (hipGraphLaunch(F->gexec, st) != hipSuccess) return api_fail(OPF_EHIP, "chol: solve graph launch");
   return OPF_OK;
 }
+
+int opf_chol_set_stop_on_pivot(opf_chol* F, int enable) {
+  if (!F) return api_fail(OPF_EINVAL, "chol is NULL");
+  F->stop_on_pivot = enable != 0;
+  return OPF_OK;
+}
+
+int opf_chol_stop_on_pivot(const opf_chol* F) { return F && F->stop_on_pivot ? 1 : 0; }
 
 int opf_chol_set_graph(opf_chol* F, int enable) {
   if (!F) return api_fail(OPF_EINVAL, "chol is NULL");

@@ -436,6 +436,14 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
     return api_fail(OPF_EINVAL, "ipm: invalid line-search options");
   std::memset(res, 0, sizeof(*res));
   const double t_start = now_s();
+  // a factorization with static pivots is discarded here, so it may stop at
+  // its first one (the caller's setting is restored on every return)
+  struct StopGuard {
+    opf_chol* f;
+    int keep;
+    ~StopGuard() { (void)opf_chol_set_stop_on_pivot(f, keep); }
+  } stop_guard{F, opf_chol_stop_on_pivot(F)};
+  if (opf_chol_set_stop_on_pivot(F, 1) != OPF_OK) return OPF_EINVAL;
   hipStream_t st = model_stream(M);
   opf_dims d;
   IPM_CHK(opf_model_dims(M, &d));

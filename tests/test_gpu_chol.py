@@ -261,3 +261,34 @@ def test_solve_graph_replays_match_eager(dev):
     assert torch.equal(x2, xe)
     F.close()
     M.close()
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged"])
+def test_stop_on_pivot(name, dev):
+    """With stop_on_pivot an indefinite K still reports static pivots (at
+    least one, at most the full count) and the next factorization of a
+    positive definite K on the same object is exact; a positive definite K
+    gives bitwise the same solution with the setting on and off."""
+    import torch
+    from paper_2405_14032_amd import capi
+    nets = CASES[name]()
+    inps = _inputs(nets, "well", 8)
+    bad = [dict(i) for i in inps]
+    for b in bad:
+        b["diag_x"] = b["diag_x"].copy()
+        b["diag_x"][::5] = -1e6
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    _, full = _gpu_solve(M, F, bad, torch, dev)
+    xa, n0 = _gpu_solve(M, F, inps, torch, dev)
+    F.set_stop_on_pivot(True)
+    _, part = _gpu_solve(M, F, bad, torch, dev)
+    print(f"{name}: static pivots {full} in full, {part} with the early stop", flush=True)
+    assert full >= 1 and 1 <= part <= full
+    xb, n1 = _gpu_solve(M, F, inps, torch, dev)
+    assert n0 == 0 and n1 == 0
+    assert np.array_equal(xa, xb)
+    _check(nets, inps, xb, "well", name + " after an early stop")
+    F.close()
+    M.close()
