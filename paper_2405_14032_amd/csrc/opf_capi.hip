@@ -286,10 +286,12 @@ std::vector<Tile> make_tiles(const opf_model* M, int op, const Shape& s, std::ve
   for (size_t k = 0; k < M->inst.size(); ++k) {
     begin[k] = (int32_t)out.size();
     const InstHost& I = M->inst[k];
-    for (int kind : kinds_of(op)) {
-      const int64_t cnt = count_of(I, kind);
-      for (int32_t t0 = 0; t0 < I.T; t0 += s.ppt) {
-        const int32_t t1 = std::min<int32_t>(I.T, t0 + s.ppt);
+    // period-major: the runs of the list that the kernels hand to each XCD
+    // then hold every element class of their periods in proportion
+    for (int32_t t0 = 0; t0 < I.T; t0 += s.ppt) {
+      const int32_t t1 = std::min<int32_t>(I.T, t0 + s.ppt);
+      for (int kind : kinds_of(op)) {
+        const int64_t cnt = count_of(I, kind);
         for (int64_t e0 = 0; e0 < cnt; e0 += s.block) {
           Tile tl;
           tl.inst = (int32_t)k;
