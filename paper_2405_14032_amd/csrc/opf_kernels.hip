@@ -1581,6 +1581,7 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
     }
   }
   const rsrc_t rAdj = rsrc(I.bus_adj), rNb = rsrc(I.bus_nb);
+  constexpr int U = 4;
   for (int t = tl.t0; t < tl.t1; ++t) {
     double* kb = K + I.k_off + kkt_period_offset_dev(I.nnzk_p, I.G, t);
     if (act) {
@@ -1590,43 +1591,73 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
       // record of line end (l, e) at byte (2 l + e) * 64 = adjacency entry * 64
       static_assert(kRecEnd * sizeof(double) == 64 && kRecLine == 2 * kRecEnd, "hand-off record layout");
       const rsrc_t rR = rsrc(rec_at(I, scr_m, t)), rS = rsrc(shared_at(I, scr_m, t));
+      const rsrc_t rD = rsrc(D + co), rX = rsrc(X + xo);
+      // Loads are grouped by dependence so that one wave waits for memory
+      // three times in the common case instead of once per step: (1) the
+      // first 2U incidence entries, the first generator of the bus and the
+      // bus's own inputs; (2) the records of the first U ends and the
+      // generator's injections; (3) the records of the next U ends.  Longer
+      // incidence lists and further generators continue in loops.  The
+      // summation orders are unchanged.
+      int ad[2 * U], nb[2 * U];
+#pragma unroll
+      for (int u = 0; u < 2 * U; ++u) {
+        ad[u] = 0;
+        nb[u] = -1;
+      }
+      if (I.B > 0) {  // (wave-uniform) entry 0 exists: lanes past their list load it and drop it
+#pragma unroll
+        for (int u = 0; u < 2 * U; ++u) {
+          const bool ok = q0 + u < q1;
+          const int aa = ok ? q0 + u : 0;
+          const int a = bldi(rAdj, (uint32_t)aa), m = bldi(rNb, (uint32_t)aa);
+          ad[u] = ok ? a : 0;
+          nb[u] = ok ? m : -1;
+        }
+      }
+      int gq = -1;
+      if (SWEEP) {
+        const int gi0 = bldi(rsrc(I.bgen), (uint32_t)(g1 > g0 ? g0 : 0));
+        gq = g1 > g0 ? gi0 : -1;
+      }
+      double dxm = 0.0, dxa = 0.0, pdn = 0.0, qdn = 0.0;
+      if (DX) {
+        const rsrc_t rDX = rsrc(DX + xo);
+        dxm = bldv(rDX, vN8, 0);
+        dxa = bldv(rDX, vN8, N8);
+      }
+      if (SWEEP) {
+        pdn = bldv(rsrc(I.pd + (int64_t)t * N), vN8, 0);
+        qdn = bldv(rsrc(I.qd + (int64_t)t * N), vN8, 0);
+      }
+      double dref = 0.0;
+      if (n == I.ref) {
+        const double jr = bld_l2(rsrc(J + I.j_off + (int64_t)t * I.nnzj_p), (uint32_t)(2 * I.G + 4 * I.B));
+        dref = bld(rD, (uint32_t)(2 * N)) * jr * jr;
+      }
       double svm_s = 0.0, svavm_s = 0.0, sva_s = 0.0;
       double cvm = 0.0, cvavm = 0.0, cva = 0.0;
       double bp = 0.0, bq = 0.0, jvm = 0.0, jva = 0.0;
-      if (SWEEP) {
-        const rsrc_t rX = rsrc(X + xo), rBg = rsrc(I.bgen);
-        for (int q = g0; q < g1; ++q) {
-          const uint32_t g8 = (uint32_t)bldi(rBg, (uint32_t)q) * 8u;
-          bp += bldv(rX, g8, 2 * N8);
-          bq += bldv(rX, g8, 2 * N8 + G * 8u);
-        }
-      }
       int gi = 0, prev = -1;
-      constexpr int U = 4;
-      for (int aa = q0; aa < q1; aa += U) {
-        // issue the incidence loads and record gathers of up to U ends together
-        int ad[U], nb[U];
-        double2 r[U][4], x2[U];
+      double2 r[U][4], x2[U];
+      // records of the ends held in ad[o .. o + U) / nb[o .. o + U)
+      auto gather = [&](const int* adu, const int* nbu) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const bool ok = aa + u < q1;
-          ad[u] = ok ? bldi(rAdj, (uint32_t)(aa + u)) : 0;
-          nb[u] = ok ? bldi(rNb, (uint32_t)(aa + u)) : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const bool ok = nb[u] >= 0;
-          const uint32_t ro = (uint32_t)ad[u] * 64u;
+          const bool ok = nbu[u] >= 0;
+          const uint32_t ro = (uint32_t)adu[u] * 64u;
           const int w1 = SWEEP ? 4 : 2;
 #pragma unroll
           for (int w = 0; w < 4; ++w)
             r[u][w] = (ok && w < w1) ? bld2v_l2(rR, ro, (uint32_t)w * 16u) : make_double2(0.0, 0.0);
-          x2[u] = (ok && nb[u] < n) ? bld2v_l2(rS, (uint32_t)(ad[u] >> 1) * 16u, 0) : make_double2(0.0, 0.0);
+          x2[u] = (ok && nbu[u] < n) ? bld2v_l2(rS, (uint32_t)(adu[u] >> 1) * 16u, 0) : make_double2(0.0, 0.0);
         }
+      };
+      auto consume = [&](const int* nbu) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          if (nb[u] < 0) break;
-          const int m = nb[u];
+          if (nbu[u] < 0) break;
+          const int m = nbu[u];
           if (prev >= 0 && m != prev) {
             if (prev < n) {
               svm[vmr + gi] = cvm;
@@ -1652,6 +1683,37 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
             jva += r[u][3].y;
           }
         }
+      };
+      gather(ad, nb);
+      if (SWEEP) {
+        const uint32_t g8 = (uint32_t)(gq >= 0 ? gq : 0) * 8u;
+        const double pg = bldv(rX, g8, 2 * N8), qg = bldv(rX, g8, 2 * N8 + G * 8u);
+        if (gq >= 0) {
+          bp += pg;
+          bq += qg;
+        }
+        const rsrc_t rBg = rsrc(I.bgen);
+        for (int q = g0 + 1; q < g1; ++q) {
+          const uint32_t h8 = (uint32_t)bldi(rBg, (uint32_t)q) * 8u;
+          bp += bldv(rX, h8, 2 * N8);
+          bq += bldv(rX, h8, 2 * N8 + G * 8u);
+        }
+      }
+      consume(nb);
+      if (q1 - q0 > U) {
+        gather(ad + U, nb + U);
+        consume(nb + U);
+      }
+      for (int aa = q0 + 2 * U; aa < q1; aa += U) {
+        int adu[U], nbu[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool ok = aa + u < q1;
+          adu[u] = ok ? bldi(rAdj, (uint32_t)(aa + u)) : 0;
+          nbu[u] = ok ? bldi(rNb, (uint32_t)(aa + u)) : -1;
+        }
+        gather(adu, nbu);
+        consume(nbu);
       }
       if (prev >= 0) {
         if (prev < n) {
@@ -1662,25 +1724,13 @@ __device__ void bus_tile(const InstDev& I, const Tile& tl, int cap_vm, const dou
           sva[var + gi + 1] = cvavm;
         }
       }
-      const rsrc_t rD = rsrc(D + co);
-      double dref = 0.0;
-      if (n == I.ref) {
-        const double jr = bld_l2(rsrc(J + I.j_off + (int64_t)t * I.nnzj_p), (uint32_t)(2 * I.G + 4 * I.B));
-        dref = bld(rD, (uint32_t)(2 * N)) * jr * jr;
-      }
-      double dxm = 0.0, dxa = 0.0;
-      if (DX) {
-        const rsrc_t rDX = rsrc(DX + xo);
-        dxm = bldv(rDX, vN8, 0);
-        dxa = bldv(rDX, vN8, N8);
-      }
       svm[vmr + clo] = dxm + svm_s;
       if (q1 > q0) sva[var + clo] = svavm_s;  // (va_n, vm_n) exists only with an incident line
       sva[var + lva - 1] = dxa + sva_s + dref;
       if (SWEEP) {
-        const rsrc_t rC = rsrc(C + co), rP = rsrc(I.pd + (int64_t)t * N), rQ = rsrc(I.qd + (int64_t)t * N);
-        bp -= bldv(rP, vN8, 0);
-        bq -= bldv(rQ, vN8, 0);
+        const rsrc_t rC = rsrc(C + co);
+        bp -= pdn;
+        bq -= qdn;
         bstvn(rC, vN8, 0, bp);
         bstvn(rC, vN8, N8, bq);
         if (n == I.ref) {
