@@ -283,12 +283,21 @@ int64_t count_of(const InstHost& I, int kind) {
 std::vector<Tile> make_tiles(const opf_model* M, int op, const Shape& s, std::vector<int32_t>& begin) {
   std::vector<Tile> out;
   begin.assign(M->inst.size() + 1, 0);
-  for (size_t k = 0; k < M->inst.size(); ++k) {
+  // The bus kernels that read the line kernels' hand-off records walk the
+  // instances and periods backwards: their first reads are then the records
+  // written last, which the memory-side cache still holds.
+  const bool rev = op == OP_SWB || op == OP_KKB || op == OP_JTB;
+  const size_t ni = M->inst.size();
+  for (size_t kk = 0; kk < ni; ++kk) {
+    const size_t k = rev ? ni - 1 - kk : kk;
     begin[k] = (int32_t)out.size();
     const InstHost& I = M->inst[k];
     // period-major: the runs of the list that the kernels hand to each XCD
     // then hold every element class of their periods in proportion
-    for (int32_t t0 = 0; t0 < I.T; t0 += s.ppt) {
+    const int32_t ngrp = (I.T + s.ppt - 1) / s.ppt;
+    for (int32_t gg = 0; gg < ngrp; ++gg) {
+      const int32_t grp = rev ? ngrp - 1 - gg : gg;
+      const int32_t t0 = grp * s.ppt;
       const int32_t t1 = std::min<int32_t>(I.T, t0 + s.ppt);
       for (int kind : kinds_of(op)) {
         const int64_t cnt = count_of(I, kind);
