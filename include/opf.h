@@ -440,7 +440,10 @@ int opf_chol_stop_on_pivot(const opf_chol *chol);
  * stall_iter iterations while max |c - s| > tol (steps accepted, no progress
  * towards feasibility), the loop stops with status OPF_IPM_STALLED (the
  * method's restoration phase is not implemented: a stall reports the
- * instance as not solved, e.g. infeasible).  Without line_search: mu = sigma * (mean
+ * instance as not solved, e.g. infeasible).  With or without the line
+ * search, an iteration whose inertia correction would need delta_w >
+ * dw_max (no positive definite condensed matrix found) also ends the loop
+ * with OPF_IPM_STALLED and the last iterate.  Without line_search: mu = sigma * (mean
  * complementarity product) and the fraction-to-the-boundary lengths (tau,
  * one primal, one dual; y moves with the dual length) are taken as they
  * are.  Both stop when max(|p_x| / sd, |p_s| / sd, |c - s|,

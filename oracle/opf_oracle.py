@@ -833,6 +833,9 @@ def ipm_solve(net, tol=1e-4, max_iter=100, relax=1e-4, sigma=0.1, tau=0.99995, d
       fallen below 0.9 of its best value for stall_iter iterations while
       max |c - s| > tol (steps still accepted, but no progress towards
       feasibility: what would send the method into restoration);
+    * an iteration whose inertia correction would need delta_w > dw_max (no
+      positive definite condensed matrix found) also ends the loop as
+      "stalled", with or without the line search;
     * without ``line_search``: mu = sigma * (mean complementarity product) and
       the fraction-to-the-boundary lengths (tau) are taken as they are; y
       moves with the dual length;
@@ -901,7 +904,12 @@ def ipm_solve(net, tol=1e-4, max_iter=100, relax=1e-4, sigma=0.1, tau=0.99995, d
             else:
                 dw *= dw_grow_first if dw_last == 0.0 else dw_grow
             if dw > dw_max:
-                raise RuntimeError("inertia correction failed")
+                break
+        if dw > dw_max:
+            # no positive definite condensed matrix within dw_max: no step
+            hist.append(dict(err=err, mu=mu, delta_w=dw, alpha_p=0.0, alpha_d=0.0, trials=0))
+            status = "stalled"
+            break
         if line_search and dw > 0.0:
             dw_last = dw
         dx = kkt_solve(n, rp_, ci_, kv_, rhs)

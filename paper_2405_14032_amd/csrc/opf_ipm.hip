@@ -605,7 +605,13 @@ int opf_ipm_solve(opf_model* M, opf_chol* F, const opf_ipm_options* opt_in, doub
         dw = dw_last == 0.0 ? opt.dw_first : std::max(opt.dw_min, opt.dw_shrink * dw_last);
       else
         dw *= dw_last == 0.0 ? opt.dw_grow_first : opt.dw_grow;
-      if (dw > opt.dw_max) return api_fail(OPF_EINVAL, "ipm: inertia correction failed");
+      if (dw > opt.dw_max) break;
+    }
+    if (dw > opt.dw_max) {
+      // no positive definite condensed matrix within dw_max: no step to take
+      if (opt.verbose) std::fprintf(stderr, "      delta_w above %.1e: no step\n", opt.dw_max);
+      status = OPF_IPM_STALLED;
+      break;
     }
     if (ls && dw > 0.0) dw_last = dw;
     t0 = now_s();

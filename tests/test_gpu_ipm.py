@@ -142,6 +142,24 @@ def test_ipm_inertia_correction_path(dev):
     assert r["err"] < 1.0  # from 40 at the start
 
 
+@pytest.mark.parametrize("line_search", [1, 0])
+def test_ipm_stops_when_inertia_correction_runs_out(line_search, dev):
+    """A static pivot threshold (1e30) that no pivot passes at any delta_w
+    up to dw_max (1e10): the first iteration's correction runs out and the
+    loop returns the start point with status stalled (as the oracle's loop
+    does when its positive-definiteness test never passes), after one
+    factorization at delta_w = 0 and one per delta_w <= dw_max."""
+    import torch
+    net = synth.config_network("tiny")
+    r, x, _, _ = _gpu_ipm([net], torch, dev, pivot_tol=1e30, max_iter=10, line_search=line_search)
+    assert r["status_name"] == "stalled" and r["converged"] == 0 and r["iterations"] == 0
+    grow = 100.0 if line_search else 8.0
+    k = int(np.floor(np.log(1e10 / 1e-4) / np.log(grow) + 1e-9)) + 1
+    assert r["factorizations"] == 1 + k, (r["factorizations"], k)
+    x0 = O.ipm_start(net, 1e-4)["x"]
+    assert np.max(np.abs(x - x0)) <= 1e-12 * max(1.0, np.max(np.abs(x0)))
+
+
 def test_ipm_rejects_bad_options(dev):
     import torch
     from paper_2405_14032_amd import capi

@@ -457,6 +457,23 @@ def test_ipm_stops_on_overloaded_instances(factor):
     assert r["status"] == "stalled" and r["iterations"] <= 60, (r["status"], r["iterations"])
 
 
+@pytest.mark.parametrize("line_search", [True, False])
+def test_ipm_stops_when_inertia_correction_runs_out(monkeypatch, line_search):
+    # a positive-definiteness test that never passes: the first iteration's
+    # inertia correction climbs past dw_max, and the loop returns the start
+    # point as "stalled" instead of raising; one factorization at delta_w = 0
+    # and one per delta_w <= dw_max (1e-4 times 100, with the line search, or
+    # 8, without it, per attempt)
+    monkeypatch.setattr(O, "kkt_is_positive_definite", lambda n, rp, ci, kv: False)
+    net = synth.config_network("tiny")
+    r = O.ipm_solve(net, max_iter=10, line_search=line_search)
+    assert r["status"] == "stalled" and not r["converged"] and r["iterations"] == 0
+    grow = 100.0 if line_search else 8.0
+    k = int(np.floor(np.log(1e10 / 1e-4) / np.log(grow) + 1e-9)) + 1
+    assert r["factorizations"] == 1 + k, (r["factorizations"], k)
+    assert np.array_equal(r["x"], O.ipm_start(net, 1e-4)["x"])
+
+
 def test_planted_blind_violation_measure(monkeypatch):
     # a filter that cannot see the violation accepts every step, so the
     # infeasible instance is no longer reported as stalled
