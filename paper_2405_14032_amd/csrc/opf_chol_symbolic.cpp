@@ -327,27 +327,44 @@ int chol_plan_build(const InstHost& I, const CholOptions& opt, CholPlan& P, std:
       }
     }
   for (auto& d : nd) std::sort(d.kids.begin(), d.kids.end());
-  // relaxed amalgamation: fold a node's last child into it while the merged
-  // front stays nearly dense (the last child's pivots directly precede the
-  // node's in postorder, so the merged pivots stay contiguous)
+  // relaxed amalgamation: fold children into a node while the merged front
+  // stays nearly dense.  Any child qualifies (the one with the largest
+  // update matrix first: merging it saves the most traffic), not only the
+  // one whose pivots directly precede the node's: the merged node's pivots
+  // are laid out contiguously afterwards, by a new elimination order.  The
+  // test: c's rows lie in s's front, so c's columns in the merged front
+  // carry c.p * (s.p + us - uc) zeros.
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> rng(nn - 1);  // pivot ranges (first, count)
+  for (int32_t k = 0; k + 1 < nn; ++k) rng[k].push_back({nd[k].f, nd[k].p});
   for (int32_t k = 0; k + 1 < nn; ++k) {
     Nd& s = nd[k];
-    while (!s.kids.empty()) {
-      const int32_t kc = s.kids.back();
-      Nd& c = nd[kc];
-      if (c.f + c.p != s.f) break;
-      const int64_t uc = (int64_t)c.rows.size(), us = (int64_t)s.rows.size();
-      const int64_t added = (int64_t)c.p * ((int64_t)s.p + us - uc);
-      const int64_t pm = (int64_t)c.p + s.p;
-      if (pm > opt.max_pivots) break;
-      const int64_t tot = pm * (pm + 1) / 2 + pm * us;
-      const int64_t zeros = added + c.zeros + s.zeros;
-      const bool small = pm <= opt.amalg_small;
-      if (!(added == 0 || (small && zeros <= tot / 2) || zeros <= (int64_t)(opt.amalg_frac * tot))) break;
-      s.f = c.f;
-      s.p = (int32_t)pm;
-      s.zeros = zeros;
-      s.kids.pop_back();
+    for (;;) {
+      int32_t best = -1;
+      int64_t best_u = -1, best_z = 0;
+      const int64_t us = (int64_t)s.rows.size();
+      for (int32_t kc : s.kids) {
+        const Nd& c = nd[kc];
+        const int64_t uc = (int64_t)c.rows.size();
+        const int64_t added = (int64_t)c.p * ((int64_t)s.p + us - uc);
+        const int64_t pm = (int64_t)c.p + s.p;
+        if (pm > opt.max_pivots) continue;
+        const int64_t tot = pm * (pm + 1) / 2 + pm * us;
+        const int64_t zeros = added + c.zeros + s.zeros;
+        const bool small = pm <= opt.amalg_small;
+        if (!(added == 0 || (small && zeros <= tot / 2) || zeros <= (int64_t)(opt.amalg_frac * tot))) continue;
+        if (uc > best_u) {
+          best = kc;
+          best_u = uc;
+          best_z = zeros;
+        }
+      }
+      if (best < 0) break;
+      Nd& c = nd[best];
+      s.p += c.p;
+      s.zeros = best_z;
+      rng[k].insert(rng[k].begin(), rng[best].begin(), rng[best].end());  // the child's pivots first
+      rng[best].clear();
+      s.kids.erase(std::find(s.kids.begin(), s.kids.end(), best));
       s.kids.insert(s.kids.end(), c.kids.begin(), c.kids.end());
       std::sort(s.kids.begin(), s.kids.end());
       for (int32_t g : c.kids) nd[g].parent = k;
@@ -357,11 +374,38 @@ int chol_plan_build(const InstHost& I, const CholOptions& opt, CholPlan& P, std:
       c.rows.shrink_to_fit();
     }
   }
-  // compact the surviving nodes (postorder kept)
-  std::vector<int32_t> newid(nn - 1, -1);
+  // the surviving nodes keep the postorder's relative order (children
+  // before parents); each takes the next block of elimination positions for
+  // its pivots, and the ordering and every row index are renumbered to match
+  std::vector<int32_t> newid(nn - 1, -1), order2;
+  order2.reserve(P.n_int);
   int32_t ns = 0;
-  for (int32_t k = 0; k + 1 < nn; ++k)
-    if (nd[k].alive) newid[k] = ns++;
+  for (int32_t k = 0; k + 1 < nn; ++k) {
+    if (!nd[k].alive) continue;
+    newid[k] = ns++;
+    nd[k].f = (int32_t)order2.size();
+    for (const auto& r : rng[k])
+      for (int32_t i = r.first; i < r.first + r.second; ++i) order2.push_back(i);
+  }
+  if ((int32_t)order2.size() != P.n_int) {
+    err = "chol analysis: merged pivots do not cover the interior";
+    return OPF_EINVAL;
+  }
+  {
+    std::vector<int32_t> map_new(P.n_int, -1);
+    for (int32_t i = 0; i < P.n_int; ++i) map_new[order2[i]] = i;
+    std::vector<int32_t> perm2(np), iperm2(np, -1);
+    for (int32_t i = 0; i < np; ++i) perm2[i] = i < P.n_int ? P.perm[order2[i]] : P.perm[i];
+    for (int32_t i = 0; i < np; ++i) iperm2[perm2[i]] = i;
+    P.perm.swap(perm2);
+    P.iperm.swap(iperm2);
+    for (int32_t k = 0; k + 1 < nn; ++k) {
+      if (!nd[k].alive) continue;
+      for (int32_t& r : nd[k].rows)
+        if (r < P.n_int) r = map_new[r];
+      std::sort(nd[k].rows.begin(), nd[k].rows.end());
+    }
+  }
   P.node_f.resize(ns);
   P.node_p.resize(ns);
   P.node_u.resize(ns);
