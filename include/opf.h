@@ -355,9 +355,12 @@ typedef struct {
  * failure); it refers to the model, which must outlive it.  Errors:
  * OPF_EINVAL (NULL arguments, a front too large for the kernels),
  * OPF_ENOMEM (host or device allocation), OPF_EHIP.  The update-matrix
- * workspace holds the fronts of as many periods as fit in 16 GiB (the
+ * workspace holds the fronts of as many periods as fit in 8 GiB (the
  * environment variable OPF_CHOL_ARENA_BYTES, read here, overrides the
- * budget); those periods are factored together. */
+ * budget); those periods are factored together.  The large trailing
+ * updates of the pg chain's single-period fronts run as rocBLAS
+ * strided-batched DGEMMs (atomics off: reproducible); OPF_CHOL_BLAS=0, read
+ * here, keeps them on the library's own kernel. */
 int opf_chol_analyze(opf_model *model, opf_chol **out);
 void opf_chol_destroy(opf_chol *chol); /* NULL is a no-op */
 int opf_chol_get_info(const opf_chol *chol, opf_chol_info *info);

@@ -28,7 +28,10 @@ def build(verbose: bool = False) -> str:
         "-ffp-contract=on",
         "-Wall", "-Wno-unused-result",
         "-o", LIB + ".tmp",
-    ] + [os.path.join(HERE, s) for s in SOURCES]
+    ] + [os.path.join(HERE, s) for s in SOURCES] + [
+        # the dense trailing updates of the pg chain's fronts in the sparse Cholesky
+        "-L/opt/rocm/lib", "-lrocblas",
+    ]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, cwd=HERE, capture_output=True, text=True)

@@ -12,10 +12,12 @@
 //     (small fronts in LDS by one wavefront, large ones by blocked panel +
 //     trailing-update kernels), batched over the periods of a chunk;
 //   * the pg front of period t (G pivots, update rows pg_{t+1}) collects the
-//     period's tree roots and the previous pg front's update: a chain over t.
+//     period's tree roots and the previous pg front's update: a chain over t
+//     (its large trailing updates as library GEMMs, see blas_update).
 // Solves run the same tree forward (update vectors pulled by the parent)
 // and backward (gathers of the ancestors' solution), batched over periods.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -37,6 +39,19 @@ constexpr int kNB = 64;      // panel width of the blocked fronts
 constexpr int kTile = 128;   // trailing-update tile (8 x 8 outputs per thread)
 constexpr int kChainCols = 128;  // column chunk of the chain's L21 z
 constexpr int kStep = 1024;      // columns per trailing update of a blocked front
+// Trailing updates of at least this many rows below the panel and panel
+// columns go to the library's strided-batched GEMM (plain dense products);
+// smaller ones stay on k_update.
+constexpr int kBlasMinRows = 512;
+constexpr int kBlasMinCols = 128;
+constexpr int kBlasCols = 512;  // target columns per library product
+// Only the pg chain's single-period fronts go to the library: one period
+// gives k_update too few tiles to fill the GPU, and the chain runs its
+// fronts in sequence (measured at paper scale: 1.132 -> 1.065 s per
+// factorization; the library on the batched interior fronts as well was
+// slower, its long-running blocks holding the CUs the chain's short
+// launches wait for).
+constexpr int kBlasMaxPeriods = 1;
 constexpr int kBwdCols = 16;     // earlier columns updated per block of a backward panel
 
 // Device view of one instance's plan.
@@ -785,6 +800,9 @@ struct opf_chol {
   double* gx = nullptr;
   bool use_graph = true;
   bool stop_on_pivot = false;  // skip the rest of a factorization after its first static pivot
+  // the library handle of the large trailing updates (NULL: every update on
+  // k_update); atomics off, so its products are reproducible run to run
+  rocblas_handle blas = nullptr;
   std::vector<void*> allocs;
   double flops = 0.0, flops_int = 0.0;
   int64_t factor_entries = 0, arena_entries = 0;
@@ -794,10 +812,10 @@ const opf_model* opf::chol_model(const opf_chol* F) { return F ? F->model : null
 
 namespace {
 
-// bytes of update-matrix workspace per instance: 20 periods of the
-// 10000-bus grid (measured per factorization: 5 periods 2.15 s, 10 1.76 s,
-// 20 1.63 s, 40 1.63 s)
-constexpr int64_t kArenaBudget = 16LL << 30;
+// bytes of update-matrix workspace per instance: 12 periods of the
+// 10000-bus grid (measured per factorization: 6 periods 1.129 s, 12 1.131 s,
+// 25 1.144 s, 51 1.170 s, 102 1.212 s)
+constexpr int64_t kArenaBudget = 8LL << 30;
 
 // Workspace budget: OPF_CHOL_ARENA_BYTES (bytes, > 0) overrides the default.
 int64_t arena_budget() {
@@ -910,8 +928,48 @@ int setup_device(opf_chol* F, CholInst& C) {
 // sub-panel's update of the second's columns in between), then one
 // trailing update with the 128-wide panel.  Each update launch also factors
 // the next diagonal block.
+// The same update through the library's strided-batched GEMM, every call
+// batched over the nt periods by their strides.  The lower part of the
+// target columns is covered by column blocks of kBlasCols: block [j, j+w)
+// takes rows [j, end) in one product, so it also writes the upper part of
+// its w x w diagonal block (no kernel reads above the diagonal of a factor
+// or update block).  The library's SYRK measured 2-12 TFLOP/s on these
+// shapes against 40-70 for GEMM.  Columns in the factor block first, then
+// those in the update block; the next diagonal block is factored by a
+// launch of its own afterwards.
+int blas_update(rocblas_handle h, const FrontArg& A, int nt, int k0, int kb, int r0, int cend, int dnext,
+                double tol, double repl, int32_t* npert, hipStream_t st) {
+  const int rows = A.p + A.u;
+  const int64_t ld = A.ld;
+  if (rocblas_set_stream(h, st) != rocblas_status_success) return api_fail(OPF_EHIP, "chol: rocblas_set_stream failed");
+  const double* P = A.L + (int64_t)k0 * ld;  // panel: row r of column k0 + c at P[c * ld + r]
+  // columns [c, c + n) of the target, rows [c, rows), at C (leading dimension ldc, period stride sc)
+  auto lower = [&](int c, int n, double* C, int64_t ldc, int64_t sc) -> int {
+    const double mone = -1.0, one = 1.0;
+    for (int j = 0; j < n; j += kBlasCols) {
+      const int w = std::min(kBlasCols, n - j);
+      const double* Aj = P + c + j;
+      if (rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, rows - c - j, w, kb,
+                                        &mone, Aj, (rocblas_int)ld, A.Lstride, Aj, (rocblas_int)ld, A.Lstride, &one,
+                                        C + (int64_t)j * ldc + j, (rocblas_int)ldc, sc, nt) != rocblas_status_success)
+        return api_fail(OPF_EHIP, "chol: rocblas_dgemm_strided_batched failed");
+    }
+    return OPF_OK;
+  };
+  const int n1 = std::min(A.p, cend) - r0;  // target columns in the factor block
+  if (n1 > 0) CHK(lower(r0, n1, A.L + (int64_t)r0 * ld + r0, ld, A.Lstride));
+  const int c0 = std::max(r0, A.p);
+  const int n3 = cend - c0;  // target columns in the update block
+  if (n3 > 0) CHK(lower(c0, n3, A.U + (int64_t)(c0 - A.p) * A.ldU + (c0 - A.p), A.ldU, A.Ustride));
+  if (dnext > 0) {
+    hipLaunchKernelGGL(k_diag, dim3(nt), dim3(64), 0, st, A, r0, dnext, tol, repl, npert);
+    LAUNCH_OK("chol diagonal block");
+  }
+  return OPF_OK;
+}
+
 int launch_update(const FrontArg& A, int nt, int k0, int kb, int r0, int cmax, int dnext, double tol, double repl,
-                  int32_t* npert, hipStream_t st) {
+                  int32_t* npert, hipStream_t st, rocblas_handle h) {
   const int rows = A.p + A.u;
   const int cend = std::min(cmax, rows);
   if (r0 >= rows || cend <= r0) {
@@ -921,6 +979,8 @@ int launch_update(const FrontArg& A, int nt, int k0, int kb, int r0, int cmax, i
     }
     return OPF_OK;
   }
+  if (h && nt <= kBlasMaxPeriods && kb >= kBlasMinCols && rows - r0 >= kBlasMinRows)
+    return blas_update(h, A, nt, k0, kb, r0, cend, dnext, tol, repl, npert, st);
   const int64_t R = (rows - r0 + kTile - 1) / kTile, Cn = (cend - r0 + kTile - 1) / kTile;
   const int64_t ntiles = Cn * R - Cn * (Cn - 1) / 2;
   if (ntiles > 0x7fffffff) return api_fail(OPF_EINVAL, "chol: front too large");
@@ -936,7 +996,8 @@ int launch_update(const FrontArg& A, int nt, int k0, int kb, int r0, int cmax, i
 // half's first diagonal block), the second half.  The rows below the block
 // get their share of the panel through the panel kernels; the trailing
 // columns are left to the caller.
-int factor_cols(const FrontArg& A, int nt, int k, int w, double tol, double repl, int32_t* npert, hipStream_t st) {
+int factor_cols(const FrontArg& A, int nt, int k, int w, double tol, double repl, int32_t* npert, hipStream_t st,
+                rocblas_handle bh) {
   const int rows = A.p + A.u;
   if (k >= A.p) return OPF_OK;
   if (w == 64) {
@@ -948,18 +1009,19 @@ int factor_cols(const FrontArg& A, int nt, int k, int w, double tol, double repl
     return OPF_OK;
   }
   const int h = w / 2;
-  CHK(factor_cols(A, nt, k, h, tol, repl, npert, st));
+  CHK(factor_cols(A, nt, k, h, tol, repl, npert, st, bh));
   const int kh = std::min(h, A.p - k);
   const int k2 = std::min(h, A.p - k - kh);
   if (k2 > 0) {
     const int r1 = k + kh;
-    CHK(launch_update(A, nt, k, kh, r1, r1 + k2, std::min(64, k2), tol, repl, npert, st));
-    CHK(factor_cols(A, nt, r1, h, tol, repl, npert, st));
+    CHK(launch_update(A, nt, k, kh, r1, r1 + k2, std::min(64, k2), tol, repl, npert, st, bh));
+    CHK(factor_cols(A, nt, r1, h, tol, repl, npert, st, bh));
   }
   return OPF_OK;
 }
 
-int factor_front(const FrontArg& A, int nt, double tol, double repl, int32_t* npert, hipStream_t st) {
+int factor_front(const FrontArg& A, int nt, double tol, double repl, int32_t* npert, hipStream_t st,
+                 rocblas_handle bh) {
   const int rows = A.p + A.u;
   hipLaunchKernelGGL(k_diag, dim3(nt), dim3(64), 0, st, A, 0, std::min(64, A.p), tol, repl, npert);
   LAUNCH_OK("chol diagonal block");
@@ -967,10 +1029,10 @@ int factor_front(const FrontArg& A, int nt, double tol, double repl, int32_t* np
   // with the kStep-wide panel; every update launch also factors the next
   // diagonal block
   for (int k0 = 0; k0 < A.p; k0 += kStep) {
-    CHK(factor_cols(A, nt, k0, kStep, tol, repl, npert, st));
+    CHK(factor_cols(A, nt, k0, kStep, tol, repl, npert, st, bh));
     const int kb = std::min(kStep, A.p - k0), r0 = k0 + kb;
     const int dnext = r0 < A.p ? std::min(64, A.p - r0) : 0;
-    CHK(launch_update(A, nt, k0, kb, r0, rows, dnext, tol, repl, npert, st));
+    CHK(launch_update(A, nt, k0, kb, r0, rows, dnext, tol, repl, npert, st, bh));
   }
   return OPF_OK;
 }
@@ -1033,7 +1095,7 @@ int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double r
         A.Ustride = P.usize;
         A.ldU = std::max(1, P.node_u[s]);
         A.stop = C.dev.stop;
-        CHK(factor_front(A, nt, tol, repl, npert, fst));
+        CHK(factor_front(A, nt, tol, repl, npert, fst, F->blas));
       }
       for (int k = 0; k < nfs; ++k)
         if (hipEventRecord(F->join_ev[k], F->fs[k]) != hipSuccess ||
@@ -1068,7 +1130,7 @@ int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double r
       A.Ustride = 0;
       A.ldU = G;
       A.stop = C.dev.stop;
-      CHK(factor_front(A, 1, tol, repl, npert, F->cs));
+      CHK(factor_front(A, 1, tol, repl, npert, F->cs, F->blas));
     }
   }
   // the model's stream waits for the chain
@@ -1254,6 +1316,16 @@ int opf_chol_analyze(opf_model* model, opf_chol** out) {
         opf_chol_destroy(F);
         return api_fail(OPF_EHIP, "chol: stream or event creation failed");
       }
+      // OPF_CHOL_BLAS=0 keeps every trailing update on k_update
+      const char* eb = std::getenv("OPF_CHOL_BLAS");
+      if (!(eb && eb[0] == '0')) {
+        if (rocblas_create_handle(&F->blas) != rocblas_status_success ||
+            rocblas_set_atomics_mode(F->blas, rocblas_atomics_not_allowed) != rocblas_status_success ||
+            rocblas_set_pointer_mode(F->blas, rocblas_pointer_mode_host) != rocblas_status_success) {
+          opf_chol_destroy(F);
+          return api_fail(OPF_EHIP, "chol: rocBLAS handle creation failed");
+        }
+      }
     } else {
       for (auto& C : F->inst) {
         C.chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(C.plan.T, arena_budget() / (C.plan.usize * 8)));
@@ -1283,6 +1355,7 @@ void opf_chol_destroy(opf_chol* chol) {
     if (chol->join_ev[k]) (void)hipEventDestroy(chol->join_ev[k]);
     if (chol->fs[k]) (void)hipStreamDestroy(chol->fs[k]);
   }
+  if (chol->blas) (void)rocblas_destroy_handle(chol->blas);
   if (chol->cs) (void)hipStreamDestroy(chol->cs);
   if (chol->gs) (void)hipStreamDestroy(chol->gs);
   release(chol);

@@ -146,6 +146,32 @@ def test_chol_mid_backward_error(dev):
     M.close()
 
 
+def test_chain_library_updates_match_own_kernel(dev, monkeypatch):
+    """The mid grid's pg chain fronts (400 pivots, 400 update rows) send
+    their 256-column inner update to the library GEMM; with OPF_CHOL_BLAS=0
+    every update stays on the matrix-core kernel.  Both factors solve the
+    same system: solutions equal to 1e-10 of their largest entry (the two
+    products sum in different orders), bitwise the same run to run."""
+    import torch
+    from paper_2405_14032_amd import capi
+    nets = [synth.config_network("mid")]
+    inps = _inputs(nets, "well", 5)
+    M = capi.Model(nets, device=0)
+    M.use_current_torch_stream()
+    F = capi.Chol(M)
+    xa, na = _gpu_solve(M, F, inps, torch, dev)
+    xa2, _ = _gpu_solve(M, F, inps, torch, dev)
+    F.close()
+    monkeypatch.setenv("OPF_CHOL_BLAS", "0")
+    F = capi.Chol(M)
+    xk, nk = _gpu_solve(M, F, inps, torch, dev)
+    F.close()
+    M.close()
+    assert na == 0 and nk == 0
+    assert np.array_equal(xa, xa2)
+    assert np.max(np.abs(xa - xk)) <= 1e-10 * np.max(np.abs(xk))
+
+
 def test_chunked_periods_bitwise_equal(dev, monkeypatch):
     """Factoring the periods one or two at a time (a small workspace budget)
     gives the same bits as all at once."""
