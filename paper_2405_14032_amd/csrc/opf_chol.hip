@@ -43,14 +43,14 @@ constexpr int kStep = 1024;      // columns per trailing update of a blocked fro
 // columns go to the library's strided-batched GEMM (plain dense products);
 // smaller ones stay on k_update.
 constexpr int kBlasMinRows = 512;
-constexpr int kBlasMinCols = 128;
+constexpr int kBlasMinCols = 64;
 constexpr int kBlasCols = 512;  // target columns per library product
 // Only the pg chain's single-period fronts go to the library: one period
 // gives k_update too few tiles to fill the GPU, and the chain runs its
 // fronts in sequence (measured at paper scale: 1.132 -> 1.065 s per
-// factorization; the library on the batched interior fronts as well was
-// slower, its long-running blocks holding the CUs the chain's short
-// launches wait for).
+// factorization from 128 panel columns, 1.000 s from 64; the library on the
+// batched interior fronts as well was slower, its long-running blocks
+// holding the CUs the chain's short launches wait for).
 constexpr int kBlasMaxPeriods = 1;
 constexpr int kBwdCols = 16;     // earlier columns updated per block of a backward panel
 
