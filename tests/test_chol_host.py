@@ -94,6 +94,38 @@ def test_fronts_cover_the_exact_factor(name):
     M.close()
 
 
+@pytest.mark.parametrize("name", ["ragged", "paper"])
+def test_amalgamation_leaves_no_near_free_merge(name):
+    # merging child c into parent s adds c.p * (s.p + us - uc) explicit
+    # zeros (c's rows lie in s's front); the amalgamation takes any child
+    # within its 5 % budget, whatever the child's place among the parent's
+    # children, so no surviving pair may cost under 0.1 % of the merged
+    # front (within the pivot cap).  The rule that merged only the child
+    # preceding its parent in postorder left 33 such pairs on the paper grid
+    # (chains of 2-pivot fronts each passing on an update matrix of ~4500
+    # rows).
+    net = CASES[name]() if name in CASES else synth.make_network(10000, 13000, 2000, 2, 3)
+    M = capi.Model([net], device=-1)
+    F = capi.Chol(M)
+    tr = F.tree(0)
+    p = tr["npiv"].astype(np.int64)
+    u = np.diff(tr["rowptr"]).astype(np.int64)
+    par = tr["parent"]
+    cheap = []
+    for c in range(len(p)):
+        s = par[c]
+        if s < 0 or p[c] + p[s] > 4096:
+            continue
+        pm = p[c] + p[s]
+        added = p[c] * (p[s] + u[s] - u[c])
+        assert added >= 0
+        if added <= 1e-3 * (pm * (pm + 1) // 2 + pm * u[s]):
+            cheap.append((c, s, int(added)))
+    assert not cheap, cheap[:5]
+    F.close()
+    M.close()
+
+
 def test_fill_close_to_exact_minimum():
     # the stored factor (front blocks, explicit zeros included) stays within
     # 2x of the exact fill of the same order, and the order's fill within 2x
