@@ -271,7 +271,10 @@ int opf_eval_jhk(opf_model *model, const double *x, const double *lambda,
 
 /* Every requested output of one iteration's evaluation, enqueued as
  * persistent tile-list kernels covering all instances; when jvals, hvals and
- * kvals are all requested the fused pass of opf_eval_jhk is used. */
+ * kvals are all requested the fused pass of opf_eval_jhk is used.  With
+ * every output requested, the objective is summed inside the two sweep
+ * passes in their own tile order: equal to opf_eval_obj up to the rounding
+ * of a reordered sum, and bitwise equal from call to call. */
 int opf_sweep(opf_model *model, const opf_sweep_args *args);
 /* The same sweep recorded once into a HIP graph (re-recorded when the
  * argument set changes) and replayed with a single graph launch. */
@@ -285,7 +288,8 @@ int opf_sweep_graph(opf_model *model, const opf_sweep_args *args);
  * (no hipMalloc, no event creation) and only enqueues kernels on the model's
  * stream; the model is still created beforehand with opf_model_create.
  * Returns OPF_ERANGE when the model needs more scratch than the static array
- * holds (22 doubles per line-period plus one per objective tile: e.g. 2000
+ * holds (22 doubles per line-period, one per 64 generators and period, and
+ * one per tile of the separate objective pass: e.g. 2000
  * buses / 3200 lines over 24 periods fit, the 13000-line grid over 168
  * periods does not).  Every call on one device shares that array and it
  * keeps the last call's contents: calls that overlap on one device (two

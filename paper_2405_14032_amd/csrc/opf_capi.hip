@@ -139,7 +139,7 @@ struct opf_model {
   InstDev* d_inst = nullptr;
   std::vector<InstDev> h_dev;  // host mirror of d_inst
   double* scratch = nullptr;
-  int64_t scratch_doubles = 0;  // size of scratch (the hand-off records)
+  int64_t scratch_doubles = 0;  // size of scratch (hand-off records, sweep objective partials)
   double* wbuf = nullptr;  // [m]: row vector of the condensation calls
   double* obj_partial = nullptr;
   // the one-launch sweep (k_sweep): per-XCD work queues built from the
@@ -153,6 +153,9 @@ struct opf_model {
   size_t sw_smem = 0;
   int obj_partial_cap = 0;
   int32_t* d_obj_begin = nullptr;
+  // the objective folded into the two-launch sweep (ObjFold); false when
+  // the line pass's block is not whole wavefronts
+  bool of_ok = false;
   TileList lists[OP_COUNT];
   // graph-replayed sweep
   hipGraphExec_t gexec = nullptr;
@@ -394,6 +397,7 @@ int set_shape(opf_model* M, int op, const Shape& s) {
     }
     OPF_HIP(hipMemcpy(M->d_obj_begin, begin.data(), begin.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
+  if (op == OP_SWA) M->of_ok = s.block % 64 == 0;
   M->gvalid = false;
   if (op == OP_SWA) return build_fused(M);
   return OPF_OK;
@@ -697,6 +701,7 @@ int upload_model(opf_model* M) {
     d.k_off = I.k_off;
     d.ld_off = I.ld_off;
     d.s_off = I.s_off;
+    d.o_off = I.o_off;
     char* base = M->arena;
 #define PTR(field, T) d.field = reinterpret_cast<T>(base + p.field)
     PTR(f_bus, const int32_t*);
@@ -847,7 +852,7 @@ int check_sweep_args(const opf_sweep_args* a) {
 int enq_sweep(opf_model* M, const Work& w, const opf_sweep_args* a) {
   int rc;
   // every per-element output requested: two fused passes (lines and
-  // generators, then buses) plus the objective reduction
+  // generators, then buses) that also carry the objective
   if (a->grad && a->c && a->jvals && a->hvals && a->jtv && a->kvals && M->sw_ok && w.ctr) {
     // one launch for lines, generators and buses (the objective's partial
     // pass first, which also clears the launch's counters)
@@ -887,13 +892,21 @@ int enq_sweep(opf_model* M, const Work& w, const opf_sweep_args* a) {
     return OPF_OK;
   }
   if (a->grad && a->c && a->jvals && a->hvals && a->jtv && a->kvals) {
+    // the objective rides along in the two kernels when the tile lists allow
+    ObjFold of;
+    const bool fold = a->f && M->of_ok && M->lists[OP_SWA].n > 0 && M->lists[OP_SWB].n > 0;
+    if (fold) {
+      of.ninst = (int)M->inst.size();
+      of.ppt = M->lists[OP_SWA].shape.ppt;
+      of.f = a->f;
+    }
     { TimerScope ts_(M, OP_SWA); OPF_LAUNCHED(launch_sweep_a(launch_of(M, OP_SWA), a->x, a->lambda, a->sigma, a->v, a->hvals, a->jvals, a->diag_x,
                                 a->dcon, a->kvals, a->c, a->jtv, a->grad, w.scr),
                  "sweep line kernel"); }
     { TimerScope ts_(M, OP_SWB); OPF_LAUNCHED(launch_sweep_b(launch_of(M, OP_SWB), a->x, a->v, a->jvals, a->diag_x, a->dcon, a->kvals, a->c,
-                                a->jtv, a->grad, w.scr),
+                                a->jtv, a->grad, w.scr, of),
                  "sweep bus kernel"); }
-    if (a->f && (rc = enq_obj(M, w, a->x, a->f)) != OPF_OK) return rc;
+    if (a->f && !fold && (rc = enq_obj(M, w, a->x, a->f)) != OPF_OK) return rc;
     return OPF_OK;
   }
   // J, H and K together: the fused pass (K from the J / H values in registers)
@@ -995,7 +1008,7 @@ int opf_model_create(const opf_instance_desc* desc, int32_t ninst, int device, o
       return fail(rc, e);
     }
     size_t scr = 0;
-    for (const auto& I : M->inst) scr += (size_t)(kScratchPerLine * (int64_t)I.B * I.T + 7) / 8 * 8;
+    for (const auto& I : M->inst) scr += (size_t)(line_scratch_doubles(I.B, I.T) + obj_scratch_doubles(I.G, I.T));
     M->scratch_doubles = (int64_t)scr;
     if (device < kMaxDevices) {
       double* sp = nullptr;
@@ -1523,7 +1536,7 @@ extern "C" int opf_autotune(opf_model* M, const char* cache_path) {
         return launch_sweep_a(launch_of(M, op), x, lam, 1.0, lam, hv, jv, dx, d, kv, out_m, out_n, dx_out,
                               M->scratch);
       case OP_SWB:
-        return launch_sweep_b(launch_of(M, op), x, lam, jv, dx, d, kv, out_m, out_n, dx_out, M->scratch);
+        return launch_sweep_b(launch_of(M, op), x, lam, jv, dx, d, kv, out_m, out_n, dx_out, M->scratch, ObjFold{});
       case OP_JV:
         return launch_jv(launch_of(M, op), x, dx, out_m);
     }

@@ -13,7 +13,7 @@ namespace opf {
 struct InstDev {
   int32_t N, B, G, T, ref, pad;
   int64_t n_p, m_p, nnzj_p, nnzh_p, nnzk_p;
-  int64_t x_off, c_off, j_off, h_off, k_off, ld_off, s_off;
+  int64_t x_off, c_off, j_off, h_off, k_off, ld_off, s_off, o_off;
   const int32_t *f_bus, *t_bus, *gen_bus;
   const double* adm;  // [8][B]: Gff Bff Gft Bft Gtf Btf Gtt Btt
   const double *c2, *c1, *c0;
@@ -130,6 +130,11 @@ __device__ __forceinline__ double* shared_at(const InstDev& I, double* scr, int 
 __device__ __forceinline__ double* jt_at(const InstDev& I, double* scr, int t) {
   return scr + I.s_off + (int64_t)(kRecLine + kShared) * I.B * I.T + (int64_t)t * I.B * kScratchJt;
 }
+// Objective partials of the whole sweep, [t][64-generator chunk]: the slot of
+// the generator tile starting at period t (only tile starts are written).
+__device__ __forceinline__ int64_t obj_part_at(const InstDev& I, int t, int chunk) {
+  return I.o_off + (int64_t)t * ((I.G + 63) >> 6) + chunk;
+}
 
 // Kernel launchers (opf_kernels.hip).  Each takes the device instance
 // array, a device tile list and a launch shape; returns the HIP error of the
@@ -158,11 +163,24 @@ hipError_t launch_kkt_a(const Launch& L, const double* h, const double* j, const
                         double* k, double* scratch);
 hipError_t launch_jhk_a(const Launch& L, const double* x, const double* lam, double sigma, double* h, double* j,
                         const double* dx, const double* d, double* k, double* scratch);
+// The objective carried by the two sweep kernels instead of two launches of
+// its own: each wavefront of a generator tile of the line pass leaves the
+// sum of its 64 generators' cost terms over the tile's periods in the
+// instance's partial block of the scratch (obj_part_at), and the bus pass's
+// first blocks sum instance k's partials into f[k] in a fixed order.  ppt:
+// the line pass's periods per tile (its generator tiles start at multiples
+// of ppt and at multiples of 64 generators).  f null: no objective.
+struct ObjFold {
+  int ninst = 0;
+  int ppt = 0;
+  double* f = nullptr;
+};
 hipError_t launch_sweep_a(const Launch& L, const double* x, const double* lam, double sigma, const double* v,
                           double* h, double* j, const double* dx, const double* d, double* k, double* c, double* jtv,
                           double* g, double* scratch);
 hipError_t launch_sweep_b(const Launch& L, const double* x, const double* v, const double* j, const double* dx,
-                          const double* d, double* k, double* c, double* jtv, double* g, const double* scratch);
+                          const double* d, double* k, double* c, double* jtv, double* g, const double* scratch,
+                          const ObjFold& of);
 hipError_t launch_kkt_b(const Launch& L, const double* j, const double* dx, const double* d, double* k,
                         const double* scratch);
 // One iterate of the lifted interior-point method (device pointers over the

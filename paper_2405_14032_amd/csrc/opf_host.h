@@ -14,6 +14,11 @@ namespace opf {
 // Doubles of line scratch per line and period (the device layout: two
 // 64-byte end records, the shared cross pair, four J^T v hand-off values).
 constexpr int64_t kLineScratchDoubles = 22;
+// Doubles of one instance's scratch: the line hand-off, then the whole
+// sweep's objective partials ([T][one per 64 generators]), each block rounded
+// up to whole 64-byte lines.
+inline int64_t line_scratch_doubles(int64_t B, int64_t T) { return (kLineScratchDoubles * B * T + 7) / 8 * 8; }
+inline int64_t obj_scratch_doubles(int64_t G, int64_t T) { return (T * ((G + 63) / 64) + 7) / 8 * 8; }
 // Largest block of doubles that a 32-bit byte offset addresses; the kernels
 // reach each per-period block of x, c, J, H, K and the line scratch, and
 // each per-instance line table, through such an offset from the block base.
@@ -33,7 +38,8 @@ struct InstHost {
   int64_t n = 0, m = 0, nnzj = 0, nnzh = 0, nnzk = 0;
   // offsets of this instance in the concatenated arrays
   int64_t x_off = 0, c_off = 0, j_off = 0, h_off = 0, k_off = 0, ld_off = 0;
-  int64_t s_off = 0;  // scratch offset (doubles)
+  int64_t s_off = 0;  // scratch offset (doubles) of the line hand-off
+  int64_t o_off = 0;  // scratch offset (doubles) of the objective partials
 
   std::vector<int32_t> f_bus, t_bus, gen_bus;
   // pi-model admittances, 8 arrays of B: Gff Bff Gft Bft Gtf Btf Gtt Btt

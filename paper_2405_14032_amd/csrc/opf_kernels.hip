@@ -39,6 +39,14 @@ __device__ __forceinline__ int remap_tile(int v, int ntiles) {
   return v;
 }
 
+// Sum over the 64 lanes of a wavefront (butterfly order; lane 0's result is
+// the same on every run).  Every lane of the wavefront must take part.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 struct Coef {
   double S[4], al[4], be[4];
 };
@@ -958,7 +966,7 @@ __device__ void kkt_gen(const InstDev& I, int g, int t0, int t1, const double* _
 // output streams use non-temporal stores; values are the same expressions
 // as kkt_gen's.
 template <bool SWEEP>
-__device__ void fused_gen(const InstDev& I, int g, int t0, int t1, double sigma, double* __restrict__ H,
+__device__ double fused_gen(const InstDev& I, int g, int t0, int t1, double sigma, double* __restrict__ H,
                           double* __restrict__ J, const double* __restrict__ DX, const double* __restrict__ D,
                           double* __restrict__ K, const double* __restrict__ X, const double* __restrict__ V,
                           double* __restrict__ C, double* __restrict__ JTV, double* __restrict__ GR) {
@@ -969,8 +977,9 @@ __device__ void fused_gen(const InstDev& I, int g, int t0, int t1, double sigma,
   double* jr = J + I.j_off + (int64_t)I.T * I.nnzj_p;   // ramp block of J
   const double* dr = D + I.c_off + (int64_t)I.T * I.m_p;  // ramp rows of D
   const double hobj = 2.0 * sigma * I.c2[g];
-  const double c2g = SWEEP ? I.c2[g] : 0.0, c1g = SWEEP ? I.c1[g] : 0.0;
+  const double c2g = SWEEP ? I.c2[g] : 0.0, c1g = SWEEP ? I.c1[g] : 0.0, c0g = SWEEP ? I.c0[g] : 0.0;
   const double* vr = SWEEP ? V + I.c_off + (int64_t)I.T * I.m_p : nullptr;
+  double obj = 0.0;  // SWEEP: sum over the periods of c2 pg^2 + c1 pg + c0
   for (int t = t0; t < t1; ++t) {
     double* jp = J + I.j_off + (int64_t)t * I.nnzj_p;
     const double* dp = D + I.c_off + (int64_t)t * I.m_p;
@@ -1028,8 +1037,10 @@ __device__ void fused_gen(const InstDev& I, int g, int t0, int t1, double sigma,
       __builtin_nontemporal_store(vqn, JTV + xo + 2 * N + G + g);
       __builtin_nontemporal_store(2.0 * c2g * xg + c1g, GR + xo + rp);
       __builtin_nontemporal_store(0.0, GR + xo + rq);
+      obj += c2g * xg * xg + c1g * xg + c0g;
     }
   }
+  return obj;
 }
 
 // Streams a K row segment from LDS to HBM with consecutive lanes on
@@ -1528,7 +1539,12 @@ __global__ void __launch_bounds__(256) k_sweep_a(const InstDev* __restrict__ ins
       fused_line_tile<true>(I, tl, X, LAM, H, J, DX, D, K, scr, lds, lds + cap_seg, V, C, JTV, GR);
     } else {
       const int e = tl.e0 + (int)threadIdx.x;
-      if (e < tl.e1) fused_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K, X, V, C, JTV, GR);
+      double o = 0.0;
+      if (e < tl.e1) o = fused_gen<true>(I, e, tl.t0, tl.t1, sigma, H, J, DX, D, K, X, V, C, JTV, GR);
+      // the objective partial of this wavefront's 64 generators
+      o = wave_sum(o);
+      const int chunk = (tl.e0 + (int)(threadIdx.x & ~63u)) >> 6;
+      if ((threadIdx.x & 63) == 0 && chunk * 64 < I.G) scr[obj_part_at(I, tl.t0, chunk)] = o;
     }
   }
 }
@@ -1771,8 +1787,31 @@ __global__ void __launch_bounds__(512) k_sweep_b(const InstDev* __restrict__ ins
                                                  const double* __restrict__ DX, const double* __restrict__ D,
                                                  double* __restrict__ K, double* __restrict__ C,
                                                  double* __restrict__ JTV, double* __restrict__ GR,
-                                                 const double* __restrict__ scr) {
+                                                 const double* __restrict__ scr, const ObjFold of) {
   extern __shared__ double lds[];
+  if (of.f) {
+    // the objective: the line pass (the previous launch) left the partials
+    __shared__ double wred[8];
+    const int nw = (int)(blockDim.x >> 6);
+    for (int k = blockIdx.x; k < of.ninst; k += gridDim.x) {
+      const InstDev& I = insts[k];
+      const int nc = (I.G + 63) >> 6, ng = (I.T + of.ppt - 1) / of.ppt;
+      double acc = 0.0;
+      for (int q = (int)threadIdx.x; q < ng * nc; q += (int)blockDim.x) {
+        const int grp = q / nc;
+        acc += scr[obj_part_at(I, grp * of.ppt, q - grp * nc)];
+      }
+      acc = wave_sum(acc);
+      if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = acc;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += wred[w];
+        of.f[k] = s;
+      }
+      __syncthreads();
+    }
+  }
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile tl = tiles[remap_tile(v, ntiles)];
     bus_tile<true>(insts[tl.inst], tl, cap_vm, J, DX, D, K, scr, lds, X, V, C, JTV, GR);
@@ -2189,10 +2228,11 @@ hipError_t launch_sweep_a(const Launch& L, const double* x, const double* lam, d
   return hipGetLastError();
 }
 hipError_t launch_sweep_b(const Launch& L, const double* x, const double* v, const double* j, const double* dx,
-                          const double* d, double* k, double* c, double* jtv, double* g, const double* scratch) {
+                          const double* d, double* k, double* c, double* jtv, double* g, const double* scratch,
+                          const ObjFold& of) {
   if (L.ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sweep_b, grid_of(L), dim3((unsigned)L.block), L.smem, L.stream, L.insts, L.tiles, L.ntiles,
-                     L.cap0, x, v, j, dx, d, k, c, jtv, g, scratch);
+                     L.cap0, x, v, j, dx, d, k, c, jtv, g, scratch, of);
   return hipGetLastError();
 }
 hipError_t launch_kkt_b(const Launch& L, const double* j, const double* dx, const double* d, double* k,

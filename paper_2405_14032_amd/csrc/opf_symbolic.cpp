@@ -339,8 +339,10 @@ int assign_offsets(std::vector<InstHost>& insts, std::string& err) {
     ko += I.nnzk;
     lo += (int64_t)I.T * I.N;
     // hand-off scratch: 22 doubles per line-period (two 8-value end records,
-    // the shared cross pair, the separate J^T v record), rounded up to 64 B
-    so += (22LL * I.B * I.T + 7) / 8 * 8;
+    // the shared cross pair, the separate J^T v record), rounded up to 64 B;
+    // then the objective partials of the whole sweep
+    I.o_off = so + line_scratch_doubles(I.B, I.T);
+    so = I.o_off + obj_scratch_doubles(I.G, I.T);
   }
   if (xo > kI32Max || co > kI32Max) {
     err = "total variables / rows exceed int32 indices";

@@ -211,7 +211,7 @@ def test_fused_jhk_bitwise_equals_separate_calls(which, torch_dev):
 
 
 @pytest.mark.parametrize("which", ["mid", "batched"])
-def test_fused_sweep_bitwise_equals_separate_calls(which, torch_dev):
+def test_fused_sweep_equals_separate_calls(which, torch_dev):
     torch, dev = torch_dev
     capi = _capi()
     if which == "mid":
@@ -234,6 +234,17 @@ def test_fused_sweep_bitwise_equals_separate_calls(which, torch_dev):
     M.use_current_torch_stream()
     M.sweep(M.sweep_args(x=X, lam=LAM, sigma=0.37, v=V, diag_x=DX, dcon=D, **out))
     torch.cuda.synchronize()
-    for key, ek in (("f", "f"), ("grad", "grad"), ("c", "c"), ("jvals", "jac"), ("hvals", "hess"),
-                    ("jtv", "jtv"), ("kvals", "kkt")):
+    for key, ek in (("grad", "grad"), ("c", "c"), ("jvals", "jac"), ("hvals", "hess"), ("jtv", "jtv"),
+                    ("kvals", "kkt")):
         assert np.array_equal(out[key].cpu().numpy(), E[ek]), key
+    # the objective is summed in the sweep's own tile order (its generator
+    # tiles' partials), so it agrees with the objective call to rounding:
+    # the same terms, a different order
+    for k, (net, pt) in enumerate(zip(nets, pts)):
+        GC.assert_close(out["f"][k:k + 1].cpu().numpy(), E["f"][k:k + 1],
+                        np.array([O.objective_mag(net, pt.x)]), GC.TOL, f"[{k}] f")
+    f1 = out["f"].clone()
+    out["f"].fill_(float("nan"))
+    M.sweep(M.sweep_args(x=X, lam=LAM, sigma=0.37, v=V, diag_x=DX, dcon=D, **out))
+    torch.cuda.synchronize()
+    assert torch.equal(out["f"], f1)
