@@ -318,6 +318,19 @@ std::vector<Tile> make_tiles(const opf_model* M, int op, const Shape& s, std::ve
     }
   }
   begin[M->inst.size()] = (int32_t)out.size();
+  // Inside each XCD's run of the list (the kernels' remap_tile: XCD x takes
+  // positions [x q, (x + 1) q), q = n / 8, and the last n mod 8 come after
+  // them), generator tiles, the short ones, go after the others: a run then
+  // ends on short blocks instead of leaving its CUs idle behind the last long
+  // ones.  The per-instance begins stay those of the list before this step
+  // (only the single-kind lists use them).
+  if (kinds_of(op).size() > 1) {
+    const size_t n = out.size(), q = n / 8;
+    for (size_t x = 0; x <= 8; ++x) {
+      const size_t a = x < 8 ? x * q : 8 * q, b = x < 8 ? (x + 1) * q : n;
+      std::stable_partition(out.begin() + a, out.begin() + b, [](const Tile& t) { return t.kind != TK_GEN; });
+    }
+  }
   return out;
 }
 
