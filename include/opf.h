@@ -337,7 +337,8 @@ int opf_autotune(opf_model *model, const char *cache_path);
  * periods: the other variables first (approximate minimum degree), the pg
  * variables last; the interior fronts of all periods are factored together,
  * then the pg fronts form a chain over the periods (block elimination in
- * time).  Instances of a batched model are factored one after another. */
+ * time), eliminated from both ends of the horizon towards its middle period.
+ * Instances of a batched model are factored one after another. */
 typedef struct opf_chol opf_chol;
 
 typedef struct {
@@ -362,7 +363,7 @@ typedef struct {
  * workspace holds the fronts of as many periods as fit in 8 GiB (the
  * environment variable OPF_CHOL_ARENA_BYTES, read here, overrides the
  * budget); those periods are factored together.  The large trailing
- * updates of the pg chain's single-period fronts run as rocBLAS
+ * updates of the pg chain's fronts (one from each end per step) run as rocBLAS
  * strided-batched DGEMMs (atomics off: reproducible); OPF_CHOL_BLAS=0, read
  * here, keeps them on the library's own kernel. */
 int opf_chol_analyze(opf_model *model, opf_chol **out);

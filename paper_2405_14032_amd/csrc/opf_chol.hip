@@ -11,9 +11,12 @@
 //     work item owns a set of the parent's columns), is factored in place
 //     (small fronts in LDS by one wavefront, large ones by blocked panel +
 //     trailing-update kernels), batched over the periods of a chunk;
-//   * the pg front of period t (G pivots, update rows pg_{t+1}) collects the
-//     period's tree roots and the previous pg front's update: a chain over t
-//     (its large trailing updates as library GEMMs, see blas_update).
+//   * the pg front of period t (G pivots) collects the period's tree roots
+//     and its chain neighbour's update: a chain over t, eliminated from both
+//     ends at once (fronts t < m carry update rows pg_{t+1}, fronts t > m
+//     update rows pg_{t-1}, front m closes it; m = (T - 1) / 2), one front of
+//     each side per launch, its large trailing updates as library GEMMs (see
+//     blas_update).
 // Solves run the same tree forward (update vectors pulled by the parent)
 // and backward (gathers of the ancestors' solution), batched over periods.
 #include <hip/hip_runtime.h>
@@ -45,13 +48,13 @@ constexpr int kStep = 1024;      // columns per trailing update of a blocked fro
 constexpr int kBlasMinRows = 512;
 constexpr int kBlasMinCols = 64;
 constexpr int kBlasCols = 512;  // target columns per library product
-// Only the pg chain's single-period fronts go to the library: one period
-// gives k_update too few tiles to fill the GPU, and the chain runs its
-// fronts in sequence (measured at paper scale: 1.132 -> 1.065 s per
-// factorization from 128 panel columns, 1.000 s from 64; the library on the
-// batched interior fronts as well was slower, its long-running blocks
-// holding the CUs the chain's short launches wait for).
-constexpr int kBlasMaxPeriods = 1;
+// Only the pg chain's fronts (one or two periods per launch) go to the
+// library: so few periods give k_update too few tiles to fill the GPU, and
+// the chain runs its steps in sequence (measured at paper scale on the
+// one-ended chain: 1.132 -> 1.065 s per factorization from 128 panel
+// columns, 1.000 s from 64; the library on the batched interior fronts as
+// well was slower, its long-running blocks holding the CUs the chain's short
+// launches wait for).  The interior passes no library handle.
 constexpr int kBwdCols = 16;     // earlier columns updated per block of a backward panel
 
 // Device view of one instance's plan.
@@ -119,14 +122,18 @@ __global__ void k_scatter(const double* __restrict__ kv, int64_t k_off, int64_t 
   }
 }
 
-// The ramp pairs (pg_t,g , pg_{t-1},g), t in [t0, t1), t >= 1: entries of
-// the L21 block of pg front t-1 (row G + g, column g).
+// The ramp pairs (pg_t,g , pg_{t-1},g), t in [t0, t0 + gridDim.y), t >= 1:
+// entries of the L21 block (row G + g, column g) of the one of the two pg
+// fronts that the chain eliminates first: front t-1 when t <= m (the chain's
+// left side), front t otherwise (its right side).
 __global__ void k_scatter_ramp(const double* __restrict__ kv, int64_t k_off, int64_t nnzk_p, int32_t G, int32_t t0,
-                               const int32_t* __restrict__ ramp_pos, double* __restrict__ Cf, int64_t csize) {
+                               int32_t m, const int32_t* __restrict__ ramp_pos, double* __restrict__ Cf,
+                               int64_t csize) {
   const int t = t0 + (int)blockIdx.y;
   const int64_t kp = k_off + (int64_t)t * nnzk_p + (int64_t)(t - 1) * G;
+  const int f = t <= m ? t - 1 : t;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x)
-    Cf[(int64_t)(t - 1) * csize + (int64_t)g * 2 * G + G + g] = kv[kp + ramp_pos[g]];
+    Cf[(int64_t)f * csize + (int64_t)g * 2 * G + G + g] = kv[kp + ramp_pos[g]];
 }
 
 // Extend-add for the fronts of one level: work item (s, c0) owns columns
@@ -777,7 +784,7 @@ struct opf_chol {
   opf_model* model = nullptr;
   int device = -1;
   std::vector<CholInst> inst;
-  double* Us = nullptr;  // G x G update block of the pg chain (largest G)
+  double* Us = nullptr;  // two G x G update blocks of the pg chain, one per end (largest G)
   // the pg chain runs on a stream of its own, chunk by chunk, behind the
   // interior fronts of the next chunk (events order the two)
   hipStream_t cs = nullptr;
@@ -979,7 +986,7 @@ int launch_update(const FrontArg& A, int nt, int k0, int kb, int r0, int cmax, i
     }
     return OPF_OK;
   }
-  if (h && nt <= kBlasMaxPeriods && kb >= kBlasMinCols && rows - r0 >= kBlasMinRows)
+  if (h && kb >= kBlasMinCols && rows - r0 >= kBlasMinRows)
     return blas_update(h, A, nt, k0, kb, r0, cend, dnext, tol, repl, npert, st);
   const int64_t R = (rows - r0 + kTile - 1) / kTile, Cn = (cend - r0 + kTile - 1) / kTile;
   const int64_t ntiles = Cn * R - Cn * (Cn - 1) / 2;
@@ -1050,12 +1057,80 @@ int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double r
   // interior runs
   if (T > 1) {
     hipLaunchKernelGGL(k_scatter_ramp, dim3(grid_for(G, 256), T - 1), dim3(256), 0, st, kv, I.k_off, I.nnzk_p, G, 1,
-                       C.d_ramp, C.Cf, C.csize);
+                       (T - 1) / 2, C.d_ramp, C.Cf, C.csize);
     LAUNCH_OK("chol ramp scatter");
   }
   const int nslots = (int)P.slot_dst.size();
-  int chunk_id = 0;
-  for (int t0 = 0; t0 < T; t0 += C.chunk, ++chunk_id) {
+  // The pg chain from both ends: left fronts kl = 0 .. m-1, right fronts
+  // kr = T-1 .. m+1, a left and a right front per step while both sides
+  // have one ready, then front m.  The interior chunks are taken from both
+  // ends of the horizon in turn so that both sides become ready together.
+  const int m = (T - 1) / 2;
+  const int nchunk = (T + C.chunk - 1) / C.chunk;
+  std::vector<int> corder;
+  for (int a = 0, b = nchunk - 1; a <= b; ++a, --b) {
+    corder.push_back(a);
+    if (b != a) corder.push_back(b);
+  }
+  std::vector<char> ready(T, 0);
+  int kl = 0, kr = T - 1;
+  double* UsL = F->Us;
+  double* UsR = F->Us + (int64_t)G * G;
+  const int64_t gg = (int64_t)G * G;
+  // front t's incoming chain update (from t-1 on the left, t+1 on the
+  // right) into its pivot block
+  auto add_in = [&](int t, const double* Ub) -> int {
+    hipLaunchKernelGGL(k_add_chain, dim3(grid_for(gg, 256)), dim3(256), 0, F->cs, Ub, G, C.Cf + (int64_t)t * C.csize);
+    LAUNCH_OK("chol chain add");
+    return OPF_OK;
+  };
+  auto clear = [&](double* Ub, int64_t n) -> int {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, F->cs, Ub, n);
+    LAUNCH_OK("chol chain clear");
+    return OPF_OK;
+  };
+  // nt = 2: fronts kl and kr in one batch (period stride kr - kl)
+  auto chain_front = [&](int t, int nt, int t2, int u, double* Ub) -> int {
+    FrontArg A;
+    A.L = C.Cf + (int64_t)t * C.csize;
+    A.Lstride = nt > 1 ? (int64_t)(t2 - t) * C.csize : 0;
+    A.ld = 2 * G;
+    A.p = G;
+    A.u = u;
+    A.U = Ub;
+    A.Ustride = nt > 1 ? gg : 0;
+    A.ldU = G;
+    A.stop = C.dev.stop;
+    return factor_front(A, nt, tol, repl, npert, F->cs, F->blas);
+  };
+  auto chain_steps = [&](bool all) -> int {
+    for (;;) {
+      const bool l = kl < m && ready[kl], r = kr > m && ready[kr];
+      if (l && r) {
+        if (kl >= 1) CHK(add_in(kl, UsL));
+        if (kr <= T - 2) CHK(add_in(kr, UsR));
+        CHK(clear(F->Us, 2 * gg));
+        CHK(chain_front(kl, 2, kr, G, UsL));
+        ++kl;
+        --kr;
+      } else if (l && (kr <= m || all)) {
+        if (kl >= 1) CHK(add_in(kl, UsL));
+        CHK(clear(UsL, gg));
+        CHK(chain_front(kl, 1, kl, G, UsL));
+        ++kl;
+      } else if (r && (kl >= m || all)) {
+        if (kr <= T - 2) CHK(add_in(kr, UsR));
+        CHK(clear(UsR, gg));
+        CHK(chain_front(kr, 1, kr, G, UsR));
+        --kr;
+      } else {
+        break;
+      }
+    }
+    return OPF_OK;
+  };
+  for (int chunk_id = 0; chunk_id < nchunk; ++chunk_id) {
+    const int t0 = corder[chunk_id] * C.chunk;
     const int nt = std::min(C.chunk, T - t0);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(nslots, 256), nt), dim3(256), 0, st, kv, I.k_off, I.nnzk_p, G, t0,
                        nslots, C.d_slot, C.d_kpos0, C.d_kpos1, C.Lf, P.lsize, C.Cf, C.csize);
@@ -1095,7 +1170,7 @@ int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double r
         A.Ustride = P.usize;
         A.ldU = std::max(1, P.node_u[s]);
         A.stop = C.dev.stop;
-        CHK(factor_front(A, nt, tol, repl, npert, fst, F->blas));
+        CHK(factor_front(A, nt, tol, repl, npert, fst, nullptr));
       }
       for (int k = 0; k < nfs; ++k)
         if (hipEventRecord(F->join_ev[k], F->fs[k]) != hipSuccess ||
@@ -1106,33 +1181,16 @@ int factor_inst(opf_chol* F, CholInst& C, const double* kv, double tol, double r
     hipLaunchKernelGGL(k_extend_root, dim3((G + cb - 1) / cb, nt), dim3(256), 0, st, C.dev, C.d_roots,
                        (int32_t)P.roots.size(), cb, t0, C.Cf, C.csize, C.Ar);
     LAUNCH_OK("chol pg front assembly");
-    // the chunk's periods along the pg chain, on the chain stream
+    // the chain steps this chunk makes ready, on the chain stream
     if (hipEventRecord(F->evs[chunk_id], st) != hipSuccess || hipStreamWaitEvent(F->cs, F->evs[chunk_id], 0) != hipSuccess)
       return api_fail(OPF_EHIP, "chol: chain stream ordering");
-    for (int t = t0; t < t0 + nt; ++t) {
-      double* Ct = C.Cf + (int64_t)t * C.csize;
-      if (t >= 1) {
-        hipLaunchKernelGGL(k_add_chain, dim3(grid_for((int64_t)G * G, 256)), dim3(256), 0, F->cs, F->Us, G, Ct);
-        LAUNCH_OK("chol chain add");
-      }
-      const int u = t + 1 < T ? G : 0;
-      if (u) {
-        hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)G * G, 256)), dim3(256), 0, F->cs, F->Us, (int64_t)G * G);
-        LAUNCH_OK("chol chain clear");
-      }
-      FrontArg A;
-      A.L = Ct;
-      A.Lstride = 0;
-      A.ld = 2 * G;
-      A.p = G;
-      A.u = u;
-      A.U = F->Us;
-      A.Ustride = 0;
-      A.ldU = G;
-      A.stop = C.dev.stop;
-      CHK(factor_front(A, 1, tol, repl, npert, F->cs, F->blas));
-    }
+    for (int t = t0; t < t0 + nt; ++t) ready[t] = 1;
+    CHK(chain_steps(chunk_id + 1 == nchunk));
   }
+  // front m: both sides' last updates, no update rows
+  if (m >= 1) CHK(add_in(m, UsL));
+  if (m + 1 <= T - 1) CHK(add_in(m, UsR));
+  CHK(chain_front(m, 1, m, 0, UsL));
   // the model's stream waits for the chain
   hipEvent_t done = F->evs.back();
   if (hipEventRecord(done, F->cs) != hipSuccess || hipStreamWaitEvent(st, done, 0) != hipSuccess)
@@ -1194,30 +1252,73 @@ int solve_inst(CholInst& C, const double* b, double* x, hipStream_t st) {
   hipLaunchKernelGGL(k_fwd_root_pull, dim3(T), dim3(256), 0, st, C.dev, C.d_roots, (int32_t)P.roots.size(), C.Y,
                      (const double*)C.W);
   LAUNCH_OK("chol forward roots");
-  // forward along the pg chain
-  for (int t = 0; t < T; ++t) {
-    const double* Ct = C.Cf + (int64_t)t * C.csize;
-    const int64_t o = (int64_t)t * np + P.n_int;
-    if (t >= 1) hipLaunchKernelGGL(k_sub, dim3((G + 255) / 256), dim3(256), 0, st, C.Y + o, (const double*)(C.Wc + (int64_t)(t - 1) * G), G);
-    CHK(fwd_tri(Ct, 0, 2 * G, G, C.Y + o, C.Z + o, 0, 1, st));
-    if (t + 1 < T) {
-      const int nch = (G + kChainCols - 1) / kChainCols;
-      hipLaunchKernelGGL(k_gemv_part, dim3((G + 255) / 256, nch), dim3(256), 0, st, Ct, 2 * G, G, G,
-                         (const double*)(C.Z + o), kChainCols, C.Gp);
-      hipLaunchKernelGGL(k_gemv_sum, dim3((G + 255) / 256), dim3(256), 0, st, (const double*)C.Gp, nch, G,
-                         C.Wc + (int64_t)t * G);
-    }
+  // forward along the pg chain, from both ends as it was factored: left
+  // fronts ascending, right fronts descending, a left and a right front per
+  // step while both sides have one, then front m
+  const int m = (T - 1) / 2;
+  auto off = [&](int t) { return (int64_t)t * np + P.n_int; };
+  auto front = [&](int t) { return (const double*)(C.Cf + (int64_t)t * C.csize); };
+  // y_t -= L21_s z_s of its chain neighbour s (held in Wc[s])
+  auto pull = [&](int t, int s) -> int {
+    hipLaunchKernelGGL(k_sub, dim3((G + 255) / 256), dim3(256), 0, st, C.Y + off(t),
+                       (const double*)(C.Wc + (int64_t)s * G), G);
     LAUNCH_OK("chol forward chain");
+    return OPF_OK;
+  };
+  // Wc[t] = L21_t z_t
+  auto push = [&](int t) -> int {
+    const int nch = (G + kChainCols - 1) / kChainCols;
+    hipLaunchKernelGGL(k_gemv_part, dim3((G + 255) / 256, nch), dim3(256), 0, st, front(t), 2 * G, G, G,
+                       (const double*)(C.Z + off(t)), kChainCols, C.Gp);
+    hipLaunchKernelGGL(k_gemv_sum, dim3((G + 255) / 256), dim3(256), 0, st, (const double*)C.Gp, nch, G,
+                       C.Wc + (int64_t)t * G);
+    LAUNCH_OK("chol forward chain");
+    return OPF_OK;
+  };
+  {
+    int kl = 0, kr = T - 1;
+    while (kl < m || kr > m) {
+      const bool l = kl < m, r = kr > m;
+      if (l && kl >= 1) CHK(pull(kl, kl - 1));
+      if (r && kr <= T - 2) CHK(pull(kr, kr + 1));
+      if (l && r)
+        CHK(fwd_tri(front(kl), (int64_t)(kr - kl) * C.csize, 2 * G, G, C.Y + off(kl), C.Z + off(kl),
+                    (int64_t)(kr - kl) * np, 2, st));
+      else
+        CHK(fwd_tri(front(l ? kl : kr), 0, 2 * G, G, C.Y + off(l ? kl : kr), C.Z + off(l ? kl : kr), 0, 1, st));
+      if (l) CHK(push(kl));
+      if (r) CHK(push(kr));
+      if (l) ++kl;
+      if (r) --kr;
+    }
+    if (m >= 1) CHK(pull(m, m - 1));
+    if (m + 1 <= T - 1) CHK(pull(m, m + 1));
+    CHK(fwd_tri(front(m), 0, 2 * G, G, C.Y + off(m), C.Z + off(m), 0, 1, st));
   }
-  // backward along the pg chain
-  for (int t = T - 1; t >= 0; --t) {
-    const double* Ct = C.Cf + (int64_t)t * C.csize;
-    const int64_t o = (int64_t)t * np + P.n_int;
-    if (t + 1 < T)
-      hipLaunchKernelGGL(k_bwd_gemv, dim3((G + 3) / 4, 1), dim3(256), 0, st, Ct, (int64_t)0, 2 * G, G, G,
-                         (const int32_t*)nullptr, (const double*)(C.Y + o + np), (int64_t)0, C.Z + o, (int64_t)0);
-    CHK(bwd_tri(Ct, 0, 2 * G, G, C.Y + o, C.Z + o, 0, 1, st));
-    LAUNCH_OK("chol backward chain");
+  // backward along the pg chain: front m, then outwards (each front reads
+  // its chain neighbour's solution, held in Y)
+  {
+    CHK(bwd_tri(front(m), 0, 2 * G, G, C.Y + off(m), C.Z + off(m), 0, 1, st));
+    int kl = m - 1, kr = m + 1;
+    while (kl >= 0 || kr <= T - 1) {
+      const bool l = kl >= 0, r = kr <= T - 1;
+      if (l)
+        hipLaunchKernelGGL(k_bwd_gemv, dim3((G + 3) / 4, 1), dim3(256), 0, st, front(kl), (int64_t)0, 2 * G, G, G,
+                           (const int32_t*)nullptr, (const double*)(C.Y + off(kl + 1)), (int64_t)0, C.Z + off(kl),
+                           (int64_t)0);
+      if (r)
+        hipLaunchKernelGGL(k_bwd_gemv, dim3((G + 3) / 4, 1), dim3(256), 0, st, front(kr), (int64_t)0, 2 * G, G, G,
+                           (const int32_t*)nullptr, (const double*)(C.Y + off(kr - 1)), (int64_t)0, C.Z + off(kr),
+                           (int64_t)0);
+      LAUNCH_OK("chol backward chain");
+      if (l && r)
+        CHK(bwd_tri(front(kl), (int64_t)(kr - kl) * C.csize, 2 * G, G, C.Y + off(kl), C.Z + off(kl),
+                    (int64_t)(kr - kl) * np, 2, st));
+      else
+        CHK(bwd_tri(front(l ? kl : kr), 0, 2 * G, G, C.Y + off(l ? kl : kr), C.Z + off(l ? kl : kr), 0, 1, st));
+      if (l) --kl;
+      if (r) ++kr;
+    }
   }
   // backward through the interior trees, top down
   for (int h = P.nlevels - 1; h >= 0; --h) {
@@ -1292,7 +1393,7 @@ int opf_chol_analyze(opf_model* model, opf_chol** out) {
         }
         F->arena_entries += C.plan.usize * C.chunk;
       }
-      const int rc = dalloc(F, (int64_t)maxG * maxG, &F->Us);
+      const int rc = dalloc(F, 2 * (int64_t)maxG * maxG, &F->Us);
       if (rc != OPF_OK) {
         release(F);
         delete F;
