@@ -360,7 +360,7 @@ typedef struct {
  * failure); it refers to the model, which must outlive it.  Errors:
  * OPF_EINVAL (NULL arguments, a front too large for the kernels),
  * OPF_ENOMEM (host or device allocation), OPF_EHIP.  The update-matrix
- * workspace holds the fronts of as many periods as fit in 8 GiB (the
+ * workspace holds the fronts of as many periods as fit in 16 GiB (the
  * environment variable OPF_CHOL_ARENA_BYTES, read here, overrides the
  * budget); those periods are factored together.  The large trailing
  * updates of the pg chain's fronts (one from each end per step) run as rocBLAS
