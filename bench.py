@@ -588,8 +588,8 @@ def bench_batched(torch, dev, args):
            "plain_64_ms": round(p_ms, 4), "speedup_vs_plain": round(p_ms / g_ms, 3),
            "nnz_per_s": nnz / (g_ms / 1e3), "sweep_bytes": sweep_bytes, "hbm_gbs": round(gbs, 1),
            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
-           "launches": "one HIP graph of four tile-list kernels (objective partials, line/generator pass, bus "
-                       "pass, objective sums) over all 64 instances, one block per tile",
+           "launches": "one HIP graph of two tile-list kernels (line/generator pass with the objective's "
+                       "partials, bus pass with its sums) over all 64 instances, one block per tile",
            "elements_bit_identical": identical, "objective_max_rel_diff": worst_f}
     for Mk, *_ in plain:
         Mk.close()
