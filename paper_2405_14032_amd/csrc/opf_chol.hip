@@ -55,7 +55,7 @@ constexpr int kBlasCols = 512;  // target columns per library product
 // columns, 1.000 s from 64; the library on the batched interior fronts as
 // well was slower, its long-running blocks holding the CUs the chain's short
 // launches wait for).  The interior passes no library handle.
-constexpr int kBwdCols = 16;     // earlier columns updated per block of a backward panel
+constexpr int kBwdCols = 16;     // earlier columns updated per block of a backward panel (a multiple of 4)
 
 // Device view of one instance's plan.
 struct CDev {
@@ -597,6 +597,13 @@ __global__ void __launch_bounds__(256) k_fwd_panel(const double* __restrict__ Lb
   double* z = zb + (int64_t)blockIdx.y * ystride;
   const int tid = (int)threadIdx.x;
   const int kb = min(64, p - k0);
+  // this thread's row of the panel below the triangle, loaded first so that
+  // its latency overlaps the triangle (summed in column order afterwards)
+  const int i = k0 + kb + (int)blockIdx.x * (int)blockDim.x + tid;
+  const bool row = i < p;
+  double rv[64];
+#pragma unroll
+  for (int l = 0; l < 64; ++l) rv[l] = (row && l < kb) ? L[(int64_t)(k0 + l) * ld + i] : 0.0;
   for (int e = tid; e < 64 * 64; e += (int)blockDim.x) {
     const int c = e >> 6, r = e & 63;
     if (c < kb && r < kb && r >= c) Tr[c * 65 + r] = L[(int64_t)(k0 + c) * ld + k0 + r];
@@ -616,10 +623,11 @@ __global__ void __launch_bounds__(256) k_fwd_panel(const double* __restrict__ Lb
     if (blockIdx.x == 0 && tid < kb) z[k0 + tid] = vi;
   }
   __syncthreads();
-  const int i = k0 + kb + (int)blockIdx.x * (int)blockDim.x + tid;
-  if (i < p) {
+  if (row) {
     double acc = 0.0;
-    for (int l = 0; l < kb; ++l) acc += L[(int64_t)(k0 + l) * ld + i] * xs[l];
+#pragma unroll
+    for (int l = 0; l < 64; ++l)
+      if (l < kb) acc += rv[l] * xs[l];
     y[i] -= acc;
   }
 }
@@ -695,6 +703,16 @@ __global__ void __launch_bounds__(256) k_bwd_panel(const double* __restrict__ Lb
   double* z = zb + (int64_t)blockIdx.y * ystride;
   const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int kb = min(64, p - k0);
+  // this wavefront's columns j < k0 (jb + wv, + 4, ...): their panel
+  // entries, loaded first so that their latency overlaps the triangle
+  const int jb = (int)blockIdx.x * kBwdCols, je = min(jb + kBwdCols, k0);
+  constexpr int kPerWave = kBwdCols / 4;
+  double cv[kPerWave];
+#pragma unroll
+  for (int q = 0; q < kPerWave; ++q) {
+    const int j = jb + wv + 4 * q;
+    cv[q] = (j < je && lane < kb) ? L[(int64_t)j * ld + k0 + lane] : 0.0;
+  }
   for (int e = tid; e < 64 * 64; e += (int)blockDim.x) {
     const int c = e >> 6, r = e & 63;
     if (c < kb && r < kb && r >= c) Tr[c * 65 + r] = L[(int64_t)(k0 + c) * ld + k0 + r];
@@ -712,11 +730,14 @@ __global__ void __launch_bounds__(256) k_bwd_panel(const double* __restrict__ Lb
     if (blockIdx.x == 0 && tid < kb) y[k0 + tid] = vj;
   }
   __syncthreads();
-  const int jb = (int)blockIdx.x * kBwdCols;
-  for (int j = jb + wv; j < min(jb + kBwdCols, k0); j += 4) {
-    double acc = lane < kb ? L[(int64_t)j * ld + k0 + lane] * xs[lane] : 0.0;
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) z[j] -= acc;
+#pragma unroll
+  for (int q = 0; q < kPerWave; ++q) {
+    const int j = jb + wv + 4 * q;
+    if (j < je) {
+      double acc = lane < kb ? cv[q] * xs[lane] : 0.0;
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if (lane == 0) z[j] -= acc;
+    }
   }
 }
 
