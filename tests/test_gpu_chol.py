@@ -34,6 +34,8 @@ CASES = {
                                              pd=np.full((3, 4), 0.2))],
     "hub": lambda: [pins.hub_network()],
     "single_period": lambda: [synth.make_network(57, 80, 11, 1, 73)],
+    # an even horizon: the pg chain's right side has one front more than its left
+    "even_horizon": lambda: [synth.make_network(120, 170, 24, 8, 43)],
     "isolated_bus": lambda: [pins.manual_network(4, [0, 1], [1, 2], [0.01, 0.02], [0.1, 0.2], [0.02, 0.01], [0, 2], T=3,
                                                  pd=np.full((3, 4), 0.3))],
     "batched": lambda: [synth.make_network(31, 45, 7, 3, 71), synth.make_network(14, 20, 5, 5, 72),
@@ -172,12 +174,16 @@ def test_chain_library_updates_match_own_kernel(dev, monkeypatch):
     assert np.max(np.abs(xa - xk)) <= 1e-10 * np.max(np.abs(xk))
 
 
-def test_chunked_periods_bitwise_equal(dev, monkeypatch):
-    """Factoring the periods one or two at a time (a small workspace budget)
-    gives the same bits as all at once."""
+@pytest.mark.parametrize("T", [7, 8])
+def test_chunked_periods_bitwise_equal(T, dev, monkeypatch):
+    """Factoring the periods one at a time (a small workspace budget) gives
+    the same bits as all at once.  The pg chain is eliminated from both ends
+    of the horizon, a front of each side per step: with T = 8 the right side
+    has one front more, factored alone after the pairs, whatever order the
+    chunks make its periods ready in."""
     import torch
     from paper_2405_14032_amd import capi
-    nets = [synth.make_network(301, 517, 63, 7, 41)]
+    nets = [synth.make_network(301, 517, 63, T, 41)]
     inps = _inputs(nets, "well", 5)
     M = capi.Model(nets, device=0)
     M.use_current_torch_stream()
@@ -187,7 +193,7 @@ def test_chunked_periods_bitwise_equal(dev, monkeypatch):
     F.close()
     monkeypatch.setenv("OPF_CHOL_ARENA_BYTES", "1")
     F = capi.Chol(M)
-    assert F.info()["chunk"] == 1 and full == 7
+    assert F.info()["chunk"] == 1 and full == T
     x2, _ = _gpu_solve(M, F, inps, torch, dev)
     assert np.array_equal(x1, x2)
     F.close()
